@@ -1,0 +1,91 @@
+"""Seeded ray sets: origins and unit directions, float32, structure of arrays ``[3][N]``.
+
+Directions are drawn uniformly on the unit sphere as normalised Gaussian
+triples (Muller's method) and stored as float32 vectors; converting them to the
+(polar, azimuth) angles the network takes is a step of the method and is not
+done here.
+
+* ``uniform_cube_rays``: origin ~ U([-1,1]^3), direction uniform on S^2.  Draw
+  order: origins (N x 3), then Gaussian directions (N x 3).
+* ``unit_ball_rays``: origin uniform in the unit ball (radius u^(1/3) times a
+  uniform direction), direction uniform on S^2.
+* ``training_rays``: the training-ray recipe, half surface-anchored and half
+  uniform in the unit ball.  A surface-anchored ray picks a triangle with
+  probability proportional to its area, a point with barycentrics
+  (1 - sqrt(u1), sqrt(u1) (1 - u2), sqrt(u1) u2), a direction uniform on S^2,
+  and backs the origin off along the ray by s ~ U(0.05, 2), shortened where
+  needed so that the origin stays inside the cube [-1,1]^3.  Rays whose origin
+  lies inside the mesh are not removed here: the labeller's crossing count
+  decides that, and the training loop drops them.
+"""
+import numpy as np
+
+
+def _unit_dirs(rng, n):
+    g = rng.normal(size=(n, 3))
+    nrm = np.linalg.norm(g, axis=1, keepdims=True)
+    nrm[nrm == 0] = 1.0
+    return g / nrm
+
+
+def _soa(o, d):
+    return (np.ascontiguousarray(o.T.astype(np.float32)), np.ascontiguousarray(d.T.astype(np.float32)))
+
+
+def uniform_cube_rays(n, seed):
+    rng = np.random.default_rng(seed)
+    o = rng.uniform(-1.0, 1.0, size=(n, 3))
+    d = _unit_dirs(rng, n)
+    return _soa(o, d)
+
+
+def _ball_points(rng, n):
+    r = rng.random(n) ** (1.0 / 3.0)
+    return _unit_dirs(rng, n) * r[:, None]
+
+
+def unit_ball_rays(n, seed):
+    rng = np.random.default_rng(seed)
+    o = _ball_points(rng, n)
+    d = _unit_dirs(rng, n)
+    return _soa(o, d)
+
+
+def area_weighted_surface_points(v, f, n, rng):
+    """Points on the mesh surface: triangle chosen with probability proportional to area."""
+    a, b, c = v[f[:, 0]], v[f[:, 1]], v[f[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    p = area / area.sum()
+    tri = rng.choice(len(f), size=n, p=p)
+    u1, u2 = rng.random(n), rng.random(n)
+    s1 = np.sqrt(u1)
+    w0, w1, w2 = 1.0 - s1, s1 * (1.0 - u2), s1 * u2
+    q = w0[:, None] * a[tri] + w1[:, None] * b[tri] + w2[:, None] * c[tri]
+    return q, tri
+
+
+def _max_backoff(q, d):
+    """Largest s >= 0 with q - s d inside [-1,1]^3 (q is inside the cube)."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lim = np.where(d > 0, (q + 1.0) / d, np.where(d < 0, (q - 1.0) / d, np.inf))
+    return lim.min(axis=1)
+
+
+def training_rays(v, f, n, seed):
+    """Returns ``(orig [3][n], dirs [3][n], anchored bool [n])``; the first half is surface-anchored."""
+    rng = np.random.default_rng(seed)
+    n_s = n // 2
+    q, _ = area_weighted_surface_points(v, f, n_s, rng)
+    d_s = _unit_dirs(rng, n_s)
+    s = rng.uniform(0.05, 2.0, size=n_s)
+    s = np.minimum(s, _max_backoff(q, d_s))
+    o_s = q - s[:, None] * d_s
+    o_u = _ball_points(rng, n - n_s)
+    d_u = _unit_dirs(rng, n - n_s)
+    o = np.concatenate([o_s, o_u])
+    d = np.concatenate([d_s, d_u])
+    o = np.clip(o, -1.0, 1.0)
+    anchored = np.zeros(n, dtype=bool)
+    anchored[:n_s] = True
+    oo, dd = _soa(o, d)
+    return oo, dd, anchored

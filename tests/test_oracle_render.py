@@ -1,0 +1,123 @@
+"""Pins of the render oracle: published SplitMix64 outputs, sampling invariants, and the
+closed-form single-bounce image of a lit quad (ray/plane intersection, no triangle test)."""
+import json
+import os
+
+import numpy as np
+
+import synthetic
+from oracle import render
+
+from conftest import GOLDEN
+
+
+def test_splitmix64_published_outputs():
+    g = json.load(open(os.path.join(GOLDEN, "splitmix64.json")))
+    for s in g["streams"]:
+        out = render.splitmix64_stream(s["seed"], len(s.get("outputs_hex", s.get("outputs", []))))
+        if "outputs_hex" in s:
+            assert [int(x, 16) for x in s["outputs_hex"]] == out
+        else:
+            assert s["outputs"] == out
+
+
+def test_counter_uniforms_vectorised_equal_scalar():
+    pix = np.arange(50, dtype=np.int64)
+    smp = (pix * 7) % 5
+    keys = render.path_keys(9, pix, smp)
+    u = render.uniform(keys, 2, 3)
+    for i in range(50):
+        assert u[i] == render.uniform_scalar(9, int(pix[i]), int(smp[i]), 2, 3)
+    # exact multiples of 2^-24 in [0, 1)
+    big = render.uniform(render.path_keys(1, np.arange(100000), np.zeros(100000, np.int64)), 0, 0)
+    assert np.all((big >= 0) & (big < 1))
+    assert np.all(big * 2 ** 24 == np.floor(big * 2 ** 24))
+    assert abs(big.mean() - 0.5) < 0.005
+
+
+def test_onb_and_cosine_sampling():
+    rng = np.random.default_rng(0)
+    n = rng.normal(size=(3, 20000))
+    n /= np.linalg.norm(n, axis=0)
+    b1, b2 = render.onb_duff(n)
+    for a, b in [(b1, b2), (b1, n), (b2, n)]:
+        np.testing.assert_allclose(np.sum(a * b, axis=0), 0, atol=1e-12)
+    for a in (b1, b2):
+        np.testing.assert_allclose(np.linalg.norm(a, axis=0), 1, rtol=1e-12)
+    # right-handed: b1 x b2 = n
+    np.testing.assert_allclose(np.cross(b1, b2, axis=0), n, atol=1e-12)
+    # Malley's method: E[cos] = 2/3 for cosine-weighted directions
+    u1, u2 = rng.random(200000), rng.random(200000)
+    lz = np.sqrt(1 - u1)
+    assert abs(lz.mean() - 2.0 / 3.0) < 0.003
+
+
+def test_camera_rays_field_of_view():
+    cfg = synthetic.small_render()
+    W, H = cfg.width, cfg.height
+    pix = np.array([0, W - 1, (H - 1) * W, H * W - 1], dtype=np.int64)
+    o, d = render.camera_rays(cfg, pix, np.zeros(4, np.int64), None)
+    f = -np.asarray(cfg.camera.eye) / np.linalg.norm(cfg.camera.eye)
+    th = np.tan(np.radians(cfg.camera.vfov_deg) / 2)
+    # corner pixel centres sit at (1 - 1/W) and (1 - 1/H) of the half extents
+    expect = 1.0 / np.sqrt(1 + (th * (1 - 1 / H)) ** 2 + (th * (1 - 1 / W) * W / H) ** 2)
+    np.testing.assert_allclose(f @ d, expect, rtol=1e-12)
+    assert np.all(o == np.asarray(cfg.camera.eye)[:, None])
+
+
+def test_single_bounce_quad_closed_form():
+    """One bounce, one sample: every pixel is (albedo / pi) I cos / r^2 at the ray/plane hit."""
+    big = 50.0
+    v = np.array([[-big, -big, 0], [big, -big, 0], [big, big, 0], [-big, big, 0]], dtype=np.float64)
+    tris = synthetic.tri_soup(v, np.array([[0, 1, 2], [0, 2, 3]]))
+    cfg = synthetic.RenderConfig(24, 16, 1, 1, 3, 0)
+    cfg.camera.eye = (0.0, -3.0, 2.0)
+    out = render.render(render.MeshScene(tris), cfg)
+    P = cfg.width * cfg.height
+    o, d = render.camera_rays(cfg, np.arange(P), np.zeros(P, np.int64), None)
+    t = -o[2] / d[2]
+    hit = t > 0
+    x = o + t * d
+    xs = x + cfg.eps * np.array([0, 0, 1.0])[:, None]
+    lv = np.asarray(cfg.light.position)[:, None] - xs
+    r2 = np.sum(lv * lv, axis=0)
+    cos = lv[2] / np.sqrt(r2)
+    expect = np.where(hit, 0.7 / np.pi * 10.0 * np.maximum(cos, 0) / r2, 0.0).reshape(cfg.height, cfg.width)
+    ok = out["robust"]
+    assert ok.mean() > 0.95
+    for c in range(3):
+        np.testing.assert_allclose(out["radiance"][c][ok], expect[ok], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(out["depth"][ok & hit.reshape(ok.shape)], t.reshape(ok.shape)[ok & hit.reshape(ok.shape)], rtol=1e-12)
+    nz = out["normal"][2][ok & hit.reshape(ok.shape)]
+    np.testing.assert_allclose(nz, 1.0)
+
+
+def test_shadowed_quad_is_dark_under_occluder():
+    """A small quad between the light and the floor casts a shadow: the NEE term vanishes there."""
+    big = 50.0
+    floor = np.array([[-big, -big, 0], [big, -big, 0], [big, big, 0], [-big, big, 0]], dtype=np.float64)
+    light = np.array([0.0, 0.0, 3.0])
+    occ = np.array([[-0.3, -0.3, 1.5], [0.3, -0.3, 1.5], [0.3, 0.3, 1.5], [-0.3, 0.3, 1.5]])
+    v = np.concatenate([floor, occ])
+    f = np.array([[0, 1, 2], [0, 2, 3], [4, 5, 6], [4, 6, 7]])
+    cfg = synthetic.RenderConfig(32, 32, 1, 1, 3, 0)
+    cfg.camera.eye = (0.0, -0.01, 6.0)
+    cfg.camera.vfov_deg = 30.0
+    cfg.light.position = tuple(light)
+    out = render.render(render.MeshScene(synthetic.tri_soup(v, f)), cfg)
+    P = cfg.width * cfg.height
+    o, d = render.camera_rays(cfg, np.arange(P), np.zeros(P, np.int64), None)
+    # floor points whose segment to the light crosses the occluder (the occluder hides some pixels too)
+    tf = -o[2] / d[2]
+    x = o + tf * d
+    s = (1.5 - x[2]) / (light[2] - x[2])
+    y = x + s * (light[:, None] - x)
+    shadow = (np.abs(y[0]) < 0.3) & (np.abs(y[1]) < 0.3)
+    to = (1.5 - o[2]) / d[2]
+    xo = o + to * d
+    sees_occluder = (np.abs(xo[0]) <= 0.3) & (np.abs(xo[1]) <= 0.3)
+    sel = (shadow & ~sees_occluder).reshape(32, 32) & out["robust"]
+    assert sel.sum() > 5
+    assert np.all(out["radiance"][0][sel] == 0.0)
+    lit = (~shadow & ~sees_occluder).reshape(32, 32) & out["robust"]
+    assert np.all(out["radiance"][0][lit] > 0.0)
