@@ -1,0 +1,129 @@
+/*
+ * ddf.h -- C ABI of libddf.so: the directional-distance-field (DDF) hot path on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow "Neural directional distance field object representation
+ * for uni-directional path-traced rendering" (Behera and Mishra, arXiv 2306.16142):
+ *   - the field phi(x, theta): distance from a point x along a direction theta to
+ *     the surface, infinite when the ray misses (Sec. III-A);
+ *   - its neural form MLP_w(x, theta) (Sec. IV-A), evaluated here on batches of rays;
+ *   - the gradient of the field with respect to the query point, which gives the
+ *     surface normal (Eq. 3, Sec. IV-B);
+ *   - the ground-truth labels from ray shooting against the triangle mesh by a
+ *     linear search over all triangles (Sec. I, Sec. VI-B) with the odd-even
+ *     inside rule (Sec. V-B);
+ *   - the path tracer whose nearest-hit search the field replaces (Fig. 1).
+ *
+ * Conventions common to every entry point
+ *   Memory    Every array argument is DEVICE memory owned by the caller unless the
+ *             comment says "host".  The library never allocates, frees or keeps
+ *             caller memory; scratch comes from a caller-supplied workspace whose
+ *             size the matching *_workspace_size call returns.
+ *   Layout    Ray batches are structure-of-arrays float32: an array "[k][n]" holds
+ *             row r of ray i at index r*n + i.  Triangles are a "[9][m]" soup of
+ *             corners v0xyz, v1xyz, v2xyz.
+ *   Streams   `stream` is a hipStream_t (NULL = the null stream).  Calls only
+ *             enqueue work; outputs are valid once the stream has synchronised.
+ *             No call synchronises the host, so every call may be captured in a
+ *             HIP graph (those needing a workspace clear it with kernels).
+ *   Errors    Arguments are validated before anything is enqueued.  On error
+ *             nothing is launched, a non-zero ddf_status is returned and
+ *             ddf_last_error() returns a thread-local message.  n == 0 is a no-op.
+ *             No C++ exception crosses this boundary.
+ */
+#ifndef DDF_H
+#define DDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ddf_status;
+#define DDF_OK 0
+#define DDF_ERR_INVALID_ARG 1
+#define DDF_ERR_UNSUPPORTED 2
+#define DDF_ERR_WORKSPACE 3
+#define DDF_ERR_HIP 4
+
+typedef void *ddf_stream;   /* hipStream_t */
+
+/* Arithmetic of the network's layer products (accumulation is always float32). */
+#define DDF_PREC_FP32 0
+#define DDF_PREC_BF16 1
+#define DDF_PREC_FP8 2      /* OCP e4m3fn operands, static per-layer scales */
+
+/* Network shape: `depth` hidden ReLU layers of `width` units on the 65 Fourier
+ * features of the ray (ox, oy, oz, theta, phi), then a 2-unit affine head
+ * (hit logit, distance).  Supported widths: 128 and 256; depth 1..8. */
+typedef struct {
+    int32_t width;
+    int32_t depth;
+    int32_t precision;      /* DDF_PREC_* */
+    const void *packed;     /* device blob written by ddf_pack_net for this shape/precision */
+} ddf_net;
+
+/* Library version of this header (DDF_ABI_VERSION). */
+#define DDF_ABI_VERSION 1
+int32_t ddf_abi_version(void);
+/* Message of the last failed call on this thread ("" if none). */
+const char *ddf_last_error(void);
+
+/* ---------------------------------------------------------------- labeller
+ * Nearest hit of each ray against every triangle (linear search; Sec. I, ray
+ * shooting for labels Sec. VI-B), two-sided Moller-Trumbore, edges inclusive,
+ * accepted when t_min < t < t_max; ties go to the lowest triangle index.
+ *   orig, dir    [3][n] ray origins and directions (any non-zero length; t is in
+ *                units of |dir|).
+ *   tris         [9][m] triangle corners.
+ *   t_out        [n] nearest t, +inf on a miss (also for NaN rays).
+ *   tri_out      [n] index of the nearest triangle, -1 on a miss.
+ *   crossings    [n] number of accepted hits (odd-even inside rule, Sec. V-B),
+ *                or NULL.
+ * Decisions are taken in float32 with a forward error bound; a test whose
+ * outcome the bound cannot settle (near an edge, near grazing, near t_min /
+ * t_max) is re-evaluated in float64 from the same float32 inputs.
+ * Errors: INVALID_ARG for n < 0, m < 0, NULL arrays with n > 0, t_min >= t_max. */
+ddf_status ddf_label_rays(const float *orig, const float *dir, int64_t n,
+                          const float *tris, int64_t m, float t_min, float t_max,
+                          float *t_out, int32_t *tri_out, uint32_t *crossings,
+                          ddf_stream stream);
+
+/* ---------------------------------------------------------------- rays
+ * Ray assembly (Eq. 1 inverted): rays_out [5][n] = (ox, oy, oz, theta, phi) with
+ * theta = polar angle of dir from +z in [0, pi] and phi = atan2(dy, dx) wrapped
+ * into [0, 2 pi) (0 on the z axis).  orig, dir [3][n].  In place is not allowed. */
+ddf_status ddf_assemble_rays(const float *orig, const float *dir, int64_t n, float *rays_out,
+                             ddf_stream stream);
+
+/* ---------------------------------------------------------------- network
+ * Size in bytes of the packed blob for a shape and precision. */
+ddf_status ddf_packed_bytes(int32_t width, int32_t depth, int32_t precision, size_t *bytes);
+
+/* Packs the flat float32 parameters (device; per affine layer the weight
+ * [out][in] row-major then the bias [out], the order of torch.nn.Linear) into the
+ * MFMA-tile blob of `precision`.  For DDF_PREC_FP8, `scales` (device, [2*(depth+1)]:
+ * weight scale and input scale per affine layer, each an absmax / 448) is required;
+ * otherwise it must be NULL.  packed: device buffer of ddf_packed_bytes bytes. */
+ddf_status ddf_pack_net(const float *params, int32_t width, int32_t depth, int32_t precision,
+                        const float *scales, void *packed, ddf_stream stream);
+
+/* Static fp8 scales from a float32 network: per affine layer, weight absmax / 448
+ * and the absmax of its input over the calibration rays / 448.  net_fp32 must be a
+ * DDF_PREC_FP32 blob of the same parameters.  calib [5][n_calib]; scales_out
+ * device [2*(depth+1)]. */
+ddf_status ddf_fp8_scales(const ddf_net *net_fp32, const float *params, const float *calib,
+                          int64_t n_calib, float *scales_out, ddf_stream stream);
+
+/* Batched network query (Sec. IV-A, MLP_w(x, theta)): rays [5][n] ->
+ * logit_out [n] (hit <=> logit > 0) and dist_out [n] (meaningful on hits).
+ * NaN rays give NaN outputs. */
+ddf_status ddf_forward(const ddf_net *net, const float *rays, int64_t n,
+                       float *logit_out, float *dist_out, ddf_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDF_H */

@@ -1,0 +1,77 @@
+"""ctypes loader of libddf.so and the argument types of its C ABI (include/ddf.h).
+
+Nothing here computes: it only marshals pointers and sizes.  Loading fails loudly
+when the library has not been built; there is no fallback implementation.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddf.so")
+
+c_f = ctypes.c_float
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_u32 = ctypes.c_uint32
+c_sz = ctypes.c_size_t
+c_p = ctypes.c_void_p
+STATUS = ctypes.c_int32
+
+DDF_OK, DDF_ERR_INVALID_ARG, DDF_ERR_UNSUPPORTED, DDF_ERR_WORKSPACE, DDF_ERR_HIP = 0, 1, 2, 3, 4
+PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
+
+
+class DdfNet(ctypes.Structure):
+    _fields_ = [("width", c_i32), ("depth", c_i32), ("precision", c_i32), ("packed", c_p)]
+
+
+# name -> argument types (every entry point returns ddf_status unless listed in _RESTYPE)
+SIGNATURES = {
+    "ddf_abi_version": [],
+    "ddf_last_error": [],
+    "ddf_label_rays": [c_p, c_p, c_i64, c_p, c_i64, c_f, c_f, c_p, c_p, c_p, c_p],
+    "ddf_assemble_rays": [c_p, c_p, c_i64, c_p, c_p],
+    "ddf_packed_bytes": [c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)],
+    "ddf_pack_net": [c_p, c_i32, c_i32, c_i32, c_p, c_p, c_p],
+    "ddf_fp8_scales": [ctypes.POINTER(DdfNet), c_p, c_p, c_i64, c_p, c_p],
+    "ddf_forward": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_p, c_p],
+}
+_RESTYPE = {"ddf_abi_version": c_i32, "ddf_last_error": ctypes.c_char_p}
+
+_lib = None
+
+
+class DdfError(RuntimeError):
+    def __init__(self, func, status, msg):
+        super().__init__("%s failed with status %d: %s" % (func, status, msg))
+        self.status = status
+
+
+def load():
+    """Load libddf.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libddf.so is not built (%s); run __graft_entry__.build() or "
+                           "python paper_2306_16142_amd/build.py" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = _RESTYPE.get(name, STATUS)
+    _lib = lib
+    return lib
+
+
+def call(name, *args):
+    """Call an entry point and raise DdfError on a non-zero status."""
+    lib = load()
+    st = getattr(lib, name)(*args)
+    if st != DDF_OK:
+        raise DdfError(name, st, lib.ddf_last_error().decode())
+    return st
+
+
+def exported_symbols():
+    return list(SIGNATURES)

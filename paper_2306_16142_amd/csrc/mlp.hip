@@ -1,0 +1,545 @@
+// Batched network query (Sec. IV-A: the field phi(x, theta) stored as MLP_w and
+// evaluated for many oriented points at once) on CDNA4 matrix cores.
+//
+// One kernel evaluates the whole network per wave of rays: the Fourier encoding is
+// computed in registers, every affine layer is a chain of 32x32 MFMAs whose result
+// stays in the accumulators, and the epilogue (bias, ReLU, conversion to the next
+// layer's operand type) writes straight into the next layer's B operands.  Only the
+// 20 input bytes and 8 output bytes per ray touch HBM.  Weights are read as A operands
+// from LDS (when the whole packed network fits in the 160 KiB of a CU) or from the
+// L2-resident blob otherwise.  See mlp_layout.hpp for the operand numbering.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "common.hpp"
+#include "mlp_layout.hpp"
+
+namespace ddf {
+namespace {
+
+constexpr float kFp8Max = 448.0f;
+constexpr int kLdsBytes = 160 * 1024;
+
+// ------------------------------------------------------------------------------ packing
+__device__ inline uint16_t bf16_bits(float x) {
+    __bf16 b = (__bf16)x;   // round to nearest even
+    return __builtin_bit_cast(uint16_t, b);
+}
+
+__device__ inline uint8_t fp8_bits(float x) {
+    x = __builtin_amdgcn_fmed3f(x, -kFp8Max, kFp8Max);   // the conversion does not saturate
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
+}
+
+// Weight of layer l (row m, input column c) from the flat parameter vector.
+__device__ inline float weight_at(const float *params, int width, int depth, int l, int m, int c) {
+    int64_t off = 0;
+    int in = kInDim;
+    for (int j = 0; j < l; ++j) {
+        off += (int64_t)width * in + width;
+        in = width;
+    }
+    const int out = l == depth ? 2 : width;
+    (void)out;
+    return params[off + (int64_t)m * in + c];
+}
+
+__device__ inline float bias_at(const float *params, int width, int depth, int l, int m) {
+    int64_t off = 0;
+    int in = kInDim;
+    for (int j = 0; j <= l; ++j) {
+        const int out = j == depth ? 2 : width;
+        off += (int64_t)out * in;
+        if (j < l) off += out;
+        in = width;
+    }
+    return params[off + m];
+}
+
+// One thread per (tile, lane, slot) of the blob, then the biases and scales.
+__global__ void pack_kernel(const float *__restrict__ params, int width, int depth, int prec,
+                            const float *__restrict__ scales, uint8_t *__restrict__ blob) {
+    const NetLayout L = make_layout(width, depth, prec);
+    const int slots = slots_per_lane(prec);
+    const int64_t elems = L.tiles * 64 * slots;
+    const int64_t nbias = (int64_t)width * depth + 4;
+    const int64_t nscale = 2 * (depth + 1);
+    const int64_t total = elems + nbias + nscale;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        if (e >= elems) {
+            const int64_t b = e - elems;
+            if (b < nbias) {
+                float v = 0.f;
+                const int l = (int)(b / width), m = (int)(b % width);
+                if (l < depth) v = bias_at(params, width, depth, l, m);
+                else if (b - (int64_t)width * depth < 2) v = bias_at(params, width, depth, depth, (int)(b - (int64_t)width * depth));
+                reinterpret_cast<float *>(blob + L.bias_off)[b] = v;
+            } else {
+                const int64_t si = b - nbias;
+                reinterpret_cast<float *>(blob + L.scale_off)[si] = scales ? scales[si] : 1.0f;
+            }
+            continue;
+        }
+        const int s = (int)(e % slots);
+        const int lane = (int)((e / slots) % 64);
+        const int64_t tile = e / (slots * 64);
+        // locate the layer and the (kb, mb) of this tile
+        int l;
+        int64_t t;
+        if (tile < L.layer_tile(1) || depth == 0) {
+            l = 0;
+            t = tile;
+        } else if (tile >= L.head_tile()) {
+            l = depth;
+            t = tile - L.head_tile();
+        } else {
+            l = 1 + (int)((tile - L.layer_tile(1)) / ((int64_t)L.nkb * L.nmb));
+            t = tile - L.layer_tile(l);
+        }
+        const int nmb = l == depth ? 1 : L.nmb;
+        const int kb = (int)(t / nmb), mb = (int)(t % nmb);
+        const int h = lane / 32;
+        const int m = mb * 32 + (lane % 32);
+        float w = 0.f;
+        if (l == 0) {
+            const int c = feature_column(h, layer0_feature(prec, kb, s));
+            if (c >= 0) w = weight_at(params, width, depth, 0, m, c);
+        } else if (l < depth || m < 2) {
+            w = weight_at(params, width, depth, l, m, prev_unit(prec, kb, h, s));
+        }
+        uint8_t *dst = blob + tile * tile_bytes(prec);
+        if (prec == kFP32) {
+            reinterpret_cast<float *>(dst)[lane] = w;
+        } else if (prec == kBF16) {
+            reinterpret_cast<uint16_t *>(dst)[lane * 8 + s] = bf16_bits(w);
+        } else {
+            const float sw = scales[2 * l];
+            dst[lane * 32 + s] = fp8_bits(sw > 0.f ? w / sw : 0.f);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------ encoding
+// Features of one variable: raw, sin(2^k v), cos(2^k v), k = 0..5.  In float32 mode every
+// frequency calls sincosf (arguments 2^k v are exact); in reduced precision the higher
+// frequencies follow the double-angle recurrence from the k = 0 values.
+template <bool kExact>
+__device__ inline void encode_var(float v, float *f) {
+    f[0] = v;
+    float s, c;
+    sincosf(v, &s, &c);
+    f[1] = s;
+    f[1 + kNFreq] = c;
+#pragma unroll
+    for (int k = 1; k < kNFreq; ++k) {
+        if constexpr (kExact) {
+            sincosf(v * (float)(1 << k), &s, &c);
+        } else {
+            const float s2 = 2.f * s * c;
+            const float c2 = 1.f - 2.f * s * s;
+            s = s2;
+            c = c2;
+        }
+        f[1 + k] = s;
+        f[1 + kNFreq + k] = c;
+    }
+}
+
+// ------------------------------------------------------------------------------ forward
+template <int P>
+struct OpOf;
+template <>
+struct OpOf<kBF16> {
+    using T = bf16x8;
+};
+template <>
+struct OpOf<kFP8> {
+    using T = i32x8;
+};
+template <>
+struct OpOf<kFP32> {
+    using T = float;
+};
+
+template <int P>
+__device__ inline f32x16 mfma(typename OpOf<P>::T a, typename OpOf<P>::T b, f32x16 c) {
+    if constexpr (P == kBF16) return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    else if constexpr (P == kFP8) return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+    else return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+template <int P, bool kLdsA>
+__device__ inline typename OpOf<P>::T load_a(const uint8_t *src, int64_t tile, int lane) {
+    using Op = typename OpOf<P>::T;
+    const uint8_t *p = src + tile * tile_bytes(P) + (int64_t)lane * (tile_bytes(P) / 64);
+    return *reinterpret_cast<const Op *>(p);
+}
+
+// Packs 4 non-negative floats (already clamped to the e4m3 range) into one dword.
+__device__ inline int pack_fp8x4(float a, float b, float c, float d) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+}
+
+// Calibration: wave maximum of non-negative values, one atomic per wave (floats >= 0
+// order as unsigned integers).
+__device__ inline void wave_absmax(float v, unsigned int *dst) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(dst, __float_as_uint(v));
+}
+
+struct LdsConsts {
+    float in_scale_inv;   // fp8: 1 / s_a of layer 0
+    float alpha[9];       // fp8: s_w s_a / s_a(next) per layer; head: s_w s_a
+};
+
+// W: width, NB: 32-ray column blocks per wave, P: precision, kLdsA: weights in LDS.
+template <int P, int W, int NB, bool kLdsA>
+__global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
+    const uint8_t *__restrict__ blob, int depth, const float *__restrict__ rays, int64_t n,
+    float *__restrict__ logit_out, float *__restrict__ dist_out, unsigned int *__restrict__ absmax) {
+    using Op = typename OpOf<P>::T;
+    constexpr int NMB = W / 32;
+    constexpr int KB = k_per_block(P);
+    constexpr int NKB = W / KB;
+    constexpr int K0 = layer0_kblocks(P);
+    static_assert(K0 <= NKB, "layer-0 operands must fit the hidden operand array");
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+
+    const NetLayout L = make_layout(W, depth, P);
+    const int64_t wbytes = kLdsA ? L.tiles * tile_bytes(P) : 0;
+    float *s_bias = reinterpret_cast<float *>(smem + wbytes);
+    LdsConsts *s_c = reinterpret_cast<LdsConsts *>(s_bias + (W * depth + 4));
+    {
+        // Stage weights (optional) and biases; fp8 biases are pre-divided by the next scale.
+        const int64_t nvec = wbytes / 16;
+        for (int64_t i = threadIdx.x; i < nvec; i += blockDim.x)
+            reinterpret_cast<i32x4 *>(smem)[i] = reinterpret_cast<const i32x4 *>(blob)[i];
+        const float *g_bias = reinterpret_cast<const float *>(blob + L.bias_off);
+        const float *g_scale = reinterpret_cast<const float *>(blob + L.scale_off);
+        for (int i = threadIdx.x; i < W * depth + 4; i += blockDim.x) {
+            float b = g_bias[i];
+            if (P == kFP8 && i < W * depth) {
+                const float sn = g_scale[2 * (i / W + 1) + 1];
+                b = sn > 0.f ? b / sn : 0.f;
+            }
+            s_bias[i] = b;
+        }
+        if (threadIdx.x == 0) {
+            if (P == kFP8) {
+                const float s0 = g_scale[1];
+                s_c->in_scale_inv = s0 > 0.f ? 1.f / s0 : 0.f;
+                for (int l = 0; l <= depth; ++l) {
+                    const float sw = g_scale[2 * l], sa = g_scale[2 * l + 1];
+                    const float sn = l < depth ? g_scale[2 * (l + 1) + 1] : 1.f;
+                    s_c->alpha[l] = sn > 0.f ? sw * sa / sn : 0.f;
+                }
+            } else {
+                s_c->in_scale_inv = 1.f;
+                for (int l = 0; l <= depth; ++l) s_c->alpha[l] = 1.f;
+            }
+        }
+    }
+    __syncthreads();
+    const uint8_t *wsrc = kLdsA ? smem : blob;
+
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5;
+    const int col = lane & 31;
+    const int wpb = blockDim.x >> 6;
+    const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
+
+    for (int64_t tile = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); tile < ntile; tile += (int64_t)gridDim.x * wpb) {
+        const int64_t base = tile * 32 * NB;
+        Op b[NKB][NB];
+        bool nan_ray[NB];   // NaN inputs give NaN outputs (ReLU's fmax would hide them)
+        // ---- encoding -> layer-0 B operands
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int64_t r = base + nb * 32 + col;
+            float v[kInRaw] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            if (r < n) {
+#pragma unroll
+                for (int j = 0; j < kInRaw; ++j) v[j] = rays[(int64_t)j * n + r];
+            }
+            nan_ray[nb] = isnan(v[0]) || isnan(v[1]) || isnan(v[2]) || isnan(v[3]) || isnan(v[4]);
+            float feat[kSlotsPerHalf];
+            encode_var<P == kFP32>(h ? v[3] : v[0], feat);
+            encode_var<P == kFP32>(h ? v[4] : v[1], feat + kFeatPerVar);
+            encode_var<P == kFP32>(h ? 0.f : v[2], feat + 2 * kFeatPerVar);
+            feat[kSlotsPerHalf - 1] = 0.f;
+            if (absmax) {
+                float m = 0.f;
+#pragma unroll
+                for (int f = 0; f < kSlotsPerHalf - 1; ++f)
+                    if (r < n && (h == 0 || f < 2 * kFeatPerVar)) m = fmaxf(m, fabsf(feat[f]));
+                wave_absmax(m, absmax + 1);
+            }
+            if constexpr (P == kBF16) {
+#pragma unroll
+                for (int kb = 0; kb < K0; ++kb)
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) b[kb][nb][s] = (__bf16)feat[kb * 8 + s];
+            } else if constexpr (P == kFP8) {
+                const float inv = s_c->in_scale_inv;
+#pragma unroll
+                for (int kb = 0; kb < K0; ++kb)
+#pragma unroll
+                    for (int w4 = 0; w4 < 8; ++w4) {
+                        float q[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int f = kb * 32 + w4 * 4 + i;
+                            q[i] = f < kSlotsPerHalf ? __builtin_amdgcn_fmed3f(feat[f] * inv, -kFp8Max, kFp8Max) : 0.f;
+                        }
+                        b[kb][nb][w4] = pack_fp8x4(q[0], q[1], q[2], q[3]);
+                    }
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < K0; ++kb) b[kb][nb] = feat[kb];
+            }
+        }
+
+        // ---- layers 0 .. depth-1 (ReLU) and the head
+        for (int l = 0; l <= depth; ++l) {
+            const bool head = l == depth;
+            const int nkb = l == 0 ? K0 : NKB;
+            const int64_t t0 = L.layer_tile(l);
+            if (!head) {
+                f32x16 acc[NMB][NB];
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
+#pragma unroll
+                for (int kb = 0; kb < NKB; ++kb) {
+                    if (kb < nkb) {
+#pragma unroll
+                        for (int mb = 0; mb < NMB; ++mb) {
+                            const Op a = load_a<P, kLdsA>(wsrc, t0 + (int64_t)kb * NMB + mb, lane);
+#pragma unroll
+                            for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(a, b[kb][nb], acc[mb][nb]);
+                        }
+                    }
+                }
+                // epilogue: bias, ReLU, conversion into the next layer's B operands
+                const float *bias = s_bias + l * W;
+                const float alpha = s_c->alpha[l];
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb) {
+                    float bv[16];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) bv[4 * g + i] = b4[i];
+                    }
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        float y[16];
+#pragma unroll
+                        for (int j = 0; j < 16; ++j) {
+                            if constexpr (P == kFP8)
+                                y[j] = __builtin_amdgcn_fmed3f(fmaf(acc[mb][nb][j], alpha, bv[j]), 0.f, kFp8Max);
+                            else
+                                y[j] = fmaxf(acc[mb][nb][j] + bv[j], 0.f);
+                        }
+                        if (absmax) {
+                            float m = 0.f;
+#pragma unroll
+                            for (int j = 0; j < 16; ++j)
+                                if (base + nb * 32 + col < n) m = fmaxf(m, y[j]);
+                            wave_absmax(m, absmax + 2 * (l + 1) + 1);
+                        }
+                        if constexpr (P == kBF16) {
+#pragma unroll
+                            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                                for (int s = 0; s < 8; ++s) b[2 * mb + c][nb][s] = (__bf16)y[8 * c + s];
+                        } else if constexpr (P == kFP8) {
+                            // M-block mb feeds K-block mb / 2, slots 16 (mb % 2) .. +15 = words 4 (mb % 2) .. +3
+#pragma unroll
+                            for (int w4 = 0; w4 < 4; ++w4)
+                                b[mb / 2][nb][4 * (mb % 2) + w4] =
+                                    pack_fp8x4(y[4 * w4], y[4 * w4 + 1], y[4 * w4 + 2], y[4 * w4 + 3]);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 16; ++j) b[16 * mb + j][nb] = y[j];
+                        }
+                    }
+                }
+            } else {
+                f32x16 acc[NB];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) acc[nb][j] = 0.f;
+#pragma unroll
+                for (int kb = 0; kb < NKB; ++kb) {
+                    const Op a = load_a<P, kLdsA>(wsrc, t0 + kb, lane);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, b[kb][nb], acc[nb]);
+                }
+                if (h == 0 && logit_out) {
+                    const float alpha = s_c->alpha[depth];
+                    const float b0 = s_bias[W * depth], b1 = s_bias[W * depth + 1];
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        const int64_t r = base + nb * 32 + col;
+                        if (r < n) {
+                            logit_out[r] = nan_ray[nb] ? NAN : fmaf(acc[nb][0], alpha, b0);
+                            dist_out[r] = nan_ray[nb] ? NAN : fmaf(acc[nb][1], alpha, b1);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Weight absmax per affine layer (one block per layer) -> scales[2 l] = absmax / 448;
+// input absmax bits (written by the calibration forward) -> scales[2 l + 1] = absmax / 448.
+__global__ void weight_absmax_kernel(const float *__restrict__ params, int width, int depth, float *scales) {
+    const int l = blockIdx.x;
+    int64_t off = 0;
+    int in = kInDim;
+    for (int j = 0; j < l; ++j) {
+        off += (int64_t)width * in + width;
+        in = width;
+    }
+    const int out = l == depth ? 2 : width;
+    const int64_t cnt = (int64_t)out * in;
+    float m = 0.f;
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) m = fmaxf(m, fabsf(params[off + i]));
+    __shared__ float red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        scales[2 * l] = red[0] / kFp8Max;
+        const float a = __uint_as_float(reinterpret_cast<unsigned int *>(scales)[2 * l + 1]);
+        scales[2 * l + 1] = a / kFp8Max;
+    }
+}
+
+__global__ void zero_kernel(float *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+// ------------------------------------------------------------------------------ dispatch
+int cu_count() {
+    static int cus = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    });
+    return cus;
+}
+
+template <int P, int W, int NB, bool kLdsA>
+ddf_status launch_forward(const NetLayout &L, const void *blob, const float *rays, int64_t n, float *logit,
+                          float *dist, unsigned int *absmax, hipStream_t stream) {
+    auto kern = forward_kernel<P, W, NB, kLdsA>;
+    const size_t lds = (kLdsA ? L.tiles * tile_bytes(P) : 0) + ((size_t)W * L.depth + 4) * 4 + sizeof(LdsConsts);
+    static std::once_flag once;
+    std::call_once(once, [&] { (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes); });
+    const int threads = NB == 2 ? 512 : 256;
+    const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
+    const int64_t wpb = threads / 64;
+    const int per_cu = kLdsA ? 1 : 2;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((ntile + wpb - 1) / wpb, (int64_t)cu_count() * per_cu));
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, (const uint8_t *)blob, L.depth, rays, n,
+                       logit, dist, absmax);
+    return launch_status("ddf_forward");
+}
+
+bool fits_lds(const NetLayout &L) {
+    return L.tiles * tile_bytes(L.prec) + ((int64_t)L.width * L.depth + 4) * 4 + (int64_t)sizeof(LdsConsts) <= kLdsBytes;
+}
+
+ddf_status check_shape(int width, int depth, int prec, const char *who) {
+    DDF_REQUIRE(width == 128 || width == 256, DDF_ERR_UNSUPPORTED, "%s: width %d not supported (128 or 256)", who, width);
+    DDF_REQUIRE(depth >= 1 && depth <= 8, DDF_ERR_UNSUPPORTED, "%s: depth %d not supported (1..8)", who, depth);
+    DDF_REQUIRE(prec == kFP32 || prec == kBF16 || prec == kFP8, DDF_ERR_UNSUPPORTED, "%s: unknown precision %d", who, prec);
+    return DDF_OK;
+}
+
+ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, float *logit, float *dist,
+                            unsigned int *absmax, hipStream_t s) {
+    const NetLayout L = make_layout(net->width, net->depth, net->precision);
+    const bool lds = fits_lds(L);
+    if (net->width == 128) {
+        if (net->precision == kBF16)
+            return lds ? launch_forward<kBF16, 128, 2, true>(L, net->packed, rays, n, logit, dist, absmax, s)
+                       : launch_forward<kBF16, 128, 2, false>(L, net->packed, rays, n, logit, dist, absmax, s);
+        if (net->precision == kFP8)
+            return lds ? launch_forward<kFP8, 128, 2, true>(L, net->packed, rays, n, logit, dist, absmax, s)
+                       : launch_forward<kFP8, 128, 2, false>(L, net->packed, rays, n, logit, dist, absmax, s);
+        return launch_forward<kFP32, 128, 1, false>(L, net->packed, rays, n, logit, dist, absmax, s);
+    }
+    if (net->precision == kBF16) return launch_forward<kBF16, 256, 1, false>(L, net->packed, rays, n, logit, dist, absmax, s);
+    if (net->precision == kFP8) return launch_forward<kFP8, 256, 1, false>(L, net->packed, rays, n, logit, dist, absmax, s);
+    return launch_forward<kFP32, 256, 1, false>(L, net->packed, rays, n, logit, dist, absmax, s);
+}
+
+}  // namespace
+}  // namespace ddf
+
+using namespace ddf;
+
+extern "C" ddf_status ddf_packed_bytes(int32_t width, int32_t depth, int32_t precision, size_t *bytes) {
+    if (ddf_status st = check_shape(width, depth, precision, "ddf_packed_bytes")) return st;
+    DDF_REQUIRE(bytes, DDF_ERR_INVALID_ARG, "ddf_packed_bytes: NULL output");
+    *bytes = (size_t)make_layout(width, depth, precision).bytes;
+    return DDF_OK;
+}
+
+extern "C" ddf_status ddf_pack_net(const float *params, int32_t width, int32_t depth, int32_t precision,
+                                   const float *scales, void *packed, ddf_stream stream) {
+    if (ddf_status st = check_shape(width, depth, precision, "ddf_pack_net")) return st;
+    DDF_REQUIRE(params && packed, DDF_ERR_INVALID_ARG, "ddf_pack_net: NULL params or output");
+    DDF_REQUIRE((precision == kFP8) == (scales != nullptr), DDF_ERR_INVALID_ARG,
+                "ddf_pack_net: fp8 needs scales, other precisions take none");
+    hipLaunchKernelGGL(pack_kernel, dim3(1024), dim3(256), 0, as_stream(stream), params, width, depth, precision, scales,
+                       (uint8_t *)packed);
+    return launch_status("ddf_pack_net");
+}
+
+extern "C" ddf_status ddf_fp8_scales(const ddf_net *net_fp32, const float *params, const float *calib, int64_t n_calib,
+                                     float *scales_out, ddf_stream stream) {
+    DDF_REQUIRE(net_fp32 && params && scales_out, DDF_ERR_INVALID_ARG, "ddf_fp8_scales: NULL argument");
+    if (ddf_status st = check_shape(net_fp32->width, net_fp32->depth, net_fp32->precision, "ddf_fp8_scales")) return st;
+    DDF_REQUIRE(net_fp32->precision == kFP32 && net_fp32->packed, DDF_ERR_INVALID_ARG,
+                "ddf_fp8_scales: needs a packed float32 network");
+    DDF_REQUIRE(n_calib > 0 && calib, DDF_ERR_INVALID_ARG, "ddf_fp8_scales: need calibration rays");
+    hipStream_t s = as_stream(stream);
+    const int nsc = 2 * (net_fp32->depth + 1);
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, scales_out, (int64_t)nsc);
+    if (ddf_status st = launch_status("ddf_fp8_scales")) return st;
+    if (ddf_status st = forward_dispatch(net_fp32, calib, n_calib, nullptr, nullptr,
+                                         reinterpret_cast<unsigned int *>(scales_out), s))
+        return st;
+    hipLaunchKernelGGL(weight_absmax_kernel, dim3(net_fp32->depth + 1), dim3(256), 0, s, params, net_fp32->width,
+                       net_fp32->depth, scales_out);
+    return launch_status("ddf_fp8_scales");
+}
+
+extern "C" ddf_status ddf_forward(const ddf_net *net, const float *rays, int64_t n, float *logit_out, float *dist_out,
+                                  ddf_stream stream) {
+    DDF_REQUIRE(net, DDF_ERR_INVALID_ARG, "ddf_forward: NULL network");
+    if (ddf_status st = check_shape(net->width, net->depth, net->precision, "ddf_forward")) return st;
+    DDF_REQUIRE(n >= 0, DDF_ERR_INVALID_ARG, "ddf_forward: negative n");
+    if (n == 0) return DDF_OK;
+    DDF_REQUIRE(net->packed && rays && logit_out && dist_out, DDF_ERR_INVALID_ARG, "ddf_forward: NULL array");
+    return forward_dispatch(net, rays, n, logit_out, dist_out, nullptr, as_stream(stream));
+}

@@ -1,0 +1,41 @@
+// Ray assembly: origins and direction vectors -> the 5-value oriented points (x, theta)
+// the network takes (Eq. 1 read backwards: theta = polar angle from +z, phi = azimuth).
+#include <cmath>
+
+#include "common.hpp"
+
+namespace ddf {
+namespace {
+
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kBelowTwoPi = 6.28318500518798828125f;   // largest float32 below fl(2 pi)
+
+__global__ void assemble_kernel(const float *__restrict__ orig, const float *__restrict__ dir, int64_t n,
+                                float *__restrict__ rays) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float dx = dir[i], dy = dir[n + i], dz = dir[2 * n + i];
+        const float theta = atan2f(sqrtf(dx * dx + dy * dy), dz);
+        float phi = atan2f(dy, dx);
+        if (phi < 0.f) phi += kTwoPi;
+        if (phi >= kTwoPi) phi = kBelowTwoPi;
+        rays[i] = orig[i];
+        rays[n + i] = orig[n + i];
+        rays[2 * n + i] = orig[2 * n + i];
+        rays[3 * n + i] = theta;
+        rays[4 * n + i] = phi;
+    }
+}
+
+}  // namespace
+}  // namespace ddf
+
+extern "C" ddf_status ddf_assemble_rays(const float *orig, const float *dir, int64_t n, float *rays_out,
+                                        ddf_stream stream) {
+    using namespace ddf;
+    DDF_REQUIRE(n >= 0, DDF_ERR_INVALID_ARG, "ddf_assemble_rays: negative n");
+    if (n == 0) return DDF_OK;
+    DDF_REQUIRE(orig && dir && rays_out, DDF_ERR_INVALID_ARG, "ddf_assemble_rays: NULL array");
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), orig, dir, n, rays_out);
+    return launch_status("ddf_assemble_rays");
+}

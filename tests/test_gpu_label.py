@@ -1,0 +1,96 @@
+"""GPU parity of ddf_label_rays against the float64 brute-force oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import geometry
+from paper_2306_16142_amd import api
+
+from gpu_common import banner, cuda, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(o, d, tris, t_min=0.0, t_max=math.inf):
+    t, tri, cr = api.label_rays(cuda(o), cuda(d), cuda(tris), t_min, t_max)
+    torch.cuda.synchronize()
+    t, tri, cr = host(t), host(tri), host(cr)
+    ref = geometry.nearest_hit(o, d, tris, t_min, t_max)
+    ok = ~ref["ambiguous"]
+    hit_ref = ref["tri"] >= 0
+    # hit flags and crossing counts: exact on rays the geometry decides
+    np.testing.assert_array_equal((tri >= 0)[ok], hit_ref[ok])
+    np.testing.assert_array_equal(cr[ok], ref["crossings"][ok])
+    assert np.all(np.isinf(t[ok & ~hit_ref])) and np.all(tri[ok & ~hit_ref] == -1)
+    h = ok & hit_ref
+    # distance: the winner is re-evaluated in float64, so only float32 rounding remains
+    np.testing.assert_allclose(t[h], ref["t"][h], rtol=2e-7, atol=1e-7)
+    # triangle id: equal unless the oracle sees two hits within 1e-6 of each other
+    diff = h & (tri != ref["tri"])
+    if diff.any():
+        assert np.all(ref["t_second"][diff] - ref["t"][diff] <= 1e-6 * (1 + ref["t"][diff]))
+    return ok.mean(), hit_ref.mean()
+
+
+def test_label_icosphere_uniform_rays():
+    banner("label: icosphere 320 tris x 65536 uniform rays (seed 0)")
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    o, d = synthetic.uniform_cube_rays(65536, 0)
+    frac_ok, frac_hit = _check(o, d, tris)
+    assert frac_ok > 0.999 and 0.2 < frac_hit < 0.9
+
+
+def test_label_training_mesh_subset_ragged():
+    banner("label: training mesh 20480 tris x 3001 training rays (seed 1)")
+    v, f = synthetic.training_mesh(1)
+    tris = synthetic.tri_soup(v, f)
+    o, d, _ = synthetic.training_rays(v, f, 3001, 1)
+    frac_ok, frac_hit = _check(o, d, tris)
+    assert frac_ok > 0.99 and frac_hit > 0.5
+
+
+def test_label_t_window_and_ragged_triangle_tail():
+    banner("label: t window [0.3, 1.2], 100 tris, 777 rays")
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = np.ascontiguousarray(synthetic.tri_soup(v, f)[:, :100])
+    o, d = synthetic.uniform_cube_rays(777, 5)
+    _check(o, d, tris, 0.3, 1.2)
+
+
+def test_label_edge_cases():
+    banner("label: empty mesh, NaN rays, n = 0")
+    v, f = synthetic.icosphere(1, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    o, d = synthetic.uniform_cube_rays(300, 6)
+    o[0, 5] = np.nan
+    d[:, 7] = 0.0
+    t, tri, cr = api.label_rays(cuda(o), cuda(d), cuda(tris))
+    t, tri, cr = host(t), host(tri), host(cr)
+    assert tri[5] == -1 and np.isinf(t[5]) and cr[5] == 0
+    assert tri[7] == -1 and np.isinf(t[7])
+    empty = np.zeros((9, 0), dtype=np.float32)
+    t, tri, cr = api.label_rays(cuda(o), cuda(d), cuda(empty))
+    assert np.all(host(tri) == -1) and np.all(np.isinf(host(t))) and np.all(host(cr) == 0)
+    z = np.zeros((3, 0), dtype=np.float32)
+    t, tri, cr = api.label_rays(cuda(z), cuda(z), cuda(tris))
+    assert t.numel() == 0
+
+
+def test_assemble_rays_matches_oracle_angles():
+    banner("assemble: 100003 rays + poles")
+    o, d = synthetic.uniform_cube_rays(100003, 7)
+    d[:, 0] = [0, 0, 1]
+    d[:, 1] = [0, 0, -1]
+    d[:, 2] = [1, -1e-30, 0]
+    r = host(api.assemble_rays(cuda(o), cuda(d)))
+    th, ph = geometry.angles_from_dirs(d)
+    np.testing.assert_array_equal(r[:3], o)
+    np.testing.assert_allclose(r[3], th, atol=1e-6)
+    dph = np.abs(r[4] - ph)
+    dph = np.minimum(dph, 2 * np.pi - dph)
+    assert dph.max() < 1e-6
+    assert np.all((r[4] >= 0) & (r[4] < 2 * np.pi))
