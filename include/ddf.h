@@ -123,6 +123,101 @@ ddf_status ddf_fp8_scales(const ddf_net *net_fp32, const float *params, const fl
 ddf_status ddf_forward(const ddf_net *net, const float *rays, int64_t n,
                        float *logit_out, float *dist_out, ddf_stream stream);
 
+/* ---------------------------------------------------------------- gradients
+ * Reverse-mode gradient of sum(g_logit * logit + g_dist * dist) over the batch.  The
+ * input gradient's origin part is the derivative of the field with respect to the
+ * query point that gives the surface normal (Eq. 3; Sec. IV-B takes it by automatic
+ * differentiation); the parameter gradient is the training backward (Sec. V-A).
+ *   net       DDF_PREC_FP32, or DDF_PREC_BF16 when g_params is NULL.
+ *   rays      [5][n]; g_logit, g_dist [n] seeds (either may be NULL = zeros).
+ *   g_rays    [5][n] d/d(ox, oy, oz, theta, phi), or NULL.
+ *   g_params  [P] float32 in the flat parameter order, or NULL.  Written, or added to
+ *             when flags has DDF_GRAD_ACCUMULATE.  Needs the workspace of
+ *             ddf_train_workspace_size(width, depth, n); with g_params NULL no
+ *             workspace is used (ws may be NULL).
+ * The forward pass is recomputed inside the kernel (ReLU masks kept on chip); the
+ * parameter gradient sums over rays in fixed-size chunks combined in a fixed order, so
+ * repeated calls give bitwise identical results. */
+#define DDF_GRAD_ACCUMULATE 1u
+ddf_status ddf_train_workspace_size(int32_t width, int32_t depth, int64_t n, size_t *bytes);
+ddf_status ddf_backward(const ddf_net *net, const float *rays, int64_t n, const float *g_logit,
+                        const float *g_dist, float *g_rays, float *g_params, uint32_t flags,
+                        void *ws, size_t ws_bytes, ddf_stream stream);
+
+/* Loss of the training labels and its seeds: binary cross-entropy with logits on the hit
+ * flag (hit <=> t_label < +inf), mean over the n rays, plus the L1 distance error
+ * |dist - t_label| averaged over hit rays (weights 1:1).  g_logit = (sigmoid(logit) -
+ * hit) / n; g_dist = sign(dist - t) / n_hit on hits, 0 elsewhere.  loss_out: device
+ * scalar.  ws: device scratch of at least 4160 bytes. */
+ddf_status ddf_loss_seeds(const float *logit, const float *dist, const float *t_label, int64_t n,
+                          float *g_logit, float *g_dist, float *loss_out, void *ws, size_t ws_bytes,
+                          ddf_stream stream);
+
+/* One Adam update (Kingma and Ba; Sec. V-A optimises with Adam) of `count` float32
+ * parameters with bias correction for the 1-based `step`; no weight decay. */
+ddf_status ddf_adam_step(float *params, const float *grads, float *m, float *v, int64_t count,
+                         int64_t step, float lr, float beta1, float beta2, float eps, ddf_stream stream);
+
+/* One training step on a labelled batch: loss seeds, parameter gradients (as
+ * ddf_backward), Adam (beta 0.9 / 0.999, eps 1e-8) on `params` / `adam_m` / `adam_v`, and
+ * repacking of `net` (a DDF_PREC_FP32 blob of `params`, rewritten in place).
+ *   rays [5][n], t_label [n] (+inf = miss); loss_out: device scalar (loss before the
+ *   update); g_params [P] receives the gradient; ws: ddf_train_workspace_size bytes. */
+ddf_status ddf_train_step(const ddf_net *net, float *params, float *adam_m, float *adam_v,
+                          int64_t step, float lr, const float *rays, const float *t_label, int64_t n,
+                          float *loss_out, float *g_params, void *ws, size_t ws_bytes,
+                          ddf_stream stream);
+
+/* ---------------------------------------------------------------- renderer
+ * Wavefront path tracer of Fig. 1 in which the nearest-hit search is either the
+ * brute-force triangle search (backend MESH) or the network (backend NET): the
+ * "modified path tracer" of Sec. I / Sec. IV.  Per bounce: query -> hit point and
+ * normal (mesh face normal, or Eq. 3 from the network's distance gradient with respect
+ * to the query point) -> next-event estimation towards one point light (shadow ray
+ * query) -> cosine-weighted Lambertian scatter -> Russian roulette -> compaction of the
+ * surviving paths (wave ballot + one atomic per wave).
+ *
+ * Readings (the paper gives no camera, light, sampler or termination rule):
+ *   pinhole camera (eye, target, up, vertical field of view), pixel centre at 1 spp,
+ *   otherwise a jitter from random dimensions 0, 1; network queries start at the
+ *   entry of the domain cube [-1,1]^3 (hit <=> logit > 0, t = entry + distance);
+ *   shadow / scatter origins x + eps n; scatter by Malley's method in the basis of Duff
+ *   et al. 2017; after the scatter of bounce b >= rr_start, survival probability
+ *   q = min(0.95, max throughput channel).  Random numbers: SplitMix64 (Steele, Lea,
+ *   Flood 2014) as a counter hash, u = (h >> 40) 2^-24 with
+ *   h = H(H(H(H(H(seed) ^ pixel) ^ sample) ^ bounce) ^ dim), H(x) = SplitMix64 output of
+ *   state x; dimensions 2, 3 scatter, 4 roulette.
+ * Every path's radiance is kept per path and summed per pixel in sample order, so the
+ * image does not depend on queue order (bitwise reproducible).                        */
+#define DDF_BACKEND_MESH 0
+#define DDF_BACKEND_NET 1
+
+typedef struct {
+    int32_t backend;            /* DDF_BACKEND_* */
+    const float *tris;          /* MESH: device [9][m] */
+    int64_t m;
+    const ddf_net *net;         /* NET: DDF_PREC_FP32 or DDF_PREC_BF16 network (host struct) */
+} ddf_scene;
+
+typedef struct {
+    int32_t width, height, spp, bounces, rr_start;
+    uint64_t seed;
+    float eps;
+    float eye[3], target[3], up[3], vfov_deg;
+    float light_pos[3], light_intensity[3], albedo[3];
+    int32_t spp_chunk;          /* samples per pixel traced together (0 = choose) */
+} ddf_render_params;
+
+/* Workspace bytes for a render (depends on width, height and the sample chunk). */
+ddf_status ddf_render_workspace_size(const ddf_render_params *p, size_t *bytes);
+
+/* radiance [3][height][width] (mean over samples; row 0 at the top); depth [height][width]
+ * and normal [3][height][width] of sample 0's primary hit (+inf / 0 on a miss) or NULL;
+ * stats: device uint32 [bounces] paths entering each bounce, summed over chunks, or NULL. */
+ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_render_params *p, float *radiance,
+                                float *depth, float *normal, uint32_t *stats, void *ws, size_t ws_bytes,
+                                ddf_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -225,6 +225,29 @@ def backward(params, width, depth, rays, g_logit, g_dist):
     return g_rays, pack(grads)
 
 
+def backward_input_bf16(params, width, depth, rays, g_logit, g_dist):
+    """Input gradient with bfloat16 operands in every product, float64 sums.
+
+    The forward pass is ``forward_bf16``; the ReLU masks come from its
+    pre-activations; the head rows stay unrounded; every transposed product rounds
+    its weights and its incoming adjoint to bfloat16.  Returns g_rays [5, N].
+    Pinned: equals ``backward`` when every operand is representable.
+    """
+    layers = unpack(params, width, depth)
+    h = round_bf16(encode(rays))
+    pres = []
+    for l, (W, b) in enumerate(layers[:-1]):
+        z = round_bf16(W) @ h + b[:, None]
+        pres.append(z)
+        h = round_bf16(np.maximum(z, 0.0))
+    Wh = layers[-1][0]
+    delta = (Wh.T @ np.stack([np.asarray(g_logit, np.float64), np.asarray(g_dist, np.float64)])) * (pres[-1] > 0.0)
+    for l in range(depth - 1, 0, -1):
+        delta = (round_bf16(layers[l][0]).T @ round_bf16(delta)) * (pres[l - 1] > 0.0)
+    g_feat = round_bf16(layers[0][0]).T @ round_bf16(delta)
+    return encode_grad(rays, g_feat)
+
+
 def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam update (Kingma & Ba) with bias correction and no weight decay.
 

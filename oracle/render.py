@@ -125,19 +125,20 @@ def onb_duff(n):
 class MeshScene:
     """Scene backend: nearest hit by brute force over a triangle soup (oracle geometry)."""
 
-    def __init__(self, tris):
+    def __init__(self, tris, amb_tol=1e-6):
         self.tris = np.asarray(tris)
         self.fn = geometry.face_normals(self.tris)
+        self.amb_tol = amb_tol
 
     def intersect(self, o, d, t_max):
-        r = geometry.nearest_hit(o, d, self.tris, 0.0, t_max)
+        r = geometry.nearest_hit(o, d, self.tris, 0.0, t_max, amb_tol=self.amb_tol)
         hit = r["tri"] >= 0
         n = self.fn[:, np.maximum(r["tri"], 0)]
         margin_ok = ~r["ambiguous"]
         return hit, r["t"], n, margin_ok
 
     def occluded(self, o, d, t_max):
-        r = geometry.nearest_hit(o, d, self.tris, 0.0, t_max)
+        r = geometry.nearest_hit(o, d, self.tris, 0.0, t_max, amb_tol=self.amb_tol)
         return r["tri"] >= 0, ~r["ambiguous"]
 
 
@@ -169,6 +170,8 @@ class NetworkScene:
 
     def occluded(self, o, d, t_max):
         hit, t, _, robust = self._query(o, d)
+        # also undecided when the predicted hit lies at the light within the margin
+        robust = robust & ~(hit & (np.abs(t - t_max) <= self.margin * (1.0 + np.abs(t_max))))
         return hit & (t < t_max), robust
 
 

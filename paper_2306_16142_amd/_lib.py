@@ -25,6 +25,19 @@ class DdfNet(ctypes.Structure):
     _fields_ = [("width", c_i32), ("depth", c_i32), ("precision", c_i32), ("packed", c_p)]
 
 
+class DdfScene(ctypes.Structure):
+    _fields_ = [("backend", c_i32), ("tris", c_p), ("m", c_i64), ("net", ctypes.POINTER(DdfNet))]
+
+
+class DdfRenderParams(ctypes.Structure):
+    _fields_ = [("width", c_i32), ("height", c_i32), ("spp", c_i32), ("bounces", c_i32), ("rr_start", c_i32),
+                ("seed", ctypes.c_uint64), ("eps", c_f), ("eye", c_f * 3), ("target", c_f * 3), ("up", c_f * 3),
+                ("vfov_deg", c_f), ("light_pos", c_f * 3), ("light_intensity", c_f * 3), ("albedo", c_f * 3),
+                ("spp_chunk", c_i32)]
+
+
+BACKEND_MESH, BACKEND_NET = 0, 1
+
 # name -> argument types (every entry point returns ddf_status unless listed in _RESTYPE)
 SIGNATURES = {
     "ddf_abi_version": [],
@@ -35,6 +48,14 @@ SIGNATURES = {
     "ddf_pack_net": [c_p, c_i32, c_i32, c_i32, c_p, c_p, c_p],
     "ddf_fp8_scales": [ctypes.POINTER(DdfNet), c_p, c_p, c_i64, c_p, c_p],
     "ddf_forward": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_p, c_p],
+    "ddf_train_workspace_size": [c_i32, c_i32, c_i64, ctypes.POINTER(c_sz)],
+    "ddf_backward": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_p, c_p, c_p, c_u32, c_p, c_sz, c_p],
+    "ddf_loss_seeds": [c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_p, c_sz, c_p],
+    "ddf_adam_step": [c_p, c_p, c_p, c_p, c_i64, c_i64, c_f, c_f, c_f, c_f, c_p],
+    "ddf_render_workspace_size": [ctypes.POINTER(DdfRenderParams), ctypes.POINTER(c_sz)],
+    "ddf_render_wavefront": [ctypes.POINTER(DdfScene), ctypes.POINTER(DdfRenderParams), c_p, c_p, c_p, c_p, c_p, c_sz,
+                             c_p],
+    "ddf_train_step": [ctypes.POINTER(DdfNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64, c_p, c_p, c_p, c_sz, c_p],
 }
 _RESTYPE = {"ddf_abi_version": c_i32, "ddf_last_error": ctypes.c_char_p}
 

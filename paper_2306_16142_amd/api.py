@@ -90,6 +90,142 @@ class Network:
     __call__ = forward
 
 
+def train_workspace_bytes(width, depth, n):
+    b = ctypes.c_size_t(0)
+    _lib.call("ddf_train_workspace_size", width, depth, n, ctypes.byref(b))
+    return b.value
+
+
+def backward(net, rays, g_logit=None, g_dist=None, want_rays=True, want_params=False, g_params=None,
+             accumulate=False, workspace=None):
+    """Reverse-mode gradient of sum(g_logit * logit + g_dist * dist): returns (g_rays, g_params)."""
+    _dev(rays, torch.float32, "rays", 5)
+    n = rays.shape[1]
+    g_rays = torch.empty((5, n), device=rays.device, dtype=torch.float32) if want_rays else None
+    ws = None
+    if want_params:
+        if g_params is None:
+            g_params = torch.zeros(net.params.numel(), device=rays.device, dtype=torch.float32)
+        nb = train_workspace_bytes(net.width, net.depth, n)
+        ws = workspace if workspace is not None and workspace.numel() >= nb else \
+            torch.empty(nb, device=rays.device, dtype=torch.uint8)
+    else:
+        g_params = None
+    _lib.call("ddf_backward", ctypes.byref(net.desc), _p(rays), n, _p(g_logit), _p(g_dist), _p(g_rays),
+              _p(g_params), 1 if accumulate else 0, _p(ws), ws.numel() if ws is not None else 0, _stream())
+    return g_rays, g_params
+
+
+def loss_seeds(logit, dist, t_label):
+    """BCE (hit) + L1 (distance over hits) loss and its seeds: returns (loss [1], g_logit, g_dist)."""
+    n = logit.numel()
+    g_logit, g_dist = torch.empty_like(logit), torch.empty_like(dist)
+    loss = torch.empty(1, device=logit.device, dtype=torch.float32)
+    ws = torch.empty(4160, device=logit.device, dtype=torch.uint8)
+    _lib.call("ddf_loss_seeds", _p(logit), _p(dist), _p(t_label), n, _p(g_logit), _p(g_dist), _p(loss), _p(ws),
+              ws.numel(), _stream())
+    return loss, g_logit, g_dist
+
+
+def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _lib.call("ddf_adam_step", _p(params), _p(grads), _p(m), _p(v), params.numel(), step, lr, beta1, beta2, eps,
+              _stream())
+
+
+class Trainer:
+    """Adam training of a float32 network on labelled rays (loss: BCE on hit + L1 on distance).
+
+    The packed network ``net`` is rewritten after every step; ``params`` is updated in place.
+    """
+
+    def __init__(self, params, width, depth, batch, lr=1e-3):
+        self.net = Network(params, width, depth, "fp32")
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.g = torch.zeros_like(params)
+        self.loss = torch.zeros(1, device=params.device, dtype=torch.float32)
+        self.lr = lr
+        self.step_count = 0
+        self.ws = torch.empty(train_workspace_bytes(width, depth, batch), device=params.device, dtype=torch.uint8)
+
+    def step(self, rays, t_label):
+        _dev(rays, torch.float32, "rays", 5)
+        _dev(t_label, torch.float32, "t_label")
+        self.step_count += 1
+        n = rays.shape[1]
+        _lib.call("ddf_train_step", ctypes.byref(self.net.desc), _p(self.params), _p(self.m), _p(self.v),
+                  self.step_count, self.lr, _p(rays), _p(t_label), n, _p(self.loss), _p(self.g), _p(self.ws),
+                  self.ws.numel(), _stream())
+        return self.loss
+
+
+class DDFQuery(torch.autograd.Function):
+    """torch.autograd wrapper: forward = ddf_forward, backward = ddf_backward (float32 network)."""
+
+    @staticmethod
+    def forward(ctx, rays, params, net):
+        ctx.net = net
+        ctx.save_for_backward(rays)
+        logit, dist = net.forward(rays.contiguous())
+        return logit, dist
+
+    @staticmethod
+    def backward(ctx, g_logit, g_dist):
+        (rays,) = ctx.saved_tensors
+        net = ctx.net
+        want_params = ctx.needs_input_grad[1]
+        g_rays, g_params = backward(net, rays.contiguous(), g_logit.contiguous(), g_dist.contiguous(),
+                                    want_rays=ctx.needs_input_grad[0], want_params=want_params)
+        return g_rays, g_params, None
+
+
+def render_params(cfg, spp_chunk=0):
+    """ddf_render_params from a scene description (camera / light / sizes)."""
+    c = _lib.DdfRenderParams()
+    c.width, c.height, c.spp, c.bounces, c.rr_start = cfg.width, cfg.height, cfg.spp, cfg.bounces, cfg.rr_start
+    c.seed, c.eps = cfg.seed, cfg.eps
+    c.eye[:] = list(cfg.camera.eye)
+    c.target[:] = list(cfg.camera.target)
+    c.up[:] = list(cfg.camera.up)
+    c.vfov_deg = cfg.camera.vfov_deg
+    c.light_pos[:] = list(cfg.light.position)
+    c.light_intensity[:] = list(cfg.light.intensity)
+    c.albedo[:] = list(cfg.albedo)
+    c.spp_chunk = spp_chunk
+    return c
+
+
+class Renderer:
+    """Wavefront path tracer with the mesh (``tris`` [9][m]) or a network (``net``) as the scene."""
+
+    def __init__(self, cfg, tris=None, net=None, spp_chunk=0, device="cuda"):
+        if (tris is None) == (net is None):
+            raise ValueError("give exactly one of tris (mesh backend) or net (network backend)")
+        self.cfg = cfg
+        self.params = render_params(cfg, spp_chunk)
+        self.net = net
+        self.tris = tris
+        if net is not None:
+            self.scene = _lib.DdfScene(_lib.BACKEND_NET, None, 0, ctypes.pointer(net.desc))
+        else:
+            _dev(tris, torch.float32, "tris", 9)
+            self.scene = _lib.DdfScene(_lib.BACKEND_MESH, tris.data_ptr(), tris.shape[1], None)
+        b = ctypes.c_size_t(0)
+        _lib.call("ddf_render_workspace_size", ctypes.byref(self.params), ctypes.byref(b))
+        self.ws = torch.empty(b.value, device=device, dtype=torch.uint8)
+        H, W = cfg.height, cfg.width
+        self.radiance = torch.empty((3, H, W), device=device, dtype=torch.float32)
+        self.depth = torch.empty((H, W), device=device, dtype=torch.float32)
+        self.normal = torch.empty((3, H, W), device=device, dtype=torch.float32)
+        self.stats = torch.empty(cfg.bounces, device=device, dtype=torch.int32)
+
+    def render(self):
+        _lib.call("ddf_render_wavefront", ctypes.byref(self.scene), ctypes.byref(self.params), _p(self.radiance),
+                  _p(self.depth), _p(self.normal), _p(self.stats), _p(self.ws), self.ws.numel(), _stream())
+        return self.radiance
+
+
 def fp8_scales(params, width, depth, calib_rays, net_fp32=None):
     """Static per-layer fp8 scales (weight absmax / 448, input absmax over calib rays / 448)."""
     _dev(calib_rays, torch.float32, "calib_rays", 5)

@@ -1,0 +1,405 @@
+// Reverse-mode sweep of the network for whole waves of rays.
+//
+// The gradient of the field with respect to the query point gives the surface normal
+// (Eq. 3, Sec. IV-B: the paper takes it with automatic differentiation; here it is a
+// hand-written adjoint).  The same sweep, with the loss gradient as its seed and the
+// layer activations and adjoints written out, is the backward half of training.
+//
+// Per wave of 32 NB rays, in registers: the forward pass is recomputed (its ReLU masks go
+// to LDS, 16 bits per lane and accumulator tile), the head's adjoint seeds the last
+// hidden layer, and every earlier adjoint is a chain of MFMAs with the transposed weight
+// tiles (rows = a layer's inputs, contraction over its outputs) masked by the saved ReLU
+// pattern.  The product with the transposed first layer leaves each lane holding the
+// adjoints of exactly the Fourier features it encoded, so the chain rule through
+// sin/cos ends in registers too.
+#include <cmath>
+#include <mutex>
+
+#include "common.hpp"
+#include "mlp_device.hpp"
+#include "mlp_layout.hpp"
+
+namespace ddf {
+
+struct GradArgs {
+    const uint8_t *blob;
+    int depth;
+    const float *rays;
+    int64_t n;                   // row length of every [k][n] array
+    const int *count_dev;        // when set, only the first *count_dev rays are processed
+    const float *g_logit_in;     // VJP seeds (NULL = 0)
+    const float *g_dist_in;
+    const float *t_label;        // training: label distance, +inf = miss (NULL: seeds from g_*_in)
+    const float *loss_scalars;   // training: {1 / N, 1 / n_hit}
+    float *logit_out;            // optional
+    float *dist_out;             // optional
+    float *g_rays;               // optional [5][n]
+    float *ws_gamma;             // side outputs: [65][n] features
+    float *ws_h;                 // side outputs: [depth][W][n] hidden activations
+    float *ws_delta;             // side outputs: [depth][W][n] adjoints, then [2][n] head seeds
+    float *loss_partial;         // training: [gridDim.x]
+};
+
+namespace {
+
+constexpr int kLdsBytes = 160 * 1024;
+
+
+
+template <int P, int W, int NB, bool kTrain>
+__global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
+    using Op = typename OpOf<P>::T;
+    constexpr int NMB = W / 32;
+    constexpr int KB = k_per_block(P);
+    constexpr int NKB = W / KB;
+    constexpr int K0 = layer0_kblocks(P);
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int depth = a.depth;
+    const int64_t n = a.n;
+    const int64_t count = a.count_dev ? min<int64_t>(*a.count_dev, n) : n;
+    const NetLayout L = make_layout(W, depth, P);
+    const uint8_t *blob = a.blob;
+    const uint8_t *gsrc = blob + L.grad_off;
+
+    float *s_bias = reinterpret_cast<float *>(smem);
+    float *s_head = s_bias + (W * depth + 4);               // [2][W]
+    uint16_t *s_mask = reinterpret_cast<uint16_t *>(s_head + 2 * W);
+    float *s_loss = reinterpret_cast<float *>(s_mask + (blockDim.x / 64) * depth * NMB * NB * 64);
+    for (int i = threadIdx.x; i < W * depth + 4; i += blockDim.x)
+        s_bias[i] = reinterpret_cast<const float *>(blob + L.bias_off)[i];
+    for (int i = threadIdx.x; i < 2 * W; i += blockDim.x)
+        s_head[i] = reinterpret_cast<const float *>(blob + L.head_rows_off)[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 5;
+    const int col = lane & 31;
+    const int wpb = blockDim.x >> 6;
+    uint16_t *wmask = s_mask + (int64_t)wave * depth * NMB * NB * 64;
+    const int64_t ntile = (count + 32 * NB - 1) / (32 * NB);
+    float loss_acc = 0.f;
+    const float inv_n = (kTrain && a.loss_scalars) ? a.loss_scalars[0] : 0.f;
+    const float inv_nhit = (kTrain && a.loss_scalars) ? a.loss_scalars[1] : 0.f;
+
+    for (int64_t tile = (int64_t)blockIdx.x * wpb + wave; tile < ntile; tile += (int64_t)gridDim.x * wpb) {
+        const int64_t base = tile * 32 * NB;
+        Op b[NKB][NB];
+        float v[NB][kInRaw];
+        bool valid[NB];
+        // ---- encoding
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int64_t r = base + nb * 32 + col;
+            valid[nb] = r < count;
+#pragma unroll
+            for (int j = 0; j < kInRaw; ++j) v[nb][j] = valid[nb] ? a.rays[(int64_t)j * n + r] : 0.f;
+            float feat[kSlotsPerHalf];
+            encode_var<P == kFP32>(h ? v[nb][3] : v[nb][0], feat);
+            encode_var<P == kFP32>(h ? v[nb][4] : v[nb][1], feat + kFeatPerVar);
+            encode_var<P == kFP32>(h ? 0.f : v[nb][2], feat + 2 * kFeatPerVar);
+            feat[kSlotsPerHalf - 1] = 0.f;
+            if constexpr (kTrain) {
+                if (valid[nb]) {
+#pragma unroll
+                    for (int f = 0; f < kSlotsPerHalf - 1; ++f) {
+                        const int c = feature_column(h, f);
+                        if (c >= 0) a.ws_gamma[(int64_t)c * n + r] = feat[f];
+                    }
+                }
+            }
+            if constexpr (P == kBF16) {
+#pragma unroll
+                for (int kb = 0; kb < K0; ++kb)
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) b[kb][nb][s] = (__bf16)feat[kb * 8 + s];
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < K0; ++kb) b[kb][nb] = feat[kb];
+            }
+        }
+        // ---- forward (ReLU masks to LDS)
+        for (int l = 0; l < depth; ++l) {
+            const int nkb = l == 0 ? K0 : NKB;
+            const int64_t t0 = L.layer_tile(l);
+            f32x16 acc[NMB][NB];
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb) {
+                if (kb < nkb) {
+#pragma unroll
+                    for (int mb = 0; mb < NMB; ++mb) {
+                        const Op w = load_a<P>(blob, t0 + (int64_t)kb * NMB + mb, lane);
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(w, b[kb][nb], acc[mb][nb]);
+                    }
+                }
+            }
+            const float *bias = s_bias + l * W;
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) {
+                float bv[16];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) bv[4 * g + i] = b4[i];
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    float y[16];
+                    uint32_t bits = 0;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        const float z = acc[mb][nb][j] + bv[j];
+                        y[j] = fmaxf(z, 0.f);
+                        bits |= (z > 0.f ? 1u : 0u) << j;
+                    }
+                    wmask[((l * NMB + mb) * NB + nb) * 64 + lane] = (uint16_t)bits;
+                    if constexpr (kTrain) {
+                        const int64_t r = base + nb * 32 + col;
+                        if (valid[nb]) {
+                            float *dst = a.ws_h + ((int64_t)l * W + mb * 32 + 4 * h) * n + r;
+#pragma unroll
+                            for (int j = 0; j < 16; ++j) dst[(int64_t)(8 * (j / 4) + (j % 4)) * n] = y[j];
+                        }
+                    }
+                    tile_to_operands<P>(y, mb, nb, b);
+                }
+            }
+        }
+        // ---- head and seeds
+        float gl[NB], gd[NB];
+        {
+            f32x16 acc[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) acc[nb][j] = 0.f;
+            const int64_t t0 = L.head_tile();
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb) {
+                const Op w = load_a<P>(blob, t0 + kb, lane);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(w, b[kb][nb], acc[nb]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                // rows 0 (logit) and 1 (distance) live in lanes 0..31; share them with the upper half
+                const float z = __shfl(acc[nb][0], col) + s_bias[W * depth];
+                const float dd = __shfl(acc[nb][1], col) + s_bias[W * depth + 1];
+                const int64_t r = base + nb * 32 + col;
+                if (h == 0 && valid[nb]) {
+                    if (a.logit_out) a.logit_out[r] = z;
+                    if (a.dist_out) a.dist_out[r] = dd;
+                }
+                if (kTrain && a.t_label) {
+                    const float t = valid[nb] ? a.t_label[r] : INFINITY;
+                    const float y = t < INFINITY ? 1.f : 0.f;
+                    const float sig = 1.f / (1.f + expf(-z));
+                    gl[nb] = valid[nb] ? (sig - y) * inv_n : 0.f;
+                    const float diff = dd - (y > 0.f ? t : 0.f);
+                    gd[nb] = y > 0.f ? (diff > 0.f ? inv_nhit : (diff < 0.f ? -inv_nhit : 0.f)) : 0.f;
+                    if (h == 0 && valid[nb]) {
+                        loss_acc += (fmaxf(z, 0.f) - z * y + log1pf(expf(-fabsf(z)))) * inv_n +
+                                    y * fabsf(diff) * inv_nhit;
+                        a.ws_delta[(int64_t)depth * W * n + r] = gl[nb];
+                        a.ws_delta[(int64_t)depth * W * n + n + r] = gd[nb];
+                    }
+                } else {
+                    gl[nb] = (valid[nb] && a.g_logit_in) ? a.g_logit_in[(base + nb * 32 + col)] : 0.f;
+                    gd[nb] = (valid[nb] && a.g_dist_in) ? a.g_dist_in[(base + nb * 32 + col)] : 0.f;
+                    if (kTrain && h == 0 && valid[nb]) {
+                        a.ws_delta[(int64_t)depth * W * n + r] = gl[nb];
+                        a.ws_delta[(int64_t)depth * W * n + n + r] = gd[nb];
+                    }
+                }
+            }
+        }
+        // ---- adjoint of the last hidden layer: head rows times the seeds, masked.  The
+        // accumulator array carries each layer's adjoint (D layout) down the network.
+        f32x16 acc[NMB][NB];
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) {
+            float w0[16], w1[16];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const f32x4 a4 = *reinterpret_cast<const f32x4 *>(s_head + mb * 32 + 8 * g + 4 * h);
+                const f32x4 b4 = *reinterpret_cast<const f32x4 *>(s_head + W + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    w0[4 * g + i] = a4[i];
+                    w1[4 * g + i] = b4[i];
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const uint32_t bits = wmask[(((depth - 1) * NMB + mb) * NB + nb) * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    acc[mb][nb][j] = ((bits >> j) & 1u) ? fmaf(gl[nb], w0[j], gd[nb] * w1[j]) : 0.f;
+            }
+        }
+        // ---- adjoints of the hidden layers, top down
+        for (int l = depth - 1; l >= 0; --l) {
+            if constexpr (kTrain) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int64_t r = base + nb * 32 + col;
+                    if (valid[nb]) {
+#pragma unroll
+                        for (int mb = 0; mb < NMB; ++mb) {
+                            float *dst = a.ws_delta + ((int64_t)l * W + mb * 32 + 4 * h) * n + r;
+#pragma unroll
+                            for (int j = 0; j < 16; ++j) dst[(int64_t)(8 * (j / 4) + (j % 4)) * n] = acc[mb][nb][j];
+                        }
+                    }
+                }
+            }
+            if (l == 0) break;
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    float y[16];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) y[j] = acc[mb][nb][j];
+                    tile_to_operands<P>(y, mb, nb, b);
+                }
+            const int64_t t0 = L.grad_layer_tile(l);
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb) {
+                    const Op w = load_a<P>(gsrc, t0 + (int64_t)kb * NMB + mb, lane);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(w, b[kb][nb], acc[mb][nb]);
+                }
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const uint32_t bits = wmask[(((l - 1) * NMB + mb) * NB + nb) * 64 + lane];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) acc[mb][nb][j] = ((bits >> j) & 1u) ? acc[mb][nb][j] : 0.f;
+                }
+        }
+        if (!a.g_rays) continue;
+        // ---- transposed first layer: adjoints of this lane's 48 feature slots
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                float y[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) y[j] = acc[mb][nb][j];
+                tile_to_operands<P>(y, mb, nb, b);
+            }
+        f32x16 acc0[kGradRowBlocks0][NB];
+#pragma unroll
+        for (int mb = 0; mb < kGradRowBlocks0; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) acc0[mb][nb][j] = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+            for (int mb = 0; mb < kGradRowBlocks0; ++mb) {
+                const Op w = load_a<P>(gsrc, (int64_t)kb * kGradRowBlocks0 + mb, lane);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc0[mb][nb] = mfma<P>(w, b[kb][nb], acc0[mb][nb]);
+            }
+        // ---- chain rule through the Fourier features
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int64_t r = base + nb * 32 + col;
+#pragma unroll
+            for (int var = 0; var < 3; ++var) {
+                if (h == 1 && var == 2) continue;
+                float f[kFeatPerVar];
+                const float x = h ? v[nb][3 + var] : v[nb][var];
+                encode_var<P == kFP32>(x, f);
+                float g = acc0[(var * kFeatPerVar) / 16][nb][(var * kFeatPerVar) % 16];
+#pragma unroll
+                for (int k = 0; k < kNFreq; ++k) {
+                    const int fs = var * kFeatPerVar + 1 + k, fc = var * kFeatPerVar + 1 + kNFreq + k;
+                    const float gs = acc0[fs / 16][nb][fs % 16], gc = acc0[fc / 16][nb][fc % 16];
+                    g = fmaf((float)(1 << k), gs * f[1 + kNFreq + k] - gc * f[1 + k], g);
+                }
+                if (valid[nb]) a.g_rays[(int64_t)(h ? 3 + var : var) * n + r] = g;
+            }
+        }
+    }
+    if constexpr (kTrain) {
+        // block sum of the loss terms -> one partial per block (summed in a fixed order later)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) loss_acc += __shfl_xor(loss_acc, off);
+        if (lane == 0) s_loss[wave] = loss_acc;
+        __syncthreads();
+        if (threadIdx.x == 0 && a.loss_partial) {
+            float t = 0.f;
+            for (int w = 0; w < wpb; ++w) t += s_loss[w];
+            a.loss_partial[blockIdx.x] = t;
+        }
+    }
+}
+
+int cu_count_grad() {
+    static int cus = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    });
+    return cus;
+}
+
+template <int P, int W, int NB, bool kTrain>
+ddf_status launch_grad(const GradArgs &args, hipStream_t s, int grid_cap) {
+    auto kern = grad_kernel<P, W, NB, kTrain>;
+    static std::once_flag once;
+    std::call_once(once, [&] { (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes); });
+    const int threads = NB == 2 ? 512 : 256;
+    const int wpb = threads / 64;
+    const size_t lds = ((size_t)W * args.depth + 4 + 2 * W) * 4 + (size_t)wpb * args.depth * (W / 32) * NB * 64 * 2 + 16 * 4;
+    const int64_t ntile = (args.n + 32 * NB - 1) / (32 * NB);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((ntile + wpb - 1) / wpb, grid_cap));
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, s, args);
+    return launch_status("ddf gradient kernel");
+}
+
+}  // namespace
+
+// Shared with the training driver: grid size used for a given batch (loss partials).
+int64_t grad_grid(int width, int precision, int64_t n) {
+    const int NB = (width == 128 && precision != kFP32) ? 2 : 1;
+    const int wpb = NB == 2 ? 8 : 4;
+    const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
+    return std::max<int64_t>(1, std::min<int64_t>((ntile + wpb - 1) / wpb, (int64_t)cu_count_grad() * 2));
+}
+
+ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, hipStream_t s) {
+    const int cap = cu_count_grad() * 2;
+    const int w = net->width, p = net->precision;
+    if (train) {
+        if (w == 128) return p == kBF16 ? launch_grad<kBF16, 128, 2, true>(args, s, cap) : launch_grad<kFP32, 128, 1, true>(args, s, cap);
+        return p == kBF16 ? launch_grad<kBF16, 256, 1, true>(args, s, cap) : launch_grad<kFP32, 256, 1, true>(args, s, cap);
+    }
+    if (w == 128) return p == kBF16 ? launch_grad<kBF16, 128, 2, false>(args, s, cap) : launch_grad<kFP32, 128, 1, false>(args, s, cap);
+    return p == kBF16 ? launch_grad<kBF16, 256, 1, false>(args, s, cap) : launch_grad<kFP32, 256, 1, false>(args, s, cap);
+}
+
+}  // namespace ddf

@@ -50,20 +50,25 @@ __device__ __noinline__ double mt_fp64(const float *__restrict__ tris, int64_t m
     return NAN;
 }
 
+// Output slot q reads ray idx[q] (or q) from [3][stride] arrays; only q < n (or *count_dev)
+// are processed.  Blocks past the count exit before touching LDS.
 __global__ __launch_bounds__(kLabelThreads) void label_kernel(
-    const float *__restrict__ orig, const float *__restrict__ dir, int64_t n, const float *__restrict__ tris,
-    int64_t m, float t_min, float t_max, float *__restrict__ t_out, int32_t *__restrict__ tri_out,
-    uint32_t *__restrict__ cross_out) {
+    const float *__restrict__ orig, const float *__restrict__ dir, int64_t stride, const int *__restrict__ idx,
+    const int *__restrict__ count_dev, const float *__restrict__ tris, int64_t m, float t_min, float t_max,
+    float *__restrict__ t_out, int32_t *__restrict__ tri_out, uint32_t *__restrict__ cross_out) {
     __shared__ TriLds s_tri[kLabelTile];
+    const int64_t n = count_dev ? min<int64_t>(*count_dev, stride) : stride;
+    if ((int64_t)blockIdx.x * kLabelThreads >= n) return;
     const int64_t ray = (int64_t)blockIdx.x * kLabelThreads + threadIdx.x;
     float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f;
     if (ray < n) {
-        ox = orig[ray];
-        oy = orig[n + ray];
-        oz = orig[2 * n + ray];
-        dx = dir[ray];
-        dy = dir[n + ray];
-        dz = dir[2 * n + ray];
+        const int64_t src = idx ? (int64_t)idx[ray] : ray;
+        ox = orig[src];
+        oy = orig[stride + src];
+        oz = orig[2 * stride + src];
+        dx = dir[src];
+        dy = dir[stride + src];
+        dz = dir[2 * stride + src];
     }
     const bool finite = isfinite(ox) && isfinite(oy) && isfinite(oz) && isfinite(dx) && isfinite(dy) &&
                         isfinite(dz) && (dx != 0.f || dy != 0.f || dz != 0.f);
@@ -184,6 +189,18 @@ extern "C" ddf_status ddf_label_rays(const float *orig, const float *dir, int64_
     const int64_t blocks = (n + kLabelThreads - 1) / kLabelThreads;
     DDF_REQUIRE(blocks < (int64_t)1 << 31, DDF_ERR_UNSUPPORTED, "ddf_label_rays: too many rays");
     hipLaunchKernelGGL(label_kernel, dim3((unsigned)blocks), dim3(kLabelThreads), 0, as_stream(stream), orig, dir,
-                       n, tris, m, t_min, t_max, t_out, tri_out, crossings);
+                       n, (const int *)nullptr, (const int *)nullptr, tris, m, t_min, t_max, t_out, tri_out, crossings);
     return launch_status("ddf_label_rays");
 }
+
+namespace ddf {
+// Labeller over a queue: slot q < *count_dev reads ray idx[q] of [3][stride] arrays.
+ddf_status label_queue(const float *orig, const float *dir, int64_t stride, const int *idx, const int *count_dev,
+                       const float *tris, int64_t m, float t_min, float t_max, float *t_out, int32_t *tri_out,
+                       hipStream_t s) {
+    const int64_t blocks = (stride + kLabelThreads - 1) / kLabelThreads;
+    hipLaunchKernelGGL(label_kernel, dim3((unsigned)blocks), dim3(kLabelThreads), 0, s, orig, dir, stride, idx,
+                       count_dev, tris, m, t_min, t_max, t_out, tri_out, (uint32_t *)nullptr);
+    return launch_status("ddf labeller (queue)");
+}
+}  // namespace ddf

@@ -13,25 +13,15 @@
 #include <mutex>
 
 #include "common.hpp"
+#include "mlp_device.hpp"
 #include "mlp_layout.hpp"
 
 namespace ddf {
 namespace {
 
-constexpr float kFp8Max = 448.0f;
 constexpr int kLdsBytes = 160 * 1024;
 
 // ------------------------------------------------------------------------------ packing
-__device__ inline uint16_t bf16_bits(float x) {
-    __bf16 b = (__bf16)x;   // round to nearest even
-    return __builtin_bit_cast(uint16_t, b);
-}
-
-__device__ inline uint8_t fp8_bits(float x) {
-    x = __builtin_amdgcn_fmed3f(x, -kFp8Max, kFp8Max);   // the conversion does not saturate
-    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
-}
-
 // Weight of layer l (row m, input column c) from the flat parameter vector.
 __device__ inline float weight_at(const float *params, int width, int depth, int l, int m, int c) {
     int64_t off = 0;
@@ -57,129 +47,115 @@ __device__ inline float bias_at(const float *params, int width, int depth, int l
     return params[off + m];
 }
 
-// One thread per (tile, lane, slot) of the blob, then the biases and scales.
+// Value of A-operand slot s of `lane` in forward tile `tile` (layer, K-block, M-block decoded
+// from the tile index), before conversion.
+__device__ inline float forward_weight(const float *params, const NetLayout &L, int64_t tile, int lane, int s) {
+    const int width = L.width, depth = L.depth, prec = L.prec;
+    int l;
+    int64_t t;
+    if (tile < L.layer_tile(1) || depth == 0) {
+        l = 0;
+        t = tile;
+    } else if (tile >= L.head_tile()) {
+        l = depth;
+        t = tile - L.head_tile();
+    } else {
+        l = 1 + (int)((tile - L.layer_tile(1)) / ((int64_t)L.nkb * L.nmb));
+        t = tile - L.layer_tile(l);
+    }
+    const int nmb = l == depth ? 1 : L.nmb;
+    const int kb = (int)(t / nmb), mb = (int)(t % nmb);
+    const int h = lane / 32;
+    const int m = mb * 32 + (lane % 32);
+    if (l == 0) {
+        const int c = feature_column(h, layer0_feature(prec, kb, s));
+        return c >= 0 ? weight_at(params, width, depth, 0, m, c) : 0.f;
+    }
+    if (l < depth || m < 2) return weight_at(params, width, depth, l, m, prev_unit(prec, kb, h, s));
+    return 0.f;
+}
+
+// Transposed tile of the input-gradient sweep: rows are the layer's inputs, K its outputs.
+__device__ inline float grad_weight(const float *params, const NetLayout &L, int64_t tile, int lane, int s) {
+    const int width = L.width, depth = L.depth, prec = L.prec;
+    int l;
+    int64_t t;
+    if (tile < L.grad_layer_tile(1) || depth == 1) {
+        l = 0;
+        t = tile;
+    } else {
+        l = 1 + (int)((tile - L.grad_layer_tile(1)) / ((int64_t)L.nkb * L.nmb));
+        t = tile - L.grad_layer_tile(l);
+    }
+    const int nmb = l == 0 ? kGradRowBlocks0 : L.nmb;
+    const int kb = (int)(t / nmb), mb = (int)(t % nmb);
+    const int m = mb * 32 + (lane % 32);
+    const int k = prev_unit(prec, kb, lane / 32, s);   // an output unit of layer l
+    if (l == 0) {
+        const int c = feature_column(grad_row_half(m), grad_row_feature(m));
+        return c >= 0 ? weight_at(params, width, depth, 0, k, c) : 0.f;
+    }
+    return weight_at(params, width, depth, l, k, m);
+}
+
+__device__ inline void store_slot(uint8_t *tile_base, int prec, int lane, int s, float w, float scale) {
+    if (prec == kFP32) reinterpret_cast<float *>(tile_base)[lane] = w;
+    else if (prec == kBF16) reinterpret_cast<uint16_t *>(tile_base)[lane * 8 + s] = bf16_bits(w);
+    else tile_base[lane * 32 + s] = fp8_bits(scale > 0.f ? w / scale : 0.f);
+}
+
+// One thread per packed element: forward tile slots, biases, scales, transposed tile
+// slots, head rows.
 __global__ void pack_kernel(const float *__restrict__ params, int width, int depth, int prec,
                             const float *__restrict__ scales, uint8_t *__restrict__ blob) {
     const NetLayout L = make_layout(width, depth, prec);
     const int slots = slots_per_lane(prec);
-    const int64_t elems = L.tiles * 64 * slots;
-    const int64_t nbias = (int64_t)width * depth + 4;
-    const int64_t nscale = 2 * (depth + 1);
-    const int64_t total = elems + nbias + nscale;
+    const int64_t n_fwd = L.tiles * 64 * slots;
+    const int64_t n_bias = (int64_t)width * depth + 4;
+    const int64_t n_scale = 2 * (depth + 1);
+    const int64_t n_grad = L.grad_tiles * 64 * slots;
+    const int64_t n_head = prec == kFP8 ? 0 : 2 * (int64_t)width;
+    const int64_t total = n_fwd + n_bias + n_scale + n_grad + n_head;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        if (e >= elems) {
-            const int64_t b = e - elems;
-            if (b < nbias) {
-                float v = 0.f;
-                const int l = (int)(b / width), m = (int)(b % width);
-                if (l < depth) v = bias_at(params, width, depth, l, m);
-                else if (b - (int64_t)width * depth < 2) v = bias_at(params, width, depth, depth, (int)(b - (int64_t)width * depth));
-                reinterpret_cast<float *>(blob + L.bias_off)[b] = v;
-            } else {
-                const int64_t si = b - nbias;
-                reinterpret_cast<float *>(blob + L.scale_off)[si] = scales ? scales[si] : 1.0f;
+        int64_t r = e;
+        if (r < n_fwd) {
+            const int s = (int)(r % slots), lane = (int)((r / slots) % 64);
+            const int64_t tile = r / (slots * 64);
+            int l = 0;
+            if (prec == kFP8) {
+                // the layer of this tile selects its weight scale
+                l = tile < L.layer_tile(1) ? 0 : tile >= L.head_tile() ? depth
+                    : 1 + (int)((tile - L.layer_tile(1)) / ((int64_t)L.nkb * L.nmb));
             }
+            store_slot(blob + tile * tile_bytes(prec), prec, lane, s, forward_weight(params, L, tile, lane, s),
+                       prec == kFP8 ? scales[2 * l] : 1.f);
             continue;
         }
-        const int s = (int)(e % slots);
-        const int lane = (int)((e / slots) % 64);
-        const int64_t tile = e / (slots * 64);
-        // locate the layer and the (kb, mb) of this tile
-        int l;
-        int64_t t;
-        if (tile < L.layer_tile(1) || depth == 0) {
-            l = 0;
-            t = tile;
-        } else if (tile >= L.head_tile()) {
-            l = depth;
-            t = tile - L.head_tile();
-        } else {
-            l = 1 + (int)((tile - L.layer_tile(1)) / ((int64_t)L.nkb * L.nmb));
-            t = tile - L.layer_tile(l);
+        r -= n_fwd;
+        if (r < n_bias) {
+            float v = 0.f;
+            const int l = (int)(r / width), m = (int)(r % width);
+            if (l < depth) v = bias_at(params, width, depth, l, m);
+            else if (r - (int64_t)width * depth < 2) v = bias_at(params, width, depth, depth, (int)(r - (int64_t)width * depth));
+            reinterpret_cast<float *>(blob + L.bias_off)[r] = v;
+            continue;
         }
-        const int nmb = l == depth ? 1 : L.nmb;
-        const int kb = (int)(t / nmb), mb = (int)(t % nmb);
-        const int h = lane / 32;
-        const int m = mb * 32 + (lane % 32);
-        float w = 0.f;
-        if (l == 0) {
-            const int c = feature_column(h, layer0_feature(prec, kb, s));
-            if (c >= 0) w = weight_at(params, width, depth, 0, m, c);
-        } else if (l < depth || m < 2) {
-            w = weight_at(params, width, depth, l, m, prev_unit(prec, kb, h, s));
+        r -= n_bias;
+        if (r < n_scale) {
+            reinterpret_cast<float *>(blob + L.scale_off)[r] = scales ? scales[r] : 1.0f;
+            continue;
         }
-        uint8_t *dst = blob + tile * tile_bytes(prec);
-        if (prec == kFP32) {
-            reinterpret_cast<float *>(dst)[lane] = w;
-        } else if (prec == kBF16) {
-            reinterpret_cast<uint16_t *>(dst)[lane * 8 + s] = bf16_bits(w);
-        } else {
-            const float sw = scales[2 * l];
-            dst[lane * 32 + s] = fp8_bits(sw > 0.f ? w / sw : 0.f);
+        r -= n_scale;
+        if (r < n_grad) {
+            const int s = (int)(r % slots), lane = (int)((r / slots) % 64);
+            const int64_t tile = r / (slots * 64);
+            store_slot(blob + L.grad_off + tile * tile_bytes(prec), prec, lane, s, grad_weight(params, L, tile, lane, s), 1.f);
+            continue;
         }
+        r -= n_grad;
+        reinterpret_cast<float *>(blob + L.head_rows_off)[r] =
+            weight_at(params, width, depth, depth, (int)(r / width), (int)(r % width));
     }
-}
-
-// ------------------------------------------------------------------------------ encoding
-// Features of one variable: raw, sin(2^k v), cos(2^k v), k = 0..5.  In float32 mode every
-// frequency calls sincosf (arguments 2^k v are exact); in reduced precision the higher
-// frequencies follow the double-angle recurrence from the k = 0 values.
-template <bool kExact>
-__device__ inline void encode_var(float v, float *f) {
-    f[0] = v;
-    float s, c;
-    sincosf(v, &s, &c);
-    f[1] = s;
-    f[1 + kNFreq] = c;
-#pragma unroll
-    for (int k = 1; k < kNFreq; ++k) {
-        if constexpr (kExact) {
-            sincosf(v * (float)(1 << k), &s, &c);
-        } else {
-            const float s2 = 2.f * s * c;
-            const float c2 = 1.f - 2.f * s * s;
-            s = s2;
-            c = c2;
-        }
-        f[1 + k] = s;
-        f[1 + kNFreq + k] = c;
-    }
-}
-
-// ------------------------------------------------------------------------------ forward
-template <int P>
-struct OpOf;
-template <>
-struct OpOf<kBF16> {
-    using T = bf16x8;
-};
-template <>
-struct OpOf<kFP8> {
-    using T = i32x8;
-};
-template <>
-struct OpOf<kFP32> {
-    using T = float;
-};
-
-template <int P>
-__device__ inline f32x16 mfma(typename OpOf<P>::T a, typename OpOf<P>::T b, f32x16 c) {
-    if constexpr (P == kBF16) return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-    else if constexpr (P == kFP8) return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
-    else return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-}
-
-template <int P, bool kLdsA>
-__device__ inline typename OpOf<P>::T load_a(const uint8_t *src, int64_t tile, int lane) {
-    using Op = typename OpOf<P>::T;
-    const uint8_t *p = src + tile * tile_bytes(P) + (int64_t)lane * (tile_bytes(P) / 64);
-    return *reinterpret_cast<const Op *>(p);
-}
-
-// Packs 4 non-negative floats (already clamped to the e4m3 range) into one dword.
-__device__ inline int pack_fp8x4(float a, float b, float c, float d) {
-    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
 }
 
 // Calibration: wave maximum of non-negative values, one atomic per wave (floats >= 0
@@ -198,8 +174,9 @@ struct LdsConsts {
 // W: width, NB: 32-ray column blocks per wave, P: precision, kLdsA: weights in LDS.
 template <int P, int W, int NB, bool kLdsA>
 __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
-    const uint8_t *__restrict__ blob, int depth, const float *__restrict__ rays, int64_t n,
-    float *__restrict__ logit_out, float *__restrict__ dist_out, unsigned int *__restrict__ absmax) {
+    const uint8_t *__restrict__ blob, int depth, const float *__restrict__ rays, int64_t stride,
+    const int *__restrict__ count_dev, float *__restrict__ logit_out, float *__restrict__ dist_out,
+    unsigned int *__restrict__ absmax) {
     using Op = typename OpOf<P>::T;
     constexpr int NMB = W / 32;
     constexpr int KB = k_per_block(P);
@@ -249,6 +226,9 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
     const int h = lane >> 5;
     const int col = lane & 31;
     const int wpb = blockDim.x >> 6;
+    // rays are rows of length `stride`; the first `n` are evaluated (n from the device when
+    // a queue produced them)
+    const int64_t n = count_dev ? min<int64_t>(*count_dev, stride) : stride;
     const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
 
     for (int64_t tile = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); tile < ntile; tile += (int64_t)gridDim.x * wpb) {
@@ -262,7 +242,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
             float v[kInRaw] = {0.f, 0.f, 0.f, 0.f, 0.f};
             if (r < n) {
 #pragma unroll
-                for (int j = 0; j < kInRaw; ++j) v[j] = rays[(int64_t)j * n + r];
+                for (int j = 0; j < kInRaw; ++j) v[j] = rays[(int64_t)j * stride + r];
             }
             nan_ray[nb] = isnan(v[0]) || isnan(v[1]) || isnan(v[2]) || isnan(v[3]) || isnan(v[4]);
             float feat[kSlotsPerHalf];
@@ -320,7 +300,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
                     if (kb < nkb) {
 #pragma unroll
                         for (int mb = 0; mb < NMB; ++mb) {
-                            const Op a = load_a<P, kLdsA>(wsrc, t0 + (int64_t)kb * NMB + mb, lane);
+                            const Op a = load_a<P>(wsrc, t0 + (int64_t)kb * NMB + mb, lane);
 #pragma unroll
                             for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(a, b[kb][nb], acc[mb][nb]);
                         }
@@ -355,21 +335,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
                                 if (base + nb * 32 + col < n) m = fmaxf(m, y[j]);
                             wave_absmax(m, absmax + 2 * (l + 1) + 1);
                         }
-                        if constexpr (P == kBF16) {
-#pragma unroll
-                            for (int c = 0; c < 2; ++c)
-#pragma unroll
-                                for (int s = 0; s < 8; ++s) b[2 * mb + c][nb][s] = (__bf16)y[8 * c + s];
-                        } else if constexpr (P == kFP8) {
-                            // M-block mb feeds K-block mb / 2, slots 16 (mb % 2) .. +15 = words 4 (mb % 2) .. +3
-#pragma unroll
-                            for (int w4 = 0; w4 < 4; ++w4)
-                                b[mb / 2][nb][4 * (mb % 2) + w4] =
-                                    pack_fp8x4(y[4 * w4], y[4 * w4 + 1], y[4 * w4 + 2], y[4 * w4 + 3]);
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < 16; ++j) b[16 * mb + j][nb] = y[j];
-                        }
+                        tile_to_operands<P>(y, mb, nb, b);
                     }
                 }
             } else {
@@ -380,7 +346,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
                     for (int j = 0; j < 16; ++j) acc[nb][j] = 0.f;
 #pragma unroll
                 for (int kb = 0; kb < NKB; ++kb) {
-                    const Op a = load_a<P, kLdsA>(wsrc, t0 + kb, lane);
+                    const Op a = load_a<P>(wsrc, t0 + kb, lane);
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, b[kb][nb], acc[nb]);
                 }
@@ -447,8 +413,8 @@ int cu_count() {
 }
 
 template <int P, int W, int NB, bool kLdsA>
-ddf_status launch_forward(const NetLayout &L, const void *blob, const float *rays, int64_t n, float *logit,
-                          float *dist, unsigned int *absmax, hipStream_t stream) {
+ddf_status launch_forward(const NetLayout &L, const void *blob, const float *rays, int64_t n, const int *count_dev,
+                          float *logit, float *dist, unsigned int *absmax, hipStream_t stream) {
     auto kern = forward_kernel<P, W, NB, kLdsA>;
     const size_t lds = (kLdsA ? L.tiles * tile_bytes(P) : 0) + ((size_t)W * L.depth + 4) * 4 + sizeof(LdsConsts);
     static std::once_flag once;
@@ -459,7 +425,7 @@ ddf_status launch_forward(const NetLayout &L, const void *blob, const float *ray
     const int per_cu = kLdsA ? 1 : 2;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((ntile + wpb - 1) / wpb, (int64_t)cu_count() * per_cu));
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, (const uint8_t *)blob, L.depth, rays, n,
-                       logit, dist, absmax);
+                       count_dev, logit, dist, absmax);
     return launch_status("ddf_forward");
 }
 
@@ -474,25 +440,27 @@ ddf_status check_shape(int width, int depth, int prec, const char *who) {
     return DDF_OK;
 }
 
-ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, float *logit, float *dist,
-                            unsigned int *absmax, hipStream_t s) {
+}  // namespace
+
+// Network query of the first n (or *count_dev) rays of a [5][n] buffer.
+ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, const int *count_dev, float *logit,
+                            float *dist, unsigned int *absmax, hipStream_t s) {
     const NetLayout L = make_layout(net->width, net->depth, net->precision);
     const bool lds = fits_lds(L);
     if (net->width == 128) {
         if (net->precision == kBF16)
-            return lds ? launch_forward<kBF16, 128, 2, true>(L, net->packed, rays, n, logit, dist, absmax, s)
-                       : launch_forward<kBF16, 128, 2, false>(L, net->packed, rays, n, logit, dist, absmax, s);
+            return lds ? launch_forward<kBF16, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
+                       : launch_forward<kBF16, 128, 2, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
         if (net->precision == kFP8)
-            return lds ? launch_forward<kFP8, 128, 2, true>(L, net->packed, rays, n, logit, dist, absmax, s)
-                       : launch_forward<kFP8, 128, 2, false>(L, net->packed, rays, n, logit, dist, absmax, s);
-        return launch_forward<kFP32, 128, 1, false>(L, net->packed, rays, n, logit, dist, absmax, s);
+            return lds ? launch_forward<kFP8, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
+                       : launch_forward<kFP8, 128, 2, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
+        return launch_forward<kFP32, 128, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
     }
-    if (net->precision == kBF16) return launch_forward<kBF16, 256, 1, false>(L, net->packed, rays, n, logit, dist, absmax, s);
-    if (net->precision == kFP8) return launch_forward<kFP8, 256, 1, false>(L, net->packed, rays, n, logit, dist, absmax, s);
-    return launch_forward<kFP32, 256, 1, false>(L, net->packed, rays, n, logit, dist, absmax, s);
+    if (net->precision == kBF16) return launch_forward<kBF16, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
+    if (net->precision == kFP8) return launch_forward<kFP8, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
+    return launch_forward<kFP32, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
 }
 
-}  // namespace
 }  // namespace ddf
 
 using namespace ddf;
@@ -526,7 +494,7 @@ extern "C" ddf_status ddf_fp8_scales(const ddf_net *net_fp32, const float *param
     const int nsc = 2 * (net_fp32->depth + 1);
     hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, scales_out, (int64_t)nsc);
     if (ddf_status st = launch_status("ddf_fp8_scales")) return st;
-    if (ddf_status st = forward_dispatch(net_fp32, calib, n_calib, nullptr, nullptr,
+    if (ddf_status st = forward_dispatch(net_fp32, calib, n_calib, nullptr, nullptr, nullptr,
                                          reinterpret_cast<unsigned int *>(scales_out), s))
         return st;
     hipLaunchKernelGGL(weight_absmax_kernel, dim3(net_fp32->depth + 1), dim3(256), 0, s, params, net_fp32->width,
@@ -541,5 +509,5 @@ extern "C" ddf_status ddf_forward(const ddf_net *net, const float *rays, int64_t
     DDF_REQUIRE(n >= 0, DDF_ERR_INVALID_ARG, "ddf_forward: negative n");
     if (n == 0) return DDF_OK;
     DDF_REQUIRE(net->packed && rays && logit_out && dist_out, DDF_ERR_INVALID_ARG, "ddf_forward: NULL array");
-    return forward_dispatch(net, rays, n, logit_out, dist_out, nullptr, as_stream(stream));
+    return forward_dispatch(net, rays, n, nullptr, logit_out, dist_out, nullptr, as_stream(stream));
 }

@@ -1,0 +1,103 @@
+// Device building blocks of the network kernels: Fourier encoding, MFMA wrappers and
+// operand loads (operand numbering in mlp_layout.hpp).
+#pragma once
+#include "common.hpp"
+#include "mlp_layout.hpp"
+
+namespace ddf {
+
+constexpr float kFp8Max = 448.0f;
+
+// ------------------------------------------------------------------------------ encoding
+// Features of one variable: raw, sin(2^k v), cos(2^k v), k = 0..5.  In float32 mode every
+// frequency calls sincosf (arguments 2^k v are exact); in reduced precision the higher
+// frequencies follow the double-angle recurrence from the k = 0 values.
+template <bool kExact>
+__device__ inline void encode_var(float v, float *f) {
+    f[0] = v;
+    float s, c;
+    sincosf(v, &s, &c);
+    f[1] = s;
+    f[1 + kNFreq] = c;
+#pragma unroll
+    for (int k = 1; k < kNFreq; ++k) {
+        if constexpr (kExact) {
+            sincosf(v * (float)(1 << k), &s, &c);
+        } else {
+            const float s2 = 2.f * s * c;
+            const float c2 = 1.f - 2.f * s * s;
+            s = s2;
+            c = c2;
+        }
+        f[1 + k] = s;
+        f[1 + kNFreq + k] = c;
+    }
+}
+
+// ------------------------------------------------------------------------------ forward
+template <int P>
+struct OpOf;
+template <>
+struct OpOf<kBF16> {
+    using T = bf16x8;
+};
+template <>
+struct OpOf<kFP8> {
+    using T = i32x8;
+};
+template <>
+struct OpOf<kFP32> {
+    using T = float;
+};
+
+template <int P>
+__device__ inline f32x16 mfma(typename OpOf<P>::T a, typename OpOf<P>::T b, f32x16 c) {
+    if constexpr (P == kBF16) return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    else if constexpr (P == kFP8) return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+    else return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+template <int P>
+__device__ inline typename OpOf<P>::T load_a(const uint8_t *src, int64_t tile, int lane) {
+    using Op = typename OpOf<P>::T;
+    const uint8_t *p = src + tile * tile_bytes(P) + (int64_t)lane * (tile_bytes(P) / 64);
+    return *reinterpret_cast<const Op *>(p);
+}
+
+// Packs 4 non-negative floats (already clamped to the e4m3 range) into one dword.
+__device__ inline int pack_fp8x4(float a, float b, float c, float d) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+}
+
+
+__device__ inline uint16_t bf16_bits(float x) {
+    __bf16 b = (__bf16)x;   // round to nearest even
+    return __builtin_bit_cast(uint16_t, b);
+}
+
+__device__ inline uint8_t fp8_bits(float x) {
+    x = __builtin_amdgcn_fmed3f(x, -kFp8Max, kFp8Max);   // the conversion does not saturate
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
+}
+
+// Converts one accumulator tile (D layout: rows 8 g + 4 h + i of M-block mb, values y[16]) of
+// a layer's output into the next product's B operands (fp32 and bf16 only).
+template <int P, int NKB, int NB>
+__device__ inline void tile_to_operands(const float *y, int mb, int nb, typename OpOf<P>::T (&b)[NKB][NB]) {
+    if constexpr (P == kBF16) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) b[2 * mb + c][nb][s] = (__bf16)y[8 * c + s];
+    } else if constexpr (P == kFP8) {
+#pragma unroll
+        for (int w4 = 0; w4 < 4; ++w4)
+            b[mb / 2][nb][4 * (mb % 2) + w4] = pack_fp8x4(y[4 * w4], y[4 * w4 + 1], y[4 * w4 + 2], y[4 * w4 + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) b[16 * mb + j][nb] = y[j];
+    }
+}
+
+}  // namespace ddf

@@ -34,18 +34,29 @@ __host__ __device__ constexpr int slots_per_lane(int prec) { return prec == kBF1
 __host__ __device__ constexpr int tile_bytes(int prec) { return prec == kBF16 ? 1024 : prec == kFP8 ? 2048 : 256; }
 __host__ __device__ constexpr int layer0_kblocks(int prec) { return prec == kBF16 ? 5 : prec == kFP8 ? 2 : 40; }
 
+// Blob sections: forward A tiles | biases | fp8 scales | (fp32 / bf16 only) transposed
+// A tiles of the input-gradient sweep | the head's two weight rows in float32.
+constexpr int kGradRowBlocks0 = 3;   // layer-0 transposed product: 96 rows = 48 feature slots per half
+
 struct NetLayout {
     int width, depth, prec;
     int nmb, nkb, k0;           // M-blocks, hidden K-blocks, layer-0 K-blocks
-    int64_t tiles;              // A tiles in total
+    int64_t tiles;              // forward A tiles in total
     int64_t bias_off;           // byte offset of float bias[width*depth + 4]
     int64_t scale_off;          // byte offset of float scales[2*(depth+1)] (fp8)
+    int64_t grad_tiles;         // transposed A tiles (0 for fp8)
+    int64_t grad_off;           // byte offset of the transposed tiles
+    int64_t head_rows_off;      // byte offset of float head_rows[2][width]
     int64_t bytes;              // total blob size
 
     __host__ __device__ int64_t layer_tile(int l) const {
         return l == 0 ? 0 : (int64_t)k0 * nmb + (int64_t)(l - 1) * nkb * nmb;
     }
     __host__ __device__ int64_t head_tile() const { return layer_tile(depth); }
+    // Transposed tiles: layer 0 (kGradRowBlocks0 x nkb), then layers 1..depth-1 (nmb x nkb each).
+    __host__ __device__ int64_t grad_layer_tile(int l) const {
+        return l == 0 ? 0 : (int64_t)kGradRowBlocks0 * nkb + (int64_t)(l - 1) * nkb * nmb;
+    }
 };
 
 __host__ __device__ inline NetLayout make_layout(int width, int depth, int prec) {
@@ -60,7 +71,10 @@ __host__ __device__ inline NetLayout make_layout(int width, int depth, int prec)
     L.bias_off = L.tiles * tile_bytes(prec);
     L.scale_off = L.bias_off + ((int64_t)width * depth + 4) * 4;
     int64_t sbytes = (int64_t)2 * (depth + 1) * 4;
-    L.bytes = L.scale_off + ((sbytes + 15) / 16) * 16;
+    L.grad_off = L.scale_off + ((sbytes + 15) / 16) * 16;
+    L.grad_tiles = prec == kFP8 ? 0 : (int64_t)kGradRowBlocks0 * L.nkb + (int64_t)(depth - 1) * L.nkb * L.nmb;
+    L.head_rows_off = L.grad_off + L.grad_tiles * tile_bytes(prec);
+    L.bytes = L.head_rows_off + (prec == kFP8 ? 0 : (int64_t)2 * width * 4);
     return L;
 }
 
@@ -81,6 +95,10 @@ __host__ __device__ inline int feature_column(int h, int f) {
 __host__ __device__ inline int layer0_feature(int prec, int kb, int s) {
     return kb * slots_per_lane(prec) + s;   // fp32: one slot per K-step
 }
+
+// Layer-0 feature slot (of the owning lane half) of row m of the transposed layer-0 product.
+__host__ __device__ inline int grad_row_half(int m) { return (m % 8) / 4; }
+__host__ __device__ inline int grad_row_feature(int m) { return (m / 32) * 16 + ((m % 32) / 8) * 4 + (m % 4); }
 
 // Previous-layer unit fed by (K-block kb, lane half h, operand slot s) of a hidden or head layer.
 __host__ __device__ inline int prev_unit(int prec, int kb, int h, int s) {

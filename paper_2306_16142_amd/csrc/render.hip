@@ -1,0 +1,533 @@
+// Wavefront path tracer of Fig. 1 with the network (or the brute-force triangle search)
+// answering every nearest-hit query: the "modified path tracer" of Sec. I / Sec. IV.
+//
+// Paths live in structure-of-arrays state indexed by path id; each bounce works on a
+// queue of live path ids: prepare the network inputs (cube entry, angles) -> one
+// kernel gives logit, distance and d(distance)/d(origin) for the whole queue (the
+// normal of Eq. 3) -> shade: next-event ray towards the light, cosine scatter, Russian
+// roulette, compaction of survivors and shadow rays with a wave ballot and one atomic
+// per wave -> shadow query -> resolve.  Queue lengths stay on the device: every kernel
+// is launched for the chunk's capacity and reads its count, so a whole render is a
+// fixed sequence of launches with no host synchronisation.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+#include "mlp_layout.hpp"
+
+namespace ddf {
+
+struct GradArgs {
+    const uint8_t *blob;
+    int depth;
+    const float *rays;
+    int64_t n;
+    const int *count_dev;
+    const float *g_logit_in;
+    const float *g_dist_in;
+    const float *t_label;
+    const float *loss_scalars;
+    float *logit_out;
+    float *dist_out;
+    float *g_rays;
+    float *ws_gamma;
+    float *ws_h;
+    float *ws_delta;
+    float *loss_partial;
+};
+ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, hipStream_t s);
+ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, const int *count_dev, float *logit,
+                            float *dist, unsigned int *absmax, hipStream_t s);
+ddf_status label_queue(const float *orig, const float *dir, int64_t stride, const int *idx, const int *count_dev,
+                       const float *tris, int64_t m, float t_min, float t_max, float *t_out, int32_t *tri_out,
+                       hipStream_t s);
+
+namespace {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kBelowTwoPi = 6.28318500518798828125f;
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+// ------------------------------------------------------------------------------ RNG
+__device__ inline uint64_t sm_hash(uint64_t x) {
+    uint64_t z = x + kGolden;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ inline uint64_t path_key(uint64_t seed, uint64_t pixel, uint64_t sample) {
+    return sm_hash(sm_hash(sm_hash(seed) ^ pixel) ^ sample);
+}
+__device__ inline float uniform01(uint64_t key, uint64_t bounce, uint64_t dim) {
+    const uint64_t k = sm_hash(sm_hash(key ^ bounce) ^ dim);
+    return (float)(k >> 40) * 5.9604644775390625e-8f;   // 2^-24
+}
+
+struct Vec3 {
+    float x, y, z;
+};
+__device__ inline Vec3 v3(float x, float y, float z) { return {x, y, z}; }
+__device__ inline Vec3 operator+(Vec3 a, Vec3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline Vec3 operator-(Vec3 a, Vec3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline Vec3 operator*(float s, Vec3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ inline float dot(Vec3 a, Vec3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline Vec3 cross(Vec3 a, Vec3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ inline Vec3 normalize(Vec3 a) { return (1.0f / sqrtf(dot(a, a))) * a; }
+__device__ inline Vec3 load3(const float *p, int64_t stride, int64_t i) { return {p[i], p[stride + i], p[2 * stride + i]}; }
+__device__ inline void store3(float *p, int64_t stride, int64_t i, Vec3 v) {
+    p[i] = v.x;
+    p[stride + i] = v.y;
+    p[2 * stride + i] = v.z;
+}
+
+// Slab test against [-1,1]^3: entry offset max(t_in, 0), or NaN when the ray misses the cube.
+__device__ inline float cube_entry(Vec3 o, Vec3 d) {
+    float lo = -INFINITY, hi = INFINITY;
+    const float oc[3] = {o.x, o.y, o.z}, dc[3] = {d.x, d.y, d.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (dc[k] == 0.f) {
+            if (oc[k] < -1.f || oc[k] > 1.f) return NAN;
+        } else {
+            const float inv = 1.0f / dc[k];
+            const float t0 = (-1.f - oc[k]) * inv, t1 = (1.f - oc[k]) * inv;
+            lo = fmaxf(lo, fminf(t0, t1));
+            hi = fminf(hi, fmaxf(t0, t1));
+        }
+    }
+    if (!(lo <= hi) || !(hi > 0.f)) return NAN;
+    return fmaxf(lo, 0.f);
+}
+
+// Network input of a ray: entry point and (polar, azimuth) of the direction.
+__device__ inline void write_query(float *rays5, int64_t stride, int64_t q, Vec3 o, Vec3 d, float t0) {
+    const float t = isnan(t0) ? 0.f : t0;
+    const Vec3 p = o + t * d;
+    const float theta = atan2f(sqrtf(d.x * d.x + d.y * d.y), d.z);
+    float phi = atan2f(d.y, d.x);
+    if (phi < 0.f) phi += kTwoPi;
+    if (phi >= kTwoPi) phi = kBelowTwoPi;
+    rays5[q] = p.x;
+    rays5[stride + q] = p.y;
+    rays5[2 * stride + q] = p.z;
+    rays5[3 * stride + q] = theta;
+    rays5[4 * stride + q] = phi;
+}
+
+// Wave-aggregated append: returns this lane's slot (or -1 when it does not append).
+__device__ inline int append(int *counter, bool want) {
+    const uint64_t mask = __ballot(want);
+    if (mask == 0) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int)__popcll(mask));
+    base = __shfl(base, leader);
+    const int rank = (int)__popcll(mask & ((1ull << lane) - 1ull));
+    return want ? base + rank : -1;
+}
+
+struct PathState {
+    float *o, *d, *thr, *L;   // [3][C]
+    int *pix, *smp;           // [C]
+};
+
+struct RenderWs {
+    PathState ps;
+    int *qa, *qb, *counts;
+    float *rays5, *t0, *logit, *dist, *grad, *ones;
+    float *tq;
+    int *triq;
+    int *sq;
+    float *srays, *st0, *stmax, *scontrib, *slogit, *sdist, *st;
+    int *stri;
+    size_t bytes;
+};
+
+inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+RenderWs render_ws(int64_t C, int bounces, void *base) {
+    RenderWs w{};
+    uint8_t *p = reinterpret_cast<uint8_t *>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *q = p ? p + off : nullptr;
+        off += a256(bytes);
+        return q;
+    };
+    const size_t f = (size_t)C * 4;
+    w.ps.o = (float *)take(3 * f);
+    w.ps.d = (float *)take(3 * f);
+    w.ps.thr = (float *)take(3 * f);
+    w.ps.L = (float *)take(3 * f);
+    w.ps.pix = (int *)take(f);
+    w.ps.smp = (int *)take(f);
+    w.qa = (int *)take(f);
+    w.qb = (int *)take(f);
+    w.counts = (int *)take((size_t)(2 * bounces + 4) * 4);
+    w.rays5 = (float *)take(5 * f);
+    w.t0 = (float *)take(f);
+    w.logit = (float *)take(f);
+    w.dist = (float *)take(f);
+    w.grad = (float *)take(5 * f);
+    w.ones = (float *)take(f);
+    w.tq = (float *)take(f);
+    w.triq = (int *)take(f);
+    w.sq = (int *)take(f);
+    w.srays = (float *)take(6 * f);
+    w.st0 = (float *)take(f);
+    w.stmax = (float *)take(f);
+    w.scontrib = (float *)take(3 * f);
+    w.slogit = (float *)take(f);
+    w.sdist = (float *)take(f);
+    w.st = (float *)take(f);
+    w.stri = (int *)take(f);
+    w.bytes = off;
+    return w;
+}
+
+struct Cam {
+    Vec3 eye, f, r, u;
+    float th, aspect;
+};
+
+Cam make_cam(const ddf_render_params &p) {
+    auto norm = [](float a[3]) {
+        const float l = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        a[0] /= l;
+        a[1] /= l;
+        a[2] /= l;
+    };
+    float f[3] = {p.target[0] - p.eye[0], p.target[1] - p.eye[1], p.target[2] - p.eye[2]};
+    norm(f);
+    float r[3] = {f[1] * p.up[2] - f[2] * p.up[1], f[2] * p.up[0] - f[0] * p.up[2], f[0] * p.up[1] - f[1] * p.up[0]};
+    norm(r);
+    float u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+    Cam c;
+    c.eye = {p.eye[0], p.eye[1], p.eye[2]};
+    c.f = {f[0], f[1], f[2]};
+    c.r = {r[0], r[1], r[2]};
+    c.u = {u[0], u[1], u[2]};
+    c.th = (float)std::tan(p.vfov_deg * 3.14159265358979323846 / 360.0);
+    c.aspect = (float)p.width / (float)p.height;
+    return c;
+}
+
+// ------------------------------------------------------------------------------ kernels
+__global__ void raygen_kernel(ddf_render_params p, Cam cam, int64_t C, int sample_base, int S, PathState ps, int *queue,
+                              int *counts, int ncounts, float *ones, float *depth, float *normal) {
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < ncounts; i += blockDim.x) counts[i] = i == 0 ? (int)C : 0;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < C; id += (int64_t)gridDim.x * blockDim.x) {
+        const int pixel = (int)(id / S);
+        const int sample = sample_base + (int)(id % S);
+        const uint64_t key = path_key(p.seed, (uint64_t)pixel, (uint64_t)sample);
+        float jx = 0.5f, jy = 0.5f;
+        if (p.spp > 1) {
+            jx = uniform01(key, 0, 0);
+            jy = uniform01(key, 0, 1);
+        }
+        const float px = (float)(pixel % p.width), py = (float)(pixel / p.width);
+        const float sx = (2.0f * (px + jx) / (float)p.width - 1.0f) * cam.th * cam.aspect;
+        const float sy = (1.0f - 2.0f * (py + jy) / (float)p.height) * cam.th;
+        const Vec3 d = normalize(cam.f + sx * cam.r + sy * cam.u);
+        store3(ps.o, C, id, cam.eye);
+        store3(ps.d, C, id, d);
+        store3(ps.thr, C, id, v3(1.f, 1.f, 1.f));
+        store3(ps.L, C, id, v3(0.f, 0.f, 0.f));
+        ps.pix[id] = pixel;
+        ps.smp[id] = sample;
+        queue[id] = (int)id;
+        ones[id] = 1.0f;
+        if (sample == 0) {
+            if (depth) depth[pixel] = INFINITY;
+            if (normal) {
+                const int64_t hw = (int64_t)p.width * p.height;
+                normal[pixel] = 0.f;
+                normal[hw + pixel] = 0.f;
+                normal[2 * hw + pixel] = 0.f;
+            }
+        }
+    }
+}
+
+__global__ void prep_kernel(int64_t C, const int *__restrict__ queue, const int *__restrict__ count, PathState ps,
+                            float *__restrict__ rays5, float *__restrict__ t0) {
+    const int n = *count;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const int id = queue[q];
+        const Vec3 o = load3(ps.o, C, id), d = load3(ps.d, C, id);
+        const float te = cube_entry(o, d);
+        t0[q] = te;
+        write_query(rays5, C, q, o, d, te);
+    }
+}
+
+__global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int backend, const int *__restrict__ queue,
+                             int *counts, int *__restrict__ next_queue, PathState ps, const float *__restrict__ t0,
+                             const float *__restrict__ logit, const float *__restrict__ dist,
+                             const float *__restrict__ grad, const float *__restrict__ tq, const int *__restrict__ triq,
+                             const float *__restrict__ tris, int64_t m, int *__restrict__ sq, float *__restrict__ srays,
+                             float *__restrict__ st0, float *__restrict__ stmax, float *__restrict__ scontrib,
+                             float *__restrict__ depth, float *__restrict__ normal) {
+    const int n = counts[2 * bounce];
+    const Vec3 light = v3(p.light_pos[0], p.light_pos[1], p.light_pos[2]);
+    const int64_t hw = (int64_t)p.width * p.height;
+    // every lane of a wave reaches both appends (wave-aggregated atomics)
+    const int64_t span = ((int64_t)n + 63) / 64 * 64;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < span; q += (int64_t)gridDim.x * blockDim.x) {
+        bool hit = false, shadow = false, alive = false;
+        int id = 0;
+        Vec3 xs{}, l{}, nd{}, contrib{}, thr{};
+        float r = 0.f;
+        if (q < n) {
+            id = queue[q];
+            const Vec3 o = load3(ps.o, C, id), d = load3(ps.d, C, id);
+            float t = 0.f;
+            Vec3 nrm{};
+            if (backend == DDF_BACKEND_NET) {
+                const float te = t0[q];
+                hit = !isnan(te) && logit[q] > 0.f;
+                t = te + dist[q];
+                const Vec3 g = load3(grad, C, q);
+                const float gn = sqrtf(dot(g, g)), gd = dot(g, d);
+                const float kappa = gd > 0.f ? -1.f : 1.f;   // Eq. 3: n . d < 0
+                nrm = gn > 0.f ? (kappa / gn) * g : (-1.0f / sqrtf(dot(d, d))) * d;
+            } else {
+                const int tri = triq[q];
+                hit = tri >= 0;
+                t = tq[q];
+                if (hit) {
+                    const Vec3 a = v3(tris[tri], tris[m + tri], tris[2 * m + tri]);
+                    const Vec3 b = v3(tris[3 * m + tri], tris[4 * m + tri], tris[5 * m + tri]);
+                    const Vec3 c = v3(tris[6 * m + tri], tris[7 * m + tri], tris[8 * m + tri]);
+                    nrm = normalize(cross(b - a, c - a));
+                    if (dot(nrm, d) > 0.f) nrm = -1.f * nrm;
+                }
+            }
+            const int pixel = ps.pix[id];
+            if (bounce == 0 && ps.smp[id] == 0) {
+                if (depth) depth[pixel] = hit ? t : INFINITY;
+                if (normal) {
+                    normal[pixel] = hit ? nrm.x : 0.f;
+                    normal[hw + pixel] = hit ? nrm.y : 0.f;
+                    normal[2 * hw + pixel] = hit ? nrm.z : 0.f;
+                }
+            }
+            if (hit) {
+                const Vec3 x = o + t * d;
+                xs = x + p.eps * nrm;
+                const Vec3 lv = light - xs;
+                const float r2 = dot(lv, lv);
+                r = sqrtf(r2);
+                l = (1.0f / r) * lv;
+                const float cosl = dot(nrm, l);
+                thr = load3(ps.thr, C, id);
+                if (cosl > 0.f) {
+                    shadow = true;
+                    const float k = cosl / (kPi * r2);
+                    contrib = v3(thr.x * p.albedo[0] * p.light_intensity[0] * k, thr.y * p.albedo[1] * p.light_intensity[1] * k,
+                                 thr.z * p.albedo[2] * p.light_intensity[2] * k);
+                }
+                if (bounce < p.bounces - 1) {
+                    const uint64_t key = path_key(p.seed, (uint64_t)pixel, (uint64_t)ps.smp[id]);
+                    const float u1 = uniform01(key, bounce, 2), u2 = uniform01(key, bounce, 3);
+                    const float rr = sqrtf(u1), ang = kTwoPi * u2;
+                    const float lx = rr * cosf(ang), ly = rr * sinf(ang), lz = sqrtf(fmaxf(0.f, 1.f - u1));
+                    // orthonormal basis around the normal (Duff et al. 2017)
+                    const float sign = nrm.z >= 0.f ? 1.f : -1.f;
+                    const float aa = -1.0f / (sign + nrm.z);
+                    const float bb = nrm.x * nrm.y * aa;
+                    const Vec3 b1 = v3(1.f + sign * nrm.x * nrm.x * aa, sign * bb, -sign * nrm.x);
+                    const Vec3 b2 = v3(bb, sign + nrm.y * nrm.y * aa, -nrm.y);
+                    nd = lx * b1 + ly * b2 + lz * nrm;
+                    Vec3 tn = v3(thr.x * p.albedo[0], thr.y * p.albedo[1], thr.z * p.albedo[2]);
+                    alive = true;
+                    if (bounce >= p.rr_start) {
+                        const float qs = fminf(0.95f, fmaxf(tn.x, fmaxf(tn.y, tn.z)));
+                        if (uniform01(key, bounce, 4) >= qs) alive = false;
+                        else tn = (1.0f / qs) * tn;
+                    }
+                    if (alive) {
+                        store3(ps.o, C, id, xs);
+                        store3(ps.d, C, id, nd);
+                        store3(ps.thr, C, id, tn);
+                    }
+                }
+            }
+        }
+        const int sslot = append(&counts[2 * bounce + 1], shadow);
+        if (shadow) {
+            sq[sslot] = id;
+            stmax[sslot] = r;
+            store3(scontrib, C, sslot, contrib);
+            if (backend == DDF_BACKEND_NET) {
+                const float te = cube_entry(xs, l);
+                st0[sslot] = te;
+                write_query(srays, C, sslot, xs, l, te);
+            } else {
+                store3(srays, C, sslot, xs);
+                store3(srays + 3 * C, C, sslot, l);
+            }
+        }
+        const int nslot = append(&counts[2 * (bounce + 1)], alive);
+        if (alive) next_queue[nslot] = id;
+    }
+}
+
+__global__ void resolve_kernel(int64_t C, int bounce, int backend, const int *__restrict__ counts,
+                               const int *__restrict__ sq, const float *__restrict__ st0,
+                               const float *__restrict__ stmax, const float *__restrict__ scontrib,
+                               const float *__restrict__ slogit, const float *__restrict__ sdist,
+                               const float *__restrict__ st, float *__restrict__ L) {
+    const int n = counts[2 * bounce + 1];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        bool occluded;
+        if (backend == DDF_BACKEND_NET) {
+            const float te = st0[q];
+            occluded = !isnan(te) && slogit[q] > 0.f && te + sdist[q] < stmax[q];
+        } else {
+            occluded = st[q] < stmax[q];
+        }
+        if (occluded) continue;
+        const int id = sq[q];
+        L[id] += scontrib[q];
+        L[C + id] += scontrib[C + q];
+        L[2 * C + id] += scontrib[2 * C + q];
+    }
+}
+
+__global__ void accumulate_kernel(int64_t hw, int S, int64_t C, const float *__restrict__ L, float *__restrict__ img) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hw; p += (int64_t)gridDim.x * blockDim.x) {
+        float a = 0.f, b = 0.f, c = 0.f;
+        for (int s = 0; s < S; ++s) {
+            const int64_t id = p * S + s;
+            a += L[id];
+            b += L[C + id];
+            c += L[2 * C + id];
+        }
+        img[p] += a;
+        img[hw + p] += b;
+        img[2 * hw + p] += c;
+    }
+}
+
+__global__ void scale_kernel(float *img, int64_t n, float s) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) img[i] *= s;
+}
+
+__global__ void fill_kernel(float *img, int64_t n, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) img[i] = v;
+}
+
+__global__ void stats_kernel(const int *counts, int bounces, uint32_t *stats) {
+    const int b = threadIdx.x;
+    if (b < bounces) stats[b] += (uint32_t)counts[2 * b];
+}
+
+int chunk_spp(const ddf_render_params &p) {
+    if (p.spp_chunk > 0) return std::min(p.spp_chunk, p.spp);
+    const int64_t hw = (int64_t)p.width * p.height;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(p.spp, ((int64_t)1 << 24) / hw));
+}
+
+unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+}  // namespace
+}  // namespace ddf
+
+using namespace ddf;
+
+extern "C" ddf_status ddf_render_workspace_size(const ddf_render_params *p, size_t *bytes) {
+    DDF_REQUIRE(p && bytes, DDF_ERR_INVALID_ARG, "ddf_render_workspace_size: NULL argument");
+    DDF_REQUIRE(p->width > 0 && p->height > 0 && p->spp > 0 && p->bounces > 0 && p->bounces <= 64, DDF_ERR_INVALID_ARG,
+                "ddf_render_workspace_size: bad image size, spp or bounces");
+    const int64_t C = (int64_t)p->width * p->height * chunk_spp(*p);
+    DDF_REQUIRE(C < ((int64_t)1 << 31), DDF_ERR_UNSUPPORTED, "ddf_render_workspace_size: sample chunk too large");
+    *bytes = render_ws(C, p->bounces, nullptr).bytes;
+    return DDF_OK;
+}
+
+extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_render_params *p, float *radiance,
+                                           float *depth, float *normal, uint32_t *stats, void *ws, size_t ws_bytes,
+                                           ddf_stream stream) {
+    DDF_REQUIRE(scene && p && radiance, DDF_ERR_INVALID_ARG, "ddf_render_wavefront: NULL argument");
+    size_t need = 0;
+    if (ddf_status st = ddf_render_workspace_size(p, &need)) return st;
+    DDF_REQUIRE(ws && ws_bytes >= need, DDF_ERR_WORKSPACE, "ddf_render_wavefront: workspace of %zu bytes needed", need);
+    DDF_REQUIRE(scene->backend == DDF_BACKEND_MESH || scene->backend == DDF_BACKEND_NET, DDF_ERR_INVALID_ARG,
+                "ddf_render_wavefront: unknown backend %d", scene->backend);
+    if (scene->backend == DDF_BACKEND_MESH) {
+        DDF_REQUIRE(scene->m >= 0 && (scene->m == 0 || scene->tris), DDF_ERR_INVALID_ARG, "ddf_render_wavefront: bad mesh");
+    } else {
+        const ddf_net *net = scene->net;
+        DDF_REQUIRE(net && net->packed, DDF_ERR_INVALID_ARG, "ddf_render_wavefront: NULL network");
+        DDF_REQUIRE(net->precision == DDF_PREC_FP32 || net->precision == DDF_PREC_BF16, DDF_ERR_UNSUPPORTED,
+                    "ddf_render_wavefront: the network backend needs a float32 or bfloat16 network (normals)");
+        DDF_REQUIRE((net->width == 128 || net->width == 256) && net->depth >= 1 && net->depth <= 8, DDF_ERR_UNSUPPORTED,
+                    "ddf_render_wavefront: unsupported network shape");
+    }
+    DDF_REQUIRE(p->rr_start >= 0 && p->eps >= 0.f && p->vfov_deg > 0.f && p->vfov_deg < 180.f, DDF_ERR_INVALID_ARG,
+                "ddf_render_wavefront: bad rr_start, eps or field of view");
+    hipStream_t s = as_stream(stream);
+    const int S = chunk_spp(*p);
+    const int64_t hw = (int64_t)p->width * p->height;
+    const int64_t C = hw * S;
+    RenderWs w = render_ws(C, p->bounces, ws);
+    const Cam cam = make_cam(*p);
+    const int ncounts = 2 * p->bounces + 4;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(3 * hw)), dim3(256), 0, s, radiance, 3 * hw, 0.f);
+    if (stats) hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, (float *)stats, (int64_t)p->bounces, 0.f);
+    for (int base = 0; base < p->spp; base += S) {
+        const int Sc = std::min(S, p->spp - base);
+        const int64_t Cc = hw * Sc;
+        hipLaunchKernelGGL(raygen_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, *p, cam, Cc, base, Sc, w.ps, w.qa,
+                           w.counts, ncounts, w.ones, depth, normal);
+        // path-state arrays use the chunk's own stride Cc (== C except in a short last chunk)
+        PathState ps = w.ps;
+        int *q = w.qa, *qn = w.qb;
+        for (int b = 0; b < p->bounces; ++b) {
+            const int *cnt = w.counts + 2 * b;
+            if (scene->backend == DDF_BACKEND_NET) {
+                hipLaunchKernelGGL(prep_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, Cc, q, cnt, ps, w.rays5, w.t0);
+                GradArgs a{};
+                a.blob = (const uint8_t *)scene->net->packed;
+                a.depth = scene->net->depth;
+                a.rays = w.rays5;
+                a.n = Cc;
+                a.count_dev = cnt;
+                a.g_dist_in = w.ones;
+                a.logit_out = w.logit;
+                a.dist_out = w.dist;
+                a.g_rays = w.grad;
+                if (ddf_status st = grad_dispatch(scene->net, a, false, s)) return st;
+            } else {
+                if (ddf_status st = label_queue(ps.o, ps.d, Cc, q, cnt, scene->tris, scene->m, 0.f, INFINITY, w.tq, w.triq, s))
+                    return st;
+            }
+            hipLaunchKernelGGL(shade_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, *p, Cc, b, scene->backend, q, w.counts,
+                               qn, ps, w.t0, w.logit, w.dist, w.grad, w.tq, w.triq, scene->tris, scene->m, w.sq, w.srays,
+                               w.st0, w.stmax, w.scontrib, depth, normal);
+            if (ddf_status st = launch_status("ddf_render_wavefront (shade)")) return st;
+            const int *scnt = w.counts + 2 * b + 1;
+            if (scene->backend == DDF_BACKEND_NET) {
+                if (ddf_status st = forward_dispatch(scene->net, w.srays, Cc, scnt, w.slogit, w.sdist, nullptr, s)) return st;
+            } else {
+                if (ddf_status st = label_queue(w.srays, w.srays + 3 * Cc, Cc, nullptr, scnt, scene->tris, scene->m, 0.f,
+                                                INFINITY, w.st, w.stri, s))
+                    return st;
+            }
+            hipLaunchKernelGGL(resolve_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, Cc, b, scene->backend, w.counts, w.sq,
+                               w.st0, w.stmax, w.scontrib, w.slogit, w.sdist, w.st, ps.L);
+            std::swap(q, qn);
+        }
+        hipLaunchKernelGGL(accumulate_kernel, dim3(grid_for(hw)), dim3(256), 0, s, hw, Sc, Cc, ps.L, radiance);
+        if (stats) hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(64), 0, s, w.counts, p->bounces, stats);
+        if (ddf_status st = launch_status("ddf_render_wavefront")) return st;
+    }
+    hipLaunchKernelGGL(scale_kernel, dim3(grid_for(3 * hw)), dim3(256), 0, s, radiance, 3 * hw, 1.0f / (float)p->spp);
+    return launch_status("ddf_render_wavefront");
+}

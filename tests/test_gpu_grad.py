@@ -1,0 +1,169 @@
+"""GPU parity of the hand-written backward (input and parameter gradients), the loss seeds,
+Adam and a whole training step, against the float64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import mlp
+from paper_2306_16142_amd import api
+
+from gpu_common import banner, cuda, host, rays5_from
+
+pytestmark = pytest.mark.gpu
+
+
+def _rays(n, seed):
+    o, d = synthetic.uniform_cube_rays(n, seed)
+    return rays5_from(o, d)
+
+
+def _away_from_kinks(p, width, depth, rays, tol=1e-4):
+    """Rays whose every hidden pre-activation is at least `tol` from the ReLU kink (float64):
+    float32 and float64 then take the same branch, so gradients can be compared tightly."""
+    _, _, _, pres = mlp.forward(p, width, depth, rays, return_acts=True)
+    m = np.ones(rays.shape[1], dtype=bool)
+    for z in pres[:-1]:
+        m &= np.abs(z).min(axis=0) > tol
+    return np.ascontiguousarray(rays[:, m])
+
+
+def _rel(g, r):
+    scale = max(np.sqrt(np.mean(r ** 2)), 1e-30)
+    return np.abs(g - r) / np.maximum(np.abs(r), scale)
+
+
+@pytest.mark.parametrize("width,depth,n", [(128, 4, 4096 + 21), (256, 6, 1024 + 3), (128, 1, 64)])
+def test_input_gradient_fp32(width, depth, n):
+    banner("input gradient fp32 %dx%d n=%d" % (depth, width, n))
+    p = synthetic.random_params(width, depth, 31)
+    rays = _away_from_kinks(p, width, depth, _rays(n, 32))
+    n = rays.shape[1]
+    rng = np.random.default_rng(0)
+    gl, gd = rng.normal(size=n).astype(np.float32), rng.normal(size=n).astype(np.float32)
+    net = api.Network(cuda(p), width, depth, "fp32")
+    g_rays, _ = api.backward(net, cuda(rays), cuda(gl), cuda(gd))
+    ref, _ = mlp.backward(p, width, depth, rays, gl, gd)
+    err = _rel(host(g_rays), ref)
+    assert err.max() < 1e-4
+    assert np.median(err) < 1e-6
+
+
+def test_input_gradient_bf16_normals():
+    banner("input gradient bf16 128x4 (distance seed = normals)")
+    width, depth, n = 128, 4, 8192
+    p = synthetic.random_params(width, depth, 33)
+    rays = _rays(n, 34)
+    net = api.Network(cuda(p), width, depth, "bf16")
+    ones = np.ones(n, np.float32)
+    g_rays, _ = api.backward(net, cuda(rays), None, cuda(ones))
+    ref, _ = mlp.backward(p, width, depth, rays, np.zeros(n), ones)
+    g = host(g_rays)
+    emu = mlp.backward_input_bf16(p, width, depth, rays, np.zeros(n), ones)
+
+    def angle(x, y):
+        a = x[:3] / np.linalg.norm(x[:3], axis=0)
+        b = y[:3] / np.linalg.norm(y[:3], axis=0)
+        return np.degrees(np.arccos(np.clip(np.sum(a * b, axis=0), -1, 1)))
+
+    # the kernel must sit much closer to the bf16 emulation than the emulation sits to float64
+    own = angle(emu, ref)
+    gap = angle(g, emu)
+    assert np.median(gap) < 0.2 * np.median(own)
+    assert np.quantile(gap, 0.9) < 0.5 * np.quantile(own, 0.9)
+    assert np.mean(angle(g, ref)) < 1.2 * np.mean(own)
+
+
+@pytest.mark.parametrize("width,depth,n", [(128, 4, 8192 + 5), (256, 6, 4096)])
+def test_parameter_gradient_fp32(width, depth, n):
+    banner("parameter gradient fp32 %dx%d n=%d" % (depth, width, n))
+    p = synthetic.random_params(width, depth, 35)
+    rays = _away_from_kinks(p, width, depth, _rays(n, 36))
+    n = rays.shape[1]
+    rng = np.random.default_rng(1)
+    gl, gd = rng.normal(size=n).astype(np.float32) / n, rng.normal(size=n).astype(np.float32) / n
+    net = api.Network(cuda(p), width, depth, "fp32")
+    g_rays, g_params = api.backward(net, cuda(rays), cuda(gl), cuda(gd), want_params=True)
+    ref_r, ref_p = mlp.backward(p, width, depth, rays, gl, gd)
+    gp = host(g_params)
+    scale = np.sqrt(np.mean(ref_p ** 2))
+    assert np.max(np.abs(gp - ref_p)) < 1e-5 * np.abs(ref_p).max()
+    assert np.median(np.abs(gp - ref_p) / np.maximum(np.abs(ref_p), scale)) < 1e-5
+    assert np.quantile(_rel(host(g_rays), ref_r), 0.999) < 1e-4
+    # accumulate flag adds, and a second identical call is bitwise identical
+    _, g2 = api.backward(net, cuda(rays), cuda(gl), cuda(gd), want_params=True)
+    assert torch.equal(g_params, g2)
+    _, g3 = api.backward(net, cuda(rays), cuda(gl), cuda(gd), want_params=True, g_params=g2.clone(), accumulate=True)
+    torch.testing.assert_close(g3, 2 * g2, rtol=1e-6, atol=0)
+
+
+def test_loss_seeds_and_adam():
+    banner("loss seeds + adam")
+    rng = np.random.default_rng(2)
+    n = 10000 + 7
+    z = (rng.normal(size=n) * 3).astype(np.float32)
+    d = rng.normal(size=n).astype(np.float32)
+    t = np.where(rng.random(n) < 0.4, rng.uniform(0, 2, n), np.inf).astype(np.float32)
+    loss, gl, gd = api.loss_seeds(cuda(z), cuda(d), cuda(t))
+    rl, rgl, rgd = mlp.loss_and_seeds(z, d, t < np.inf, t)
+    assert abs(host(loss)[0] - rl) < 1e-5 * abs(rl)
+    np.testing.assert_allclose(host(gl), rgl, rtol=1e-5, atol=1e-10)
+    np.testing.assert_array_equal(host(gd), rgd.astype(np.float32))
+    P = 5000
+    p0 = rng.normal(size=P).astype(np.float32)
+    pg, mg, vg = cuda(p0), torch.zeros(P, device="cuda"), torch.zeros(P, device="cuda")
+    pr, mr, vr = p0.astype(np.float64), np.zeros(P), np.zeros(P)
+    for s in range(1, 4):
+        g = rng.normal(size=P).astype(np.float32)
+        api.adam_step(pg, cuda(g), mg, vg, s)
+        pr, mr, vr = mlp.adam_step(pr, g, mr, vr, s)
+    np.testing.assert_allclose(host(pg), pr, rtol=1e-6, atol=1e-7)
+
+
+def test_train_step_matches_oracle():
+    banner("train step 128x4 batch 4096")
+    width, depth, n = 128, 4, 4096
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    o, d, _ = synthetic.training_rays(v, f, n, 3)
+    from oracle import geometry
+    lab = geometry.nearest_hit(o, d, tris)
+    t = lab["t"].astype(np.float32)
+    rays = rays5_from(o, d)
+    p = synthetic.xavier_params(width, depth, 0)
+    pg = cuda(p)
+    tr = api.Trainer(pg, width, depth, n, lr=1e-3)
+    loss = host(tr.step(cuda(rays), cuda(t)))[0]
+    # oracle step
+    lg, ds = mlp.forward(p, width, depth, rays)
+    rl, sl, sd = mlp.loss_and_seeds(lg, ds, t < np.inf, t)
+    _, gref = mlp.backward(p, width, depth, rays, sl, sd)
+    pnew, _, _ = mlp.adam_step(p, gref, np.zeros_like(gref), np.zeros_like(gref), 1)
+    assert abs(loss - rl) < 1e-5 * abs(rl)
+    g = host(tr.g)
+    scale = np.sqrt(np.mean(gref ** 2))
+    assert np.median(np.abs(g - gref) / np.maximum(np.abs(gref), scale)) < 1e-4
+    # the first Adam step moves every parameter by lr * sign(g) (up to eps): compare moves
+    moved = host(pg) - p
+    ref_moved = pnew - p
+    agree = np.abs(moved - ref_moved) < 1e-6
+    assert agree.mean() > 0.999
+    # the repacked network reflects the update
+    lg2, _ = tr.net.forward(cuda(rays))
+    lref, _ = mlp.forward(host(pg).astype(np.float64), width, depth, rays)
+    assert np.max(_rel(host(lg2), lref)) < 1e-4
+
+
+def test_autograd_function_matches_backward():
+    banner("autograd.Function")
+    width, depth, n = 128, 2, 512
+    p = synthetic.random_params(width, depth, 37)
+    rays = cuda(_rays(n, 38)).requires_grad_(True)
+    pg = cuda(p).requires_grad_(True)
+    net = api.Network(pg.detach(), width, depth, "fp32")
+    logit, dist = api.DDFQuery.apply(rays, pg, net)
+    (logit.sum() * 0.5 + (dist ** 2).sum()).backward()
+    lg, ds = mlp.forward(p, width, depth, host(rays.detach()))
+    ref_r, ref_p = mlp.backward(p, width, depth, host(rays.detach()), np.full(n, 0.5), 2 * ds)
+    assert np.quantile(_rel(host(rays.grad), ref_r), 0.99) < 1e-4
+    assert np.median(_rel(host(pg.grad), ref_p)) < 1e-4

@@ -229,6 +229,24 @@ def test_emulated_precisions_exact_on_representable_inputs():
     np.testing.assert_array_equal(mlp.forward_fp8(p, width, depth, rays, scales), ref)
 
 
+def test_bf16_input_gradient_exact_on_representable_inputs():
+    """With every operand representable in bfloat16 the emulated input gradient equals float64."""
+    width, depth = 8, 3
+    rng = np.random.default_rng(8)
+    layers = mlp.unpack(np.zeros(synthetic.param_count(width, depth)), width, depth)
+    layers = [(W.copy(), b.copy()) for W, b in layers]
+    layers[0][0][:, :5] = rng.integers(-2, 3, size=(width, 5)) * 0.25
+    for l in range(1, depth + 1):
+        layers[l][0][:] = rng.integers(-2, 3, size=layers[l][0].shape) * 0.5
+    for l in range(depth):
+        layers[l][1][:] = 0.125
+    rays = (rng.integers(-4, 5, size=(5, 40)) * 0.25).astype(np.float64)
+    p = mlp.pack(layers)
+    gl, gd = rng.integers(-2, 3, size=40) * 0.5, rng.integers(-2, 3, size=40) * 0.25
+    ref, _ = mlp.backward(p, width, depth, rays, gl, gd)
+    np.testing.assert_array_equal(mlp.backward_input_bf16(p, width, depth, rays, gl, gd), ref)
+
+
 def test_adam_matches_torch():
     rng = np.random.default_rng(6)
     p0 = rng.normal(size=50)
