@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="primary line only (no secondary workloads)")
     ap.add_argument("--n-log2", type=int, default=24)
+    ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--render-spp", type=int, default=64)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -73,6 +77,92 @@ def error_stats(logit, dist, ref_logit, ref_dist):
             "dist_abs_err_p99": float(np.quantile(e, 0.99)), "dist_abs_err_max": float(e.max())}
 
 
+def bench_label_train_render(args, torch, api, dev):
+    """Labeller and training on the 20,480-triangle workload; render with the trained network."""
+    import synthetic
+    out = {}
+    v, f = synthetic.training_mesh(1)
+    tris = torch.from_numpy(synthetic.tri_soup(v, f)).to(dev)
+    nl = 1 << 20
+    lo, ld, _ = synthetic.training_rays(v, f, nl, 1)
+    lo_g, ld_g = torch.from_numpy(lo).to(dev), torch.from_numpy(ld).to(dev)
+    t, tri, cr = api.label_rays(lo_g, ld_g, tris)
+    torch.cuda.synchronize()
+    timer = event_timer(torch)
+    for _ in range(3):
+        timer.start()
+        api.label_rays(lo_g, ld_g, tris)
+        timer.stop()
+    torch.cuda.synchronize()
+    lms = timer.mean_ms()
+    out["label"] = {"workload": "2^20 training rays x 20,480-triangle mesh", "kernel_ms": lms,
+                    "rays_per_s": nl / (lms * 1e-3), "tests_per_s": nl * f.shape[0] / (lms * 1e-3),
+                    "hit_fraction": float((tri >= 0).float().mean())}
+    # training set: drop rays whose origin is inside the mesh (odd crossing count)
+    keep = (cr % 2) == 0
+    rays_all = api.assemble_rays(lo_g, ld_g)[:, keep].contiguous()
+    t_all = t[keep].contiguous()
+    nvalid = rays_all.shape[1]
+    width, depth, batch = 256, 6, 65536
+    params = torch.from_numpy(synthetic.xavier_params(width, depth, 1)).to(dev)
+    trainer = api.Trainer(params, width, depth, batch, lr=1e-3)
+    nb = nvalid // batch
+    batches = [(rays_all[:, i * batch:(i + 1) * batch].contiguous(), t_all[i * batch:(i + 1) * batch].contiguous())
+               for i in range(nb)]
+    losses = []
+    for i in range(3):
+        losses.append(float(trainer.step(*batches[i % nb])))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.train_steps):
+        trainer.step(*batches[i % nb])
+    torch.cuda.synchronize()
+    tms = (time.perf_counter() - t0) * 1e3 / args.train_steps
+    losses.append(float(trainer.loss))
+    # keep training (untimed) so the rendered network has learned something
+    for i in range(200):
+        trainer.step(*batches[i % nb])
+    losses.append(float(trainer.loss))
+    torch.cuda.synchronize()
+    out["train"] = {"workload": "6x256 fp32, batch 65,536, Adam 1e-3, labels from the labeller (%d valid rays)" % nvalid,
+                    "ms_per_step": tms, "steps_per_s": 1e3 / tms,
+                    "loss_first_step": losses[0], "loss_after_%d_steps" % (3 + args.train_steps): losses[-2],
+                    "loss_after_%d_steps" % (203 + args.train_steps): losses[-1]}
+    # render: 1920 x 1080, spp samples, 4 bounces, Russian roulette after bounce 2, bf16 queries
+    cfg = synthetic.full_render(args.render_spp)
+    net16 = api.Network(params, width, depth, "bf16")
+    r = api.Renderer(cfg, net=net16)
+    r.render()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 2
+    for _ in range(reps):
+        r.render()
+    torch.cuda.synchronize()
+    rs = (time.perf_counter() - t0) / reps
+    paths = cfg.width * cfg.height * cfg.spp
+    stats = [int(x) for x in r.stats.cpu().numpy()]
+    # shading normals against the mesh normal at the brute-force hit point (primary hits)
+    cfg1 = synthetic.full_render(1)
+    cfg1.bounces = 1
+    rm = api.Renderer(cfg1, tris=tris)
+    rm.render()
+    rn = api.Renderer(cfg1, net=net16)
+    rn.render()
+    torch.cuda.synchronize()
+    both = torch.isfinite(rm.depth) & torch.isfinite(rn.depth)
+    cosang = (rm.normal * rn.normal).sum(0)[both].clamp(-1, 1)
+    ang = torch.rad2deg(torch.acos(cosang)).cpu().numpy()
+    hit_agree = float((torch.isfinite(rm.depth) == torch.isfinite(rn.depth)).float().mean()) * 100
+    out["render"] = {"workload": "1920x1080, %d spp, 4 bounces, RR after bounce 2, bf16 6x256 network "
+                                 "(trained %d steps)" % (cfg.spp, 203 + args.train_steps),
+                     "seconds_per_frame": rs, "path_samples_per_s": paths / rs, "paths_per_bounce": stats,
+                     "normal_angle_err_deg_mean": float(ang.mean()) if ang.size else None,
+                     "normal_angle_err_deg_median": float(np.median(ang)) if ang.size else None,
+                     "primary_hit_agreement_vs_mesh_pct": hit_agree}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -85,6 +175,12 @@ def main():
     from paper_2306_16142_amd import api
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = 1 << args.n_log2
     o, d = synthetic.uniform_cube_rays(n, 3)
     p = synthetic.xavier_params(W, D, 0)
@@ -166,23 +262,8 @@ def main():
     extra["bf16"] = {k: v for k, v in bf.items() if k not in ("queries_per_s",)}
 
     if not args.quick:
-        # labeller on the training workload
-        v, f = synthetic.training_mesh(1)
-        tris = torch.from_numpy(synthetic.tri_soup(v, f)).to(dev)
-        lo, ld, _ = synthetic.training_rays(v, f, 1 << 20, 1)
-        lo_g, ld_g = torch.from_numpy(lo).to(dev), torch.from_numpy(ld).to(dev)
-        api.label_rays(lo_g, ld_g, tris)
-        torch.cuda.synchronize()
-        timer = event_timer(torch)
-        for _ in range(3):
-            timer.start()
-            api.label_rays(lo_g, ld_g, tris)
-            timer.stop()
-        torch.cuda.synchronize()
-        lms = timer.mean_ms()
-        extra["label"] = {"rays": 1 << 20, "triangles": int(f.shape[0]), "kernel_ms": lms,
-                          "rays_per_s": (1 << 20) / (lms * 1e-3),
-                          "tests_per_s": (1 << 20) * f.shape[0] / (lms * 1e-3)}
+        extra.update(bench_label_train_render(args, torch, api, dev))
+    if not args.quick:
         # the float64 oracle on the host cores, bounded sample of the same query workload
         from oracle import mlp
         from threadpoolctl import threadpool_info

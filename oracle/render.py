@@ -166,6 +166,9 @@ class NetworkScene:
         hit, t, rays, robust = self._query(o, d)
         g, _ = mlp.backward(self.params, self.width, self.depth, rays, np.zeros(rays.shape[1]),
                             np.ones(rays.shape[1]))
+        # a nearly vanishing gradient leaves the normal (and every later bounce) undecided
+        gn = np.linalg.norm(g[0:3], axis=0)
+        robust = robust & ~(hit & (gn < self.margin * 10.0))
         return hit, t, g[0:3], robust
 
     def occluded(self, o, d, t_max):

@@ -109,6 +109,9 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
                 }
             }
             if constexpr (P == kBF16) {
+                // layer-0 bias rides in two unused feature slots of lane half 1
+                feat[kBiasSlot0] = h ? 1.f : feat[kBiasSlot0];
+                feat[kBiasSlot1] = h ? 1.f : 0.f;
 #pragma unroll
                 for (int kb = 0; kb < K0; ++kb)
 #pragma unroll
@@ -140,13 +143,25 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
                     }
                 }
             }
+            if constexpr (P == kBF16) {
+                if (l > 0) {   // bias K-block of a hidden layer
+                    const Op one = bias_operand(h);
+#pragma unroll
+                    for (int mb = 0; mb < NMB; ++mb) {
+                        const Op w = load_a<P>(blob, t0 + (int64_t)NKB * NMB + mb, lane);
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(w, one, acc[mb][nb]);
+                    }
+                }
+            }
             const float *bias = s_bias + l * W;
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb) {
                 float bv[16];
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
+                    const f32x4 b4 = P == kBF16 ? f32x4{0.f, 0.f, 0.f, 0.f}   // bf16: bias already accumulated
+                                                : *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) bv[4 * g + i] = b4[i];
                 }
@@ -188,11 +203,19 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(w, b[kb][nb], acc[nb]);
             }
+            float hb0 = s_bias[W * depth], hb1 = s_bias[W * depth + 1];
+            if constexpr (P == kBF16) {
+                const Op w = load_a<P>(blob, t0 + NKB, lane);
+                const Op one = bias_operand(h);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(w, one, acc[nb]);
+                hb0 = hb1 = 0.f;
+            }
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 // rows 0 (logit) and 1 (distance) live in lanes 0..31; share them with the upper half
-                const float z = __shfl(acc[nb][0], col) + s_bias[W * depth];
-                const float dd = __shfl(acc[nb][1], col) + s_bias[W * depth + 1];
+                const float z = __shfl(acc[nb][0], col) + hb0;
+                const float dd = __shfl(acc[nb][1], col) + hb1;
                 const int64_t r = base + nb * 32 + col;
                 if (h == 0 && valid[nb]) {
                     if (a.logit_out) a.logit_out[r] = z;

