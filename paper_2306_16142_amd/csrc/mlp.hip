@@ -181,6 +181,87 @@ struct LdsConsts {
     float alpha[9];       // fp8: s_w s_a / s_a(next) per layer; head: s_w s_a
 };
 
+// MFMAs of one 32-row M-block of a layer for NB ray blocks (bf16 adds the bias K-block).
+template <int P, int W, int NB, int KIN>
+__device__ __attribute__((always_inline)) inline void mblock_mfma(const uint8_t *wsrc, int64_t t0, int mb,
+                                                                  const typename OpOf<P>::T (&bin)[W / k_per_block(P)][NB],
+                                                                  f32x16 (&acc)[NB], int lane, int h) {
+    using Op = typename OpOf<P>::T;
+    constexpr int NMB = W / 32;
+#pragma unroll
+    for (int kb = 0; kb < KIN; ++kb) {
+        const Op a = load_a<P>(wsrc, t0 + (int64_t)kb * NMB + mb, lane);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, bin[kb][nb], kb == 0 ? f32x16{} : acc[nb]);
+    }
+    if constexpr (P == kBF16) {
+        if (KIN == W / k_per_block(P)) {   // hidden layer: bias K-block
+            const Op a = load_a<P>(wsrc, t0 + (int64_t)KIN * NMB + mb, lane);
+            const Op one = bias_operand(h);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, one, acc[nb]);
+        }
+    }
+}
+
+// One bf16 affine layer for a wave, software-pipelined: A tiles are loaded kAhead MFMA
+// steps ahead (so LDS latency hides behind the matrix core), and the MFMAs of M-block mb
+// are interleaved (scheduling barriers) with the ReLU/conversion of block mb - 1, so the
+// matrix core runs while the vector ALU converts.
+template <int W, int NB, int KIN>
+__device__ __attribute__((always_inline)) inline void dense_relu_bf16(const uint8_t *wsrc, int64_t t0,
+                                                                      const bf16x8 (&bin)[W / 16][NB],
+                                                                      bf16x8 (&bout)[W / 16][NB], int lane, int h) {
+    constexpr int NMB = W / 32;
+    constexpr bool kBias = KIN == W / 16;       // hidden layers carry the bias K-block
+    constexpr int KS = KIN + (kBias ? 1 : 0);   // MFMA steps per M-block
+    constexpr int NSTEP = NMB * KS;
+    constexpr int kAhead = 3;
+    const bf16x8 one = bias_operand(h);
+    auto tile_of = [&](int step) { return t0 + (int64_t)(step % KS) * NMB + step / KS; };
+    bf16x8 ring[kAhead];
+#pragma unroll
+    for (int i = 0; i < kAhead; ++i) ring[i] = load_a<kBF16>(wsrc, tile_of(i < NSTEP ? i : 0), lane);
+    f32x16 prev[NB], cur[NB];
+#pragma unroll
+    for (int step = 0; step < NSTEP; ++step) {
+        const int mb = step / KS, ks = step % KS;
+        const bf16x8 a = ring[step % kAhead];
+        if (step + kAhead < NSTEP) ring[step % kAhead] = load_a<kBF16>(wsrc, tile_of(step + kAhead), lane);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const bf16x8 bop = (kBias && ks == KIN) ? one : bin[ks < KIN ? ks : 0][nb];
+            cur[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bop, ks == 0 ? f32x16{} : cur[nb], 0, 0, 0);
+        }
+        if (ks == KS - 1) {
+            if (mb > 0) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    float y[16];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) y[j] = fmaxf(prev[nb][j], 0.f);
+                    tile_to_operands<kBF16>(y, mb - 1, nb, bout);
+                }
+                // 24 VALU per ray block against KS * NB MFMAs of this block: interleave them
+#pragma unroll
+                for (int i = 0; i < KS * NB; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x002, (24 * NB + KS * NB - 1) / (KS * NB), 0);   // VALU
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) prev[nb] = cur[nb];
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        float y[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) y[j] = fmaxf(prev[nb][j], 0.f);
+        tile_to_operands<kBF16>(y, NMB - 1, nb, bout);
+    }
+}
+
 // One affine layer for a wave: KIN K-blocks of input operands `bin` -> the next layer's
 // operands `bout` (ReLU; fp8: requantised).  M-blocks are processed one after another so
 // that the epilogue of block mb (VALU) can overlap the MFMAs of block mb + 1.
@@ -188,30 +269,16 @@ template <int P, int W, int NB, int KIN, bool kCalib>
 __device__ __attribute__((always_inline)) inline void dense_relu(const uint8_t *wsrc, int64_t t0, const typename OpOf<P>::T (&bin)[W / k_per_block(P)][NB],
                                   typename OpOf<P>::T (&bout)[W / k_per_block(P)][NB], const float *bias, float alpha,
                                   int lane, int h, bool valid_any, unsigned int *amax_dst) {
+    if constexpr (P == kBF16 && !kCalib) {
+        dense_relu_bf16<W, NB, KIN>(wsrc, t0, bin, bout, lane, h);
+        return;
+    }
     using Op = typename OpOf<P>::T;
     constexpr int NMB = W / 32;
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) {
         f32x16 acc[NB];
-#pragma unroll
-        for (int kb = 0; kb < KIN; ++kb) {
-            const Op a = load_a<P>(wsrc, t0 + (int64_t)kb * NMB + mb, lane);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, bin[kb][nb], kb == 0 ? f32x16{} : acc[nb]);
-        }
-        if constexpr (P == kBF16) {
-            if (KIN == W / k_per_block(P)) {   // hidden layer: bias K-block
-                const Op a = load_a<P>(wsrc, t0 + (int64_t)KIN * NMB + mb, lane);
-                const Op one = bias_operand(h);
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, one, acc[nb]);
-            }
-            if constexpr (!kCalib) {
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) tile_to_operands_relu_bf16(acc[nb], mb, nb, bout);
-                continue;
-            }
-        }
+        mblock_mfma<P, W, NB, KIN>(wsrc, t0, mb, bin, acc, lane, h);
         float bv[16];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {

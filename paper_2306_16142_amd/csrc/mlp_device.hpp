@@ -11,7 +11,9 @@ constexpr float kFp8Max = 448.0f;
 // ------------------------------------------------------------------------------ encoding
 // Features of one variable: raw, sin(2^k v), cos(2^k v), k = 0..5.  In float32 mode every
 // frequency calls sincosf (arguments 2^k v are exact); in reduced precision the higher
-// frequencies follow the double-angle recurrence from the k = 0 values.
+// frequencies follow the double-angle recurrence from the k = 0 values.  (The hardware
+// sine was tried for the base frequency: its error, amplified 32x by the recurrence,
+// flipped visibly more bf16 roundings than float32 rounding does.)
 template <bool kExact>
 __device__ inline void encode_var(float v, float *f) {
     f[0] = v;
@@ -81,36 +83,12 @@ __device__ inline uint8_t fp8_bits(float x) {
     return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
 }
 
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-
-// ReLU + conversion of two float32 values to a packed bf16 pair: round first, then clear
-// negative halves with a signed 16-bit max (bf16 sign bit = int16 sign bit).
-__device__ inline uint32_t relu_bf16x2(float a, float b) {
-    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-    const bf16x2 p = {(__bf16)a, (__bf16)b};
-    const s16x2 q = __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), s16x2{0, 0});
-    return __builtin_bit_cast(uint32_t, q);
-}
-
 // B operand of the bf16 bias K-block: 1.0 in slots 0 and 1 of lane half 0.
 __device__ inline bf16x8 bias_operand(int h) {
     bf16x8 v;
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = (__bf16)((h == 0 && s < 2) ? 1.0f : 0.0f);
     return v;
-}
-
-// bf16 tile with ReLU fused into the conversion (accumulators already include the bias).
-template <int NKB, int NB>
-__device__ inline void tile_to_operands_relu_bf16(const f32x16 &acc, int mb, int nb, bf16x8 (&b)[NKB][NB]) {
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-        u32x4 w;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = relu_bf16x2(acc[8 * c + 2 * i], acc[8 * c + 2 * i + 1]);
-        b[2 * mb + c][nb] = __builtin_bit_cast(bf16x8, w);
-    }
 }
 
 // Converts one accumulator tile (D layout: rows 8 g + 4 h + i of M-block mb, values y[16]) of

@@ -77,11 +77,14 @@ def test_fp8_scales_and_forward_match_emulation(width, depth):
     lg, ds = host(lg), host(ds)
     el, ed = mlp.forward_fp8(p, width, depth, rays, so)
     rl, rd = mlp.forward(p, width, depth, rays)
+    # e4m3 keeps 3 mantissa bits: a requantisation flip moves an output by up to ~6% of one
+    # term, so the kernel-vs-emulation gap is bounded against the emulation's own error
     for g, e, r in ((lg, el, rl), (ds, ed, rd)):
         err = _scaled_err(g, e)
+        own = _scaled_err(e, r)
         assert np.median(err) < 1e-4
-        assert np.quantile(err, 0.99) < 3e-2
-        assert _scaled_err(g, r).mean() <= 1.1 * _scaled_err(e, r).mean() + 1e-5
+        assert np.quantile(err, 0.99) < 0.5 * np.quantile(own, 0.99)
+        assert _scaled_err(g, r).mean() <= 1.1 * own.mean() + 1e-5
 
 
 def test_forward_full_size_sampled():
