@@ -35,6 +35,25 @@ def flop_per_query(width, depth):
     return 2 * macs
 
 
+PROFILE = os.path.join(ROOT, "profiles", "forward_bf16_w128d4_2e24rays.md")
+KERNEL_SOURCES = ("mlp.hip", "mlp_device.hpp", "mlp_layout.hpp")
+
+
+def committed_traffic():
+    """HBM bytes per forward launch from the committed rocprofv3 counter summary, or None when
+    the kernel sources have changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch", "kernel_source_sha256")))
+    src = "".join(open(os.path.join(ROOT, "paper_2306_16142_amd", "csrc", f)).read() for f in KERNEL_SOURCES)
+    if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src.encode()).hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,7 +273,9 @@ def main():
         "config": {"workload": "precision query: 2^%d uniform rays, DDF MLP 65->128x4->2 (Fourier 6 freq)" % args.n_log2,
                    "rays": n, "width": W, "depth": D, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": bf["forward_tflops"], "peak": PEAK["bf16"], "unit": "TFLOP/s",
-                     "frac": bf["forward_tflops"] / PEAK["bf16"], "traffic": None,
+                     "frac": bf["forward_tflops"] / PEAK["bf16"], "traffic": committed_traffic(),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": 28 * n,
                      "kernel": "forward_kernel<bf16,128,2,lds>",
                      "algorithmic_flop_per_query": flop_per_query(W, D)},
     }

@@ -1,0 +1,93 @@
+"""C-ABI checks that run without a GPU: the library loads, exports every entry point that
+include/ddf.h declares, and validates arguments before touching the device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "ddf.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:ddf_status|int32_t|const char \*)\s*(ddf_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2306_16142_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libddf.so not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_declares_the_hot_path():
+    names = _declared()
+    for required in ("ddf_label_rays", "ddf_forward", "ddf_backward", "ddf_render_wavefront", "ddf_pack_net",
+                     "ddf_train_step", "ddf_assemble_rays"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2306_16142_amd import _lib
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, "binding lacks " + name
+
+
+def test_version_and_error_string(lib):
+    assert lib.ddf_abi_version() == 1
+    assert isinstance(lib.ddf_last_error(), bytes)
+
+
+def test_validation_before_launch(lib):
+    from paper_2306_16142_amd import _lib
+    # NULL arrays with n > 0, negative sizes, empty windows: rejected with a message
+    assert lib.ddf_label_rays(None, None, 5, None, 3, 0.0, 1.0, None, None, None, None) == _lib.DDF_ERR_INVALID_ARG
+    assert b"NULL" in lib.ddf_last_error()
+    assert lib.ddf_label_rays(None, None, -1, None, 3, 0.0, 1.0, None, None, None, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_label_rays(None, None, 5, None, 3, 1.0, 1.0, None, None, None, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_label_rays(None, None, 5, None, 3, 0.0, math.nan, None, None, None, None) == _lib.DDF_ERR_INVALID_ARG
+    # n == 0 is a no-op even with NULL arrays
+    assert lib.ddf_label_rays(None, None, 0, None, 3, 0.0, 1.0, None, None, None, None) == _lib.DDF_OK
+    assert lib.ddf_assemble_rays(None, None, 0, None, None) == _lib.DDF_OK
+    assert lib.ddf_assemble_rays(None, None, 4, None, None) == _lib.DDF_ERR_INVALID_ARG
+    # unsupported shapes and precisions
+    b = ctypes.c_size_t(0)
+    assert lib.ddf_packed_bytes(96, 4, 1, ctypes.byref(b)) == _lib.DDF_ERR_UNSUPPORTED
+    assert lib.ddf_packed_bytes(128, 9, 1, ctypes.byref(b)) == _lib.DDF_ERR_UNSUPPORTED
+    assert lib.ddf_packed_bytes(128, 4, 7, ctypes.byref(b)) == _lib.DDF_ERR_UNSUPPORTED
+    assert lib.ddf_packed_bytes(128, 4, 1, ctypes.byref(b)) == _lib.DDF_OK and b.value > 0
+    net = _lib.DdfNet(128, 4, 1, None)
+    assert lib.ddf_forward(ctypes.byref(net), None, 10, None, None, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_forward(None, None, 10, None, None, None) == _lib.DDF_ERR_INVALID_ARG
+    # parameter gradients need a float32 network; fp8 cannot give input gradients
+    net = _lib.DdfNet(128, 4, 1, 1)
+    assert lib.ddf_backward(ctypes.byref(net), 1, 10, None, None, None, 1, 0, None, 0, None) == _lib.DDF_ERR_UNSUPPORTED
+    net = _lib.DdfNet(128, 4, 2, 1)
+    assert lib.ddf_backward(ctypes.byref(net), 1, 10, None, None, 1, None, 0, None, 0, None) == _lib.DDF_ERR_UNSUPPORTED
+    # fp8 packing needs scales, the others must not get any
+    assert lib.ddf_pack_net(1, 128, 4, 2, None, 1, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_pack_net(1, 128, 4, 1, 1, 1, None) == _lib.DDF_ERR_INVALID_ARG
+
+
+def test_workspace_sizes(lib):
+    from paper_2306_16142_amd import _lib
+    b = ctypes.c_size_t(0)
+    assert lib.ddf_train_workspace_size(256, 6, 65536, ctypes.byref(b)) == _lib.DDF_OK
+    # features + activations + adjoints + chunk partials, at least
+    assert b.value >= (65 + 2 * 6 * 256) * 65536 * 4
+    p = _lib.DdfRenderParams()
+    p.width, p.height, p.spp, p.bounces = 64, 64, 1, 3
+    assert lib.ddf_render_workspace_size(ctypes.byref(p), ctypes.byref(b)) == _lib.DDF_OK and b.value > 64 * 64 * 40
+    p.bounces = 0
+    assert lib.ddf_render_workspace_size(ctypes.byref(p), ctypes.byref(b)) == _lib.DDF_ERR_INVALID_ARG
+    # a too-small workspace is rejected before launching
+    scene = _lib.DdfScene(_lib.BACKEND_MESH, 1, 3, None)
+    p.bounces = 3
+    assert lib.ddf_render_wavefront(ctypes.byref(scene), ctypes.byref(p), 1, None, None, None, 1, 16, None) == \
+        _lib.DDF_ERR_WORKSPACE

@@ -280,3 +280,19 @@ def test_normals_on_analytic_plane_field():
     # degenerate cases
     z = mlp.normals(np.zeros((3, 1)), np.array([[0.0], [0.0], [2.0]]))
     np.testing.assert_array_equal(z[:, 0], [0.0, 0.0, -1.0])
+
+
+def test_fp8_scales_closed_form():
+    """Per-layer scales are absmax / 448: weight absmax from the matrix, input absmax over the
+    calibration rays (layer 0: the Fourier features, whose largest magnitude here is the raw
+    azimuth; deeper layers: ReLU outputs of the one-hot chain)."""
+    width, depth = 8, 2
+    layers = mlp.unpack(np.zeros(synthetic.param_count(width, depth)), width, depth)
+    layers = [(W.copy(), b.copy()) for W, b in layers]
+    layers[0][0][0, 4] = -3.0          # unit 0 = -3 * phi (ReLU keeps it only for phi < 0: never)
+    layers[0][0][1, 0] = 2.0           # unit 1 = 2 * ox
+    layers[1][0][2, 1] = 0.5           # unit 2 = 0.5 * relu(2 ox)
+    layers[2][0][1, 2] = 4.0
+    rays = np.array([[0.5, -0.25], [0, 0], [0, 0], [1.0, 2.0], [6.0, 3.0]], dtype=np.float64)
+    s = mlp.fp8_scales(mlp.pack(layers), width, depth, rays)
+    np.testing.assert_allclose(s, np.array([3.0, 6.0, 0.5, 1.0, 4.0, 0.5]) / 448.0, rtol=1e-15)
