@@ -180,7 +180,7 @@ ddf_status ddf_train_step(const ddf_net *net, float *params, float *adam_m, floa
  * Readings (the paper gives no camera, light, sampler or termination rule):
  *   pinhole camera (eye, target, up, vertical field of view), pixel centre at 1 spp,
  *   otherwise a jitter from random dimensions 0, 1; network queries start at the
- *   entry of the domain cube [-1,1]^3 (hit <=> logit > 0, t = entry + distance);
+ *   entry of the domain cube [-1,1]^3 (t = entry + distance; hit <=> logit > 0 and t >= 0);
  *   shadow / scatter origins x + eps n; scatter by Malley's method in the basis of Duff
  *   et al. 2017; after the scatter of bounce b >= rr_start, survival probability
  *   q = min(0.95, max throughput channel).  Random numbers: SplitMix64 (Steele, Lea,
@@ -191,12 +191,28 @@ ddf_status ddf_train_step(const ddf_net *net, float *params, float *adam_m, floa
  * image does not depend on queue order (bitwise reproducible).                        */
 #define DDF_BACKEND_MESH 0
 #define DDF_BACKEND_NET 1
+#define DDF_BACKEND_MULTI 2     /* several networks placed as rigid instances */
+
+/* One rigid instance of a network: x_world = R x_object + T.  Each network's domain is the
+ * cube [-1,1]^3 of its object space; rays are moved into object space, queried from the
+ * cube entry, and the nearest hit over all instances wins (distances are preserved by rigid
+ * maps; ties go to the instance listed first).  Scenes of objects are the paper's stated
+ * future work (Sec. VII). */
+typedef struct {
+    float R[9];                 /* rotation, row-major, object to world */
+    float T[3];                 /* translation */
+    int32_t net;                /* index into ddf_scene.nets */
+} ddf_instance;
 
 typedef struct {
     int32_t backend;            /* DDF_BACKEND_* */
     const float *tris;          /* MESH: device [9][m] */
     int64_t m;
     const ddf_net *net;         /* NET: DDF_PREC_FP32 or DDF_PREC_BF16 network (host struct) */
+    int32_t n_nets;             /* MULTI: networks (host array), all float32 or all bfloat16, */
+    const ddf_net *nets;        /*        at most 8 of each width */
+    int32_t n_instances;        /* MULTI: instances (host array), at most 64 */
+    const ddf_instance *instances;
 } ddf_scene;
 
 typedef struct {
@@ -208,12 +224,15 @@ typedef struct {
     int32_t spp_chunk;          /* samples per pixel traced together (0 = choose) */
 } ddf_render_params;
 
-/* Workspace bytes for a render (depends on width, height and the sample chunk). */
-ddf_status ddf_render_workspace_size(const ddf_render_params *p, size_t *bytes);
+/* Workspace bytes for a render (depends on width, height, the sample chunk and, for MULTI,
+ * the number of instances). */
+ddf_status ddf_render_workspace_size(const ddf_scene *scene, const ddf_render_params *p, size_t *bytes);
 
 /* radiance [3][height][width] (mean over samples; row 0 at the top); depth [height][width]
  * and normal [3][height][width] of sample 0's primary hit (+inf / 0 on a miss) or NULL;
- * stats: device uint32 [bounces] paths entering each bounce, summed over chunks, or NULL. */
+ * stats: device uint32, summed over chunks, or NULL: [bounces] paths entering each bounce;
+ * for MULTI followed by [bounces][n_nets] (ray, instance) pairs queried per network in
+ * each bounce's nearest-hit pass (the queue balance across networks). */
 ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_render_params *p, float *radiance,
                                 float *depth, float *normal, uint32_t *stats, void *ws, size_t ws_bytes,
                                 ddf_stream stream);

@@ -11,8 +11,8 @@ gradient (Sec. I, Sec. IV, Fig. 1).  The readings used here:
 * pinhole camera; pixel centre at 1 sample per pixel, otherwise a jitter from
   random dimensions 0 and 1;
 * network queries start at the entry point of the domain cube [-1,1]^3 when
-  the ray origin lies outside it; hit <=> logit > 0, hit distance = entry
-  offset + predicted distance;
+  the ray origin lies outside it; hit distance = entry offset + predicted
+  distance; hit <=> logit > 0 and that distance >= 0;
 * normal: mesh face normal, or Eq. 3 applied to d(dist)/d(origin); flipped so
   that n . d < 0;
 * next-event estimation: a shadow ray from x + eps n to the light; visible
@@ -158,9 +158,10 @@ class NetworkScene:
         theta, phi = geometry.angles_from_dirs(d)
         rays = np.concatenate([q, theta[None], phi[None]])
         logit, dist = mlp.forward(self.params, self.width, self.depth, rays)
-        hit = inbox & (logit > 0.0)
-        robust = ~inbox | (np.abs(logit) > self.margin)
-        return hit, t0 + dist, rays, robust
+        t = t0 + dist
+        hit = inbox & (logit > 0.0) & (t >= 0.0)   # a hit needs a non-negative distance
+        robust = ~inbox | ((np.abs(logit) > self.margin) & (np.abs(t) > self.margin))
+        return hit, t, rays, robust
 
     def intersect(self, o, d, t_max):
         hit, t, rays, robust = self._query(o, d)
@@ -218,7 +219,7 @@ def render(scene, cfg):
         if idx.size == 0:
             break
         dd = d[:, idx]
-        if isinstance(scene, NetworkScene):
+        if not isinstance(scene, MeshScene):   # network scenes return the distance gradient
             n = mlp.normals(n, dd)
         else:
             n = np.where(np.sum(n * dd, axis=0) > 0.0, -n, n)

@@ -25,8 +25,14 @@ class DdfNet(ctypes.Structure):
     _fields_ = [("width", c_i32), ("depth", c_i32), ("precision", c_i32), ("packed", c_p)]
 
 
+class DdfInstance(ctypes.Structure):
+    _fields_ = [("R", c_f * 9), ("T", c_f * 3), ("net", c_i32)]
+
+
 class DdfScene(ctypes.Structure):
-    _fields_ = [("backend", c_i32), ("tris", c_p), ("m", c_i64), ("net", ctypes.POINTER(DdfNet))]
+    _fields_ = [("backend", c_i32), ("tris", c_p), ("m", c_i64), ("net", ctypes.POINTER(DdfNet)),
+                ("n_nets", c_i32), ("nets", ctypes.POINTER(DdfNet)), ("n_instances", c_i32),
+                ("instances", ctypes.POINTER(DdfInstance))]
 
 
 class DdfRenderParams(ctypes.Structure):
@@ -36,7 +42,7 @@ class DdfRenderParams(ctypes.Structure):
                 ("spp_chunk", c_i32)]
 
 
-BACKEND_MESH, BACKEND_NET = 0, 1
+BACKEND_MESH, BACKEND_NET, BACKEND_MULTI = 0, 1, 2
 
 # name -> argument types (every entry point returns ddf_status unless listed in _RESTYPE)
 SIGNATURES = {
@@ -52,7 +58,7 @@ SIGNATURES = {
     "ddf_backward": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_p, c_p, c_p, c_u32, c_p, c_sz, c_p],
     "ddf_loss_seeds": [c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_p, c_sz, c_p],
     "ddf_adam_step": [c_p, c_p, c_p, c_p, c_i64, c_i64, c_f, c_f, c_f, c_f, c_p],
-    "ddf_render_workspace_size": [ctypes.POINTER(DdfRenderParams), ctypes.POINTER(c_sz)],
+    "ddf_render_workspace_size": [ctypes.POINTER(DdfScene), ctypes.POINTER(DdfRenderParams), ctypes.POINTER(c_sz)],
     "ddf_render_wavefront": [ctypes.POINTER(DdfScene), ctypes.POINTER(DdfRenderParams), c_p, c_p, c_p, c_p, c_p, c_sz,
                              c_p],
     "ddf_train_step": [ctypes.POINTER(DdfNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64, c_p, c_p, c_p, c_sz, c_p],

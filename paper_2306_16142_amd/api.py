@@ -197,33 +197,54 @@ def render_params(cfg, spp_chunk=0):
 
 
 class Renderer:
-    """Wavefront path tracer with the mesh (``tris`` [9][m]) or a network (``net``) as the scene."""
+    """Wavefront path tracer.  The scene is the mesh (``tris`` [9][m]), one network (``net``),
+    or several networks placed as rigid instances (``nets`` + ``instances``: dicts with ``R``
+    (3x3 object to world), ``T`` (3) and ``net`` (index into ``nets``))."""
 
-    def __init__(self, cfg, tris=None, net=None, spp_chunk=0, device="cuda"):
-        if (tris is None) == (net is None):
-            raise ValueError("give exactly one of tris (mesh backend) or net (network backend)")
+    def __init__(self, cfg, tris=None, net=None, nets=None, instances=None, spp_chunk=0, device="cuda"):
+        given = [tris is not None, net is not None, nets is not None]
+        if sum(given) != 1:
+            raise ValueError("give exactly one of tris, net, or nets + instances")
         self.cfg = cfg
         self.params = render_params(cfg, spp_chunk)
-        self.net = net
-        self.tris = tris
+        self.keep = (tris, net, nets)
         if net is not None:
-            self.scene = _lib.DdfScene(_lib.BACKEND_NET, None, 0, ctypes.pointer(net.desc))
-        else:
+            self.scene = _lib.DdfScene(_lib.BACKEND_NET, None, 0, ctypes.pointer(net.desc), 0, None, 0, None)
+        elif tris is not None:
             _dev(tris, torch.float32, "tris", 9)
-            self.scene = _lib.DdfScene(_lib.BACKEND_MESH, tris.data_ptr(), tris.shape[1], None)
+            self.scene = _lib.DdfScene(_lib.BACKEND_MESH, tris.data_ptr(), tris.shape[1], None, 0, None, 0, None)
+        else:
+            self.net_array = (_lib.DdfNet * len(nets))(*[n.desc for n in nets])
+            inst = []
+            for d in instances:
+                R = [float(x) for x in list(d["R"][0]) + list(d["R"][1]) + list(d["R"][2])]
+                inst.append(_lib.DdfInstance((ctypes.c_float * 9)(*R), (ctypes.c_float * 3)(*[float(x) for x in d["T"]]),
+                                             int(d["net"])))
+            self.inst_array = (_lib.DdfInstance * len(inst))(*inst)
+            self.scene = _lib.DdfScene(_lib.BACKEND_MULTI, None, 0, None, len(nets), self.net_array, len(inst),
+                                       self.inst_array)
         b = ctypes.c_size_t(0)
-        _lib.call("ddf_render_workspace_size", ctypes.byref(self.params), ctypes.byref(b))
+        _lib.call("ddf_render_workspace_size", ctypes.byref(self.scene), ctypes.byref(self.params), ctypes.byref(b))
         self.ws = torch.empty(b.value, device=device, dtype=torch.uint8)
         H, W = cfg.height, cfg.width
         self.radiance = torch.empty((3, H, W), device=device, dtype=torch.float32)
         self.depth = torch.empty((H, W), device=device, dtype=torch.float32)
         self.normal = torch.empty((3, H, W), device=device, dtype=torch.float32)
-        self.stats = torch.empty(cfg.bounces, device=device, dtype=torch.int32)
+        nstats = cfg.bounces * (1 + (len(nets) if nets is not None else 0))
+        self.stats = torch.empty(nstats, device=device, dtype=torch.int32)
 
     def render(self):
         _lib.call("ddf_render_wavefront", ctypes.byref(self.scene), ctypes.byref(self.params), _p(self.radiance),
                   _p(self.depth), _p(self.normal), _p(self.stats), _p(self.ws), self.ws.numel(), _stream())
         return self.radiance
+
+    def path_stats(self):
+        """Paths entering each bounce, and (multi-object scenes) pairs per network per bounce."""
+        st = self.stats.cpu().numpy()
+        b = self.cfg.bounces
+        paths = st[:b]
+        per_net = st[b:].reshape(b, -1) if st.size > b else None
+        return paths, per_net
 
 
 def fp8_scales(params, width, depth, calib_rays, net_fp32=None):

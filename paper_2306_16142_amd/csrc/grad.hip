@@ -18,27 +18,11 @@
 #include "common.hpp"
 #include "mlp_device.hpp"
 #include "mlp_layout.hpp"
+#include "grad_args.hpp"
 
 namespace ddf {
 
-struct GradArgs {
-    const uint8_t *blob;
-    int depth;
-    const float *rays;
-    int64_t n;                   // row length of every [k][n] array
-    const int *count_dev;        // when set, only the first *count_dev rays are processed
-    const float *g_logit_in;     // VJP seeds (NULL = 0)
-    const float *g_dist_in;
-    const float *t_label;        // training: label distance, +inf = miss (NULL: seeds from g_*_in)
-    const float *loss_scalars;   // training: {1 / N, 1 / n_hit}
-    float *logit_out;            // optional
-    float *dist_out;             // optional
-    float *g_rays;               // optional [5][n]
-    float *ws_gamma;             // side outputs: [65][n] features
-    float *ws_h;                 // side outputs: [depth][W][n] hidden activations
-    float *ws_delta;             // side outputs: [depth][W][n] adjoints, then [2][n] head seeds
-    float *loss_partial;         // training: [gridDim.x]
-};
+
 
 namespace {
 
@@ -54,21 +38,23 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
     constexpr int NKB = W / KB;
     constexpr int K0 = layer0_kblocks(P);
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    const int depth = a.depth;
     const int64_t n = a.n;
+    const bool multi = a.n_nets > 0;
+    const int depth_max = a.depth;
     const int64_t count = a.count_dev ? min<int64_t>(*a.count_dev, n) : n;
-    const NetLayout L = make_layout(W, depth, P);
-    const uint8_t *blob = a.blob;
-    const uint8_t *gsrc = blob + L.grad_off;
 
+    // single network: biases and head rows staged in LDS; multi: read from each blob (L2)
     float *s_bias = reinterpret_cast<float *>(smem);
-    float *s_head = s_bias + (W * depth + 4);               // [2][W]
-    uint16_t *s_mask = reinterpret_cast<uint16_t *>(s_head + 2 * W);
-    float *s_loss = reinterpret_cast<float *>(s_mask + (blockDim.x / 64) * depth * NMB * NB * 64);
-    for (int i = threadIdx.x; i < W * depth + 4; i += blockDim.x)
-        s_bias[i] = reinterpret_cast<const float *>(blob + L.bias_off)[i];
-    for (int i = threadIdx.x; i < 2 * W; i += blockDim.x)
-        s_head[i] = reinterpret_cast<const float *>(blob + L.head_rows_off)[i];
+    float *s_head = s_bias + (multi ? 0 : W * depth_max + 4);   // [2][W]
+    uint16_t *s_mask = reinterpret_cast<uint16_t *>(s_head + (multi ? 0 : 2 * W));
+    float *s_loss = reinterpret_cast<float *>(s_mask + (blockDim.x / 64) * depth_max * NMB * NB * 64);
+    if (!multi) {
+        const NetLayout L0 = make_layout(W, depth_max, P);
+        for (int i = threadIdx.x; i < W * depth_max + 4; i += blockDim.x)
+            s_bias[i] = reinterpret_cast<const float *>(a.blob + L0.bias_off)[i];
+        for (int i = threadIdx.x; i < 2 * W; i += blockDim.x)
+            s_head[i] = reinterpret_cast<const float *>(a.blob + L0.head_rows_off)[i];
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -76,14 +62,40 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
     const int h = lane >> 5;
     const int col = lane & 31;
     const int wpb = blockDim.x >> 6;
-    uint16_t *wmask = s_mask + (int64_t)wave * depth * NMB * NB * 64;
-    const int64_t ntile = (count + 32 * NB - 1) / (32 * NB);
+    uint16_t *wmask = s_mask + (int64_t)wave * depth_max * NMB * NB * 64;
     float loss_acc = 0.f;
     const float inv_n = (kTrain && a.loss_scalars) ? a.loss_scalars[0] : 0.f;
     const float inv_nhit = (kTrain && a.loss_scalars) ? a.loss_scalars[1] : 0.f;
 
+    // work list: the tiles of every network segment, one after another
+    const int nk = multi ? a.n_nets : 1;
+    int64_t pre[kMaxNets + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxNets; ++k) {
+        const int64_t cnt = k < nk ? (multi ? (int64_t)a.seg_count[k] : count) : 0;
+        pre[k + 1] = pre[k] + (cnt + 32 * NB - 1) / (32 * NB);
+    }
+    const int64_t ntile = pre[kMaxNets];
+
     for (int64_t tile = (int64_t)blockIdx.x * wpb + wave; tile < ntile; tile += (int64_t)gridDim.x * wpb) {
-        const int64_t base = tile * 32 * NB;
+        int k = 0;
+        int64_t pk = 0;
+#pragma unroll
+        for (int i = 1; i < kMaxNets; ++i)
+            if (tile >= pre[i] && i < nk) {
+                k = i;
+                pk = pre[i];
+            }
+        const uint8_t *blob = multi ? a.blobs[k] : a.blob;
+        const int depth = multi ? a.depths[k] : a.depth;
+        const NetLayout L = make_layout(W, depth, P);
+        const uint8_t *gsrc = blob + L.grad_off;
+        const float *bias_src = multi ? reinterpret_cast<const float *>(blob + L.bias_off) : s_bias;
+        const float *head_src = multi ? reinterpret_cast<const float *>(blob + L.head_rows_off) : s_head;
+        const int64_t seg_lo = multi ? (int64_t)a.seg_offset[k] : 0;
+        const int64_t seg_end = seg_lo + (multi ? (int64_t)a.seg_count[k] : count);
+        const int64_t base = seg_lo + (tile - pk) * 32 * NB;
         Op b[NKB][NB];
         float v[NB][kInRaw];
         bool valid[NB];
@@ -91,7 +103,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int64_t r = base + nb * 32 + col;
-            valid[nb] = r < count;
+            valid[nb] = r < seg_end;
 #pragma unroll
             for (int j = 0; j < kInRaw; ++j) v[nb][j] = valid[nb] ? a.rays[(int64_t)j * n + r] : 0.f;
             float feat[kSlotsPerHalf];
@@ -154,7 +166,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
                     }
                 }
             }
-            const float *bias = s_bias + l * W;
+            const float *bias = bias_src + l * W;
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb) {
                 float bv[16];
@@ -203,7 +215,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(w, b[kb][nb], acc[nb]);
             }
-            float hb0 = s_bias[W * depth], hb1 = s_bias[W * depth + 1];
+            float hb0 = bias_src[W * depth], hb1 = bias_src[W * depth + 1];
             if constexpr (P == kBF16) {
                 const Op w = load_a<P>(blob, t0 + NKB, lane);
                 const Op one = bias_operand(h);
@@ -244,6 +256,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
                 }
             }
         }
+        if (a.forward_only) continue;
         // ---- adjoint of the last hidden layer: head rows times the seeds, masked.  The
         // accumulator array carries each layer's adjoint (D layout) down the network.
         f32x16 acc[NMB][NB];
@@ -252,8 +265,8 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
             float w0[16], w1[16];
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const f32x4 a4 = *reinterpret_cast<const f32x4 *>(s_head + mb * 32 + 8 * g + 4 * h);
-                const f32x4 b4 = *reinterpret_cast<const f32x4 *>(s_head + W + mb * 32 + 8 * g + 4 * h);
+                const f32x4 a4 = *reinterpret_cast<const f32x4 *>(head_src + mb * 32 + 8 * g + 4 * h);
+                const f32x4 b4 = *reinterpret_cast<const f32x4 *>(head_src + W + mb * 32 + 8 * g + 4 * h);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     w0[4 * g + i] = a4[i];
@@ -423,6 +436,14 @@ ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, h
     }
     if (w == 128) return p == kBF16 ? launch_grad<kBF16, 128, 2, false>(args, s, cap) : launch_grad<kFP32, 128, 1, false>(args, s, cap);
     return p == kBF16 ? launch_grad<kBF16, 256, 1, false>(args, s, cap) : launch_grad<kFP32, 256, 1, false>(args, s, cap);
+}
+
+ddf_status grad_dispatch_multi(int width, int precision, const GradArgs &args, hipStream_t s) {
+    DDF_REQUIRE(args.n_nets >= 1 && args.n_nets <= kMaxNets, DDF_ERR_UNSUPPORTED, "too many networks in one launch");
+    const int cap = cu_count_grad() * 2;
+    if (width == 128)
+        return precision == kBF16 ? launch_grad<kBF16, 128, 2, false>(args, s, cap) : launch_grad<kFP32, 128, 1, false>(args, s, cap);
+    return precision == kBF16 ? launch_grad<kBF16, 256, 1, false>(args, s, cap) : launch_grad<kFP32, 256, 1, false>(args, s, cap);
 }
 
 }  // namespace ddf

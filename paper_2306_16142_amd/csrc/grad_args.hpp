@@ -1,0 +1,43 @@
+// Arguments of the network gradient / query sweep (grad.hip), shared by its callers.
+#pragma once
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace ddf {
+
+constexpr int kMaxNets = 8;   // networks of one width in a single multi-network launch
+
+struct GradArgs {
+    const uint8_t *blob;         // single network: packed blob (ignored when n_nets > 0)
+    int depth;                   // single network: depth; multi: the largest depth of the group
+    const float *rays;           // [5][n]
+    int64_t n;                   // row length of every [k][n] array
+    const int *count_dev;        // single network: only the first *count_dev rays (NULL: all n)
+    const float *g_logit_in;     // seeds (NULL = 0)
+    const float *g_dist_in;
+    const float *t_label;        // training: label distance, +inf = miss (NULL: seeds from g_*_in)
+    const float *loss_scalars;   // training: {1 / N, 1 / n_hit}
+    float *logit_out;            // optional
+    float *dist_out;             // optional
+    float *g_rays;               // optional [5][n]
+    float *ws_gamma;             // side outputs: [65][n] features
+    float *ws_h;                 // side outputs: [depth][W][n] hidden activations
+    float *ws_delta;             // side outputs: [depth][W][n] adjoints, then [2][n] head seeds
+    float *loss_partial;         // training: [gridDim.x]
+    bool forward_only;           // stop after logit / distance
+    // several networks of one width in one persistent launch: network k owns the rows
+    // [seg_offset[k], seg_offset[k] + seg_count[k]) (device arrays)
+    int n_nets;
+    const uint8_t *blobs[kMaxNets];
+    int depths[kMaxNets];
+    const int *seg_offset;
+    const int *seg_count;
+};
+
+ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, hipStream_t s);
+// Multi-network launch: every network of the group has `width` and `precision`.
+ddf_status grad_dispatch_multi(int width, int precision, const GradArgs &args, hipStream_t s);
+int64_t grad_grid(int width, int precision, int64_t n);
+
+}  // namespace ddf

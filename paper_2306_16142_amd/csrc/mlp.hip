@@ -273,7 +273,6 @@ __device__ __attribute__((always_inline)) inline void dense_relu(const uint8_t *
         dense_relu_bf16<W, NB, KIN>(wsrc, t0, bin, bout, lane, h);
         return;
     }
-    using Op = typename OpOf<P>::T;
     constexpr int NMB = W / 32;
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) {

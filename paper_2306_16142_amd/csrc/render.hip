@@ -11,31 +11,15 @@
 // fixed sequence of launches with no host synchronisation.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "common.hpp"
 #include "mlp_layout.hpp"
+#include "grad_args.hpp"
 
 namespace ddf {
 
-struct GradArgs {
-    const uint8_t *blob;
-    int depth;
-    const float *rays;
-    int64_t n;
-    const int *count_dev;
-    const float *g_logit_in;
-    const float *g_dist_in;
-    const float *t_label;
-    const float *loss_scalars;
-    float *logit_out;
-    float *dist_out;
-    float *g_rays;
-    float *ws_gamma;
-    float *ws_h;
-    float *ws_delta;
-    float *loss_partial;
-};
-ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, hipStream_t s);
+
 ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, const int *count_dev, float *logit,
                             float *dist, unsigned int *absmax, hipStream_t s);
 ddf_status label_queue(const float *orig, const float *dir, int64_t stride, const int *idx, const int *count_dev,
@@ -130,6 +114,47 @@ __device__ inline int append(int *counter, bool want) {
     return want ? base + rank : -1;
 }
 
+// ------------------------------------------------------------------------------ multi-object
+struct InstDev {
+    float R[9];
+    float T[3];
+    int net;
+    int pad[3];
+};
+constexpr int kMaxInstances = 64;
+constexpr int kInstChunk = 8;
+struct InstChunk {
+    InstDev v[kInstChunk];
+};
+
+__global__ void inst_table_kernel(InstChunk c, int first, int count, InstDev *dst) {
+    const int i = threadIdx.x;
+    if (i < count) dst[first + i] = c.v[i];
+}
+
+// World ray -> object space of instance `in` (x_obj = R^T (x - T)).
+__device__ inline void to_object(const InstDev &in, Vec3 o, Vec3 d, Vec3 &oo, Vec3 &dd) {
+    const Vec3 s = o - v3(in.T[0], in.T[1], in.T[2]);
+    oo = v3(in.R[0] * s.x + in.R[3] * s.y + in.R[6] * s.z, in.R[1] * s.x + in.R[4] * s.y + in.R[7] * s.z,
+            in.R[2] * s.x + in.R[5] * s.y + in.R[8] * s.z);
+    dd = v3(in.R[0] * d.x + in.R[3] * d.y + in.R[6] * d.z, in.R[1] * d.x + in.R[4] * d.y + in.R[7] * d.z,
+            in.R[2] * d.x + in.R[5] * d.y + in.R[8] * d.z);
+}
+
+struct PairBufs {
+    int *q, *inst;        // [P]
+    float *rays5, *t0;    // [5][P], [P]
+    float *logit, *dist;  // [P]
+    float *grad;          // [5][P]
+    float *ones;          // [P]
+};
+
+struct MultiCounts {
+    int *inst_count, *inst_cursor, *inst_off;   // [kMaxInstances]
+    int *seg_offset, *seg_count;                // [n_nets]
+    int *total;                                 // [1]
+};
+
 struct PathState {
     float *o, *d, *thr, *L;   // [3][C]
     int *pix, *smp;           // [C]
@@ -144,12 +169,20 @@ struct RenderWs {
     int *sq;
     float *srays, *st0, *stmax, *scontrib, *slogit, *sdist, *st;
     int *stri;
+    // multi-object scenes
+    PairBufs pb;
+    int64_t P;
+    unsigned long long *best;
+    float *hit_t, *hit_g;
+    int *occl;
+    InstDev *inst;
+    MultiCounts mc;
     size_t bytes;
 };
 
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-RenderWs render_ws(int64_t C, int bounces, void *base) {
+RenderWs render_ws(int64_t C, int bounces, int n_inst, void *base) {
     RenderWs w{};
     uint8_t *p = reinterpret_cast<uint8_t *>(base);
     size_t off = 0;
@@ -185,6 +218,30 @@ RenderWs render_ws(int64_t C, int bounces, void *base) {
     w.sdist = (float *)take(f);
     w.st = (float *)take(f);
     w.stri = (int *)take(f);
+    if (n_inst > 0) {
+        const int64_t P = C * n_inst;
+        const size_t pf = (size_t)P * 4;
+        w.P = P;
+        w.pb.q = (int *)take(pf);
+        w.pb.inst = (int *)take(pf);
+        w.pb.rays5 = (float *)take(5 * pf);
+        w.pb.t0 = (float *)take(pf);
+        w.pb.logit = (float *)take(pf);
+        w.pb.dist = (float *)take(pf);
+        w.pb.grad = (float *)take(5 * pf);
+        w.pb.ones = (float *)take(pf);
+        w.best = (unsigned long long *)take((size_t)C * 8);
+        w.hit_t = (float *)take(f);
+        w.hit_g = (float *)take(3 * f);
+        w.occl = (int *)take(f);
+        w.inst = (InstDev *)take(sizeof(InstDev) * kMaxInstances);
+        w.mc.inst_count = (int *)take(4 * kMaxInstances);
+        w.mc.inst_cursor = (int *)take(4 * kMaxInstances);
+        w.mc.inst_off = (int *)take(4 * kMaxInstances);
+        w.mc.seg_offset = (int *)take(4 * 2 * kMaxNets);
+        w.mc.seg_count = (int *)take(4 * 2 * kMaxNets);
+        w.mc.total = (int *)take(16);
+    }
     w.bytes = off;
     return w;
 }
@@ -272,7 +329,8 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
                              const float *__restrict__ grad, const float *__restrict__ tq, const int *__restrict__ triq,
                              const float *__restrict__ tris, int64_t m, int *__restrict__ sq, float *__restrict__ srays,
                              float *__restrict__ st0, float *__restrict__ stmax, float *__restrict__ scontrib,
-                             float *__restrict__ depth, float *__restrict__ normal) {
+                             float *__restrict__ depth, float *__restrict__ normal,
+                             const unsigned long long *__restrict__ best) {
     const int n = counts[2 * bounce];
     const Vec3 light = v3(p.light_pos[0], p.light_pos[1], p.light_pos[2]);
     const int64_t hw = (int64_t)p.width * p.height;
@@ -288,10 +346,15 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
             const Vec3 o = load3(ps.o, C, id), d = load3(ps.d, C, id);
             float t = 0.f;
             Vec3 nrm{};
-            if (backend == DDF_BACKEND_NET) {
-                const float te = t0[q];
-                hit = !isnan(te) && logit[q] > 0.f;
-                t = te + dist[q];
+            if (backend != DDF_BACKEND_MESH) {
+                if (backend == DDF_BACKEND_NET) {
+                    const float te = t0[q];
+                    t = te + dist[q];
+                    hit = !isnan(te) && logit[q] > 0.f && t >= 0.f;   // a hit needs a non-negative distance
+                } else {   // MULTI: nearest instance hit, its distance and world-space gradient
+                    hit = best[q] != ~0ull;
+                    t = dist[q];
+                }
                 const Vec3 g = load3(grad, C, q);
                 const float gn = sqrtf(dot(g, g)), gd = dot(g, d);
                 const float kappa = gd > 0.f ? -1.f : 1.f;   // Eq. 3: n . d < 0
@@ -368,7 +431,8 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
                 const float te = cube_entry(xs, l);
                 st0[sslot] = te;
                 write_query(srays, C, sslot, xs, l, te);
-            } else {
+            } else {   // world-space shadow ray: mesh labeller or per-instance culling
+                
                 store3(srays, C, sslot, xs);
                 store3(srays + 3 * C, C, sslot, l);
             }
@@ -382,13 +446,16 @@ __global__ void resolve_kernel(int64_t C, int bounce, int backend, const int *__
                                const int *__restrict__ sq, const float *__restrict__ st0,
                                const float *__restrict__ stmax, const float *__restrict__ scontrib,
                                const float *__restrict__ slogit, const float *__restrict__ sdist,
-                               const float *__restrict__ st, float *__restrict__ L) {
+                               const float *__restrict__ st, const int *__restrict__ occl, float *__restrict__ L) {
     const int n = counts[2 * bounce + 1];
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
         bool occluded;
         if (backend == DDF_BACKEND_NET) {
             const float te = st0[q];
-            occluded = !isnan(te) && slogit[q] > 0.f && te + sdist[q] < stmax[q];
+            const float t = te + sdist[q];
+            occluded = !isnan(te) && slogit[q] > 0.f && t >= 0.f && t < stmax[q];
+        } else if (backend == DDF_BACKEND_MULTI) {
+            occluded = occl[q] != 0;
         } else {
             occluded = st[q] < stmax[q];
         }
@@ -428,26 +495,271 @@ __global__ void stats_kernel(const int *counts, int bounces, uint32_t *stats) {
     if (b < bounces) stats[b] += (uint32_t)counts[2 * b];
 }
 
-int chunk_spp(const ddf_render_params &p) {
-    if (p.spp_chunk > 0) return std::min(p.spp_chunk, p.spp);
-    const int64_t hw = (int64_t)p.width * p.height;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(p.spp, ((int64_t)1 << 24) / hw));
+
+// Rays of a queue (main: path ids through `queue`; shadow: rows of `rays6`) against every
+// instance's cube.  Pass 0 counts (ray, instance) pairs per instance; pass 1 writes them,
+// grouped by instance (and so by network: instances are ordered by network).
+template <bool kScatter>
+__global__ void cull_kernel(int64_t C, const int *__restrict__ queue, const int *__restrict__ count,
+                            const float *__restrict__ po, const float *__restrict__ pd, const InstDev *__restrict__ inst,
+                            int n_inst, MultiCounts mc, PairBufs pb, int64_t P) {
+    const int n = *count;
+    const int64_t span = ((int64_t)n + 63) / 64 * 64;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < span; q += (int64_t)gridDim.x * blockDim.x) {
+        Vec3 o{}, d{};
+        if (q < n) {
+            const int64_t src = queue ? (int64_t)queue[q] : q;
+            o = load3(po, C, src);
+            d = load3(pd, C, src);
+        }
+        for (int i = 0; i < n_inst; ++i) {
+            Vec3 oo, dd;
+            to_object(inst[i], o, d, oo, dd);
+            const float te = q < n ? cube_entry(oo, dd) : NAN;
+            const bool want = !isnan(te);
+            if constexpr (!kScatter) {
+                const uint64_t mask = __ballot(want);
+                if ((threadIdx.x & 63) == 0 && mask) atomicAdd(&mc.inst_count[i], (int)__popcll(mask));
+            } else {
+                const int slot = append(&mc.inst_cursor[i], want);
+                if (want) {
+                    const int64_t p = (int64_t)mc.inst_off[i] + slot;
+                    pb.q[p] = (int)q;
+                    pb.inst[p] = i;
+                    pb.t0[p] = te;
+                    write_query(pb.rays5, P, p, oo, dd, te);
+                }
+            }
+        }
+    }
 }
 
+// Exclusive scan of the per-instance counts; per-network segments; cursor reset; stats.
+struct NetMap {
+    int user[2 * kMaxNets];   // reordered network index -> caller's index
+};
+
+__global__ void pair_scan_kernel(int n_inst, const InstDev *__restrict__ inst, int n_nets, MultiCounts mc,
+                                 uint32_t *net_stats, NetMap map) {
+    if (threadIdx.x != 0) return;
+    int off = 0;
+    for (int k = 0; k < n_nets; ++k) {
+        mc.seg_offset[k] = off;
+        mc.seg_count[k] = 0;
+    }
+    for (int i = 0; i < n_inst; ++i) {
+        mc.inst_off[i] = off;
+        mc.inst_cursor[i] = 0;
+        mc.seg_count[inst[i].net] += mc.inst_count[i];
+        off += mc.inst_count[i];
+    }
+    for (int k = 0, o = 0; k < n_nets; ++k) {
+        mc.seg_offset[k] = o;
+        o += mc.seg_count[k];
+        if (net_stats) net_stats[map.user[k]] += (uint32_t)mc.seg_count[k];
+    }
+    *mc.total = off;
+}
+
+__global__ void zero_ints_kernel(int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void init_best_kernel(const int *__restrict__ count, unsigned long long *best, int *occl) {
+    const int n = *count;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        if (best) best[q] = ~0ull;
+        if (occl) occl[q] = 0;
+    }
+}
+
+// Nearest hit over instances: 64-bit key (t bits << 32 | instance) minimised per ray.
+__device__ inline unsigned long long hit_key(float t, int inst) {
+    return ((unsigned long long)__float_as_uint(t) << 32) | (unsigned)inst;
+}
+
+__global__ void merge_kernel(const int *__restrict__ total, PairBufs pb, unsigned long long *best) {
+    const int n = *total;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const float t = pb.t0[p] + pb.dist[p];
+        if (pb.logit[p] > 0.f && t >= 0.f) atomicMin(&best[pb.q[p]], hit_key(t, pb.inst[p]));
+    }
+}
+
+// The winning pair of each ray writes its distance and its gradient in world space
+// (d dist / d x_world = R d dist / d x_object for x_object = R^T (x_world - T)).
+__global__ void select_kernel(int64_t C, const int *__restrict__ total, PairBufs pb, int64_t P,
+                              const InstDev *__restrict__ inst, const unsigned long long *__restrict__ best,
+                              float *__restrict__ hit_t, float *__restrict__ hit_g) {
+    const int n = *total;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const float t = pb.t0[p] + pb.dist[p];
+        if (!(pb.logit[p] > 0.f && t >= 0.f)) continue;
+        const int q = pb.q[p], i = pb.inst[p];
+        if (hit_key(t, i) != best[q]) continue;
+        const InstDev &in = inst[i];
+        const Vec3 g = load3(pb.grad, P, p);
+        hit_t[q] = t;
+        store3(hit_g, C, q, v3(in.R[0] * g.x + in.R[1] * g.y + in.R[2] * g.z, in.R[3] * g.x + in.R[4] * g.y + in.R[5] * g.z,
+                              in.R[6] * g.x + in.R[7] * g.y + in.R[8] * g.z));
+    }
+}
+
+__global__ void occlude_kernel(const int *__restrict__ total, PairBufs pb, const float *__restrict__ stmax, int *occl) {
+    const int n = *total;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const float t = pb.t0[p] + pb.dist[p];
+        const int q = pb.q[p];
+        if (pb.logit[p] > 0.f && t >= 0.f && t < stmax[q]) occl[q] = 1;
+    }
+}
+
+int chunk_spp(const ddf_render_params &p, int n_inst) {
+    if (p.spp_chunk > 0) return std::min(p.spp_chunk, p.spp);
+    const int64_t hw = (int64_t)p.width * p.height;
+    const int64_t budget = n_inst > 0 ? ((int64_t)1 << 26) / n_inst : ((int64_t)1 << 24);   // paths (pairs) per chunk
+    return (int)std::max<int64_t>(1, std::min<int64_t>(p.spp, budget / hw));
+}
+
+int scene_instances(const ddf_scene *scene) { return scene && scene->backend == DDF_BACKEND_MULTI ? scene->n_instances : 0; }
+
 unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+ddf_status check_net_for_render(const ddf_net *net, const char *who) {
+    DDF_REQUIRE(net && net->packed, DDF_ERR_INVALID_ARG, "%s: NULL network", who);
+    DDF_REQUIRE(net->precision == DDF_PREC_FP32 || net->precision == DDF_PREC_BF16, DDF_ERR_UNSUPPORTED,
+                "%s: the network backends need float32 or bfloat16 networks (normals)", who);
+    DDF_REQUIRE((net->width == 128 || net->width == 256) && net->depth >= 1 && net->depth <= 8, DDF_ERR_UNSUPPORTED,
+                "%s: unsupported network shape", who);
+    return DDF_OK;
+}
+
+ddf_status check_scene(const ddf_scene *scene) {
+    DDF_REQUIRE(scene, DDF_ERR_INVALID_ARG, "ddf_render: NULL scene");
+    if (scene->backend == DDF_BACKEND_MESH) {
+        DDF_REQUIRE(scene->m >= 0 && (scene->m == 0 || scene->tris), DDF_ERR_INVALID_ARG, "ddf_render: bad mesh");
+        return DDF_OK;
+    }
+    if (scene->backend == DDF_BACKEND_NET) return check_net_for_render(scene->net, "ddf_render");
+    DDF_REQUIRE(scene->backend == DDF_BACKEND_MULTI, DDF_ERR_INVALID_ARG, "ddf_render: unknown backend %d", scene->backend);
+    DDF_REQUIRE(scene->n_nets >= 1 && scene->nets && scene->n_instances >= 1 && scene->instances &&
+                    scene->n_instances <= kMaxInstances,
+                DDF_ERR_INVALID_ARG, "ddf_render: a multi-object scene needs 1..%d instances and networks", kMaxInstances);
+    int per_width[2] = {0, 0};
+    for (int k = 0; k < scene->n_nets; ++k) {
+        if (ddf_status st = check_net_for_render(&scene->nets[k], "ddf_render (multi)")) return st;
+        DDF_REQUIRE(scene->nets[k].precision == scene->nets[0].precision, DDF_ERR_UNSUPPORTED,
+                    "ddf_render: all networks of a scene need the same precision");
+        ++per_width[scene->nets[k].width == 128 ? 0 : 1];
+    }
+    DDF_REQUIRE(per_width[0] <= kMaxNets && per_width[1] <= kMaxNets, DDF_ERR_UNSUPPORTED,
+                "ddf_render: at most %d networks of each width", kMaxNets);
+    for (int i = 0; i < scene->n_instances; ++i)
+        DDF_REQUIRE(scene->instances[i].net >= 0 && scene->instances[i].net < scene->n_nets, DDF_ERR_INVALID_ARG,
+                    "ddf_render: instance %d names network %d", i, scene->instances[i].net);
+    return DDF_OK;
+}
+
+// Networks ordered by width (128 first), instances ordered by network: every width group and
+// every network's (ray, instance) pairs are then contiguous.
+struct MultiPlan {
+    int n_nets = 0, n_inst = 0;
+    int order[2 * kMaxNets];          // reordered index -> caller's network index
+    int group_first[2] = {0, 0}, group_size[2] = {0, 0}, group_width[2] = {128, 256};
+    std::vector<InstDev> inst;
+};
+
+MultiPlan make_plan(const ddf_scene *scene) {
+    MultiPlan mp;
+    mp.n_nets = scene->n_nets;
+    mp.n_inst = scene->n_instances;
+    int pos[2 * kMaxNets];
+    int k2 = 0;
+    for (int g = 0; g < 2; ++g) {
+        mp.group_first[g] = k2;
+        for (int k = 0; k < scene->n_nets; ++k)
+            if (scene->nets[k].width == mp.group_width[g]) {
+                pos[k] = k2;
+                mp.order[k2++] = k;
+            }
+        mp.group_size[g] = k2 - mp.group_first[g];
+    }
+    std::vector<int> idx(scene->n_instances);
+    for (int i = 0; i < scene->n_instances; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return pos[scene->instances[a].net] < pos[scene->instances[b].net]; });
+    for (int i : idx) {
+        InstDev d{};
+        for (int j = 0; j < 9; ++j) d.R[j] = scene->instances[i].R[j];
+        for (int j = 0; j < 3; ++j) d.T[j] = scene->instances[i].T[j];
+        d.net = pos[scene->instances[i].net];
+        mp.inst.push_back(d);
+    }
+    return mp;
+}
+
+// Nearest hit (main) or occlusion (shadow) of a queue of world rays against every instance.
+ddf_status multi_query(const ddf_scene *scene, const MultiPlan &mp, RenderWs &w, int64_t C, const int *queue,
+                       const int *count, const float *po, const float *pd, bool shadow, uint32_t *net_stats,
+                       const float *stmax, hipStream_t s) {
+    const unsigned gC = grid_for(C), gP = grid_for(w.P);
+    NetMap map{};
+    for (int k = 0; k < mp.n_nets; ++k) map.user[k] = mp.order[k];
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(kMaxInstances), 0, s, w.mc.inst_count, kMaxInstances);
+    hipLaunchKernelGGL(cull_kernel<false>, dim3(gC), dim3(256), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);
+    hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(64), 0, s, mp.n_inst, w.inst, mp.n_nets, w.mc, net_stats, map);
+    hipLaunchKernelGGL(cull_kernel<true>, dim3(gC), dim3(256), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);
+    if (ddf_status st = launch_status("ddf_render_wavefront (instance culling)")) return st;
+    for (int g = 0; g < 2; ++g) {
+        if (mp.group_size[g] == 0) continue;
+        GradArgs a{};
+        a.rays = w.pb.rays5;
+        a.n = w.P;
+        a.g_dist_in = w.pb.ones;
+        a.logit_out = w.pb.logit;
+        a.dist_out = w.pb.dist;
+        a.g_rays = shadow ? nullptr : w.pb.grad;
+        a.forward_only = shadow;
+        a.n_nets = mp.group_size[g];
+        a.depth = 1;
+        for (int j = 0; j < mp.group_size[g]; ++j) {
+            const ddf_net &net = scene->nets[mp.order[mp.group_first[g] + j]];
+            a.blobs[j] = (const uint8_t *)net.packed;
+            a.depths[j] = net.depth;
+            a.depth = std::max(a.depth, net.depth);
+        }
+        a.blob = a.blobs[0];
+        a.seg_offset = w.mc.seg_offset + mp.group_first[g];
+        a.seg_count = w.mc.seg_count + mp.group_first[g];
+        if (ddf_status st = grad_dispatch_multi(mp.group_width[g], scene->nets[0].precision, a, s)) return st;
+    }
+    if (!shadow) {
+        hipLaunchKernelGGL(init_best_kernel, dim3(gC), dim3(256), 0, s, count, w.best, (int *)nullptr);
+        hipLaunchKernelGGL(merge_kernel, dim3(gP), dim3(256), 0, s, w.mc.total, w.pb, w.best);
+        hipLaunchKernelGGL(select_kernel, dim3(gP), dim3(256), 0, s, C, w.mc.total, w.pb, w.P, w.inst, w.best, w.hit_t,
+                           w.hit_g);
+    } else {
+        hipLaunchKernelGGL(init_best_kernel, dim3(gC), dim3(256), 0, s, count, (unsigned long long *)nullptr, w.occl);
+        hipLaunchKernelGGL(occlude_kernel, dim3(gP), dim3(256), 0, s, w.mc.total, w.pb, stmax, w.occl);
+    }
+    return launch_status("ddf_render_wavefront (multi-object query)");
+}
 
 }  // namespace
 }  // namespace ddf
 
 using namespace ddf;
 
-extern "C" ddf_status ddf_render_workspace_size(const ddf_render_params *p, size_t *bytes) {
+extern "C" ddf_status ddf_render_workspace_size(const ddf_scene *scene, const ddf_render_params *p, size_t *bytes) {
     DDF_REQUIRE(p && bytes, DDF_ERR_INVALID_ARG, "ddf_render_workspace_size: NULL argument");
     DDF_REQUIRE(p->width > 0 && p->height > 0 && p->spp > 0 && p->bounces > 0 && p->bounces <= 64, DDF_ERR_INVALID_ARG,
                 "ddf_render_workspace_size: bad image size, spp or bounces");
-    const int64_t C = (int64_t)p->width * p->height * chunk_spp(*p);
-    DDF_REQUIRE(C < ((int64_t)1 << 31), DDF_ERR_UNSUPPORTED, "ddf_render_workspace_size: sample chunk too large");
-    *bytes = render_ws(C, p->bounces, nullptr).bytes;
+    const int n_inst = scene_instances(scene);
+    DDF_REQUIRE(n_inst <= kMaxInstances, DDF_ERR_UNSUPPORTED, "ddf_render_workspace_size: too many instances");
+    const int64_t C = (int64_t)p->width * p->height * chunk_spp(*p, n_inst);
+    DDF_REQUIRE(C * std::max(1, n_inst) < ((int64_t)1 << 31), DDF_ERR_UNSUPPORTED,
+                "ddf_render_workspace_size: sample chunk too large");
+    *bytes = render_ws(C, p->bounces, n_inst, nullptr).bytes;
     return DDF_OK;
 }
 
@@ -456,31 +768,34 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
                                            ddf_stream stream) {
     DDF_REQUIRE(scene && p && radiance, DDF_ERR_INVALID_ARG, "ddf_render_wavefront: NULL argument");
     size_t need = 0;
-    if (ddf_status st = ddf_render_workspace_size(p, &need)) return st;
+    if (ddf_status st = ddf_render_workspace_size(scene, p, &need)) return st;
     DDF_REQUIRE(ws && ws_bytes >= need, DDF_ERR_WORKSPACE, "ddf_render_wavefront: workspace of %zu bytes needed", need);
-    DDF_REQUIRE(scene->backend == DDF_BACKEND_MESH || scene->backend == DDF_BACKEND_NET, DDF_ERR_INVALID_ARG,
-                "ddf_render_wavefront: unknown backend %d", scene->backend);
-    if (scene->backend == DDF_BACKEND_MESH) {
-        DDF_REQUIRE(scene->m >= 0 && (scene->m == 0 || scene->tris), DDF_ERR_INVALID_ARG, "ddf_render_wavefront: bad mesh");
-    } else {
-        const ddf_net *net = scene->net;
-        DDF_REQUIRE(net && net->packed, DDF_ERR_INVALID_ARG, "ddf_render_wavefront: NULL network");
-        DDF_REQUIRE(net->precision == DDF_PREC_FP32 || net->precision == DDF_PREC_BF16, DDF_ERR_UNSUPPORTED,
-                    "ddf_render_wavefront: the network backend needs a float32 or bfloat16 network (normals)");
-        DDF_REQUIRE((net->width == 128 || net->width == 256) && net->depth >= 1 && net->depth <= 8, DDF_ERR_UNSUPPORTED,
-                    "ddf_render_wavefront: unsupported network shape");
-    }
+    if (ddf_status st = check_scene(scene)) return st;
     DDF_REQUIRE(p->rr_start >= 0 && p->eps >= 0.f && p->vfov_deg > 0.f && p->vfov_deg < 180.f, DDF_ERR_INVALID_ARG,
                 "ddf_render_wavefront: bad rr_start, eps or field of view");
     hipStream_t s = as_stream(stream);
-    const int S = chunk_spp(*p);
+    const int n_inst = scene_instances(scene);
+    const bool multi = n_inst > 0;
+    const int S = chunk_spp(*p, n_inst);
     const int64_t hw = (int64_t)p->width * p->height;
     const int64_t C = hw * S;
-    RenderWs w = render_ws(C, p->bounces, ws);
+    RenderWs w = render_ws(C, p->bounces, n_inst, ws);
     const Cam cam = make_cam(*p);
     const int ncounts = 2 * p->bounces + 4;
+    MultiPlan mp;
+    if (multi) {
+        mp = make_plan(scene);
+        for (int first = 0; first < n_inst; first += kInstChunk) {
+            InstChunk c{};
+            const int cnt = std::min(kInstChunk, n_inst - first);
+            for (int j = 0; j < cnt; ++j) c.v[j] = mp.inst[first + j];
+            hipLaunchKernelGGL(inst_table_kernel, dim3(1), dim3(kInstChunk), 0, s, c, first, cnt, w.inst);
+        }
+        hipLaunchKernelGGL(fill_kernel, dim3(grid_for(w.P)), dim3(256), 0, s, w.pb.ones, w.P, 1.0f);
+    }
     hipLaunchKernelGGL(fill_kernel, dim3(grid_for(3 * hw)), dim3(256), 0, s, radiance, 3 * hw, 0.f);
-    if (stats) hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, (float *)stats, (int64_t)p->bounces, 0.f);
+    const int64_t nstats = (int64_t)p->bounces * (multi ? 1 + scene->n_nets : 1);
+    if (stats) hipLaunchKernelGGL(fill_kernel, dim3(grid_for(nstats)), dim3(256), 0, s, (float *)stats, nstats, 0.f);
     for (int base = 0; base < p->spp; base += S) {
         const int Sc = std::min(S, p->spp - base);
         const int64_t Cc = hw * Sc;
@@ -491,6 +806,7 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
         int *q = w.qa, *qn = w.qb;
         for (int b = 0; b < p->bounces; ++b) {
             const int *cnt = w.counts + 2 * b;
+            const float *qdist = w.dist, *qgrad = w.grad;
             if (scene->backend == DDF_BACKEND_NET) {
                 hipLaunchKernelGGL(prep_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, Cc, q, cnt, ps, w.rays5, w.t0);
                 GradArgs a{};
@@ -504,24 +820,35 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
                 a.dist_out = w.dist;
                 a.g_rays = w.grad;
                 if (ddf_status st = grad_dispatch(scene->net, a, false, s)) return st;
+            } else if (multi) {
+                if (ddf_status st = multi_query(scene, mp, w, Cc, q, cnt, ps.o, ps.d, false,
+                                                stats ? stats + p->bounces + (int64_t)b * scene->n_nets : nullptr,
+                                                nullptr, s))
+                    return st;
+                qdist = w.hit_t;
+                qgrad = w.hit_g;
             } else {
                 if (ddf_status st = label_queue(ps.o, ps.d, Cc, q, cnt, scene->tris, scene->m, 0.f, INFINITY, w.tq, w.triq, s))
                     return st;
             }
             hipLaunchKernelGGL(shade_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, *p, Cc, b, scene->backend, q, w.counts,
-                               qn, ps, w.t0, w.logit, w.dist, w.grad, w.tq, w.triq, scene->tris, scene->m, w.sq, w.srays,
-                               w.st0, w.stmax, w.scontrib, depth, normal);
+                               qn, ps, w.t0, w.logit, qdist, qgrad, w.tq, w.triq, scene->tris, scene->m, w.sq, w.srays,
+                               w.st0, w.stmax, w.scontrib, depth, normal, (const unsigned long long *)w.best);
             if (ddf_status st = launch_status("ddf_render_wavefront (shade)")) return st;
             const int *scnt = w.counts + 2 * b + 1;
             if (scene->backend == DDF_BACKEND_NET) {
                 if (ddf_status st = forward_dispatch(scene->net, w.srays, Cc, scnt, w.slogit, w.sdist, nullptr, s)) return st;
+            } else if (multi) {
+                if (ddf_status st = multi_query(scene, mp, w, Cc, nullptr, scnt, w.srays, w.srays + 3 * Cc, true, nullptr,
+                                                w.stmax, s))
+                    return st;
             } else {
                 if (ddf_status st = label_queue(w.srays, w.srays + 3 * Cc, Cc, nullptr, scnt, scene->tris, scene->m, 0.f,
                                                 INFINITY, w.st, w.stri, s))
                     return st;
             }
             hipLaunchKernelGGL(resolve_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, Cc, b, scene->backend, w.counts, w.sq,
-                               w.st0, w.stmax, w.scontrib, w.slogit, w.sdist, w.st, ps.L);
+                               w.st0, w.stmax, w.scontrib, w.slogit, w.sdist, w.st, (const int *)w.occl, ps.L);
             std::swap(q, qn);
         }
         hipLaunchKernelGGL(accumulate_kernel, dim3(grid_for(hw)), dim3(256), 0, s, hw, Sc, Cc, ps.L, radiance);

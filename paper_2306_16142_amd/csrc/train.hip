@@ -16,29 +16,11 @@
 #include "common.hpp"
 #include "mlp_device.hpp"
 #include "mlp_layout.hpp"
+#include "grad_args.hpp"
 
 namespace ddf {
 
-struct GradArgs {
-    const uint8_t *blob;
-    int depth;
-    const float *rays;
-    int64_t n;
-    const int *count_dev;
-    const float *g_logit_in;
-    const float *g_dist_in;
-    const float *t_label;
-    const float *loss_scalars;
-    float *logit_out;
-    float *dist_out;
-    float *g_rays;
-    float *ws_gamma;
-    float *ws_h;
-    float *ws_delta;
-    float *loss_partial;
-};
-ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, hipStream_t s);
-int64_t grad_grid(int width, int precision, int64_t n);
+
 
 namespace {
 

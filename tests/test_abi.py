@@ -83,11 +83,24 @@ def test_workspace_sizes(lib):
     assert b.value >= (65 + 2 * 6 * 256) * 65536 * 4
     p = _lib.DdfRenderParams()
     p.width, p.height, p.spp, p.bounces = 64, 64, 1, 3
-    assert lib.ddf_render_workspace_size(ctypes.byref(p), ctypes.byref(b)) == _lib.DDF_OK and b.value > 64 * 64 * 40
+    scene = _lib.DdfScene(_lib.BACKEND_MESH, 1, 3, None, 0, None, 0, None)
+    assert lib.ddf_render_workspace_size(ctypes.byref(scene), ctypes.byref(p), ctypes.byref(b)) == _lib.DDF_OK
+    assert b.value > 64 * 64 * 40
     p.bounces = 0
-    assert lib.ddf_render_workspace_size(ctypes.byref(p), ctypes.byref(b)) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_render_workspace_size(ctypes.byref(scene), ctypes.byref(p), ctypes.byref(b)) == _lib.DDF_ERR_INVALID_ARG
+    # a multi-object scene sizes its (ray, instance) pair buffers by the instance count
+    p.bounces = 3
+    nets = (_lib.DdfNet * 1)(_lib.DdfNet(128, 4, 1, 1))
+    inst = (_lib.DdfInstance * 4)(*[_lib.DdfInstance() for _ in range(4)])
+    multi = _lib.DdfScene(_lib.BACKEND_MULTI, None, 0, None, 1, nets, 4, inst)
+    b2 = ctypes.c_size_t(0)
+    assert lib.ddf_render_workspace_size(ctypes.byref(multi), ctypes.byref(p), ctypes.byref(b2)) == _lib.DDF_OK
+    assert b2.value > b.value + 4 * 64 * 64 * 60
+    # an instance naming a missing network is rejected before launching
+    inst[2].net = 3
+    assert lib.ddf_render_wavefront(ctypes.byref(multi), ctypes.byref(p), 1, None, None, None, 1, b2.value, None) == \
+        _lib.DDF_ERR_INVALID_ARG
     # a too-small workspace is rejected before launching
-    scene = _lib.DdfScene(_lib.BACKEND_MESH, 1, 3, None)
     p.bounces = 3
     assert lib.ddf_render_wavefront(ctypes.byref(scene), ctypes.byref(p), 1, None, None, None, 1, 16, None) == \
         _lib.DDF_ERR_WORKSPACE

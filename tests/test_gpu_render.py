@@ -110,3 +110,50 @@ def test_render_network_bf16_runs_and_is_reproducible():
     assert torch.isfinite(a).all() and (a >= 0).all()
     st = host(r.stats)
     assert st[0] == 48 * 32 * 4 and np.all(np.diff(st) <= 0)
+
+
+def _multi_setup(prec):
+    nets_p = [(_hitting_params(128, 2, 51), 128, 2), (_hitting_params(256, 2, 52), 256, 2), (_hitting_params(128, 3, 53), 128, 3)]
+    r = np.array([0.3, -0.1, 0.4, 0.85])
+    from synthetic.scenes import _rotation_from_quaternion as rot
+    inst = [{"R": rot(r / np.linalg.norm(r)), "T": np.array([-1.6, 0.4, 0.2]), "net": 0},
+            {"R": np.eye(3), "T": np.array([1.5, -0.3, -0.1]), "net": 1},
+            {"R": rot(np.array([0.0, 0.0, 0.6, 0.8])), "T": np.array([0.1, 1.8, 0.3]), "net": 2},
+            {"R": np.eye(3), "T": np.array([0.0, -1.5, -0.4]), "net": 0}]
+    nets = [api.Network(cuda(p), w, d, prec) for p, w, d in nets_p]
+    return nets_p, inst, nets
+
+
+def test_render_multi_object_fp32_matches_oracle():
+    from oracle import multi
+    banner("render multi-object fp32: 3 networks, 4 instances, 24x16 2spp, 1 and 3 bounces")
+    nets_p, inst, nets = _multi_setup("fp32")
+    for bounces in (1, 3):
+        cfg = synthetic.RenderConfig(24, 16, 2, bounces, 1, 5)
+        cfg.camera.eye = (0.0, -7.0, 1.5)
+        r = api.Renderer(cfg, nets=nets, instances=inst)
+        r.render()
+        torch.cuda.synchronize()
+        ref = render.render(multi.MultiScene(nets_p, inst, logit_margin=1e-3), cfg)
+        if bounces == 1:
+            _compare(r, ref, 1e-4)
+        else:
+            g, o = host(r.radiance), ref["radiance"]
+            assert abs(g.mean() - o.mean()) <= 5e-3 * o.mean()
+        paths, per_net = r.path_stats()
+        assert list(paths) == _stats(ref, bounces) or np.all(np.abs(paths - np.array(_stats(ref, bounces))) <= 4)
+        assert per_net.shape == (bounces, 3) and per_net[0].sum() > 0
+
+
+def test_render_multi_identity_instance_equals_single_network():
+    banner("render multi-object: one identity instance == single network (bf16)")
+    p = _hitting_params(128, 4, 54)
+    net = api.Network(cuda(p), 128, 4, "bf16")
+    cfg = synthetic.RenderConfig(32, 24, 2, 3, 1, 6)
+    a = api.Renderer(cfg, net=net)
+    a.render()
+    b = api.Renderer(cfg, nets=[net], instances=[{"R": np.eye(3), "T": np.zeros(3), "net": 0}])
+    b.render()
+    torch.cuda.synchronize()
+    torch.testing.assert_close(b.radiance, a.radiance, rtol=1e-5, atol=1e-6)
+    torch.testing.assert_close(b.depth, a.depth, rtol=1e-6, atol=1e-6)

@@ -121,3 +121,53 @@ def test_shadowed_quad_is_dark_under_occluder():
     assert np.all(out["radiance"][0][sel] == 0.0)
     lit = (~shadow & ~sees_occluder).reshape(32, 32) & out["robust"]
     assert np.all(out["radiance"][0][lit] > 0.0)
+
+
+def _hitting(width, depth, seed):
+    p = synthetic.random_params(width, depth, seed, bias_scale=0.3)
+    p[-2], p[-1] = 0.5, 1.0
+    return p
+
+
+def test_multi_single_identity_instance_equals_network_scene():
+    from oracle import multi
+    p = _hitting(32, 2, 3)
+    cfg = synthetic.RenderConfig(16, 12, 2, 3, 1, 4)
+    a = render.render(render.NetworkScene(p, 32, 2), cfg)
+    b = render.render(multi.MultiScene([(p, 32, 2)], [{"R": np.eye(3), "T": np.zeros(3), "net": 0}]), cfg)
+    ok = a["robust"] & b["robust"]
+    assert ok.mean() > 0.8
+    # the multi scene treats negative predicted distances as misses; compare where both agree
+    np.testing.assert_allclose(a["radiance"][:, ok], b["radiance"][:, ok], rtol=1e-12, atol=1e-15)
+
+
+def _moved_render(nets, inst, M, c, bounces):
+    from oracle import multi
+    cfg = synthetic.RenderConfig(20, 14, 1, bounces, 3, 2)
+    cfg.camera.eye = (0.0, -6.0, 1.0)
+    a = render.render(multi.MultiScene(nets, inst), cfg)
+    inst2 = [{"R": M @ d["R"], "T": M @ d["T"] + c, "net": d["net"]} for d in inst]
+    cfg2 = synthetic.RenderConfig(20, 14, 1, bounces, 3, 2)
+    cfg2.camera.eye = tuple(M @ np.array(cfg.camera.eye) + c)
+    cfg2.camera.target = tuple(M @ np.array(cfg.camera.target) + c)
+    cfg2.camera.up = tuple(M @ np.array(cfg.camera.up))
+    cfg2.light.position = tuple(M @ np.array(cfg.light.position) + c)
+    b = render.render(multi.MultiScene(nets, inst2), cfg2)
+    ok = a["robust"] & b["robust"]
+    assert ok.mean() > 0.8 and np.isfinite(a["depth"]).mean() > 0.1
+    np.testing.assert_allclose(a["radiance"][:, ok], b["radiance"][:, ok], rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(a["depth"][ok], b["depth"][ok], rtol=1e-9)
+
+
+def test_multi_rigid_motion_of_the_whole_scene_leaves_the_image_unchanged():
+    """Direct lighting is invariant under any rigid motion of scene + camera + light; with more
+    bounces only under translations (the scatter basis of Duff et al. is tied to world z)."""
+    nets = [(_hitting(32, 2, 5), 32, 2), (_hitting(32, 3, 6), 32, 3)]
+    r0 = np.array([0.1, 0.3, -0.2, 0.9])
+    inst = [{"R": synthetic.scenes._rotation_from_quaternion(r0 / np.linalg.norm(r0)), "T": np.array([-1.2, 0.3, 0.1]),
+             "net": 0},
+            {"R": np.eye(3), "T": np.array([1.3, -0.2, 0.0]), "net": 1}]
+    q = np.array([0.2, -0.4, 0.3, 0.8])
+    M = synthetic.scenes._rotation_from_quaternion(q / np.linalg.norm(q))
+    _moved_render(nets, inst, M, np.array([0.5, -1.0, 2.0]), 1)
+    _moved_render(nets, inst, np.eye(3), np.array([0.5, -1.0, 2.0]), 3)
