@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--render-spp", type=int, default=64)
+    ap.add_argument("--multi-spp", type=int, default=16)
+    ap.add_argument("--multi-train-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -182,6 +184,55 @@ def bench_label_train_render(args, torch, api, dev):
     return out
 
 
+def bench_multi(args, torch, api, dev):
+    """Multi-object scene: 8 procedural objects (seeds 2-9), each with its own network (width
+    128 or 256, depth 4-8, briefly trained on labeller output), 16 rigid instances, 1280 x 720,
+    16 spp, 3 bounces, bf16 queries."""
+    import synthetic
+    nets, shapes, tris_counts = [], [], []
+    for seed in range(2, 10):
+        v, f = synthetic.multi_object_mesh(seed)
+        tris_counts.append(int(f.shape[0]))
+        width, depth = synthetic.multi_object_network_shape(seed)
+        shapes.append((width, depth))
+        tris = torch.from_numpy(synthetic.tri_soup(v, f)).to(dev)
+        o, d, _ = synthetic.training_rays(v, f, 1 << 18, seed)
+        og, dg = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+        t, tri, cr = api.label_rays(og, dg, tris)
+        keep = (cr % 2) == 0
+        rays = api.assemble_rays(og, dg)[:, keep].contiguous()
+        t = t[keep].contiguous()
+        params = torch.from_numpy(synthetic.xavier_params(width, depth, seed)).to(dev)
+        batch = 32768
+        tr = api.Trainer(params, width, depth, batch)
+        nb = rays.shape[1] // batch
+        for i in range(args.multi_train_steps):
+            j = i % nb
+            tr.step(rays[:, j * batch:(j + 1) * batch].contiguous(), t[j * batch:(j + 1) * batch].contiguous())
+        nets.append(api.Network(params, width, depth, "bf16"))
+    inst = synthetic.instance_layout(16, 8, seed=10)
+    cfg = synthetic.multi_object_render(args.multi_spp)
+    r = api.Renderer(cfg, nets=nets, instances=inst)
+    r.render()
+    torch.cuda.synchronize()
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r.render()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    paths, per_net = r.path_stats()
+    per_net = per_net.astype(np.float64)
+    imb = [float(row.max() / row.mean()) if row.mean() > 0 else None for row in per_net]
+    return {"multi_object": {
+        "workload": "8 objects (seeds 2-9, %s triangles), 16 instances, 1280x720, %d spp, 3 bounces, bf16 networks "
+                    "(width, depth) = %s trained %d steps each" % (tris_counts, cfg.spp, shapes, args.multi_train_steps),
+        "seconds_per_frame": sec, "path_samples_per_s": cfg.width * cfg.height * cfg.spp / sec,
+        "paths_per_bounce": [int(x) for x in paths],
+        "pairs_per_network_per_bounce": per_net.astype(np.int64).tolist(),
+        "queue_imbalance_max_over_mean": imb}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -284,6 +335,7 @@ def main():
 
     if not args.quick:
         extra.update(bench_label_train_render(args, torch, api, dev))
+        extra.update(bench_multi(args, torch, api, dev))
     if not args.quick:
         # the float64 oracle on the host cores, bounded sample of the same query workload
         from oracle import mlp

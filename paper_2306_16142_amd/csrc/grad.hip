@@ -135,26 +135,12 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
         }
         // ---- forward (ReLU masks to LDS)
         for (int l = 0; l < depth; ++l) {
-            const int nkb = l == 0 ? K0 : NKB;
             const int64_t t0 = L.layer_tile(l);
             f32x16 acc[NMB][NB];
-#pragma unroll
-            for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
-#pragma unroll
-            for (int kb = 0; kb < NKB; ++kb) {
-                if (kb < nkb) {
-#pragma unroll
-                    for (int mb = 0; mb < NMB; ++mb) {
-                        const Op w = load_a<P>(blob, t0 + (int64_t)kb * NMB + mb, lane);
-#pragma unroll
-                        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(w, b[kb][nb], acc[mb][nb]);
-                    }
-                }
-            }
+            if (l == 0)
+                mfma_tiles<P, NMB, NB, K0, NKB>(blob, t0, b, acc, lane);
+            else
+                mfma_tiles<P, NMB, NB, NKB, NKB>(blob, t0, b, acc, lane);
             if constexpr (P == kBF16) {
                 if (l > 0) {   // bias K-block of a hidden layer
                     const Op one = bias_operand(h);
@@ -209,11 +195,11 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
 #pragma unroll
                 for (int j = 0; j < 16; ++j) acc[nb][j] = 0.f;
             const int64_t t0 = L.head_tile();
+            {
+                f32x16 hacc[1][NB];
+                mfma_tiles<P, 1, NB, NKB, NKB>(blob, t0, b, hacc, lane);
 #pragma unroll
-            for (int kb = 0; kb < NKB; ++kb) {
-                const Op w = load_a<P>(blob, t0 + kb, lane);
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(w, b[kb][nb], acc[nb]);
+                for (int nb = 0; nb < NB; ++nb) acc[nb] = hacc[0][nb];
             }
             float hb0 = bias_src[W * depth], hb1 = bias_src[W * depth + 1];
             if constexpr (P == kBF16) {
@@ -308,20 +294,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
                     tile_to_operands<P>(y, mb, nb, b);
                 }
             const int64_t t0 = L.grad_layer_tile(l);
-#pragma unroll
-            for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
-#pragma unroll
-            for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-                for (int mb = 0; mb < NMB; ++mb) {
-                    const Op w = load_a<P>(gsrc, t0 + (int64_t)kb * NMB + mb, lane);
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(w, b[kb][nb], acc[mb][nb]);
-                }
+            mfma_tiles<P, NMB, NB, NKB, NKB>(gsrc, t0, b, acc, lane);
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
@@ -343,20 +316,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
                 tile_to_operands<P>(y, mb, nb, b);
             }
         f32x16 acc0[kGradRowBlocks0][NB];
-#pragma unroll
-        for (int mb = 0; mb < kGradRowBlocks0; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                for (int j = 0; j < 16; ++j) acc0[mb][nb][j] = 0.f;
-#pragma unroll
-        for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-            for (int mb = 0; mb < kGradRowBlocks0; ++mb) {
-                const Op w = load_a<P>(gsrc, (int64_t)kb * kGradRowBlocks0 + mb, lane);
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc0[mb][nb] = mfma<P>(w, b[kb][nb], acc0[mb][nb]);
-            }
+        mfma_tiles<P, kGradRowBlocks0, NB, NKB, NKB>(gsrc, 0, b, acc0, lane);
         // ---- chain rule through the Fourier features
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {

@@ -309,28 +309,46 @@ __device__ __attribute__((always_inline)) inline void dense_relu(const uint8_t *
 }
 
 // Same layer with the products ordered K-block outermost and the operands updated in place
-// (fewer live registers; used for float32, whose MFMAs dominate anyway).
+// (fewer live registers: used for float32, for fp8, and whenever the weights are read from
+// the L2-resident blob).  A tiles stream through a ring of kRing registers loaded kRing
+// steps ahead, so global-memory latency hides behind the MFMAs.
 template <int P, int W, int NB, int KIN, bool kCalib>
 __device__ __attribute__((always_inline)) inline void dense_relu_inplace(
     const uint8_t *wsrc, int64_t t0, typename OpOf<P>::T (&b)[W / k_per_block(P)][NB], const float *bias, float alpha,
     int lane, int h, bool valid_any, unsigned int *amax_dst) {
     using Op = typename OpOf<P>::T;
     constexpr int NMB = W / 32;
+    constexpr bool kBias = P == kBF16 && KIN == W / k_per_block(P);   // bf16 hidden layers: bias K-block
+    constexpr int KS = KIN + (kBias ? 1 : 0);
+    constexpr int NSTEP = KS * NMB;
+    constexpr int kRing = P == kFP32 ? 8 : (P == kFP8 ? 2 : 4);   // fp8 tiles are 8 registers each
     f32x16 acc[NMB][NB];
+    Op ring[kRing];
 #pragma unroll
-    for (int kb = 0; kb < KIN; ++kb)
+    for (int i = 0; i < kRing; ++i) ring[i] = load_a<P>(wsrc, t0 + (i < NSTEP ? i : 0), lane);
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb) {
-            const Op a = load_a<P>(wsrc, t0 + (int64_t)kb * NMB + mb, lane);
+    for (int step = 0; step < NSTEP; ++step) {
+        const int kb = step / NMB, mb = step % NMB;   // tiles are stored K-block major: tile = kb * NMB + mb
+        const Op a = ring[step % kRing];
+        if (step + kRing < NSTEP) ring[step % kRing] = load_a<P>(wsrc, t0 + step + kRing, lane);
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(a, b[kb][nb], kb == 0 ? f32x16{} : acc[mb][nb]);
+        for (int nb = 0; nb < NB; ++nb) {
+            if constexpr (kBias) {
+                if (kb == KIN) {
+                    acc[mb][nb] = mfma<P>(a, bias_operand(h), acc[mb][nb]);
+                    continue;
+                }
+            }
+            acc[mb][nb] = mfma<P>(a, b[kb < KIN ? kb : 0][nb], kb == 0 ? f32x16{} : acc[mb][nb]);
         }
+    }
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) {
         float bv[16];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
+            const f32x4 b4 = P == kBF16 ? f32x4{0.f, 0.f, 0.f, 0.f}   // bf16: bias already accumulated
+                                        : *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
 #pragma unroll
             for (int i = 0; i < 4; ++i) bv[4 * g + i] = b4[i];
         }
@@ -507,7 +525,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
                 for (int kb = 0; kb < K0; ++kb) b0[kb][nb] = feat[kb];
             }
         }
-        if constexpr (P != kBF16) {
+        if constexpr (P != kBF16 || !kLdsA) {
             dense_relu_inplace<P, W, NB, K0, kCalib>(wsrc, L.layer_tile(0), b0, s_bias, s_c->alpha[0], lane, h,
                                                       valid_any, absmax + 3);
             for (int l = 1; l < depth; ++l)

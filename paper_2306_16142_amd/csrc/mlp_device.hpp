@@ -110,4 +110,26 @@ __device__ inline void tile_to_operands(const float *y, int mb, int nb, typename
     }
 }
 
+// acc[mb][nb] = sum over the KIN K-blocks of A tile (kb * NMB + mb) x b[kb][nb], with the A
+// tiles streamed through a ring loaded kRing steps ahead (tiles are stored K-block major).
+template <int P, int NMB, int NB, int KIN, int NKB>
+__device__ __attribute__((always_inline)) inline void mfma_tiles(const uint8_t *src, int64_t t0,
+                                                                 const typename OpOf<P>::T (&b)[NKB][NB],
+                                                                 f32x16 (&acc)[NMB][NB], int lane) {
+    using Op = typename OpOf<P>::T;
+    constexpr int NSTEP = KIN * NMB;
+    constexpr int kRing = P == kFP32 ? 8 : (P == kFP8 ? 2 : 4);   // fp8 tiles are 8 registers each
+    Op ring[kRing];
+#pragma unroll
+    for (int i = 0; i < kRing; ++i) ring[i] = load_a<P>(src, t0 + (i < NSTEP ? i : 0), lane);
+#pragma unroll
+    for (int step = 0; step < NSTEP; ++step) {
+        const int kb = step / NMB, mb = step % NMB;
+        const Op a = ring[step % kRing];
+        if (step + kRing < NSTEP) ring[step % kRing] = load_a<P>(src, t0 + step + kRing, lane);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma<P>(a, b[kb][nb], kb == 0 ? f32x16{} : acc[mb][nb]);
+    }
+}
+
 }  // namespace ddf

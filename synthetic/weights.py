@@ -43,3 +43,12 @@ def random_params(width, depth, seed, bias_scale=0.1, in_dim=IN_DIM, out_dim=OUT
         parts.append(rng.uniform(-a, a, size=(o, i)).ravel())
         parts.append(rng.uniform(-bias_scale, bias_scale, size=o))
     return np.concatenate(parts).astype(np.float32)
+
+
+def multi_object_network_shape(seed):
+    """Width in {128, 256} and depth in 4..8 of the network of one multi-object scene object,
+    drawn from ``default_rng(seed)`` (width first)."""
+    rng = np.random.default_rng(seed)
+    width = int(rng.choice([128, 256]))
+    depth = int(rng.integers(4, 9))
+    return width, depth
