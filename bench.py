@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--render-spp", type=int, default=64)
     ap.add_argument("--multi-spp", type=int, default=16)
+    ap.add_argument("--icosphere-train-steps", type=int, default=1500)
+    ap.add_argument("--render-train-steps", type=int, default=1500)
     ap.add_argument("--multi-train-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
@@ -96,6 +98,28 @@ def error_stats(logit, dist, ref_logit, ref_dist):
     e = np.abs(dist[hit_ref] - ref_dist[hit_ref])
     return {"hit_agreement_pct": round(agree, 4), "dist_abs_err_mean": float(e.mean()),
             "dist_abs_err_p99": float(np.quantile(e, 0.99)), "dist_abs_err_max": float(e.max())}
+
+
+def train_network(torch, api, dev, v, f, tris, width, depth, seed, steps, n_rays=1 << 20, batch=65536, lr=1e-3):
+    """Xavier init (seed), then `steps` Adam steps on labeller-labelled training rays of the mesh."""
+    import synthetic
+    params = torch.from_numpy(synthetic.xavier_params(width, depth, seed)).to(dev)
+    if steps == 0:
+        return params, {"steps": 0}
+    o, d, _ = synthetic.training_rays(v, f, n_rays, seed + 1)
+    og, dg = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+    t, tri, cr = api.label_rays(og, dg, tris)
+    keep = (cr % 2) == 0
+    rays = api.assemble_rays(og, dg)[:, keep].contiguous()
+    t = t[keep].contiguous()
+    tr = api.Trainer(params, width, depth, batch, lr=lr)
+    nb = rays.shape[1] // batch
+    batches = [(rays[:, i * batch:(i + 1) * batch].contiguous(), t[i * batch:(i + 1) * batch].contiguous()) for i in range(nb)]
+    first = float(tr.step(*batches[0]))
+    for i in range(1, steps):
+        tr.step(*batches[i % nb])
+    torch.cuda.synchronize()
+    return params, {"steps": steps, "loss_first": first, "loss_last": float(tr.loss)}
 
 
 def bench_label_train_render(args, torch, api, dev):
@@ -140,15 +164,15 @@ def bench_label_train_render(args, torch, api, dev):
     torch.cuda.synchronize()
     tms = (time.perf_counter() - t0) * 1e3 / args.train_steps
     losses.append(float(trainer.loss))
-    # keep training (untimed) so the rendered network has learned something
-    for i in range(200):
+    # keep training (untimed) so the rendered network has learned the object
+    for i in range(args.render_train_steps):
         trainer.step(*batches[i % nb])
     losses.append(float(trainer.loss))
     torch.cuda.synchronize()
     out["train"] = {"workload": "6x256 fp32, batch 65,536, Adam 1e-3, labels from the labeller (%d valid rays)" % nvalid,
                     "ms_per_step": tms, "steps_per_s": 1e3 / tms,
                     "loss_first_step": losses[0], "loss_after_%d_steps" % (3 + args.train_steps): losses[-2],
-                    "loss_after_%d_steps" % (203 + args.train_steps): losses[-1]}
+                    "loss_after_%d_steps" % (3 + args.train_steps + args.render_train_steps): losses[-1]}
     # render: 1920 x 1080, spp samples, 4 bounces, Russian roulette after bounce 2, bf16 queries
     cfg = synthetic.full_render(args.render_spp)
     net16 = api.Network(params, width, depth, "bf16")
@@ -176,7 +200,7 @@ def bench_label_train_render(args, torch, api, dev):
     ang = torch.rad2deg(torch.acos(cosang)).cpu().numpy()
     hit_agree = float((torch.isfinite(rm.depth) == torch.isfinite(rn.depth)).float().mean()) * 100
     out["render"] = {"workload": "1920x1080, %d spp, 4 bounces, RR after bounce 2, bf16 6x256 network "
-                                 "(trained %d steps)" % (cfg.spp, 203 + args.train_steps),
+                                 "(trained %d steps)" % (cfg.spp, 3 + args.train_steps + args.render_train_steps),
                      "seconds_per_frame": rs, "path_samples_per_s": paths / rs, "paths_per_bounce": stats,
                      "normal_angle_err_deg_mean": float(ang.mean()) if ang.size else None,
                      "normal_angle_err_deg_median": float(np.median(ang)) if ang.size else None,
@@ -253,10 +277,15 @@ def main():
         del src, dst
     n = 1 << args.n_log2
     o, d = synthetic.uniform_cube_rays(n, 3)
-    p = synthetic.xavier_params(W, D, 0)
     o_g = torch.from_numpy(o).to(dev)
     d_g = torch.from_numpy(d).to(dev)
-    p_g = torch.from_numpy(p).to(dev)
+    # the precision workload queries the 4 x 128 network trained on the icosphere (labels from
+    # the labeller, the training recipe of the 20k-triangle workload, fixed step count)
+    ico_v, ico_f = synthetic.icosphere(2, 0.8)
+    ico_tris = torch.from_numpy(synthetic.tri_soup(ico_v, ico_f)).to(dev)
+    p_g, train_info = train_network(torch, api, dev, ico_v, ico_f, ico_tris, W, D, seed=0,
+                                    steps=0 if args.quick else args.icosphere_train_steps)
+    p = p_g.cpu().numpy()
     rays = torch.empty((5, n), device=dev)
     logit = torch.empty(n, device=dev)
     dist = torch.empty(n, device=dev)
@@ -305,7 +334,18 @@ def main():
                 results["ref"] = mlp.forward(p, W, D, sub.astype(np.float64))
             rl, rd = results["ref"]
             results[prec]["error_vs_fp64"] = error_stats(logit[idx].cpu().numpy(), dist[idx].cpu().numpy(), rl, rd)
+            # against the mesh: brute-force labels of the same rays (the query starts at the ray origin)
+            if "mesh" not in results:
+                mt, mtri, mcr = api.label_rays(o_g[:, idx].contiguous(), d_g[:, idx].contiguous(), ico_tris)
+                results["mesh"] = (mt.cpu().numpy(), mtri.cpu().numpy(), mcr.cpu().numpy())
+            mt, mtri, mcr = results["mesh"]
+            lg, ds = logit[idx].cpu().numpy(), dist[idx].cpu().numpy()
+            ml, md = np.where(mtri >= 0, 1.0, -1.0), np.where(mtri >= 0, mt, 0.0)
+            out = mcr % 2 == 0   # origin outside the mesh (the training distribution)
+            results[prec]["error_vs_mesh"] = {"all_rays": error_stats(lg, ds, ml, md),
+                                              "outside_origins": error_stats(lg[out], ds[out], ml[out], md[out])}
     results.pop("ref", None)
+    results.pop("mesh", None)
 
     bf = results["bf16"]
     line = {
@@ -320,8 +360,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "bf16",
-        "data": "synthetic: seeded uniform rays; Xavier-initialised network (no trained weights)",
-        "config": {"workload": "precision query: 2^%d uniform rays, DDF MLP 65->128x4->2 (Fourier 6 freq)" % args.n_log2,
+        "data": "synthetic: seeded uniform rays; network trained in-run on the icosphere (%d steps)" % train_info["steps"],
+        "config": {"workload": "precision query: 2^%d uniform rays, DDF MLP 65->128x4->2 (Fourier 6 freq), "
+                               "trained on the 320-triangle icosphere" % args.n_log2,
                    "rays": n, "width": W, "depth": D, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": bf["forward_tflops"], "peak": PEAK["bf16"], "unit": "TFLOP/s",
                      "frac": bf["forward_tflops"] / PEAK["bf16"], "traffic": committed_traffic(),
@@ -331,6 +372,7 @@ def main():
                      "algorithmic_flop_per_query": flop_per_query(W, D)},
     }
     extra = {k: v for k, v in results.items() if k != "bf16"}
+    extra["icosphere_training"] = train_info
     extra["bf16"] = {k: v for k, v in bf.items() if k not in ("queries_per_s",)}
 
     if not args.quick:
