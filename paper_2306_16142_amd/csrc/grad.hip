@@ -165,6 +165,14 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
                 }
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
+                    if constexpr (P == kBF16 && !kTrain) {   // bias already accumulated; packed ReLU
+                        uint32_t bits = 0;
+#pragma unroll
+                        for (int j = 0; j < 16; ++j) bits |= (acc[mb][nb][j] > 0.f ? 1u : 0u) << j;
+                        wmask[((l * NMB + mb) * NB + nb) * 64 + lane] = (uint16_t)bits;
+                        relu_tile_to_bf16(acc[mb][nb], mb, nb, b);
+                        continue;
+                    }
                     float y[16];
                     uint32_t bits = 0;
 #pragma unroll

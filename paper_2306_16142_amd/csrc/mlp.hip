@@ -236,17 +236,14 @@ __device__ __attribute__((always_inline)) inline void dense_relu_bf16(const uint
         if (ks == KS - 1) {
             if (mb > 0) {
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    float y[16];
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) y[j] = fmaxf(prev[nb][j], 0.f);
-                    tile_to_operands<kBF16>(y, mb - 1, nb, bout);
-                }
-                // 24 VALU per ray block against KS * NB MFMAs of this block: interleave them
+                for (int nb = 0; nb < NB; ++nb) relu_tile_to_bf16(prev[nb], mb - 1, nb, bout);
+                // 16 VALU per ray block (8 packed conversions, 8 packed max) against KS * NB
+                // MFMAs of this block: one VALU after each MFMA, the rest after the chain
+                // (a denser interleave keeps more values live and spills)
 #pragma unroll
                 for (int i = 0; i < KS * NB; ++i) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-                    __builtin_amdgcn_sched_group_barrier(0x002, (24 * NB + KS * NB - 1) / (KS * NB), 0);   // VALU
+                    __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);   // VALU
                 }
             }
 #pragma unroll
@@ -254,12 +251,7 @@ __device__ __attribute__((always_inline)) inline void dense_relu_bf16(const uint
         }
     }
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        float y[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) y[j] = fmaxf(prev[nb][j], 0.f);
-        tile_to_operands<kBF16>(y, NMB - 1, nb, bout);
-    }
+    for (int nb = 0; nb < NB; ++nb) relu_tile_to_bf16(prev[nb], NMB - 1, nb, bout);
 }
 
 // One affine layer for a wave: KIN K-blocks of input operands `bin` -> the next layer's
@@ -354,6 +346,10 @@ __device__ __attribute__((always_inline)) inline void dense_relu_inplace(
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
+            if constexpr (P == kBF16 && !kCalib) {
+                relu_tile_to_bf16(acc[mb][nb], mb, nb, b);   // bias already accumulated
+                continue;
+            }
             float y[16];
 #pragma unroll
             for (int j = 0; j < 16; ++j) {

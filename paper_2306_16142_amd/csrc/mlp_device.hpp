@@ -91,6 +91,32 @@ __device__ inline bf16x8 bias_operand(int h) {
     return v;
 }
 
+// ReLU of two floats rounded to a packed bf16 pair.  Read as 16-bit integers, every bf16
+// with the sign bit set (-0 included) is negative and every other one non-negative, so a
+// signed integer max with 0 is the ReLU; rounding to bf16 keeps the sign, so ReLU after
+// rounding equals rounding after ReLU.  One packed conversion and one packed integer max
+// per two values.
+__device__ inline uint32_t relu_pk_bf16(float a, float b) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 v = __builtin_convertvector((f32x2){a, b}, bf16x2);   // round to nearest even
+    const s16x2 m = __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), (s16x2){0, 0});
+    return __builtin_bit_cast(uint32_t, m);
+}
+
+// ReLU of one accumulator tile (M-block mb) into the next product's bf16 B operands.
+template <int NKB, int NB>
+__device__ inline void relu_tile_to_bf16(const f32x16 &y, int mb, int nb, bf16x8 (&b)[NKB][NB]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        u32x4 w;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = relu_pk_bf16(y[8 * c + 2 * q], y[8 * c + 2 * q + 1]);
+        b[2 * mb + c][nb] = __builtin_bit_cast(bf16x8, w);
+    }
+}
+
 // Converts one accumulator tile (D layout: rows 8 g + 4 h + i of M-block mb, values y[16]) of
 // a layer's output into the next product's B operands (fp32 and bf16 only).
 template <int P, int NKB, int NB>
