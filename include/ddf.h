@@ -105,13 +105,17 @@ ddf_status ddf_packed_bytes(int32_t width, int32_t depth, int32_t precision, siz
 /* Packs the flat float32 parameters (device; per affine layer the weight
  * [out][in] row-major then the bias [out], the order of torch.nn.Linear) into the
  * MFMA-tile blob of `precision`.  For DDF_PREC_FP8, `scales` (device, [2*(depth+1)]:
- * weight scale and input scale per affine layer, each an absmax / 448) is required;
- * otherwise it must be NULL.  packed: device buffer of ddf_packed_bytes bytes. */
+ * weight scale and input scale per affine layer, each a positive power of two, as
+ * ddf_fp8_scales returns them) is required; otherwise it must be NULL.  A forward of
+ * an fp8 blob whose scales are not powers of two writes NaN.  packed: device buffer
+ * of ddf_packed_bytes bytes. */
 ddf_status ddf_pack_net(const float *params, int32_t width, int32_t depth, int32_t precision,
                         const float *scales, void *packed, ddf_stream stream);
 
-/* Static fp8 scales from a float32 network: per affine layer, weight absmax / 448
- * and the absmax of its input over the calibration rays / 448.  net_fp32 must be a
+/* Static fp8 scales from a float32 network: per affine layer, the smallest power of
+ * two s with absmax / s <= 448 for the weight and for its input over the calibration
+ * rays (power-of-two scales make every rescaling between layers exact, so the
+ * kernels apply it through the MFMA's operand scale).  net_fp32 must be a
  * DDF_PREC_FP32 blob of the same parameters.  calib [5][n_calib]; scales_out
  * device [2*(depth+1)]. */
 ddf_status ddf_fp8_scales(const ddf_net *net_fp32, const float *params, const float *calib,

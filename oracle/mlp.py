@@ -146,18 +146,37 @@ def forward_bf16(params, width, depth, rays):
     return h[0], h[1]
 
 
-def fp8_scales(params, width, depth, calib_rays):
-    """Per-layer static scales: weight absmax / 448 and layer-input absmax / 448.
+def pow2_scale(absmax):
+    """Smallest power of two s with absmax / s <= 448 (1 for an all-zero tensor).
 
-    The layer-input absmax is taken over the calibration rays with the float64
-    forward.  Returns an array ``[2 * (depth + 1)]``: (s_w, s_a) per layer.
+    A power-of-two scale makes every rescaling between layers exact: the ratio
+    s_w s_a / s_next is itself a power of two.
+    """
+    a = float(absmax)
+    if not a > 0.0:
+        return 1.0
+    e = int(np.ceil(np.log2(a / FP8_MAX)))
+    # the guess can be one off where a / 448 rounds; comparisons with 448 * 2^e are exact
+    while a > FP8_MAX * 2.0 ** e:
+        e += 1
+    while a <= FP8_MAX * 2.0 ** (e - 1):
+        e -= 1
+    return float(2.0 ** e)
+
+
+def fp8_scales(params, width, depth, calib_rays):
+    """Per-layer static power-of-two scales for the weight and for the layer input.
+
+    s_w covers the weight absmax and s_a the layer-input absmax over the
+    calibration rays (float64 forward), each as ``pow2_scale``.  Returns an
+    array ``[2 * (depth + 1)]``: (s_w, s_a) per layer.
     """
     layers = unpack(params, width, depth)
     _, _, acts, _ = forward(params, width, depth, calib_rays, return_acts=True)
     s = []
     for l, (W, _) in enumerate(layers):
-        s.append(np.abs(W).max() / FP8_MAX)
-        s.append(np.abs(acts[l]).max() / FP8_MAX)
+        s.append(pow2_scale(np.abs(W).max()))
+        s.append(pow2_scale(np.abs(acts[l]).max()))
     return np.array(s)
 
 

@@ -248,7 +248,7 @@ class Renderer:
 
 
 def fp8_scales(params, width, depth, calib_rays, net_fp32=None):
-    """Static per-layer fp8 scales (weight absmax / 448, input absmax over calib rays / 448)."""
+    """Static per-layer fp8 scales: powers of two covering the weight absmax and the input absmax over the calibration rays."""
     _dev(calib_rays, torch.float32, "calib_rays", 5)
     net_fp32 = net_fp32 or Network(params, width, depth, "fp32")
     out = torch.empty(2 * (depth + 1), device=params.device, dtype=torch.float32)

@@ -179,7 +179,132 @@ __device__ inline void wave_absmax(float v, unsigned int *dst) {
 struct LdsConsts {
     float in_scale_inv;   // fp8: 1 / s_a of layer 0
     float alpha[9];       // fp8: s_w s_a / s_a(next) per layer; head: s_w s_a
+    int aexp[9];          // fp8: alpha as an E8M0 exponent (127 + log2 alpha) for the MFMA scale
+    int bad;              // fp8: some scale is not a positive power of two (outputs are NaN)
 };
+
+// fp8 epilogue of one accumulator tile: ReLU and the e4m3 range in one med3, then packed
+// conversions (the conversion does not saturate, so the clamp must come first).
+template <int NKB, int NB>
+__device__ inline void fp8_tile_to_operands(const f32x16 &y, int mb, int nb, i32x8 (&b)[NKB][NB]) {
+#pragma unroll
+    for (int w4 = 0; w4 < 4; ++w4)
+        b[mb / 2][nb][4 * (mb % 2) + w4] = pack_fp8x4(
+            __builtin_amdgcn_fmed3f(y[4 * w4], 0.f, kFp8Max), __builtin_amdgcn_fmed3f(y[4 * w4 + 1], 0.f, kFp8Max),
+            __builtin_amdgcn_fmed3f(y[4 * w4 + 2], 0.f, kFp8Max), __builtin_amdgcn_fmed3f(y[4 * w4 + 3], 0.f, kFp8Max));
+}
+
+__device__ inline f32x16 mfma_fp8_scaled(i32x8 a, i32x8 b, f32x16 c, int aexp) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, aexp, 0, 127);
+}
+
+// Bias values of the 16 accumulator rows a lane holds in M-block mb (rows 8 g + 4 h + i).
+__device__ inline f32x16 bias_tile(const float *bias, int mb, int h) {
+    f32x16 v;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[4 * g + i] = b4[i];
+    }
+    return v;
+}
+
+// Scheduling groups of one step of dense_fp8 (constant arguments, hence the recursion).
+template <int STEP, int NSTEP, int KIN, int NMB, int NB, int kAhead>
+__device__ __attribute__((always_inline)) inline void fp8_schedule() {
+    if constexpr (STEP < NSTEP) {
+        constexpr int mb = STEP / KIN, ks = STEP % KIN;
+        constexpr int nds = (STEP + kAhead < NSTEP ? 2 : 0) + (ks == 0 && mb + 1 < NMB ? 4 : 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NB, 0);   // MFMA
+        if constexpr (nds > 0) __builtin_amdgcn_sched_group_barrier(0x100, nds, 0);   // LDS read
+        if constexpr (mb > 0) __builtin_amdgcn_sched_group_barrier(0x002, (24 * NB + KIN - 1) / KIN, 0);   // VALU
+        fp8_schedule<STEP + 1, NSTEP, KIN, NMB, NB, kAhead>();
+    }
+}
+
+// One fp8 affine layer with the weights in LDS, M-block outermost and software-pipelined
+// like the bf16 layer.  The first MFMA of an M-block starts from the bias (stored in the
+// next layer's activation units), the power-of-two rescale s_w s_a / s_next rides in the
+// MFMA's A-operand scale, and the epilogue (one med3 and half a packed conversion per
+// value) of block mb - 1 is interleaved with the MFMAs of block mb.
+template <int W, int NB, int KIN>
+__device__ __attribute__((always_inline)) inline void dense_fp8(const uint8_t *wsrc, int64_t t0,
+                                                                const i32x8 (&bin)[W / 64][NB],
+                                                                i32x8 (&bout)[W / 64][NB], const float *bias, int aexp,
+                                                                int lane, int h) {
+    constexpr int NMB = W / 32;
+    constexpr int NSTEP = NMB * KIN;
+    constexpr int kAhead = 2;
+    auto tile_of = [&](int step) { return t0 + (int64_t)(step % KIN) * NMB + step / KIN; };
+    __builtin_amdgcn_sched_barrier(0);   // nothing of this layer moves above its start
+    i32x8 ring[kAhead];
+#pragma unroll
+    for (int i = 0; i < kAhead; ++i) ring[i] = load_a<kFP8>(wsrc, tile_of(i < NSTEP ? i : 0), lane);
+    f32x16 acc[2][NB];   // M-blocks alternate between the two sets (no copies)
+    f32x16 bnext = bias_tile(bias, 0, h);
+#pragma unroll
+    for (int step = 0; step < NSTEP; ++step) {
+        const int mb = step / KIN, ks = step % KIN;
+        const i32x8 a = ring[step % kAhead];
+        if (step + kAhead < NSTEP) ring[step % kAhead] = load_a<kFP8>(wsrc, tile_of(step + kAhead), lane);
+        f32x16 bv;
+        if (ks == 0) {
+            bv = bnext;
+            if (mb + 1 < NMB) bnext = bias_tile(bias, mb + 1, h);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            acc[mb & 1][nb] = mfma_fp8_scaled(a, bin[ks][nb], ks == 0 ? bv : acc[mb & 1][nb], aexp);
+        if (ks == KIN - 1) {
+            if (mb > 0) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) fp8_tile_to_operands(acc[(mb - 1) & 1][nb], mb - 1, nb, bout);
+            }
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) fp8_tile_to_operands(acc[(NMB - 1) & 1][nb], NMB - 1, nb, bout);
+    // Schedule: the ring and the first bias tile, then per step its MFMAs, its LDS refills
+    // (A tile; the next M-block's bias at the first K-step) and a share of the previous
+    // block's epilogue (24 VALU per ray block).  Without it the compiler issues every LDS
+    // read of the layer first and runs out of registers.
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * kAhead + 4, 0);
+    fp8_schedule<0, NSTEP, KIN, NMB, NB, kAhead>();
+}
+
+// fp8 head with the weights in LDS: rows 0 (logit) and 1 (distance), bias as the start
+// value, the power-of-two s_w s_a in the MFMA scale.  Lanes of half 0 hold both rows; the
+// distance moves to half 1 so that every lane stores one value (no divergent branch near
+// the matrix ops).
+template <int W, int NB>
+__device__ __attribute__((always_inline)) inline void head_fp8(const uint8_t *wsrc, int64_t th,
+                                                               const i32x8 (&bin)[W / 64][NB], const float *bias,
+                                                               int aexp, bool bad, int lane, int h, int col,
+                                                               int64_t base, int64_t n, const bool (&nan_ray)[NB],
+                                                               float *logit_out, float *dist_out) {
+    __builtin_amdgcn_sched_barrier(0);
+    const f32x4 hb = *reinterpret_cast<const f32x4 *>(bias);   // logit, distance biases, 0, 0
+    const float keep = (float)(1 - h);
+    f32x16 c{};
+    c[0] = hb[0] * keep;
+    c[1] = hb[1] * keep;
+    f32x16 acc[NB];
+#pragma unroll
+    for (int kb = 0; kb < W / 64; ++kb) {
+        const i32x8 a = load_a<kFP8>(wsrc, th + kb, lane);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma_fp8_scaled(a, bin[kb][nb], kb == 0 ? c : acc[nb], aexp);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const float d = __shfl(acc[nb][1], col);
+        const float v = h ? d : acc[nb][0];
+        const int64_t r = base + nb * 32 + col;
+        float *dst = h ? dist_out : logit_out;
+        if (r < n) dst[r] = (nan_ray[nb] || bad) ? NAN : v;
+    }
+}
 
 // MFMAs of one 32-row M-block of a layer for NB ray blocks (bf16 adds the bias K-block).
 template <int P, int W, int NB, int KIN>
@@ -373,8 +498,8 @@ __device__ __attribute__((always_inline)) inline void dense_relu_inplace(
 template <int P, int W, int NB>
 __device__ __attribute__((always_inline)) inline void head_out(const uint8_t *wsrc, int64_t th,
                                                                const typename OpOf<P>::T (&bin)[W / k_per_block(P)][NB],
-                                                               const float *bias, float alpha, int lane, int h, int col,
-                                                               int64_t base, int64_t n, const bool (&nan_ray)[NB],
+                                                               const float *bias, float alpha, bool bad, int lane, int h,
+                                                               int col, int64_t base, int64_t n, const bool (&nan_ray)[NB],
                                                                float *logit_out, float *dist_out) {
     using Op = typename OpOf<P>::T;
     constexpr int NKB = W / k_per_block(P);
@@ -398,8 +523,8 @@ __device__ __attribute__((always_inline)) inline void head_out(const uint8_t *ws
         for (int nb = 0; nb < NB; ++nb) {
             const int64_t r = base + nb * 32 + col;
             if (r < n) {
-                logit_out[r] = nan_ray[nb] ? NAN : fmaf(acc[nb][0], alpha, c0);
-                dist_out[r] = nan_ray[nb] ? NAN : fmaf(acc[nb][1], alpha, c1);
+                logit_out[r] = (nan_ray[nb] || bad) ? NAN : fmaf(acc[nb][0], alpha, c0);
+                dist_out[r] = (nan_ray[nb] || bad) ? NAN : fmaf(acc[nb][1], alpha, c1);
             }
         }
     }
@@ -439,17 +564,30 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
             s_bias[i] = b;
         }
         if (threadIdx.x == 0) {
+            s_c->bad = 0;
             if (P == kFP8) {
                 const float s0 = g_scale[1];
                 s_c->in_scale_inv = s0 > 0.f ? 1.f / s0 : 0.f;
+                auto pow2 = [](float x) {
+                    int e;
+                    return x > 0.f && x < INFINITY && frexpf(x, &e) == 0.5f;
+                };
                 for (int l = 0; l <= depth; ++l) {
                     const float sw = g_scale[2 * l], sa = g_scale[2 * l + 1];
                     const float sn = l < depth ? g_scale[2 * (l + 1) + 1] : 1.f;
-                    s_c->alpha[l] = sn > 0.f ? sw * sa / sn : 0.f;
+                    const float alpha = sn > 0.f ? sw * sa / sn : 0.f;
+                    s_c->alpha[l] = alpha;
+                    int e = 0;
+                    frexpf(alpha, &e);
+                    s_c->aexp[l] = 127 + e - 1;
+                    if (!pow2(sw) || !pow2(sa) || !pow2(sn) || !pow2(alpha) || e - 1 < -126 || e - 1 > 127) s_c->bad = 1;
                 }
             } else {
                 s_c->in_scale_inv = 1.f;
-                for (int l = 0; l <= depth; ++l) s_c->alpha[l] = 1.f;
+                for (int l = 0; l <= depth; ++l) {
+                    s_c->alpha[l] = 1.f;
+                    s_c->aexp[l] = 127;
+                }
             }
         }
     }
@@ -521,6 +659,25 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
                 for (int kb = 0; kb < K0; ++kb) b0[kb][nb] = feat[kb];
             }
         }
+        if constexpr (P == kFP8 && kLdsA && !kCalib) {
+            static_assert(K0 == NKB, "fp8 layer 0 and hidden layers share the operand shape");
+            const bool bad = s_c->bad != 0;
+            dense_fp8<W, NB, K0>(wsrc, L.layer_tile(0), b0, b1, s_bias, s_c->aexp[0], lane, h);
+            int l = 1;
+            for (; l + 1 < depth; l += 2) {
+                dense_fp8<W, NB, NKB>(wsrc, L.layer_tile(l), b1, b0, s_bias + l * W, s_c->aexp[l], lane, h);
+                dense_fp8<W, NB, NKB>(wsrc, L.layer_tile(l + 1), b0, b1, s_bias + (l + 1) * W, s_c->aexp[l + 1], lane, h);
+            }
+            if (l < depth) {
+                dense_fp8<W, NB, NKB>(wsrc, L.layer_tile(l), b1, b0, s_bias + l * W, s_c->aexp[l], lane, h);
+                head_fp8<W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->aexp[depth], bad, lane, h, col, base,
+                                n, nan_ray, logit_out, dist_out);
+            } else {
+                head_fp8<W, NB>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->aexp[depth], bad, lane, h, col, base,
+                                n, nan_ray, logit_out, dist_out);
+            }
+            continue;
+        }
         if constexpr (P != kBF16 || !kLdsA) {
             dense_relu_inplace<P, W, NB, K0, kCalib>(wsrc, L.layer_tile(0), b0, s_bias, s_c->alpha[0], lane, h,
                                                       valid_any, absmax + 3);
@@ -528,7 +685,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
                 dense_relu_inplace<P, W, NB, NKB, kCalib>(wsrc, L.layer_tile(l), b0, s_bias + l * W, s_c->alpha[l], lane,
                                                            h, valid_any, absmax + 2 * (l + 1) + 1);
             if constexpr (!kCalib)
-                head_out<P, W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], lane, h, col, base, n,
+                head_out<P, W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
                                    nan_ray, logit_out, dist_out);
             continue;
         }
@@ -549,16 +706,29 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
         if constexpr (kCalib) continue;
         // ---- head: rows 0 (logit) and 1 (distance) of one 32-row block
         if (last_in_b0)
-            head_out<P, W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], lane, h, col, base, n,
+            head_out<P, W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
                                nan_ray, logit_out, dist_out);
         else
-            head_out<P, W, NB>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->alpha[depth], lane, h, col, base, n,
+            head_out<P, W, NB>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
                                nan_ray, logit_out, dist_out);
     }
 }
 
-// Weight absmax per affine layer (one block per layer) -> scales[2 l] = absmax / 448;
-// input absmax bits (written by the calibration forward) -> scales[2 l + 1] = absmax / 448.
+// Smallest power of two s with a / s <= 448 (1 for a = 0; a non-finite absmax is passed
+// through, which the forward kernels reject).
+__device__ inline float pow2_scale(float a) {
+    if (!(a > 0.f)) return 1.f;
+    if (!(a < INFINITY)) return a;
+    int e;
+    frexpf(a / kFp8Max, &e);
+    float s = ldexpf(1.f, e);
+    while (a > kFp8Max * s) s *= 2.f;   // a / 448 may have rounded: compare exactly
+    while (a <= kFp8Max * 0.5f * s) s *= 0.5f;
+    return s;
+}
+
+// Weight absmax per affine layer (one block per layer) -> scales[2 l]; input absmax bits
+// (written by the calibration forward) -> scales[2 l + 1]; each as pow2_scale.
 __global__ void weight_absmax_kernel(const float *__restrict__ params, int width, int depth, float *scales) {
     const int l = blockIdx.x;
     int64_t off = 0;
@@ -579,9 +749,9 @@ __global__ void weight_absmax_kernel(const float *__restrict__ params, int width
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        scales[2 * l] = red[0] / kFp8Max;
+        scales[2 * l] = pow2_scale(red[0]);
         const float a = __uint_as_float(reinterpret_cast<unsigned int *>(scales)[2 * l + 1]);
-        scales[2 * l + 1] = a / kFp8Max;
+        scales[2 * l + 1] = pow2_scale(a);
     }
 }
 
@@ -658,10 +828,9 @@ ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, co
         if (net->precision == kBF16)
             return lds ? launch_forward<kBF16, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
                        : launch_forward<kBF16, 128, 2, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
-        // fp8 runs one 32-ray block per wave: the two-block variant spilled heavily and did not
-        // reproduce the emulation, so it is not used
+        // fp8 from L2 runs one 32-ray block per wave (two blocks spilled in that variant)
         if (net->precision == kFP8)
-            return lds ? launch_forward<kFP8, 128, 1, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
+            return lds ? launch_forward<kFP8, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
                        : launch_forward<kFP8, 128, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
         return launch_forward<kFP32, 128, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
     }

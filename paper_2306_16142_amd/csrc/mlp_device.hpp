@@ -68,7 +68,9 @@ __device__ inline typename OpOf<P>::T load_a(const uint8_t *src, int64_t tile, i
 
 // Packs 4 non-negative floats (already clamped to the e4m3 range) into one dword.
 __device__ inline int pack_fp8x4(float a, float b, float c, float d) {
-    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    // the first conversion writes the low half and keeps the high half of its third
+    // operand, which the second conversion overwrites: any register will do there
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, __builtin_bit_cast(int, a), false);
     return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
 }
 

@@ -123,3 +123,19 @@ def test_forward_edge_cases():
     lg, ds = host(lg), host(ds)
     assert np.isnan(lg[3]) and np.isnan(ds[3])
     assert np.all(np.isfinite(np.delete(lg, 3))) and np.all(np.isfinite(np.delete(ds, 3)))
+
+
+def test_fp8_scales_not_powers_of_two_give_nan():
+    """The fp8 kernels rescale through the MFMA's power-of-two operand scale: a blob packed with
+    other scales is rejected by writing NaN (both the LDS and the L2 kernel)."""
+    for width, depth in ((128, 4), (256, 3)):
+        banner("forward fp8 non-power-of-two scales: %dx%d" % (depth, width))
+        p = synthetic.random_params(width, depth, 15)
+        rays = _rays(257, 16)
+        good = mlp.fp8_scales(p, width, depth, _rays(4096, 4))
+        bad = good.copy()
+        bad[3] *= 1.5
+        out = api.Network(cuda(p), width, depth, "fp8", scales=cuda(bad))(cuda(rays))
+        assert np.all(np.isnan(host(out[0]))) and np.all(np.isnan(host(out[1])))
+        out = api.Network(cuda(p), width, depth, "fp8", scales=cuda(good))(cuda(rays))
+        assert np.all(np.isfinite(host(out[0]))) and np.all(np.isfinite(host(out[1])))

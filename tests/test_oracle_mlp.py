@@ -283,9 +283,10 @@ def test_normals_on_analytic_plane_field():
 
 
 def test_fp8_scales_closed_form():
-    """Per-layer scales are absmax / 448: weight absmax from the matrix, input absmax over the
-    calibration rays (layer 0: the Fourier features, whose largest magnitude here is the raw
-    azimuth; deeper layers: ReLU outputs of the one-hot chain)."""
+    """Per-layer scales are the smallest powers of two that map the absmax into [-448, 448]:
+    weight absmax from the matrix, input absmax over the calibration rays (layer 0: the
+    Fourier features, whose largest magnitude here is the raw azimuth; deeper layers: ReLU
+    outputs of the one-hot chain)."""
     width, depth = 8, 2
     layers = mlp.unpack(np.zeros(synthetic.param_count(width, depth)), width, depth)
     layers = [(W.copy(), b.copy()) for W, b in layers]
@@ -295,4 +296,23 @@ def test_fp8_scales_closed_form():
     layers[2][0][1, 2] = 4.0
     rays = np.array([[0.5, -0.25], [0, 0], [0, 0], [1.0, 2.0], [6.0, 3.0]], dtype=np.float64)
     s = mlp.fp8_scales(mlp.pack(layers), width, depth, rays)
-    np.testing.assert_allclose(s, np.array([3.0, 6.0, 0.5, 1.0, 4.0, 0.5]) / 448.0, rtol=1e-15)
+    # absmax values 3, 6, 0.5, 1, 4, 0.5: 3 / 2^-7 = 384, 6 / 2^-6 = 384, 0.5 / 2^-9 = 256,
+    # 1 / 2^-8 = 256, 4 / 2^-6 = 256
+    np.testing.assert_array_equal(s, 2.0 ** np.array([-7, -6, -9, -8, -6, -9]))
+
+
+def test_pow2_scale_edges():
+    """The scale is the smallest power of two with absmax / s <= 448: exact at 448 * 2^k, one
+    binade up just above it; zero tensors get 1."""
+    for k in (-12, -3, 0, 5):
+        a = 448.0 * 2.0 ** k
+        assert mlp.pow2_scale(a) == 2.0 ** k
+        assert mlp.pow2_scale(np.nextafter(a, np.inf)) == 2.0 ** (k + 1)
+        assert mlp.pow2_scale(np.nextafter(a, 0.0)) == 2.0 ** k
+        assert mlp.pow2_scale(a / 2 + 1e-9 * a) == 2.0 ** k
+    assert mlp.pow2_scale(0.0) == 1.0
+    rng = np.random.default_rng(11)
+    for a in rng.uniform(1e-6, 1e6, size=200):
+        s = mlp.pow2_scale(a)
+        assert np.log2(s) == np.round(np.log2(s))
+        assert 224.0 < a / s <= 448.0
