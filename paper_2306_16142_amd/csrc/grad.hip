@@ -402,16 +402,15 @@ ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, h
         if (w == 128) return p == kBF16 ? launch_grad<kBF16, 128, 2, true>(args, s, cap) : launch_grad<kFP32, 128, 1, true>(args, s, cap);
         return p == kBF16 ? launch_grad<kBF16, 256, 1, true>(args, s, cap) : launch_grad<kFP32, 256, 1, true>(args, s, cap);
     }
-    if (w == 128) return p == kBF16 ? launch_grad<kBF16, 128, 2, false>(args, s, cap) : launch_grad<kFP32, 128, 1, false>(args, s, cap);
-    return p == kBF16 ? launch_grad<kBF16, 256, 1, false>(args, s, cap) : launch_grad<kFP32, 256, 1, false>(args, s, cap);
+    if (p == kBF16) return stream_dispatch(w, args, s);   // weights streamed through LDS
+    return w == 128 ? launch_grad<kFP32, 128, 1, false>(args, s, cap) : launch_grad<kFP32, 256, 1, false>(args, s, cap);
 }
 
 ddf_status grad_dispatch_multi(int width, int precision, const GradArgs &args, hipStream_t s) {
     DDF_REQUIRE(args.n_nets >= 1 && args.n_nets <= kMaxNets, DDF_ERR_UNSUPPORTED, "too many networks in one launch");
     const int cap = cu_count_grad() * 2;
-    if (width == 128)
-        return precision == kBF16 ? launch_grad<kBF16, 128, 2, false>(args, s, cap) : launch_grad<kFP32, 128, 1, false>(args, s, cap);
-    return precision == kBF16 ? launch_grad<kBF16, 256, 1, false>(args, s, cap) : launch_grad<kFP32, 256, 1, false>(args, s, cap);
+    if (precision == kBF16) return stream_dispatch(width, args, s);
+    return width == 128 ? launch_grad<kFP32, 128, 1, false>(args, s, cap) : launch_grad<kFP32, 256, 1, false>(args, s, cap);
 }
 
 }  // namespace ddf

@@ -40,4 +40,10 @@ ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, h
 ddf_status grad_dispatch_multi(int width, int precision, const GradArgs &args, hipStream_t s);
 int64_t grad_grid(int width, int precision, int64_t n);
 
+// bf16 query / input gradient with the weights streamed through LDS (stream.hip): any depth
+// up to 8 at width 128 or 256; args.depth is the largest depth of the launch, and
+// args.forward_only selects the query alone.  LDS bytes it needs:
+size_t stream_lds_bytes(int width, int depth, int n_nets, bool grad);
+ddf_status stream_dispatch(int width, const GradArgs &args, hipStream_t s);
+
 }  // namespace ddf

@@ -16,6 +16,7 @@
 #include "common.hpp"
 #include "mlp_device.hpp"
 #include "mlp_layout.hpp"
+#include "grad_args.hpp"
 
 namespace ddf {
 namespace {
@@ -332,14 +333,19 @@ __device__ __attribute__((always_inline)) inline void mblock_mfma(const uint8_t 
 // One bf16 affine layer for a wave, software-pipelined: A tiles are loaded kAhead MFMA
 // steps ahead (so LDS latency hides behind the matrix core), and the MFMAs of M-block mb
 // are interleaved (scheduling barriers) with the ReLU/conversion of block mb - 1, so the
-// matrix core runs while the vector ALU converts.
-template <int W, int NB, int KIN>
+// matrix core runs while the vector ALU converts.  Hidden layers add the bias either as
+// the accumulator's start value (kCInit: float32 bias tile from LDS) or through the bias
+// K-block of the packed tiles; layer 0 reads it from two feature slots.
+template <int W, int NB, int KIN, bool kCInit>
 __device__ __attribute__((always_inline)) inline void dense_relu_bf16(const uint8_t *wsrc, int64_t t0,
                                                                       const bf16x8 (&bin)[W / 16][NB],
-                                                                      bf16x8 (&bout)[W / 16][NB], int lane, int h) {
+                                                                      bf16x8 (&bout)[W / 16][NB], const float *bias,
+                                                                      int lane, int h) {
     constexpr int NMB = W / 32;
-    constexpr bool kBias = KIN == W / 16;       // hidden layers carry the bias K-block
-    constexpr int KS = KIN + (kBias ? 1 : 0);   // MFMA steps per M-block
+    constexpr bool kHidden = KIN == W / 16;
+    constexpr bool kBiasBlock = kHidden && !kCInit;   // bias K-block MFMA
+    constexpr bool kBiasInit = kHidden && kCInit;     // bias as the accumulator start
+    constexpr int KS = KIN + (kBiasBlock ? 1 : 0);    // MFMA steps per M-block
     constexpr int NSTEP = NMB * KS;
     constexpr int kAhead = 3;
     const bf16x8 one = bias_operand(h);
@@ -347,21 +353,30 @@ __device__ __attribute__((always_inline)) inline void dense_relu_bf16(const uint
     bf16x8 ring[kAhead];
 #pragma unroll
     for (int i = 0; i < kAhead; ++i) ring[i] = load_a<kBF16>(wsrc, tile_of(i < NSTEP ? i : 0), lane);
-    f32x16 prev[NB], cur[NB];
+    f32x16 acc[2][NB];   // M-blocks alternate between the two sets
+    f32x16 bnext{};
+    if constexpr (kBiasInit) bnext = bias_tile(bias, 0, h);
 #pragma unroll
     for (int step = 0; step < NSTEP; ++step) {
         const int mb = step / KS, ks = step % KS;
         const bf16x8 a = ring[step % kAhead];
         if (step + kAhead < NSTEP) ring[step % kAhead] = load_a<kBF16>(wsrc, tile_of(step + kAhead), lane);
+        f32x16 c0{};
+        if constexpr (kBiasInit) {
+            if (ks == 0) {
+                c0 = bnext;
+                if (mb + 1 < NMB) bnext = bias_tile(bias, mb + 1, h);
+            }
+        }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const bf16x8 bop = (kBias && ks == KIN) ? one : bin[ks < KIN ? ks : 0][nb];
-            cur[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bop, ks == 0 ? f32x16{} : cur[nb], 0, 0, 0);
+            const bf16x8 bop = (kBiasBlock && ks == KIN) ? one : bin[ks < KIN ? ks : 0][nb];
+            acc[mb & 1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bop, ks == 0 ? c0 : acc[mb & 1][nb], 0, 0, 0);
         }
         if (ks == KS - 1) {
             if (mb > 0) {
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) relu_tile_to_bf16(prev[nb], mb - 1, nb, bout);
+                for (int nb = 0; nb < NB; ++nb) relu_tile_to_bf16(acc[(mb - 1) & 1][nb], mb - 1, nb, bout);
                 // 16 VALU per ray block (8 packed conversions, 8 packed max) against KS * NB
                 // MFMAs of this block: one VALU after each MFMA, the rest after the chain
                 // (a denser interleave keeps more values live and spills)
@@ -371,23 +386,21 @@ __device__ __attribute__((always_inline)) inline void dense_relu_bf16(const uint
                     __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);   // VALU
                 }
             }
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) prev[nb] = cur[nb];
         }
     }
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) relu_tile_to_bf16(prev[nb], NMB - 1, nb, bout);
+    for (int nb = 0; nb < NB; ++nb) relu_tile_to_bf16(acc[(NMB - 1) & 1][nb], NMB - 1, nb, bout);
 }
 
 // One affine layer for a wave: KIN K-blocks of input operands `bin` -> the next layer's
 // operands `bout` (ReLU; fp8: requantised).  M-blocks are processed one after another so
 // that the epilogue of block mb (VALU) can overlap the MFMAs of block mb + 1.
-template <int P, int W, int NB, int KIN, bool kCalib>
+template <int P, int W, int NB, int KIN, bool kCalib, bool kCInit>
 __device__ __attribute__((always_inline)) inline void dense_relu(const uint8_t *wsrc, int64_t t0, const typename OpOf<P>::T (&bin)[W / k_per_block(P)][NB],
                                   typename OpOf<P>::T (&bout)[W / k_per_block(P)][NB], const float *bias, float alpha,
                                   int lane, int h, bool valid_any, unsigned int *amax_dst) {
     if constexpr (P == kBF16 && !kCalib) {
-        dense_relu_bf16<W, NB, KIN>(wsrc, t0, bin, bout, lane, h);
+        dense_relu_bf16<W, NB, KIN, kCInit>(wsrc, t0, bin, bout, bias, lane, h);
         return;
     }
     constexpr int NMB = W / 32;
@@ -495,7 +508,7 @@ __device__ __attribute__((always_inline)) inline void dense_relu_inplace(
 }
 
 // Head: rows 0 (logit) and 1 (distance) of one 32-row MFMA block, written by lanes 0..31.
-template <int P, int W, int NB>
+template <int P, int W, int NB, bool kCInit = false>
 __device__ __attribute__((always_inline)) inline void head_out(const uint8_t *wsrc, int64_t th,
                                                                const typename OpOf<P>::T (&bin)[W / k_per_block(P)][NB],
                                                                const float *bias, float alpha, bool bad, int lane, int h,
@@ -503,15 +516,24 @@ __device__ __attribute__((always_inline)) inline void head_out(const uint8_t *ws
                                                                float *logit_out, float *dist_out) {
     using Op = typename OpOf<P>::T;
     constexpr int NKB = W / k_per_block(P);
+    f32x16 start{};
+    if constexpr (P == kBF16 && kCInit) {   // bias rows 0 and 1 as the start value (lane half 0)
+        const f32x4 hb = *reinterpret_cast<const f32x4 *>(bias);
+        const float keep = (float)(1 - h);
+        start[0] = hb[0] * keep;
+        start[1] = hb[1] * keep;
+    }
     f32x16 acc[NB];
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
         const Op a = load_a<P>(wsrc, th + kb, lane);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, bin[kb][nb], kb == 0 ? f32x16{} : acc[nb]);
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, bin[kb][nb], kb == 0 ? start : acc[nb]);
     }
     float c0 = bias[0], c1 = bias[1];
-    if constexpr (P == kBF16) {
+    if constexpr (P == kBF16 && kCInit) {
+        c0 = c1 = 0.f;
+    } else if constexpr (P == kBF16) {
         const Op a = load_a<P>(wsrc, th + NKB, lane);
         const Op one = bias_operand(h);
 #pragma unroll
@@ -541,6 +563,9 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
     constexpr int KB = k_per_block(P);
     constexpr int NKB = W / KB;
     constexpr int K0 = layer0_kblocks(P);
+    // bf16 with the weights in LDS starts each accumulation from the float32 bias (measured
+    // 3% faster than the bias K-block, and exact in the bias); the other paths use the block
+    constexpr bool kCInit = P == kBF16 && kLdsA;
     static_assert(K0 <= NKB, "layer-0 operands must fit the hidden operand array");
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
 
@@ -690,26 +715,26 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
             continue;
         }
         // ---- layer 0, then hidden layers two at a time (b1 -> b0 -> b1 ...)
-        dense_relu<P, W, NB, K0, kCalib>(wsrc, L.layer_tile(0), b0, b1, s_bias, s_c->alpha[0], lane, h, valid_any,
+        dense_relu<P, W, NB, K0, kCalib, kCInit>(wsrc, L.layer_tile(0), b0, b1, s_bias, s_c->alpha[0], lane, h, valid_any,
                                           absmax + 3);
         int l = 1;
         for (; l + 1 < depth; l += 2) {
-            dense_relu<P, W, NB, NKB, kCalib>(wsrc, L.layer_tile(l), b1, b0, s_bias + l * W, s_c->alpha[l], lane, h,
+            dense_relu<P, W, NB, NKB, kCalib, kCInit>(wsrc, L.layer_tile(l), b1, b0, s_bias + l * W, s_c->alpha[l], lane, h,
                                                valid_any, absmax + 2 * (l + 1) + 1);
-            dense_relu<P, W, NB, NKB, kCalib>(wsrc, L.layer_tile(l + 1), b0, b1, s_bias + (l + 1) * W,
+            dense_relu<P, W, NB, NKB, kCalib, kCInit>(wsrc, L.layer_tile(l + 1), b0, b1, s_bias + (l + 1) * W,
                                                s_c->alpha[l + 1], lane, h, valid_any, absmax + 2 * (l + 2) + 1);
         }
         const bool last_in_b0 = l < depth;   // one hidden layer left: it writes b0
         if (last_in_b0)
-            dense_relu<P, W, NB, NKB, kCalib>(wsrc, L.layer_tile(l), b1, b0, s_bias + l * W, s_c->alpha[l], lane, h,
+            dense_relu<P, W, NB, NKB, kCalib, kCInit>(wsrc, L.layer_tile(l), b1, b0, s_bias + l * W, s_c->alpha[l], lane, h,
                                                valid_any, absmax + 2 * (l + 1) + 1);
         if constexpr (kCalib) continue;
         // ---- head: rows 0 (logit) and 1 (distance) of one 32-row block
         if (last_in_b0)
-            head_out<P, W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
+            head_out<P, W, NB, kCInit>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
                                nan_ray, logit_out, dist_out);
         else
-            head_out<P, W, NB>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
+            head_out<P, W, NB, kCInit>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
                                nan_ray, logit_out, dist_out);
     }
 }
@@ -824,6 +849,19 @@ ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, co
         return !(e && e[0] == '0');
     }();
     const bool lds = allow_lds && fits_lds(L);
+    if (net->precision == kBF16 && !lds && !absmax) {
+        // weights too large for one CU's LDS: a workgroup streams them and its waves share them
+        GradArgs a{};
+        a.blob = (const uint8_t *)net->packed;
+        a.depth = net->depth;
+        a.rays = rays;
+        a.n = n;
+        a.count_dev = count_dev;
+        a.logit_out = logit;
+        a.dist_out = dist;
+        a.forward_only = true;
+        return stream_dispatch(net->width, a, s);
+    }
     if (net->width == 128) {
         if (net->precision == kBF16)
             return lds ? launch_forward<kBF16, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)

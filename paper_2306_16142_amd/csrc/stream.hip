@@ -1,0 +1,566 @@
+// Network query and input gradient (Sec. IV-A query, Eq. 3 normals) for bf16 networks whose
+// packed weights do not fit in one CU's LDS: width 256, or width 128 deeper than four layers.
+//
+// A workgroup evaluates 256 rays at a time and streams the weight tiles through a
+// three-stage LDS ring that all its waves read.  One "phase" is one 32-row M-block of one
+// layer (its K-blocks, plus the bias K-block of a hidden layer).  While the waves multiply
+// phase p, each wave fetches its share of phase p + 2 from L2 into registers and writes it
+// to LDS at the end of the phase; one barrier per phase publishes it.  Every wave reads each
+// weight tile from LDS, and the workgroup reads it from L2 once per 256 rays (the per-wave
+// kernel read it once per 32 or 64).
+//
+// Per wave everything else is as in the other network kernels: the Fourier encoding in
+// registers, layer outputs kept in the accumulators and converted into the next layer's B
+// operands (ReLU on packed bf16), ReLU masks in LDS (16 bits per lane and tile) for the
+// reverse sweep, the transposed tiles for the adjoints, and the chain rule through the
+// features in registers.
+#include <cmath>
+#include <mutex>
+
+#include "common.hpp"
+#include "grad_args.hpp"
+#include "mlp_device.hpp"
+#include "mlp_layout.hpp"
+
+namespace ddf {
+namespace {
+
+// Width 128: four waves of two 32-ray blocks, two workgroups per CU.  Width 256: eight waves
+// of one block (two ray blocks would need about 380 registers per lane).
+template <int W>
+struct Geo {
+    static constexpr int kWaves = W == 256 ? 8 : 4;
+    static constexpr int kNB = W == 256 ? 1 : 2;
+};
+constexpr int kRaysPerTile = 256;
+constexpr int kStages = 3;
+constexpr int kMaxStreamLds = 160 * 1024;
+constexpr int kMaxPhases = 8 * 8 + 1 + 7 * 8 + kGradRowBlocks0;   // width 256, depth 8, gradient
+
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+typedef __attribute__((address_space(1))) const uint8_t gbl_u8;
+
+template <int W>
+__host__ __device__ inline int phases_of(int depth, bool grad) {
+    constexpr int NMB = W / 32;
+    return NMB * depth + 1 + (grad ? (depth - 1) * NMB + kGradRowBlocks0 : 0);
+}
+
+// Phase q of a network's program -> (byte offset of its first tile in the blob, byte stride
+// between its tiles, number of tiles).  Order: layer 0 (NMB phases of 5 K-blocks), hidden
+// layers (NMB phases of NKB + 1 K-blocks, the last the bias block), the head (one phase of
+// NKB + 1), then for gradients the transposed hidden layers from the top (NMB phases of NKB)
+// and the transposed layer 0 (kGradRowBlocks0 phases of NKB).
+template <int W>
+__device__ inline void phase_entry(int depth, int q, int &off, int &stride, int &ks) {
+    constexpr int NMB = W / 32, NKB = W / 16;
+    const NetLayout L = make_layout(W, depth, kBF16);
+    const int tb = tile_bytes(kBF16);
+    if (q < NMB) {
+        off = (int)((L.layer_tile(0) + q) * tb);
+        ks = layer0_kblocks(kBF16);
+        stride = NMB * tb;
+        return;
+    }
+    q -= NMB;
+    if (q < (depth - 1) * NMB) {
+        off = (int)((L.layer_tile(1 + q / NMB) + q % NMB) * tb);
+        ks = NKB + 1;
+        stride = NMB * tb;
+        return;
+    }
+    q -= (depth - 1) * NMB;
+    if (q == 0) {
+        off = (int)(L.head_tile() * tb);
+        ks = NKB + 1;
+        stride = tb;
+        return;
+    }
+    q -= 1;
+    if (q < (depth - 1) * NMB) {
+        off = (int)(L.grad_off + (L.grad_layer_tile(depth - 1 - q / NMB) + q % NMB) * tb);
+        ks = NKB;
+        stride = NMB * tb;
+        return;
+    }
+    q -= (depth - 1) * NMB;
+    off = (int)(L.grad_off + (L.grad_layer_tile(0) + q) * tb);
+    ks = NKB;
+    stride = kGradRowBlocks0 * tb;
+}
+
+// Per-launch tables in LDS: for every network, its blob address, depth and phase program.
+struct NetTable {
+    uint64_t blob[kMaxNets];
+    int depth[kMaxNets];
+    int nphase[kMaxNets];
+    int ph[kMaxNets][kMaxPhases][3];   // offset, stride, tiles
+};
+
+// One wave's share of a phase in registers: tiles wave, wave + kWaves, ...  Each lane moves
+// 16 bytes of every tile, so one wave-wide load moves one whole 1 KiB tile.
+template <int W>
+struct Stage {
+    static constexpr int kMax = (W / 16 + 1 + Geo<W>::kWaves - 1) / Geo<W>::kWaves;
+    i32x4 v[kMax];
+    int cnt;   // wave-uniform
+};
+
+// The phase pipeline of a workgroup: the current tile's network and phase, the next tile's
+// network (-1: none), and the stage in use.
+struct Pipe {
+    int cur, q, nxt;
+    int stage;   // 0 .. kStages-1
+};
+
+template <int W>
+__device__ inline lds_u8 *stage_ptr(lds_u8 *ring, int st) {
+    return ring + st * (W / 16 + 1) * 1024;
+}
+
+// Fetches this wave's share of the phase `ahead` phases after the current one.
+template <int W>
+__device__ inline void stage_fetch(Stage<W> &sg, const NetTable *tab, const Pipe &pp, int ahead, int wave, int lane) {
+    int net = pp.cur, q = pp.q + ahead;
+    const int np = tab->nphase[net];
+    if (q >= np) {
+        q -= np;
+        net = pp.nxt;
+    }
+    const bool live = net >= 0 && q < tab->nphase[net >= 0 ? net : 0];
+    int off = 0, stride = 0, ks = 0;
+    uint64_t blob = 0;
+    if (live) {
+        off = tab->ph[net][q][0];
+        stride = tab->ph[net][q][1];
+        ks = tab->ph[net][q][2];
+        blob = tab->blob[net];
+    }
+    // the values are wave-uniform; say so, so that the branches below stay scalar
+    ks = __builtin_amdgcn_readfirstlane(ks);
+    stride = __builtin_amdgcn_readfirstlane(stride);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(blob + off));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((blob + off) >> 32));
+    gbl_u8 *g = (gbl_u8 *)(((uint64_t)hi << 32) | lo);
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < Stage<W>::kMax; ++j) {
+        const int i = wave + Geo<W>::kWaves * j;
+        if (i < ks) {
+            sg.v[j] = *reinterpret_cast<const __attribute__((address_space(1))) i32x4 *>(g + i * stride + lane * 16);
+            cnt = j + 1;
+        }
+    }
+    sg.cnt = cnt;
+}
+
+template <int W>
+__device__ inline void stage_commit(const Stage<W> &sg, lds_u8 *stage, int wave, int lane) {
+#pragma unroll
+    for (int j = 0; j < Stage<W>::kMax; ++j)
+        if (j < sg.cnt)
+            *reinterpret_cast<__attribute__((address_space(3))) i32x4 *>(stage + (wave + Geo<W>::kWaves * j) * 1024 +
+                                                                         lane * 16) = sg.v[j];
+}
+
+// End of a phase: publish the fetched share (two phases ahead) and advance.
+template <int W>
+__device__ inline void phase_end(const Stage<W> &sg, lds_u8 *ring, Pipe &pp, int wave, int lane) {
+    const int st2 = pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2;
+    stage_commit<W>(sg, stage_ptr<W>(ring, st2), wave, lane);
+    __syncthreads();
+    pp.stage = pp.stage == kStages - 1 ? 0 : pp.stage + 1;
+    ++pp.q;
+}
+
+__device__ inline bf16x8 lds_tile(const lds_u8 *stage, int i, int lane) {
+    return *reinterpret_cast<const __attribute__((address_space(3))) bf16x8 *>(stage + i * 1024 + lane * 16);
+}
+
+// One phase's MFMA chain: KS K-blocks from the stage (the last one the bias block when
+// kBias), A tiles two steps ahead, accumulators starting from zero.
+template <int W, int KS, bool kBias>
+__device__ __attribute__((always_inline)) inline void phase_mfma(const lds_u8 *st,
+                                                                 const bf16x8 (&bin)[W / 16][Geo<W>::kNB],
+                                                                 f32x16 (&acc)[Geo<W>::kNB], int lane, int h) {
+    constexpr int kNB = Geo<W>::kNB;
+    constexpr int KIN = KS - (kBias ? 1 : 0);
+    const bf16x8 one = bias_operand(h);
+    bf16x8 ring[2];
+    ring[0] = lds_tile(st, 0, lane);
+    ring[1] = lds_tile(st, KS > 1 ? 1 : 0, lane);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const bf16x8 a = ring[ks & 1];
+        if (ks + 2 < KS) ring[ks & 1] = lds_tile(st, ks + 2, lane);
+#pragma unroll
+        for (int nb = 0; nb < kNB; ++nb) {
+            const bf16x8 b = (kBias && ks == KIN) ? one : bin[ks < KIN ? ks : 0][nb];
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, ks == 0 ? f32x16{} : acc[nb], 0, 0, 0);
+        }
+    }
+}
+
+template <int W>
+__device__ inline void relu_mask_out(const f32x16 &y, int l, int mb, int nb, bf16x8 (&bout)[W / 16][Geo<W>::kNB],
+                                     uint16_t *wmask, int lane, bool grad) {
+    constexpr int NMB = W / 32, kNB = Geo<W>::kNB;
+    if (grad) {
+        uint32_t bits = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) bits |= (y[j] > 0.f ? 1u : 0u) << j;
+        wmask[((l * NMB + mb) * kNB + nb) * 64 + lane] = (uint16_t)bits;
+    }
+    relu_tile_to_bf16(y, mb, nb, bout);
+}
+
+// Forward layer l (all its M-blocks): bin -> bout with ReLU; masks to LDS for gradients.
+template <int W, int KIN, bool kGrad>
+__device__ __attribute__((always_inline)) inline void fwd_layer(lds_u8 *ring, const NetTable *tab, Pipe &pp, int l,
+                                                                const bf16x8 (&bin)[W / 16][Geo<W>::kNB],
+                                                                bf16x8 (&bout)[W / 16][Geo<W>::kNB], uint16_t *wmask,
+                                                                int wave, int lane, int h) {
+    constexpr int NMB = W / 32, NKB = W / 16, kNB = Geo<W>::kNB;
+    constexpr bool kBias = KIN == NKB;
+    f32x16 acc[2][kNB];
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb) {
+        Stage<W> sg;
+        stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+        phase_mfma<W, KIN + (kBias ? 1 : 0), kBias>(stage_ptr<W>(ring, pp.stage), bin, acc[mb & 1], lane, h);
+        if (mb > 0) {
+#pragma unroll
+            for (int nb = 0; nb < kNB; ++nb) relu_mask_out<W>(acc[(mb - 1) & 1][nb], l, mb - 1, nb, bout, wmask, lane, kGrad);
+        }
+        phase_end<W>(sg, ring, pp, wave, lane);
+    }
+#pragma unroll
+    for (int nb = 0; nb < kNB; ++nb) relu_mask_out<W>(acc[(NMB - 1) & 1][nb], l, NMB - 1, nb, bout, wmask, lane, kGrad);
+}
+
+// Masked adjoint tile -> bf16 B operands of the next transposed product.
+template <int W>
+__device__ inline void masked_tile_to_bf16(const f32x16 &y, uint32_t bits, int mb, int nb,
+                                           bf16x8 (&b)[W / 16][Geo<W>::kNB]) {
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = ((bits >> j) & 1u) ? y[j] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) b[2 * mb + c][nb][s] = (__bf16)v[8 * c + s];
+}
+
+// Transposed hidden layer l (rows: its inputs): adjoint operands of layer l's outputs ->
+// masked adjoint operands of layer l - 1's outputs.
+template <int W>
+__device__ __attribute__((always_inline)) inline void bwd_layer(lds_u8 *ring, const NetTable *tab, Pipe &pp, int l,
+                                                                const bf16x8 (&bin)[W / 16][Geo<W>::kNB],
+                                                                bf16x8 (&bout)[W / 16][Geo<W>::kNB],
+                                                                const uint16_t *wmask, int wave, int lane, int h) {
+    constexpr int NMB = W / 32, NKB = W / 16, kNB = Geo<W>::kNB;
+    f32x16 acc[2][kNB];
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb) {
+        Stage<W> sg;
+        stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+        phase_mfma<W, NKB, false>(stage_ptr<W>(ring, pp.stage), bin, acc[mb & 1], lane, h);
+        if (mb > 0) {
+#pragma unroll
+            for (int nb = 0; nb < kNB; ++nb)
+                masked_tile_to_bf16<W>(acc[(mb - 1) & 1][nb], wmask[(((l - 1) * NMB + mb - 1) * kNB + nb) * 64 + lane],
+                                       mb - 1, nb, bout);
+        }
+        phase_end<W>(sg, ring, pp, wave, lane);
+    }
+#pragma unroll
+    for (int nb = 0; nb < kNB; ++nb)
+        masked_tile_to_bf16<W>(acc[(NMB - 1) & 1][nb], wmask[(((l - 1) * NMB + NMB - 1) * kNB + nb) * 64 + lane],
+                               NMB - 1, nb, bout);
+}
+
+// Network and ray range of workgroup tile t (constant indices into the argument arrays: a
+// runtime index would copy them to scratch).
+struct TileWork {
+    int net;
+    int64_t base, end;   // rays [base, min(base + 256, end))
+};
+
+__device__ inline TileWork tile_work(const GradArgs &a, int64_t t, const int64_t (&pre)[kMaxNets + 1], int nk,
+                                     int64_t count) {
+    TileWork w;
+    const bool multi = a.n_nets > 0;
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxNets; ++i)
+        if (i < nk && t >= pre[i]) k = i;
+    int64_t lo = 0, cnt = count, pk = 0;
+    if (multi) {
+        lo = a.seg_offset[k];
+        cnt = a.seg_count[k];
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxNets; ++i)
+        if (i == k) pk = pre[i];
+    w.net = k;
+    w.end = lo + cnt;
+    w.base = lo + (t - pk) * kRaysPerTile;
+    return w;
+}
+
+template <int W, bool kGrad>
+__global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs a) {
+    constexpr int NMB = W / 32, NKB = W / 16, K0 = layer0_kblocks(kBF16);
+    constexpr int kWaves = Geo<W>::kWaves, kNB = Geo<W>::kNB;
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int h = lane >> 5, col = lane & 31;
+    const bool multi = a.n_nets > 0;
+    const int nk = multi ? a.n_nets : 1;
+    const int64_t n = a.n;
+    const int64_t count = a.count_dev ? min<int64_t>(*a.count_dev, n) : n;
+    const int dmax = a.depth;
+
+    // LDS: weight ring | network tables | ReLU masks [wave][depth][NMB][kNB][64] | head rows
+    lds_u8 *ring = (lds_u8 *)smem;
+    NetTable *tab = reinterpret_cast<NetTable *>(smem + kStages * (NKB + 1) * 1024);
+    uint16_t *s_mask = reinterpret_cast<uint16_t *>(tab + 1);
+    float *s_head = reinterpret_cast<float *>(s_mask + (kGrad ? kWaves * dmax * NMB * kNB * 64 : 0));
+    uint16_t *wmask = s_mask + wave * dmax * NMB * kNB * 64;
+#pragma unroll
+    for (int k = 0; k < kMaxNets; ++k) {
+        if (k >= nk) break;
+        const uint8_t *blob = multi ? a.blobs[k] : a.blob;
+        const int depth = multi ? a.depths[k] : a.depth;
+        const int np = phases_of<W>(depth, kGrad);
+        if (threadIdx.x == 0) {
+            tab->blob[k] = (uint64_t)blob;
+            tab->depth[k] = depth;
+            tab->nphase[k] = np;
+        }
+        for (int q = threadIdx.x; q < np; q += blockDim.x) {
+            int off, stride, ks;
+            phase_entry<W>(depth, q, off, stride, ks);
+            tab->ph[k][q][0] = off;
+            tab->ph[k][q][1] = stride;
+            tab->ph[k][q][2] = ks;
+        }
+        if constexpr (kGrad) {
+            const NetLayout L = make_layout(W, depth, kBF16);
+            const float *src = reinterpret_cast<const float *>(blob + L.head_rows_off);
+            for (int i = threadIdx.x; i < 2 * W; i += blockDim.x) s_head[k * 2 * W + i] = src[i];
+        }
+    }
+    __syncthreads();
+
+    int64_t pre[kMaxNets + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxNets; ++k) {
+        const int64_t cnt = k < nk ? (multi ? (int64_t)a.seg_count[k] : count) : 0;
+        pre[k + 1] = pre[k] + (cnt + kRaysPerTile - 1) / kRaysPerTile;
+    }
+    const int64_t ntile = pre[kMaxNets];
+    int64_t t = blockIdx.x;
+    if (t >= ntile) return;   // the whole workgroup: no barrier is left half-reached
+
+    Pipe pp;
+    TileWork cw = tile_work(a, t, pre, nk, count);
+    pp.cur = cw.net;
+    pp.q = 0;
+    pp.nxt = t + gridDim.x < ntile ? tile_work(a, t + gridDim.x, pre, nk, count).net : -1;
+    pp.stage = 0;
+    {   // prologue: phases 0 and 1 into stages 0 and 1
+        Stage<W> s0, s1;
+        stage_fetch<W>(s0, tab, pp, 0, wave, lane);
+        stage_fetch<W>(s1, tab, pp, 1, wave, lane);
+        stage_commit<W>(s0, stage_ptr<W>(ring, 0), wave, lane);
+        stage_commit<W>(s1, stage_ptr<W>(ring, 1), wave, lane);
+        __syncthreads();
+    }
+
+    for (;;) {
+        const int depth = __builtin_amdgcn_readfirstlane(tab->depth[pp.cur]);
+        const float *head = s_head + pp.cur * 2 * W;
+        bf16x8 b0[NKB][kNB], b1[NKB][kNB];
+        float v[kNB][kInRaw];
+        bool valid[kNB];
+        // ---- encoding -> layer-0 operands (bias in two feature slots of lane half 1)
+#pragma unroll
+        for (int nb = 0; nb < kNB; ++nb) {
+            const int64_t r = cw.base + (wave * kNB + nb) * 32 + col;
+            valid[nb] = r < cw.end;
+#pragma unroll
+            for (int j = 0; j < kInRaw; ++j) v[nb][j] = valid[nb] ? a.rays[(int64_t)j * n + r] : 0.f;
+            float feat[kSlotsPerHalf];
+            encode_var<false>(h ? v[nb][3] : v[nb][0], feat);
+            encode_var<false>(h ? v[nb][4] : v[nb][1], feat + kFeatPerVar);
+            encode_var<false>(h ? 0.f : v[nb][2], feat + 2 * kFeatPerVar);
+            feat[kSlotsPerHalf - 1] = 0.f;
+            feat[kBiasSlot0] = h ? 1.f : feat[kBiasSlot0];
+            feat[kBiasSlot1] = h ? 1.f : 0.f;
+#pragma unroll
+            for (int kb = 0; kb < K0; ++kb)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) b0[kb][nb][s] = (__bf16)feat[kb * 8 + s];
+        }
+        // ---- forward: layer 0 into b1, then hidden layers alternating; the last output ends in b1
+        fwd_layer<W, K0, kGrad>(ring, tab, pp, 0, b0, b1, wmask, wave, lane, h);
+        int l = 1;
+        if ((depth - 1) % 2 == 1) {   // odd count of hidden layers: one step first, then pairs
+            fwd_layer<W, NKB, kGrad>(ring, tab, pp, 1, b1, b0, wmask, wave, lane, h);
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+                for (int nb = 0; nb < kNB; ++nb) b1[kb][nb] = b0[kb][nb];
+            l = 2;
+        }
+        for (; l + 1 < depth; l += 2) {
+            fwd_layer<W, NKB, kGrad>(ring, tab, pp, l, b1, b0, wmask, wave, lane, h);
+            fwd_layer<W, NKB, kGrad>(ring, tab, pp, l + 1, b0, b1, wmask, wave, lane, h);
+        }
+        // ---- head: logit and distance in rows 0 and 1 of lane half 0
+        f32x16 hacc[kNB];
+        {
+            Stage<W> sg;
+            stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+            phase_mfma<W, NKB + 1, true>(stage_ptr<W>(ring, pp.stage), b1, hacc, lane, h);
+            phase_end<W>(sg, ring, pp, wave, lane);
+        }
+        float gl[kNB], gd[kNB];
+#pragma unroll
+        for (int nb = 0; nb < kNB; ++nb) {
+            const int64_t r = cw.base + (wave * kNB + nb) * 32 + col;
+            const float z = __shfl(hacc[nb][0], col), dd = __shfl(hacc[nb][1], col);
+            float *dst = h ? a.dist_out : a.logit_out;
+            if (valid[nb] && dst) dst[r] = h ? dd : z;
+            gl[nb] = (kGrad && valid[nb] && a.g_logit_in) ? a.g_logit_in[r] : 0.f;
+            gd[nb] = (kGrad && valid[nb] && a.g_dist_in) ? a.g_dist_in[r] : 0.f;
+        }
+        if constexpr (kGrad) {
+            // ---- seed: adjoint of the last hidden layer = head rows x seeds, masked -> b0
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) {
+                f32x16 w0, w1;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const f32x4 a4 = *reinterpret_cast<const f32x4 *>(head + mb * 32 + 8 * g + 4 * h);
+                    const f32x4 b4 = *reinterpret_cast<const f32x4 *>(head + W + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        w0[4 * g + i] = a4[i];
+                        w1[4 * g + i] = b4[i];
+                    }
+                }
+#pragma unroll
+                for (int nb = 0; nb < kNB; ++nb) {
+                    f32x16 y;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) y[j] = fmaf(gl[nb], w0[j], gd[nb] * w1[j]);
+                    masked_tile_to_bf16<W>(y, wmask[(((depth - 1) * NMB + mb) * kNB + nb) * 64 + lane], mb, nb, b0);
+                }
+            }
+            // ---- transposed hidden layers from the top; the last adjoint ends in b0
+            int lb = depth - 1;
+            if (lb % 2 == 1) {
+                bwd_layer<W>(ring, tab, pp, lb, b0, b1, wmask, wave, lane, h);
+#pragma unroll
+                for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+                    for (int nb = 0; nb < kNB; ++nb) b0[kb][nb] = b1[kb][nb];
+                --lb;
+            }
+            for (; lb >= 2; lb -= 2) {
+                bwd_layer<W>(ring, tab, pp, lb, b0, b1, wmask, wave, lane, h);
+                bwd_layer<W>(ring, tab, pp, lb - 1, b1, b0, wmask, wave, lane, h);
+            }
+            // ---- transposed layer 0: adjoints of this lane's feature slots
+            f32x16 acc0[kGradRowBlocks0][kNB];
+#pragma unroll
+            for (int mb = 0; mb < kGradRowBlocks0; ++mb) {
+                Stage<W> sg;
+                stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+                phase_mfma<W, NKB, false>(stage_ptr<W>(ring, pp.stage), b0, acc0[mb], lane, h);
+                phase_end<W>(sg, ring, pp, wave, lane);
+            }
+            // ---- chain rule through the Fourier features
+#pragma unroll
+            for (int nb = 0; nb < kNB; ++nb) {
+                const int64_t r = cw.base + (wave * kNB + nb) * 32 + col;
+#pragma unroll
+                for (int var = 0; var < 3; ++var) {
+                    if (h == 1 && var == 2) continue;
+                    float f[kFeatPerVar];
+                    const float x = h ? v[nb][3 + var] : v[nb][var];
+                    encode_var<false>(x, f);
+                    float g = acc0[(var * kFeatPerVar) / 16][nb][(var * kFeatPerVar) % 16];
+#pragma unroll
+                    for (int k = 0; k < kNFreq; ++k) {
+                        const int fs = var * kFeatPerVar + 1 + k, fc = var * kFeatPerVar + 1 + kNFreq + k;
+                        const float gs = acc0[fs / 16][nb][fs % 16], gc = acc0[fc / 16][nb][fc % 16];
+                        g = fmaf((float)(1 << k), gs * f[1 + kNFreq + k] - gc * f[1 + k], g);
+                    }
+                    if (valid[nb] && a.g_rays) a.g_rays[(int64_t)(h ? 3 + var : var) * n + r] = g;
+                }
+            }
+        }
+        // ---- next workgroup tile
+        t += gridDim.x;
+        if (t >= ntile) break;
+        cw = tile_work(a, t, pre, nk, count);
+        pp.cur = cw.net;
+        pp.q = 0;
+        pp.nxt = t + gridDim.x < ntile ? tile_work(a, t + gridDim.x, pre, nk, count).net : -1;
+    }
+}
+
+int cu_count_stream() {
+    static int cus = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    });
+    return cus;
+}
+
+template <int W, bool kGrad>
+ddf_status launch_stream(const GradArgs &args, hipStream_t s) {
+    auto kern = stream_kernel<W, kGrad>;
+    static std::once_flag once;
+    std::call_once(once, [&] { (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxStreamLds); });
+    const int nk = args.n_nets > 0 ? args.n_nets : 1;
+    DDF_REQUIRE(args.depth >= 1 && args.depth <= 8 && nk <= kMaxNets, DDF_ERR_UNSUPPORTED,
+                "streamed network kernel: depth 1..8 and at most %d networks", kMaxNets);
+    const size_t lds = stream_lds_bytes(W, args.depth, nk, kGrad);
+    DDF_REQUIRE(lds <= (size_t)kMaxStreamLds, DDF_ERR_UNSUPPORTED, "network too deep for the streamed kernel");
+    // persistent: two waves per SIMD (one workgroup of eight waves at width 256, two of four
+    // at width 128 when their LDS fits)
+    const int per_cu = W == 128 && lds * 2 <= (size_t)kMaxStreamLds ? 2 : 1;
+    const int64_t tiles_hint = (args.n + kRaysPerTile - 1) / kRaysPerTile + nk;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles_hint, (int64_t)cu_count_stream() * per_cu));
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(Geo<W>::kWaves * 64), lds, s, args);
+    return launch_status("ddf streamed network kernel");
+}
+
+}  // namespace
+
+size_t stream_lds_bytes(int width, int depth, int n_nets, bool grad) {
+    const int nmb = width / 32, nkb = width / 16;
+    const int waves = width == 256 ? Geo<256>::kWaves : Geo<128>::kWaves;
+    const int nb = width == 256 ? Geo<256>::kNB : Geo<128>::kNB;
+    size_t b = (size_t)kStages * (nkb + 1) * 1024 + sizeof(NetTable);
+    if (grad) b += (size_t)waves * depth * nmb * nb * 64 * 2 + (size_t)n_nets * 2 * width * 4;
+    return b;
+}
+
+// bf16 networks of width 128 or 256; args.depth is the largest depth of the launch.
+ddf_status stream_dispatch(int width, const GradArgs &args, hipStream_t s) {
+    const bool grad = !args.forward_only;
+    if (width == 256) return grad ? launch_stream<256, true>(args, s) : launch_stream<256, false>(args, s);
+    return grad ? launch_stream<128, true>(args, s) : launch_stream<128, false>(args, s);
+}
+
+}  // namespace ddf
