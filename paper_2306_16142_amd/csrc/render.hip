@@ -498,39 +498,74 @@ __global__ void stats_kernel(const int *counts, int bounces, uint32_t *stats) {
 
 // Rays of a queue (main: path ids through `queue`; shadow: rows of `rays6`) against every
 // instance's cube.  Pass 0 counts (ray, instance) pairs per instance; pass 1 writes them,
-// grouped by instance (and so by network: instances are ordered by network).
+// grouped by instance (and so by network: instances are ordered by network).  Each block
+// owns a contiguous range of the queue and aggregates in LDS, so the global counters see
+// one atomic per block and instance (per-wave atomics on the same few counters serialised
+// in L2).  Pass 1 culls its range twice: once to reserve its slots, once to write.
+constexpr int kCullBlock = 256;
+
 template <bool kScatter>
-__global__ void cull_kernel(int64_t C, const int *__restrict__ queue, const int *__restrict__ count,
-                            const float *__restrict__ po, const float *__restrict__ pd, const InstDev *__restrict__ inst,
-                            int n_inst, MultiCounts mc, PairBufs pb, int64_t P) {
+__global__ __launch_bounds__(kCullBlock) void cull_kernel(int64_t C, const int *__restrict__ queue,
+                                                          const int *__restrict__ count, const float *__restrict__ po,
+                                                          const float *__restrict__ pd,
+                                                          const InstDev *__restrict__ inst, int n_inst, MultiCounts mc,
+                                                          PairBufs pb, int64_t P) {
+    __shared__ InstDev s_inst[kMaxInstances];
+    __shared__ int s_cnt[kMaxInstances], s_base[kMaxInstances];
+    for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+        s_inst[i] = inst[i];
+        s_cnt[i] = 0;
+    }
+    __syncthreads();
     const int n = *count;
-    const int64_t span = ((int64_t)n + 63) / 64 * 64;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < span; q += (int64_t)gridDim.x * blockDim.x) {
-        Vec3 o{}, d{};
-        if (q < n) {
-            const int64_t src = queue ? (int64_t)queue[q] : q;
-            o = load3(po, C, src);
-            d = load3(pd, C, src);
-        }
-        for (int i = 0; i < n_inst; ++i) {
-            Vec3 oo, dd;
-            to_object(inst[i], o, d, oo, dd);
-            const float te = q < n ? cube_entry(oo, dd) : NAN;
-            const bool want = !isnan(te);
-            if constexpr (!kScatter) {
-                const uint64_t mask = __ballot(want);
-                if ((threadIdx.x & 63) == 0 && mask) atomicAdd(&mc.inst_count[i], (int)__popcll(mask));
-            } else {
-                const int slot = append(&mc.inst_cursor[i], want);
-                if (want) {
-                    const int64_t p = (int64_t)mc.inst_off[i] + slot;
-                    pb.q[p] = (int)q;
-                    pb.inst[p] = i;
-                    pb.t0[p] = te;
-                    write_query(pb.rays5, P, p, oo, dd, te);
+    // contiguous range of this block, a multiple of 64 rays long
+    const int64_t per = ((((int64_t)n + gridDim.x - 1) / gridDim.x) + 63) / 64 * 64;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min<int64_t>(lo + per, n);
+    const int64_t span = lo < hi ? (hi - lo + 63) / 64 * 64 : 0;   // whole waves: ballots see 64 lanes
+    auto sweep = [&](bool write) {
+        for (int64_t k = threadIdx.x; k < span; k += blockDim.x) {
+            const int64_t q = lo + k;
+            const bool live = q < hi;
+            Vec3 o{}, d{};
+            if (live) {
+                const int64_t src = queue ? (int64_t)queue[q] : q;
+                o = load3(po, C, src);
+                d = load3(pd, C, src);
+            }
+            for (int i = 0; i < n_inst; ++i) {
+                Vec3 oo, dd;
+                to_object(s_inst[i], o, d, oo, dd);
+                const float te = live ? cube_entry(oo, dd) : NAN;
+                const bool want = !isnan(te);
+                if (!write) {
+                    const uint64_t mask = __ballot(want);
+                    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(&s_cnt[i], (int)__popcll(mask));
+                } else {
+                    const int slot = append(&s_cnt[i], want);   // LDS counter of this block
+                    if (want) {
+                        const int64_t p = (int64_t)s_base[i] + slot;
+                        pb.q[p] = (int)q;
+                        pb.inst[p] = i;
+                        pb.t0[p] = te;
+                        write_query(pb.rays5, P, p, oo, dd, te);
+                    }
                 }
             }
         }
+    };
+    sweep(false);
+    __syncthreads();
+    if constexpr (!kScatter) {
+        for (int i = threadIdx.x; i < n_inst; i += blockDim.x)
+            if (s_cnt[i]) atomicAdd(&mc.inst_count[i], s_cnt[i]);
+        return;
+    } else {
+        for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+            s_base[i] = mc.inst_off[i] + (s_cnt[i] ? atomicAdd(&mc.inst_cursor[i], s_cnt[i]) : 0);
+            s_cnt[i] = 0;
+        }
+        __syncthreads();
+        sweep(true);
     }
 }
 
@@ -706,9 +741,11 @@ ddf_status multi_query(const ddf_scene *scene, const MultiPlan &mp, RenderWs &w,
     NetMap map{};
     for (int k = 0; k < mp.n_nets; ++k) map.user[k] = mp.order[k];
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(kMaxInstances), 0, s, w.mc.inst_count, kMaxInstances);
-    hipLaunchKernelGGL(cull_kernel<false>, dim3(gC), dim3(256), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);
+    // a few thousand rays per block: one global atomic per block and instance
+    const unsigned gCull = (unsigned)std::max<int64_t>(1, std::min<int64_t>((C + 2047) / 2048, 2048));
+    hipLaunchKernelGGL(cull_kernel<false>, dim3(gCull), dim3(kCullBlock), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);
     hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(64), 0, s, mp.n_inst, w.inst, mp.n_nets, w.mc, net_stats, map);
-    hipLaunchKernelGGL(cull_kernel<true>, dim3(gC), dim3(256), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);
+    hipLaunchKernelGGL(cull_kernel<true>, dim3(gCull), dim3(kCullBlock), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);
     if (ddf_status st = launch_status("ddf_render_wavefront (instance culling)")) return st;
     for (int g = 0; g < 2; ++g) {
         if (mp.group_size[g] == 0) continue;

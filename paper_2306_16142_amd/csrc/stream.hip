@@ -118,7 +118,10 @@ __device__ inline lds_u8 *stage_ptr(lds_u8 *ring, int st) {
     return ring + st * (W / 16 + 1) * 1024;
 }
 
-// Fetches this wave's share of the phase `ahead` phases after the current one.
+// Fetches this wave's share of the phase `ahead` phases after the current one.  Branch-free
+// over the share: slot i takes tile min(i, ks - 1) and is written at min(i, NKB), so extra
+// slots of a short phase receive copies of its last tile, which nothing reads, and a wave
+// whose share runs past the stage writes the last slot with that slot's own tile.
 template <int W>
 __device__ inline void stage_fetch(Stage<W> &sg, const NetTable *tab, const Pipe &pp, int ahead, int wave, int lane) {
     int net = pp.cur, q = pp.q + ahead;
@@ -128,39 +131,30 @@ __device__ inline void stage_fetch(Stage<W> &sg, const NetTable *tab, const Pipe
         net = pp.nxt;
     }
     const bool live = net >= 0 && q < tab->nphase[net >= 0 ? net : 0];
-    int off = 0, stride = 0, ks = 0;
-    uint64_t blob = 0;
-    if (live) {
-        off = tab->ph[net][q][0];
-        stride = tab->ph[net][q][1];
-        ks = tab->ph[net][q][2];
-        blob = tab->blob[net];
-    }
-    // the values are wave-uniform; say so, so that the branches below stay scalar
-    ks = __builtin_amdgcn_readfirstlane(ks);
-    stride = __builtin_amdgcn_readfirstlane(stride);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(blob + off));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((blob + off) >> 32));
-    gbl_u8 *g = (gbl_u8 *)(((uint64_t)hi << 32) | lo);
-    int cnt = 0;
+    sg.cnt = __builtin_amdgcn_readfirstlane(live ? 1 : 0);
+    if (!sg.cnt) return;
+    const int off = __builtin_amdgcn_readfirstlane(tab->ph[net][q][0]);
+    const int stride = __builtin_amdgcn_readfirstlane(tab->ph[net][q][1]);
+    const int ks = __builtin_amdgcn_readfirstlane(tab->ph[net][q][2]);
+    const uint64_t blob = tab->blob[net];
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)blob);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(blob >> 32));
+    gbl_u8 *g = (gbl_u8 *)(((uint64_t)hi << 32) | lo) + off + lane * 16;
 #pragma unroll
     for (int j = 0; j < Stage<W>::kMax; ++j) {
-        const int i = wave + Geo<W>::kWaves * j;
-        if (i < ks) {
-            sg.v[j] = *reinterpret_cast<const __attribute__((address_space(1))) i32x4 *>(g + i * stride + lane * 16);
-            cnt = j + 1;
-        }
+        const int i = min(wave + Geo<W>::kWaves * j, ks - 1);
+        sg.v[j] = *reinterpret_cast<const __attribute__((address_space(1))) i32x4 *>(g + i * stride);
     }
-    sg.cnt = cnt;
 }
 
 template <int W>
 __device__ inline void stage_commit(const Stage<W> &sg, lds_u8 *stage, int wave, int lane) {
+    if (!sg.cnt) return;
 #pragma unroll
-    for (int j = 0; j < Stage<W>::kMax; ++j)
-        if (j < sg.cnt)
-            *reinterpret_cast<__attribute__((address_space(3))) i32x4 *>(stage + (wave + Geo<W>::kWaves * j) * 1024 +
-                                                                         lane * 16) = sg.v[j];
+    for (int j = 0; j < Stage<W>::kMax; ++j) {
+        const int i = min(wave + Geo<W>::kWaves * j, W / 16);
+        *reinterpret_cast<__attribute__((address_space(3))) i32x4 *>(stage + i * 1024 + lane * 16) = sg.v[j];
+    }
 }
 
 // End of a phase: publish the fetched share (two phases ahead) and advance.
@@ -177,28 +171,47 @@ __device__ inline bf16x8 lds_tile(const lds_u8 *stage, int i, int lane) {
     return *reinterpret_cast<const __attribute__((address_space(3))) bf16x8 *>(stage + i * 1024 + lane * 16);
 }
 
+// A tiles in flight: the first two tiles of the current phase are loaded during the
+// previous phase (its stage was published one barrier earlier), so a phase starts without
+// waiting on LDS.
+struct ARing {
+    bf16x8 r[2];
+};
+
 // One phase's MFMA chain: KS K-blocks from the stage (the last one the bias block when
-// kBias), A tiles two steps ahead, accumulators starting from zero.
+// kBias), A tiles two steps ahead; the last two steps load the next phase's first tiles.
 template <int W, int KS, bool kBias>
-__device__ __attribute__((always_inline)) inline void phase_mfma(const lds_u8 *st,
+__device__ __attribute__((always_inline)) inline void phase_mfma(const lds_u8 *st, const lds_u8 *st_next, ARing &ar,
                                                                  const bf16x8 (&bin)[W / 16][Geo<W>::kNB],
                                                                  f32x16 (&acc)[Geo<W>::kNB], int lane, int h) {
     constexpr int kNB = Geo<W>::kNB;
     constexpr int KIN = KS - (kBias ? 1 : 0);
     const bf16x8 one = bias_operand(h);
-    bf16x8 ring[2];
-    ring[0] = lds_tile(st, 0, lane);
-    ring[1] = lds_tile(st, KS > 1 ? 1 : 0, lane);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        const bf16x8 a = ring[ks & 1];
-        if (ks + 2 < KS) ring[ks & 1] = lds_tile(st, ks + 2, lane);
+        const bf16x8 a = ar.r[ks & 1];
+        // every phase has at least two tiles, so the next phase's tiles 0 and 1 exist
+        ar.r[ks & 1] = ks + 2 < KS ? lds_tile(st, ks + 2, lane) : lds_tile(st_next, ks + 2 - KS, lane);
 #pragma unroll
         for (int nb = 0; nb < kNB; ++nb) {
             const bf16x8 b = (kBias && ks == KIN) ? one : bin[ks < KIN ? ks : 0][nb];
             acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, ks == 0 ? f32x16{} : acc[nb], 0, 0, 0);
         }
     }
+    if constexpr (KS % 2 == 1) {   // the next phase's tile 0 landed in slot 1: restore the order
+        const bf16x8 t = ar.r[0];
+        ar.r[0] = ar.r[1];
+        ar.r[1] = t;
+    }
+}
+
+template <int W>
+__device__ inline const lds_u8 *cur_stage(lds_u8 *ring, const Pipe &pp) {
+    return stage_ptr<W>(ring, pp.stage);
+}
+template <int W>
+__device__ inline const lds_u8 *nxt_stage(lds_u8 *ring, const Pipe &pp) {
+    return stage_ptr<W>(ring, pp.stage == kStages - 1 ? 0 : pp.stage + 1);
 }
 
 template <int W>
@@ -216,7 +229,7 @@ __device__ inline void relu_mask_out(const f32x16 &y, int l, int mb, int nb, bf1
 
 // Forward layer l (all its M-blocks): bin -> bout with ReLU; masks to LDS for gradients.
 template <int W, int KIN, bool kGrad>
-__device__ __attribute__((always_inline)) inline void fwd_layer(lds_u8 *ring, const NetTable *tab, Pipe &pp, int l,
+__device__ __attribute__((always_inline)) inline void fwd_layer(lds_u8 *ring, const NetTable *tab, Pipe &pp, ARing &ar, int l,
                                                                 const bf16x8 (&bin)[W / 16][Geo<W>::kNB],
                                                                 bf16x8 (&bout)[W / 16][Geo<W>::kNB], uint16_t *wmask,
                                                                 int wave, int lane, int h) {
@@ -227,7 +240,8 @@ __device__ __attribute__((always_inline)) inline void fwd_layer(lds_u8 *ring, co
     for (int mb = 0; mb < NMB; ++mb) {
         Stage<W> sg;
         stage_fetch<W>(sg, tab, pp, 2, wave, lane);
-        phase_mfma<W, KIN + (kBias ? 1 : 0), kBias>(stage_ptr<W>(ring, pp.stage), bin, acc[mb & 1], lane, h);
+        phase_mfma<W, KIN + (kBias ? 1 : 0), kBias>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin, acc[mb & 1],
+                                                    lane, h);
         if (mb > 0) {
 #pragma unroll
             for (int nb = 0; nb < kNB; ++nb) relu_mask_out<W>(acc[(mb - 1) & 1][nb], l, mb - 1, nb, bout, wmask, lane, kGrad);
@@ -244,7 +258,8 @@ __device__ inline void masked_tile_to_bf16(const f32x16 &y, uint32_t bits, int m
                                            bf16x8 (&b)[W / 16][Geo<W>::kNB]) {
     float v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = ((bits >> j) & 1u) ? y[j] : 0.f;
+    for (int j = 0; j < 16; ++j)   // bit j sign-extended to 0 or all ones, then AND: y_j or +0
+        v[j] = __uint_as_float(__float_as_uint(y[j]) & (uint32_t)__builtin_amdgcn_sbfe((int)bits, j, 1));
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -254,7 +269,7 @@ __device__ inline void masked_tile_to_bf16(const f32x16 &y, uint32_t bits, int m
 // Transposed hidden layer l (rows: its inputs): adjoint operands of layer l's outputs ->
 // masked adjoint operands of layer l - 1's outputs.
 template <int W>
-__device__ __attribute__((always_inline)) inline void bwd_layer(lds_u8 *ring, const NetTable *tab, Pipe &pp, int l,
+__device__ __attribute__((always_inline)) inline void bwd_layer(lds_u8 *ring, const NetTable *tab, Pipe &pp, ARing &ar, int l,
                                                                 const bf16x8 (&bin)[W / 16][Geo<W>::kNB],
                                                                 bf16x8 (&bout)[W / 16][Geo<W>::kNB],
                                                                 const uint16_t *wmask, int wave, int lane, int h) {
@@ -264,7 +279,7 @@ __device__ __attribute__((always_inline)) inline void bwd_layer(lds_u8 *ring, co
     for (int mb = 0; mb < NMB; ++mb) {
         Stage<W> sg;
         stage_fetch<W>(sg, tab, pp, 2, wave, lane);
-        phase_mfma<W, NKB, false>(stage_ptr<W>(ring, pp.stage), bin, acc[mb & 1], lane, h);
+        phase_mfma<W, NKB, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin, acc[mb & 1], lane, h);
         if (mb > 0) {
 #pragma unroll
             for (int nb = 0; nb < kNB; ++nb)
@@ -379,6 +394,9 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
         stage_commit<W>(s1, stage_ptr<W>(ring, 1), wave, lane);
         __syncthreads();
     }
+    ARing ar;
+    ar.r[0] = lds_tile(stage_ptr<W>(ring, 0), 0, lane);
+    ar.r[1] = lds_tile(stage_ptr<W>(ring, 0), 1, lane);
 
     for (;;) {
         const int depth = __builtin_amdgcn_readfirstlane(tab->depth[pp.cur]);
@@ -406,10 +424,10 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
                 for (int s = 0; s < 8; ++s) b0[kb][nb][s] = (__bf16)feat[kb * 8 + s];
         }
         // ---- forward: layer 0 into b1, then hidden layers alternating; the last output ends in b1
-        fwd_layer<W, K0, kGrad>(ring, tab, pp, 0, b0, b1, wmask, wave, lane, h);
+        fwd_layer<W, K0, kGrad>(ring, tab, pp, ar, 0, b0, b1, wmask, wave, lane, h);
         int l = 1;
         if ((depth - 1) % 2 == 1) {   // odd count of hidden layers: one step first, then pairs
-            fwd_layer<W, NKB, kGrad>(ring, tab, pp, 1, b1, b0, wmask, wave, lane, h);
+            fwd_layer<W, NKB, kGrad>(ring, tab, pp, ar, 1, b1, b0, wmask, wave, lane, h);
 #pragma unroll
             for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
@@ -417,15 +435,15 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
             l = 2;
         }
         for (; l + 1 < depth; l += 2) {
-            fwd_layer<W, NKB, kGrad>(ring, tab, pp, l, b1, b0, wmask, wave, lane, h);
-            fwd_layer<W, NKB, kGrad>(ring, tab, pp, l + 1, b0, b1, wmask, wave, lane, h);
+            fwd_layer<W, NKB, kGrad>(ring, tab, pp, ar, l, b1, b0, wmask, wave, lane, h);
+            fwd_layer<W, NKB, kGrad>(ring, tab, pp, ar, l + 1, b0, b1, wmask, wave, lane, h);
         }
         // ---- head: logit and distance in rows 0 and 1 of lane half 0
         f32x16 hacc[kNB];
         {
             Stage<W> sg;
             stage_fetch<W>(sg, tab, pp, 2, wave, lane);
-            phase_mfma<W, NKB + 1, true>(stage_ptr<W>(ring, pp.stage), b1, hacc, lane, h);
+            phase_mfma<W, NKB + 1, true>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b1, hacc, lane, h);
             phase_end<W>(sg, ring, pp, wave, lane);
         }
         float gl[kNB], gd[kNB];
@@ -464,7 +482,7 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
             // ---- transposed hidden layers from the top; the last adjoint ends in b0
             int lb = depth - 1;
             if (lb % 2 == 1) {
-                bwd_layer<W>(ring, tab, pp, lb, b0, b1, wmask, wave, lane, h);
+                bwd_layer<W>(ring, tab, pp, ar, lb, b0, b1, wmask, wave, lane, h);
 #pragma unroll
                 for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
@@ -472,8 +490,8 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
                 --lb;
             }
             for (; lb >= 2; lb -= 2) {
-                bwd_layer<W>(ring, tab, pp, lb, b0, b1, wmask, wave, lane, h);
-                bwd_layer<W>(ring, tab, pp, lb - 1, b1, b0, wmask, wave, lane, h);
+                bwd_layer<W>(ring, tab, pp, ar, lb, b0, b1, wmask, wave, lane, h);
+                bwd_layer<W>(ring, tab, pp, ar, lb - 1, b1, b0, wmask, wave, lane, h);
             }
             // ---- transposed layer 0: adjoints of this lane's feature slots
             f32x16 acc0[kGradRowBlocks0][kNB];
@@ -481,7 +499,7 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
             for (int mb = 0; mb < kGradRowBlocks0; ++mb) {
                 Stage<W> sg;
                 stage_fetch<W>(sg, tab, pp, 2, wave, lane);
-                phase_mfma<W, NKB, false>(stage_ptr<W>(ring, pp.stage), b0, acc0[mb], lane, h);
+                phase_mfma<W, NKB, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b0, acc0[mb], lane, h);
                 phase_end<W>(sg, ring, pp, wave, lane);
             }
             // ---- chain rule through the Fourier features
