@@ -24,16 +24,32 @@ namespace ddf {
 
 namespace {
 
-constexpr int kChunk = 2048;      // rays per split of the batch contraction
-constexpr int kGemmTile = 64;     // output tile per wave (2 x 2 MFMA blocks)
+constexpr int kChunk = 1024;      // rays per split of the batch contraction
 
 // ------------------------------------------------------------------------------ scalars
-__global__ void loss_scalars_kernel(const float *__restrict__ t_label, int64_t n, float *scalars,
-                                    unsigned int *count) {
-    // single block: count hits (t < +inf) in a fixed order, then write {1/N, 1/max(1, hits)}
+// Hit count of the labels in two kernels: per-block counts, then one block sums them
+// (integer sums: any order gives the same result) and writes {1/N, 1/max(1, hits)}.
+constexpr int kCountBlocks = 1024;
+
+__global__ void hit_count_kernel(const float *__restrict__ t_label, int64_t n, unsigned int *part) {
     __shared__ unsigned int red[256];
     unsigned int c = 0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) c += t_label[i] < INFINITY ? 1u : 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += t_label[i] < INFINITY ? 1u : 0u;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void loss_scalars_kernel(const unsigned int *__restrict__ part, int nparts, int64_t n, float *scalars,
+                                    unsigned int *count) {
+    __shared__ unsigned int red[256];
+    unsigned int c = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) c += part[i];
     red[threadIdx.x] = c;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -45,6 +61,14 @@ __global__ void loss_scalars_kernel(const float *__restrict__ t_label, int64_t n
         scalars[0] = 1.0f / (float)n;
         scalars[1] = 1.0f / (float)(red[0] > 0 ? red[0] : 1u);
     }
+}
+
+// Launches both; `part` holds kCountBlocks counts (it is overwritten later in the stream).
+void launch_loss_scalars(const float *t_label, int64_t n, unsigned int *part, float *scalars, unsigned int *count,
+                         hipStream_t s) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, kCountBlocks));
+    hipLaunchKernelGGL(hit_count_kernel, dim3(blocks), dim3(256), 0, s, t_label, n, part);
+    hipLaunchKernelGGL(loss_scalars_kernel, dim3(1), dim3(256), 0, s, part, blocks, n, scalars, count);
 }
 
 __global__ void sum_partials_kernel(const float *__restrict__ part, int64_t cnt, float *out) {
@@ -61,79 +85,101 @@ __global__ void sum_partials_kernel(const float *__restrict__ part, int64_t cnt,
 }
 
 // ------------------------------------------------------------------------------ dW = A B^T
-// A: [M][n] adjoints, B: [N][n] layer inputs (rows contiguous over rays).  One wave per
-// (64 x 64 output tile, chunk of kChunk rays); lane half h contracts the first or the
-// second half of the chunk (the MFMA's k index pairs the same ray in A and B).
+// A: [M][n] adjoints, B: [N][n] layer inputs (rows contiguous over rays).  One workgroup
+// per (128 x 128 output tile, chunk of kChunk rays).  Stages of 32 rays of both operands
+// go through LDS (coalesced 16-byte global loads, rows padded to 36 floats so that the
+// MFMA operand reads are free of bank conflicts), double-buffered; each wave owns a 64 x 64
+// sub-tile (2 x 2 blocks of v_mfma_f32_32x32x2f32).  Lane half h contracts rays 16 h ..
+// 16 h + 15 of a stage (the contraction order only pairs A and B of the same ray).
 // part[s][M][N] and dbpart[s][M] receive the chunk's sums.
+constexpr int kDwTile = 128;
+constexpr int kDwStep = 32;
+constexpr int kDwPad = 36;
+
 template <bool kVec4>
 __global__ __launch_bounds__(256) void dw_kernel(const float *__restrict__ A, const float *__restrict__ B, int M,
                                                  int N, int64_t n, int splits, float *__restrict__ part,
                                                  float *__restrict__ dbpart) {
-    const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
-    const int mt = (M + kGemmTile - 1) / kGemmTile, nt = (N + kGemmTile - 1) / kGemmTile;
-    const int64_t job = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (job >= (int64_t)mt * nt * splits) return;
-    const int s = (int)(job % splits);
-    const int tile = (int)(job / splits);
-    const int m0 = (tile / nt) * kGemmTile, n0 = (tile % nt) * kGemmTile;
-    // rays of this chunk: lane half 0 takes the first kChunk / 2, half 1 the rest; every
-    // loop bound below is the same for the whole wave (MFMAs must not run divergent)
-    const int64_t chunk_len = std::min<int64_t>(kChunk, n - (int64_t)s * kChunk);
-    const int64_t len0 = std::min<int64_t>(kChunk / 2, chunk_len);
-    const int64_t len1 = std::max<int64_t>(0, chunk_len - kChunk / 2);
-    const int64_t len = h ? len1 : len0;
-    const int64_t r0 = (int64_t)s * kChunk + h * (kChunk / 2);
-    const float *arow[2];
-    const float *brow[2];
-    bool aok[2], bok[2];
+    __shared__ __attribute__((aligned(16))) float sA[2][kDwTile][kDwPad];
+    __shared__ __attribute__((aligned(16))) float sB[2][kDwTile][kDwPad];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31;
+    const int ntn = (N + kDwTile - 1) / kDwTile;
+    const int s = blockIdx.x % splits, tile = blockIdx.x / splits;
+    const int m0 = (tile / ntn) * kDwTile, n0 = (tile % ntn) * kDwTile;
+    const int64_t k0 = (int64_t)s * kChunk;
+    const int klen = (int)min<int64_t>(kChunk, n - k0);
+    const int nstep = (klen + kDwStep - 1) / kDwStep;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    // global -> register staging: 128 rows x 32 rays per operand = 1024 float4, 4 per thread
+    f32x4 ra[4], rb[4];
+    auto fetch = [&](int st) {
+        const int kb = st * kDwStep;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int m = m0 + 32 * i + c, k = n0 + 32 * i + c;
-        aok[i] = m < M;
-        bok[i] = k < N;
-        arow[i] = A + (int64_t)(aok[i] ? m : 0) * n + r0;
-        brow[i] = B + (int64_t)(bok[i] ? k : 0) * n + r0;
-    }
+        for (int r = 0; r < 4; ++r) {
+            const int idx = tid + 256 * r, row = idx >> 3, k4 = (idx & 7) * 4;
+            const int ma = m0 + row, nb = n0 + row;
+            const int kk = kb + k4;
+            f32x4 va{0.f, 0.f, 0.f, 0.f}, vb{0.f, 0.f, 0.f, 0.f};
+            if constexpr (kVec4) {
+                if (kk < klen) {   // klen is a multiple of 4 here
+                    if (ma < M) va = *reinterpret_cast<const f32x4 *>(A + (int64_t)ma * n + k0 + kk);
+                    if (nb < N) vb = *reinterpret_cast<const f32x4 *>(B + (int64_t)nb * n + k0 + kk);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (kk + e < klen) {
+                        if (ma < M) va[e] = A[(int64_t)ma * n + k0 + kk + e];
+                        if (nb < N) vb[e] = B[(int64_t)nb * n + k0 + kk + e];
+                    }
+            }
+            ra[r] = va;
+            rb[r] = vb;
+        }
+    };
+    auto commit = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int idx = tid + 256 * r, row = idx >> 3, k4 = (idx & 7) * 4;
+            *reinterpret_cast<f32x4 *>(&sA[buf][row][k4]) = ra[r];
+            *reinterpret_cast<f32x4 *>(&sB[buf][row][k4]) = rb[r];
+        }
+    };
     f32x16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
+    float dbs = 0.f;   // bias gradient: thread t sums half a row (row t / 2) of the A tile
+    fetch(0);
+    commit(0);
+    __syncthreads();
+    for (int st = 0; st < nstep; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nstep) fetch(st + 1);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
-    float dbs[2] = {0.f, 0.f};
-    int64_t ks = 0;
-    if constexpr (kVec4) {
-        const int64_t vlen = (len1 / 4) * 4;   // len1 <= len0: both halves have these rays
-        for (; ks < vlen; ks += 4) {
-            f32x4 av[2], bv[2];
+        for (int q = 0; q < 4; ++q) {   // four rays per lane half at a time
+            f32x4 a4[2], b4[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                av[i] = aok[i] ? *reinterpret_cast<const f32x4 *>(arow[i] + ks) : f32x4{0.f, 0.f, 0.f, 0.f};
-                bv[i] = bok[i] ? *reinterpret_cast<const f32x4 *>(brow[i] + ks) : f32x4{0.f, 0.f, 0.f, 0.f};
-                dbs[i] += (av[i][0] + av[i][1]) + (av[i][2] + av[i][3]);
+                a4[i] = *reinterpret_cast<const f32x4 *>(&sA[buf][wm + 32 * i + c][16 * h + 4 * q]);
+                b4[i] = *reinterpret_cast<const f32x4 *>(&sB[buf][wn + 32 * i + c][16 * h + 4 * q]);
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int e = 0; e < 4; ++e)
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[i][e], b4[j][e], acc[i][j], 0, 0, 0);
         }
-    }
-    for (; ks < len0; ++ks) {
-        float av[2], bv[2];
+        if (n0 == 0) {
+            const f32x4 *row = reinterpret_cast<const f32x4 *>(&sA[buf][tid >> 1][16 * (tid & 1)]);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            av[i] = (aok[i] && ks < len) ? arow[i][ks] : 0.f;
-            bv[i] = (bok[i] && ks < len) ? brow[i][ks] : 0.f;
-            dbs[i] += av[i];
+            for (int e = 0; e < 4; ++e) dbs += (row[e][0] + row[e][1]) + (row[e][2] + row[e][3]);
         }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        if (st + 1 < nstep) commit(buf ^ 1);
+        __syncthreads();
     }
     float *dst = part + (int64_t)s * M * N;
 #pragma unroll
@@ -142,17 +188,14 @@ __global__ __launch_bounds__(256) void dw_kernel(const float *__restrict__ A, co
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                const int m = m0 + 32 * i + 8 * (q / 4) + 4 * h + (q % 4);
-                const int k = n0 + 32 * j + c;
+                const int m = m0 + wm + 32 * i + 8 * (q / 4) + 4 * h + (q % 4);
+                const int k = n0 + wn + 32 * j + c;
                 if (m < M && k < N) dst[(int64_t)m * N + k] = acc[i][j][q];
             }
     if (n0 == 0) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const float t = dbs[i] + __shfl_xor(dbs[i], 32);
-            const int m = m0 + 32 * i + c;
-            if (h == 0 && m < M) dbpart[(int64_t)s * M + m] = t;
-        }
+        const float t = dbs + __shfl_xor(dbs, 1);
+        const int m = m0 + (tid >> 1);
+        if ((tid & 1) == 0 && m < M) dbpart[(int64_t)s * M + m] = t;
     }
 }
 
@@ -252,8 +295,7 @@ ddf_status param_grads(int width, int depth, int64_t n, const TrainWs &w, float 
         const int N = l == 0 ? kInDim : width;
         const float *A = l == depth ? w.delta + (int64_t)depth * width * n : w.delta + (int64_t)l * width * n;
         const float *B = l == 0 ? w.gamma : w.h + (int64_t)(l - 1) * width * n;
-        const int64_t jobs = (int64_t)((M + kGemmTile - 1) / kGemmTile) * ((N + kGemmTile - 1) / kGemmTile) * splits;
-        const unsigned blocks = (unsigned)((jobs + 3) / 4);
+        const unsigned blocks = (unsigned)(((M + kDwTile - 1) / kDwTile) * ((N + kDwTile - 1) / kDwTile) * splits);
         if (n % 4 == 0)
             hipLaunchKernelGGL(dw_kernel<true>, dim3(blocks), dim3(256), 0, s, A, B, M, N, n, splits, w.part, w.dbpart);
         else
@@ -334,7 +376,7 @@ extern "C" ddf_status ddf_loss_seeds(const float *logit, const float *dist, cons
     float *part = reinterpret_cast<float *>(ws);
     float *scalars = part + 1024;
     unsigned int *count = reinterpret_cast<unsigned int *>(scalars + 4);
-    hipLaunchKernelGGL(loss_scalars_kernel, dim3(1), dim3(256), 0, s, t_label, n, scalars, count);
+    launch_loss_scalars(t_label, n, reinterpret_cast<unsigned int *>(part), scalars, count, s);
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(loss_seeds_kernel, dim3(blocks), dim3(256), 0, s, logit, dist, t_label, n, scalars, g_logit,
                        g_dist, part);
@@ -367,7 +409,7 @@ extern "C" ddf_status ddf_train_step(const ddf_net *net, float *params, float *a
     DDF_REQUIRE(grid <= 4096, DDF_ERR_UNSUPPORTED, "ddf_train_step: grid too large");
     hipStream_t s = as_stream(stream);
     const TrainWs w = train_ws(net->width, net->depth, n, ws);
-    hipLaunchKernelGGL(loss_scalars_kernel, dim3(1), dim3(256), 0, s, t_label, n, w.scalars, w.count);
+    launch_loss_scalars(t_label, n, reinterpret_cast<unsigned int *>(w.loss_part), w.scalars, w.count, s);
     if (ddf_status st = launch_status("ddf_train_step")) return st;
     GradArgs a{};
     a.blob = (const uint8_t *)net->packed;
