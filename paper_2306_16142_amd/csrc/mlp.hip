@@ -628,8 +628,30 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
     const int64_t n = count_dev ? min<int64_t>(*count_dev, stride) : stride;
     const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
 
-    for (int64_t tile = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); tile < ntile; tile += (int64_t)gridDim.x * wpb) {
+    // With the weights in LDS the rays of the next tile are loaded while this one is computed
+    // (HBM latency hides behind the layers instead of stalling the encoding); the L2 variants
+    // have no registers to spare for that and load at the top of the tile.
+    const int64_t tstride = (int64_t)gridDim.x * wpb;
+    float vnext[NB][kInRaw];
+    auto load_rays = [&](int64_t t) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int64_t r = t * 32 * NB + nb * 32 + col;
+#pragma unroll
+            for (int j = 0; j < kInRaw; ++j) vnext[nb][j] = r < n ? rays[(int64_t)j * stride + r] : 0.f;
+        }
+    };
+    int64_t tile = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    if constexpr (kLdsA) load_rays(tile);
+    for (; tile < ntile; tile += tstride) {
         const int64_t base = tile * 32 * NB;
+        if constexpr (!kLdsA) load_rays(tile);
+        float vcur[NB][kInRaw];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < kInRaw; ++j) vcur[nb][j] = vnext[nb][j];
+        if constexpr (kLdsA) load_rays(tile + tstride);
         Op b0[NKB][NB], b1[NKB][NB];   // ping-pong operands of consecutive layers
         bool nan_ray[NB];              // NaN inputs give NaN outputs (ReLU's fmax would hide them)
         bool valid_any = false;
@@ -637,11 +659,7 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int64_t r = base + nb * 32 + col;
-            float v[kInRaw] = {0.f, 0.f, 0.f, 0.f, 0.f};
-            if (r < n) {
-#pragma unroll
-                for (int j = 0; j < kInRaw; ++j) v[j] = rays[(int64_t)j * stride + r];
-            }
+            const float *v = vcur[nb];
             valid_any |= r < n;
             nan_ray[nb] = isnan(v[0]) || isnan(v[1]) || isnan(v[2]) || isnan(v[3]) || isnan(v[4]);
             float feat[kSlotsPerHalf];
