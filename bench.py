@@ -177,12 +177,13 @@ def bench_label_train_render(args, torch, api, dev):
     cfg = synthetic.full_render(args.render_spp)
     net16 = api.Network(params, width, depth, "bf16")
     r = api.Renderer(cfg, net=net16)
-    r.render()
+    r.capture()   # the frame as one HIP graph; path samples/s from its warm replays
+    r.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = 2
     for _ in range(reps):
-        r.render()
+        r.replay()
     torch.cuda.synchronize()
     rs = (time.perf_counter() - t0) / reps
     paths = cfg.width * cfg.height * cfg.spp
@@ -201,7 +202,7 @@ def bench_label_train_render(args, torch, api, dev):
     hit_agree = float((torch.isfinite(rm.depth) == torch.isfinite(rn.depth)).float().mean()) * 100
     out["render"] = {"workload": "1920x1080, %d spp, 4 bounces, RR after bounce 2, bf16 6x256 network "
                                  "(trained %d steps)" % (cfg.spp, 3 + args.train_steps + args.render_train_steps),
-                     "seconds_per_frame": rs, "path_samples_per_s": paths / rs, "paths_per_bounce": stats,
+                     "seconds_per_frame": rs, "path_samples_per_s": paths / rs, "timing": "warm hipGraph replay of the whole frame", "paths_per_bounce": stats,
                      "normal_angle_err_deg_mean": float(ang.mean()) if ang.size else None,
                      "normal_angle_err_deg_median": float(np.median(ang)) if ang.size else None,
                      "primary_hit_agreement_vs_mesh_pct": hit_agree}
@@ -237,12 +238,13 @@ def bench_multi(args, torch, api, dev):
     inst = synthetic.instance_layout(16, 8, seed=10)
     cfg = synthetic.multi_object_render(args.multi_spp)
     r = api.Renderer(cfg, nets=nets, instances=inst)
-    r.render()
+    r.capture()   # one HIP graph per frame (every launch of every bounce and chunk)
+    r.replay()
     torch.cuda.synchronize()
     reps = 2
     t0 = time.perf_counter()
     for _ in range(reps):
-        r.render()
+        r.replay()
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
     paths, per_net = r.path_stats()
@@ -252,6 +254,7 @@ def bench_multi(args, torch, api, dev):
         "workload": "8 objects (seeds 2-9, %s triangles), 16 instances, 1280x720, %d spp, 3 bounces, bf16 networks "
                     "(width, depth) = %s trained %d steps each" % (tris_counts, cfg.spp, shapes, args.multi_train_steps),
         "seconds_per_frame": sec, "path_samples_per_s": cfg.width * cfg.height * cfg.spp / sec,
+        "timing": "warm hipGraph replay of the whole frame",
         "paths_per_bounce": [int(x) for x in paths],
         "pairs_per_network_per_bounce": per_net.astype(np.int64).tolist(),
         "queue_imbalance_max_over_mean": imb}}

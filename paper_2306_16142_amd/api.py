@@ -238,6 +238,23 @@ class Renderer:
                   _p(self.depth), _p(self.normal), _p(self.stats), _p(self.ws), self.ws.numel(), _stream())
         return self.radiance
 
+    def capture(self):
+        """Records one render() into a HIP graph; replay() re-runs it.  The call makes no host
+        synchronisation (every queue count lives in device memory) and clears its outputs with
+        kernels, so the whole frame is capturable.  One eager render runs first so that
+        one-time launch setup stays outside the capture."""
+        self.render()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.render()
+        torch.cuda.synchronize()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+        return self.radiance
+
     def path_stats(self):
         """Paths entering each bounce, and (multi-object scenes) pairs per network per bounce."""
         st = self.stats.cpu().numpy()
