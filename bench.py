@@ -238,6 +238,16 @@ def bench_multi(args, torch, api, dev):
     inst = synthetic.instance_layout(16, 8, seed=10)
     cfg = synthetic.multi_object_render(args.multi_spp)
     r = api.Renderer(cfg, nets=nets, instances=inst)
+
+    def frame():
+        r.render()
+        return [r.radiance, r.depth, r.normal, r.stats]
+
+    # launch shapes of the persistent network kernel and of the culling, chosen by the
+    # autotuner on this scene (outputs checked bit for bit per candidate), then captured
+    from paper_2306_16142_amd import autotune
+    tuned = autotune.tune("multi_object_%dx%d_%dspp" % (cfg.width, cfg.height, cfg.spp), frame,
+                          ["stream_wg_per_cu", "cull_rays_per_block"], reps=5, use_cache=False)
     r.capture()   # one HIP graph per frame (every launch of every bounce and chunk)
     r.replay()
     torch.cuda.synchronize()
@@ -255,6 +265,8 @@ def bench_multi(args, torch, api, dev):
                     "(width, depth) = %s trained %d steps each" % (tris_counts, cfg.spp, shapes, args.multi_train_steps),
         "seconds_per_frame": sec, "path_samples_per_s": cfg.width * cfg.height * cfg.spp / sec,
         "timing": "warm hipGraph replay of the whole frame",
+        "autotune": {"chosen": tuned["chosen"],
+                     "median_ms": {k: {str(v): round(ms, 3) for v, ms in t.items()} for k, t in tuned["median_ms"].items()}},
         "paths_per_bounce": [int(x) for x in paths],
         "pairs_per_network_per_bounce": per_net.astype(np.int64).tolist(),
         "queue_imbalance_max_over_mean": imb}}

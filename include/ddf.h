@@ -98,6 +98,23 @@ ddf_status ddf_label_rays(const float *orig, const float *dir, int64_t n,
 ddf_status ddf_assemble_rays(const float *orig, const float *dir, int64_t n, float *rays_out,
                              ddf_stream stream);
 
+/* ---------------------------------------------------------------- launch tuning
+ * Process-wide launch-shape knobs.  They decide how work is spread over the GPU and
+ * never change a result (each candidate gives bit-identical outputs); an autotuner times
+ * the candidates on a workload and keeps the fastest.  Read when a call launches its
+ * kernels: change knobs between calls, not while another thread is inside a call.
+ * Invalid knob or value: DDF_ERR_INVALID_ARG, nothing changes. */
+#define DDF_TUNE_STREAM_WG_PER_CU 0     /* workgroups per CU of the streamed bf16 network kernel:
+                                           1 or 2 (2 applies where registers and LDS allow it,
+                                           that is width 128); default 2 */
+#define DDF_TUNE_CULL_RAYS_PER_BLOCK 1  /* rays per block of the multi-object instance culling:
+                                           power of two in [256, 16384]; default 2048 */
+#define DDF_TUNE_GRAD_WG_PER_CU 2       /* workgroups per CU of the float32 gradient kernel: 1, 2 or
+                                           4; default 2 */
+#define DDF_TUNE_COUNT 3
+ddf_status ddf_set_tuning(int32_t knob, int32_t value);
+ddf_status ddf_get_tuning(int32_t knob, int32_t *value);
+
 /* ---------------------------------------------------------------- network
  * Size in bytes of the packed blob for a shape and precision. */
 ddf_status ddf_packed_bytes(int32_t width, int32_t depth, int32_t precision, size_t *bytes);

@@ -62,7 +62,11 @@ SIGNATURES = {
     "ddf_render_wavefront": [ctypes.POINTER(DdfScene), ctypes.POINTER(DdfRenderParams), c_p, c_p, c_p, c_p, c_p, c_sz,
                              c_p],
     "ddf_train_step": [ctypes.POINTER(DdfNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64, c_p, c_p, c_p, c_sz, c_p],
+    "ddf_set_tuning": [c_i32, c_i32],
+    "ddf_get_tuning": [c_i32, ctypes.POINTER(c_i32)],
 }
+# launch-shape knobs (DDF_TUNE_* in ddf.h)
+TUNE_KNOBS = {"stream_wg_per_cu": 0, "cull_rays_per_block": 1, "grad_wg_per_cu": 2}
 _RESTYPE = {"ddf_abi_version": c_i32, "ddf_last_error": ctypes.c_char_p}
 
 _lib = None

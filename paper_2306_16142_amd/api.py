@@ -272,3 +272,14 @@ def fp8_scales(params, width, depth, calib_rays, net_fp32=None):
     _lib.call("ddf_fp8_scales", ctypes.byref(net_fp32.desc), _p(params), _p(calib_rays), calib_rays.shape[1],
               _p(out), _stream())
     return out
+
+
+def set_tuning(name, value):
+    """Set a launch-shape knob (``_lib.TUNE_KNOBS``); results do not change, only speed."""
+    _lib.call("ddf_set_tuning", _lib.TUNE_KNOBS[name], int(value))
+
+
+def get_tuning(name):
+    v = ctypes.c_int32(0)
+    _lib.call("ddf_get_tuning", _lib.TUNE_KNOBS[name], ctypes.byref(v))
+    return v.value

@@ -19,6 +19,7 @@
 #include "mlp_device.hpp"
 #include "mlp_layout.hpp"
 #include "grad_args.hpp"
+#include "tuning.hpp"
 
 namespace ddf {
 
@@ -392,11 +393,12 @@ int64_t grad_grid(int width, int precision, int64_t n) {
     const int NB = (width == 128 && precision != kFP32) ? 2 : 1;
     const int wpb = NB == 2 ? 8 : 4;
     const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
-    return std::max<int64_t>(1, std::min<int64_t>((ntile + wpb - 1) / wpb, (int64_t)cu_count_grad() * 2));
+    return std::max<int64_t>(1, std::min<int64_t>((ntile + wpb - 1) / wpb,
+                                                  (int64_t)cu_count_grad() * tuning(DDF_TUNE_GRAD_WG_PER_CU)));
 }
 
 ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, hipStream_t s) {
-    const int cap = cu_count_grad() * 2;
+    const int cap = cu_count_grad() * tuning(DDF_TUNE_GRAD_WG_PER_CU);
     const int w = net->width, p = net->precision;
     if (train) {
         if (w == 128) return p == kBF16 ? launch_grad<kBF16, 128, 2, true>(args, s, cap) : launch_grad<kFP32, 128, 1, true>(args, s, cap);
@@ -408,7 +410,7 @@ ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, h
 
 ddf_status grad_dispatch_multi(int width, int precision, const GradArgs &args, hipStream_t s) {
     DDF_REQUIRE(args.n_nets >= 1 && args.n_nets <= kMaxNets, DDF_ERR_UNSUPPORTED, "too many networks in one launch");
-    const int cap = cu_count_grad() * 2;
+    const int cap = cu_count_grad() * tuning(DDF_TUNE_GRAD_WG_PER_CU);
     if (precision == kBF16) return stream_dispatch(width, args, s);
     return width == 128 ? launch_grad<kFP32, 128, 1, false>(args, s, cap) : launch_grad<kFP32, 256, 1, false>(args, s, cap);
 }

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "tuning.hpp"
 #include "mlp_layout.hpp"
 #include "grad_args.hpp"
 
@@ -741,8 +742,9 @@ ddf_status multi_query(const ddf_scene *scene, const MultiPlan &mp, RenderWs &w,
     NetMap map{};
     for (int k = 0; k < mp.n_nets; ++k) map.user[k] = mp.order[k];
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(kMaxInstances), 0, s, w.mc.inst_count, kMaxInstances);
-    // a few thousand rays per block: one global atomic per block and instance
-    const unsigned gCull = (unsigned)std::max<int64_t>(1, std::min<int64_t>((C + 2047) / 2048, 2048));
+    // a few thousand rays per block (a tuning knob): one global atomic per block and instance
+    const int64_t rpb = tuning(DDF_TUNE_CULL_RAYS_PER_BLOCK);
+    const unsigned gCull = (unsigned)std::max<int64_t>(1, std::min<int64_t>((C + rpb - 1) / rpb, 8192));
     hipLaunchKernelGGL(cull_kernel<false>, dim3(gCull), dim3(kCullBlock), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);
     hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(64), 0, s, mp.n_inst, w.inst, mp.n_nets, w.mc, net_stats, map);
     hipLaunchKernelGGL(cull_kernel<true>, dim3(gCull), dim3(kCullBlock), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);

@@ -21,6 +21,7 @@
 #include "grad_args.hpp"
 #include "mlp_device.hpp"
 #include "mlp_layout.hpp"
+#include "tuning.hpp"
 
 namespace ddf {
 namespace {
@@ -554,9 +555,9 @@ ddf_status launch_stream(const GradArgs &args, hipStream_t s) {
                 "streamed network kernel: depth 1..8 and at most %d networks", kMaxNets);
     const size_t lds = stream_lds_bytes(W, args.depth, nk, kGrad);
     DDF_REQUIRE(lds <= (size_t)kMaxStreamLds, DDF_ERR_UNSUPPORTED, "network too deep for the streamed kernel");
-    // persistent: two waves per SIMD (one workgroup of eight waves at width 256, two of four
-    // at width 128 when their LDS fits)
-    const int per_cu = W == 128 && lds * 2 <= (size_t)kMaxStreamLds ? 2 : 1;
+    // persistent: one workgroup of eight waves per CU at width 256; at width 128 one or two
+    // workgroups of four waves (a tuning knob; two only when their LDS fits)
+    const int per_cu = W == 128 && lds * 2 <= (size_t)kMaxStreamLds ? tuning(DDF_TUNE_STREAM_WG_PER_CU) : 1;
     const int64_t tiles_hint = (args.n + kRaysPerTile - 1) / kRaysPerTile + nk;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles_hint, (int64_t)cu_count_stream() * per_cu));
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(Geo<W>::kWaves * 64), lds, s, args);

@@ -104,3 +104,21 @@ def test_workspace_sizes(lib):
     p.bounces = 3
     assert lib.ddf_render_wavefront(ctypes.byref(scene), ctypes.byref(p), 1, None, None, None, 1, 16, None) == \
         _lib.DDF_ERR_WORKSPACE
+
+
+def test_tuning_knobs_validate_and_round_trip(lib):
+    from paper_2306_16142_amd import _lib
+    v = ctypes.c_int32(0)
+    defaults = {"stream_wg_per_cu": 2, "cull_rays_per_block": 2048, "grad_wg_per_cu": 2}
+    for name, knob in _lib.TUNE_KNOBS.items():
+        assert lib.ddf_get_tuning(knob, ctypes.byref(v)) == _lib.DDF_OK
+        assert v.value == defaults[name]
+    assert lib.ddf_set_tuning(99, 1) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_set_tuning(_lib.TUNE_KNOBS["stream_wg_per_cu"], 3) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_set_tuning(_lib.TUNE_KNOBS["cull_rays_per_block"], 3000) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_set_tuning(_lib.TUNE_KNOBS["grad_wg_per_cu"], 3) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_get_tuning(0, None) == _lib.DDF_ERR_INVALID_ARG
+    k = _lib.TUNE_KNOBS["cull_rays_per_block"]
+    assert lib.ddf_set_tuning(k, 4096) == _lib.DDF_OK
+    assert lib.ddf_get_tuning(k, ctypes.byref(v)) == _lib.DDF_OK and v.value == 4096
+    assert lib.ddf_set_tuning(k, 2048) == _lib.DDF_OK

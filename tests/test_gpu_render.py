@@ -188,3 +188,31 @@ def test_render_graph_replay_matches_eager(backend):
         torch.cuda.synchronize()
         for got, want in zip([r.radiance, r.depth, r.normal, r.stats], ref):
             assert torch.equal(got, want)
+
+
+def test_autotune_knobs_keep_results_identical(tmp_path):
+    """Every candidate of the launch-shape knobs gives the same multi-object frame bit for bit
+    (the tuner raises otherwise), and the tuner leaves the fastest value set and cached."""
+    from paper_2306_16142_amd import autotune
+    banner("autotune: multi-object 40x24 3spp 3 bounces, stream and cull knobs")
+    cfg = synthetic.RenderConfig(40, 24, 3, 3, 1, 9)
+    cfg.camera.eye = (0.0, -7.0, 1.5)
+    _, inst, nets = _multi_setup("bf16")
+    r = api.Renderer(cfg, nets=nets, instances=inst, spp_chunk=2)
+
+    def run():
+        r.render()
+        return [r.radiance, r.depth, r.normal, r.stats]
+
+    path = str(tmp_path / "tune.json")
+    try:
+        res = autotune.tune("test_multi", run, ["stream_wg_per_cu", "cull_rays_per_block"], reps=3, path=path)
+        assert not res["cached"]
+        for knob, v in res["chosen"].items():
+            assert api.get_tuning(knob) == v
+            assert len(res["median_ms"][knob]) == len(autotune.CANDIDATES[knob])
+        again = autotune.tune("test_multi", run, ["stream_wg_per_cu"], path=path)
+        assert again["cached"] and again["chosen"] == res["chosen"]
+    finally:
+        api.set_tuning("stream_wg_per_cu", 2)
+        api.set_tuning("cull_rays_per_block", 2048)
