@@ -115,6 +115,45 @@ __device__ inline int append(int *counter, bool want) {
     return want ? base + rank : -1;
 }
 
+// Block-aggregated append to two queues at once: every thread of the block must call it
+// (the same number of times).  Waves rank their lanes with ballots, wave leaders take
+// offsets from LDS counters, and one thread per block reserves the block's ranges in the
+// global counters: two global atomics per block and call instead of two per wave (on the
+// same two counters, per-wave atomics serialise).  Slot order inside a queue varies between
+// runs; consumers address paths by id, so results do not.
+struct Append2 {
+    int a, b;   // per-wave offsets (LDS), then the block bases
+};
+
+__device__ inline void block_append2(int *ctr_a, bool want_a, int *ctr_b, bool want_b, Append2 *s, int &slot_a,
+                                     int &slot_b) {
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) {
+        s->a = 0;
+        s->b = 0;
+    }
+    __syncthreads();
+    const uint64_t ma = __ballot(want_a), mb = __ballot(want_b);
+    const uint64_t below = (1ull << lane) - 1ull;
+    int wa = 0, wb = 0;
+    if (lane == 0) {
+        wa = ma ? atomicAdd(&s->a, (int)__popcll(ma)) : 0;
+        wb = mb ? atomicAdd(&s->b, (int)__popcll(mb)) : 0;
+    }
+    wa = __shfl(wa, 0);
+    wb = __shfl(wb, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int ta = s->a, tb = s->b;
+        s->a = ta ? atomicAdd(ctr_a, ta) : 0;
+        s->b = tb ? atomicAdd(ctr_b, tb) : 0;
+    }
+    __syncthreads();
+    slot_a = want_a ? s->a + wa + (int)__popcll(ma & below) : -1;
+    slot_b = want_b ? s->b + wb + (int)__popcll(mb & below) : -1;
+    __syncthreads();   // s is reused by the next call
+}
+
 // ------------------------------------------------------------------------------ multi-object
 struct InstDev {
     float R[9];
@@ -335,8 +374,9 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
     const int n = counts[2 * bounce];
     const Vec3 light = v3(p.light_pos[0], p.light_pos[1], p.light_pos[2]);
     const int64_t hw = (int64_t)p.width * p.height;
-    // every lane of a wave reaches both appends (wave-aggregated atomics)
-    const int64_t span = ((int64_t)n + 63) / 64 * 64;
+    // every thread of the block reaches the append (block-aggregated atomics)
+    __shared__ Append2 s_app;
+    const int64_t span = ((int64_t)n + blockDim.x - 1) / blockDim.x * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < span; q += (int64_t)gridDim.x * blockDim.x) {
         bool hit = false, shadow = false, alive = false;
         int id = 0;
@@ -423,7 +463,8 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
                 }
             }
         }
-        const int sslot = append(&counts[2 * bounce + 1], shadow);
+        int sslot, nslot;
+        block_append2(&counts[2 * bounce + 1], shadow, &counts[2 * (bounce + 1)], alive, &s_app, sslot, nslot);
         if (shadow) {
             sq[sslot] = id;
             stmax[sslot] = r;
@@ -438,7 +479,6 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
                 store3(srays + 3 * C, C, sslot, l);
             }
         }
-        const int nslot = append(&counts[2 * (bounce + 1)], alive);
         if (alive) next_queue[nslot] = id;
     }
 }
