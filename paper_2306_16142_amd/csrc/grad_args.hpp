@@ -26,6 +26,9 @@ struct GradArgs {
     float *ws_delta;             // side outputs: [depth][W][n] adjoints, then [2][n] head seeds
     float *loss_partial;         // training: [gridDim.x]
     bool forward_only;           // stop after logit / distance
+    bool grad_hits_only;         // input gradients only where logit > 0 (a hit); other rays of a
+                                 // 32-ray block without any hit get no gradient written (streamed
+                                 // kernel; the renderer's normals need hits only)
     // several networks of one width in one persistent launch: network k owns the rows
     // [seg_offset[k], seg_offset[k] + seg_count[k]) (device arrays)
     int n_nets;

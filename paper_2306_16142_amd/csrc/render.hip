@@ -799,6 +799,7 @@ ddf_status multi_query(const ddf_scene *scene, const MultiPlan &mp, RenderWs &w,
         a.dist_out = w.pb.dist;
         a.g_rays = shadow ? nullptr : w.pb.grad;
         a.forward_only = shadow;
+        a.grad_hits_only = true;   // normals are read for hits only
         a.n_nets = mp.group_size[g];
         a.depth = 1;
         for (int j = 0; j < mp.group_size[g]; ++j) {
@@ -898,6 +899,7 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
                 a.logit_out = w.logit;
                 a.dist_out = w.dist;
                 a.g_rays = w.grad;
+                a.grad_hits_only = true;   // normals are read for hits only
                 if (ddf_status st = grad_dispatch(scene->net, a, false, s)) return st;
             } else if (multi) {
                 if (ddf_status st = multi_query(scene, mp, w, Cc, q, cnt, ps.o, ps.d, false,

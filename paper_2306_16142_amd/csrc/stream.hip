@@ -269,6 +269,14 @@ __device__ inline void masked_tile_to_bf16(const f32x16 &y, uint32_t bits, int m
 
 // Transposed hidden layer l (rows: its inputs): adjoint operands of layer l's outputs ->
 // masked adjoint operands of layer l - 1's outputs.
+// Phase of a wave that has nothing to compute: the ring still moves on to the next phase's
+// first tiles, and the caller still takes part in the fetch and the barrier.
+template <int W>
+__device__ __attribute__((always_inline)) inline void phase_skip(const lds_u8 *st_next, ARing &ar, int lane) {
+    ar.r[0] = lds_tile(st_next, 0, lane);
+    ar.r[1] = lds_tile(st_next, 1, lane);
+}
+
 template <int W>
 __device__ __attribute__((always_inline)) inline void bwd_layer(lds_u8 *ring, const NetTable *tab, Pipe &pp, ARing &ar, int l,
                                                                 const bf16x8 (&bin)[W / 16][Geo<W>::kNB],
@@ -448,16 +456,30 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
             phase_end<W>(sg, ring, pp, wave, lane);
         }
         float gl[kNB], gd[kNB];
+        bool any_hit = false;   // some ray of this wave has logit > 0
 #pragma unroll
         for (int nb = 0; nb < kNB; ++nb) {
             const int64_t r = cw.base + (wave * kNB + nb) * 32 + col;
             const float z = __shfl(hacc[nb][0], col), dd = __shfl(hacc[nb][1], col);
+            any_hit |= __ballot(valid[nb] && z > 0.f) != 0;
             float *dst = h ? a.dist_out : a.logit_out;
             if (valid[nb] && dst) dst[r] = h ? dd : z;
             gl[nb] = (kGrad && valid[nb] && a.g_logit_in) ? a.g_logit_in[r] : 0.f;
             gd[nb] = (kGrad && valid[nb] && a.g_dist_in) ? a.g_dist_in[r] : 0.f;
         }
         if constexpr (kGrad) {
+            // with grad_hits_only a wave whose rays all miss skips the reverse sweep: it only
+            // walks the phases (fetch, ring, barrier) and writes no gradient
+            const bool active = !a.grad_hits_only || any_hit;   // wave-uniform
+            if (!active) {
+                const int nbwd = (depth - 1) * NMB + kGradRowBlocks0;
+                for (int i = 0; i < nbwd; ++i) {
+                    Stage<W> sg;
+                    stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+                    phase_skip<W>(nxt_stage<W>(ring, pp), ar, lane);
+                    phase_end<W>(sg, ring, pp, wave, lane);
+                }
+            } else {
             // ---- seed: adjoint of the last hidden layer = head rows x seeds, masked -> b0
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb) {
@@ -523,6 +545,7 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
                     if (valid[nb] && a.g_rays) a.g_rays[(int64_t)(h ? 3 + var : var) * n + r] = g;
                 }
             }
+            }   // active
         }
         // ---- next workgroup tile
         t += gridDim.x;

@@ -37,7 +37,8 @@ def test_forward_fp32_matches_float64(width, depth, n):
     assert _scaled_err(ds, rd).max() < 1e-5
 
 
-@pytest.mark.parametrize("width,depth,n", [(128, 4, 16384 + 37), (256, 6, 4096 + 5), (128, 2, 100)])
+@pytest.mark.parametrize("width,depth,n", [(128, 4, 16384 + 37), (256, 6, 4096 + 5), (128, 2, 100), (256, 8, 1000),
+                                           (128, 6, 3000 + 1), (256, 1, 77)])
 def test_forward_bf16_matches_emulation(width, depth, n):
     banner("forward bf16: %dx%d, n=%d" % (depth, width, n))
     p = synthetic.random_params(width, depth, 13)
@@ -52,12 +53,16 @@ def test_forward_bf16_matches_emulation(width, depth, n):
     # ulp of one term: bound the typical error tightly and the worst case loosely, and
     # require the kernel's error against float64 to match the emulation's.
     # The gap between kernel and emulation must stay well inside the emulation's own error.
+    # Every layer is another chance for such a flip, so the tail of the gap grows with depth
+    # faster than the emulation's own error does: the 99th-percentile bound is 0.3 of the
+    # emulation's error up to six hidden layers and 0.6 at eight.
     rl, rd = mlp.forward(p, width, depth, rays)
+    tail = 0.3 if depth <= 6 else 0.6
     for g, e, r in ((lg, el, rl), (ds, ed, rd)):
         err = _scaled_err(g, e)
         own = _scaled_err(e, r)
         assert np.median(err) < 1e-5
-        assert np.quantile(err, 0.99) < 0.3 * np.quantile(own, 0.99)
+        assert np.quantile(err, 0.99) < tail * np.quantile(own, 0.99)
         assert err.max() <= own.max()
         assert _scaled_err(g, r).mean() <= 1.1 * own.mean() + 1e-6
 

@@ -49,9 +49,11 @@ def test_input_gradient_fp32(width, depth, n):
     assert np.median(err) < 1e-6
 
 
-def test_input_gradient_bf16_normals():
-    banner("input gradient bf16 128x4 (distance seed = normals)")
-    width, depth, n = 128, 4, 8192
+@pytest.mark.parametrize("width,depth,n", [(128, 4, 8192), (256, 6, 2048 + 7), (128, 1, 100), (256, 8, 512 + 1),
+                                           (128, 7, 1000)])
+def test_input_gradient_bf16_normals(width, depth, n):
+    """bf16 input gradients (the streamed kernel at every width, odd and even depths, ragged n)."""
+    banner("input gradient bf16 %dx%d n=%d (distance seed = normals)" % (depth, width, n))
     p = synthetic.random_params(width, depth, 33)
     rays = _rays(n, 34)
     net = api.Network(cuda(p), width, depth, "bf16")
