@@ -144,6 +144,14 @@ ddf_status ddf_fp8_scales(const ddf_net *net_fp32, const float *params, const fl
 ddf_status ddf_forward(const ddf_net *net, const float *rays, int64_t n,
                        float *logit_out, float *dist_out, ddf_stream stream);
 
+/* The same query straight from origins orig [3][n] and unit directions dir [3][n] (device,
+ * float32, row r of ray i at r * n + i): ray assembly (as ddf_assemble_rays, Eq. 1 read
+ * backwards) and the network in one kernel, results bit-identical to ddf_assemble_rays
+ * followed by ddf_forward.  Needs a bf16 or fp8 network whose packed weights fit in one
+ * CU's LDS (width 128, depth <= 4); other networks: DDF_ERR_UNSUPPORTED. */
+ddf_status ddf_query(const ddf_net *net, const float *orig, const float *dir, int64_t n, float *logit_out,
+                     float *dist_out, ddf_stream stream);
+
 /* ---------------------------------------------------------------- gradients
  * Reverse-mode gradient of sum(g_logit * logit + g_dist * dist) over the batch.  The
  * input gradient's origin part is the derivative of the field with respect to the

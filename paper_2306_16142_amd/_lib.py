@@ -54,6 +54,7 @@ SIGNATURES = {
     "ddf_pack_net": [c_p, c_i32, c_i32, c_i32, c_p, c_p, c_p],
     "ddf_fp8_scales": [ctypes.POINTER(DdfNet), c_p, c_p, c_i64, c_p, c_p],
     "ddf_forward": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_p, c_p],
+    "ddf_query": [ctypes.POINTER(DdfNet), c_p, c_p, c_i64, c_p, c_p, c_p],
     "ddf_train_workspace_size": [c_i32, c_i32, c_i64, ctypes.POINTER(c_sz)],
     "ddf_backward": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_p, c_p, c_p, c_u32, c_p, c_sz, c_p],
     "ddf_loss_seeds": [c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_p, c_sz, c_p],

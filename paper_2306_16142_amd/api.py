@@ -89,6 +89,19 @@ class Network:
 
     __call__ = forward
 
+    def query(self, orig, dirs, logit=None, dist=None):
+        """origins [3][n] + unit directions [3][n] -> (logit [n], dist [n]) in one kernel
+        (bf16 / fp8 networks held in LDS; equal to assemble_rays + forward)."""
+        _dev(orig, torch.float32, "orig", 3)
+        _dev(dirs, torch.float32, "dirs", 3)
+        n = orig.shape[1]
+        if dirs.shape[1] != n:
+            raise ValueError("orig and dirs differ in length")
+        logit = torch.empty(n, device=orig.device, dtype=torch.float32) if logit is None else logit
+        dist = torch.empty(n, device=orig.device, dtype=torch.float32) if dist is None else dist
+        _lib.call("ddf_query", ctypes.byref(self.desc), _p(orig), _p(dirs), n, _p(logit), _p(dist), _stream())
+        return logit, dist
+
 
 def train_workspace_bytes(width, depth, n):
     b = ctypes.c_size_t(0)

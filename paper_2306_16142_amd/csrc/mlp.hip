@@ -17,6 +17,7 @@
 #include "mlp_device.hpp"
 #include "mlp_layout.hpp"
 #include "grad_args.hpp"
+#include "rays_device.hpp"
 
 namespace ddf {
 namespace {
@@ -554,11 +555,13 @@ __device__ __attribute__((always_inline)) inline void head_out(const uint8_t *ws
 
 // W: width, NB: 32-ray column blocks per wave, P: precision, kLdsA: weights in LDS,
 // kCalib: record per-layer input absmax (fp8 calibration) instead of writing outputs.
-template <int P, int W, int NB, bool kLdsA, bool kCalib>
+// kOD: the inputs are origins [3][stride] (`rays`) and unit directions [3][stride] (`dirs`),
+// assembled into the 5-value query in registers (one kernel for ray assembly and query).
+template <int P, int W, int NB, bool kLdsA, bool kCalib, bool kOD = false>
 __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
     const uint8_t *__restrict__ blob, int depth, const float *__restrict__ rays, int64_t stride,
     const int *__restrict__ count_dev, float *__restrict__ logit_out, float *__restrict__ dist_out,
-    unsigned int *__restrict__ absmax) {
+    unsigned int *__restrict__ absmax, const float *__restrict__ dirs = nullptr) {
     using Op = typename OpOf<P>::T;
     constexpr int KB = k_per_block(P);
     constexpr int NKB = W / KB;
@@ -633,12 +636,22 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
     // have no registers to spare for that and load at the top of the tile.
     const int64_t tstride = (int64_t)gridDim.x * wpb;
     float vnext[NB][kInRaw];
+    float dz_next[NB];   // kOD: third direction component
     auto load_rays = [&](int64_t t) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int64_t r = t * 32 * NB + nb * 32 + col;
+            if constexpr (kOD) {
 #pragma unroll
-            for (int j = 0; j < kInRaw; ++j) vnext[nb][j] = r < n ? rays[(int64_t)j * stride + r] : 0.f;
+                for (int j = 0; j < 3; ++j) vnext[nb][j] = r < n ? rays[(int64_t)j * stride + r] : 0.f;
+                // the direction is kept raw here and turned into angles at the encoding
+                vnext[nb][3] = r < n ? dirs[r] : 0.f;
+                vnext[nb][4] = r < n ? dirs[stride + r] : 0.f;
+                dz_next[nb] = r < n ? dirs[2 * stride + r] : 1.f;
+            } else {
+#pragma unroll
+                for (int j = 0; j < kInRaw; ++j) vnext[nb][j] = r < n ? rays[(int64_t)j * stride + r] : 0.f;
+            }
         }
     };
     int64_t tile = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
@@ -648,9 +661,21 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
         if constexpr (!kLdsA) load_rays(tile);
         float vcur[NB][kInRaw];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
+        for (int nb = 0; nb < NB; ++nb) {
 #pragma unroll
             for (int j = 0; j < kInRaw; ++j) vcur[nb][j] = vnext[nb][j];
+            if constexpr (kOD) {
+                // lane half 0 takes the polar angle, half 1 the azimuth (one atan2 per lane), and
+                // the partner lane (l xor 32, the same ray) passes the other one across
+                const float dx = vnext[nb][3], dy = vnext[nb][4];
+                const float ay = h ? dy : polar_y(dx, dy), ax = h ? dx : dz_next[nb];
+                float ang = atan2f(ay, ax);
+                if (h) ang = wrap_azimuth(ang);
+                const float other = __shfl_xor(ang, 32);
+                vcur[nb][3] = h ? other : ang;   // theta
+                vcur[nb][4] = h ? ang : other;   // phi
+            }
+        }
         if constexpr (kLdsA) load_rays(tile + tstride);
         Op b0[NKB][NB], b1[NKB][NB];   // ping-pong operands of consecutive layers
         bool nan_ray[NB];              // NaN inputs give NaN outputs (ReLU's fmax would hide them)
@@ -817,30 +842,41 @@ int cu_count() {
 
 template <int P, int W, int NB, bool kLdsA>
 ddf_status launch_forward(const NetLayout &L, const void *blob, const float *rays, int64_t n, const int *count_dev,
-                          float *logit, float *dist, unsigned int *absmax, hipStream_t stream) {
+                          float *logit, float *dist, unsigned int *absmax, hipStream_t stream,
+                          const float *dirs = nullptr) {
     if (absmax) {
         if constexpr (P == kFP32 && !kLdsA) {
             auto kc = forward_kernel<P, W, NB, kLdsA, true>;
             const int threads = NB == 2 ? 512 : 256;
             const size_t lds = ((size_t)W * L.depth + 4) * 4 + sizeof(LdsConsts);
             hipLaunchKernelGGL(kc, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 32 * NB * 4 - 1) / (32 * NB * 4), 512))),
-                               dim3(threads), lds, stream, (const uint8_t *)blob, L.depth, rays, n, count_dev, logit, dist, absmax);
+                               dim3(threads), lds, stream, (const uint8_t *)blob, L.depth, rays, n, count_dev, logit, dist, absmax,
+                               (const float *)nullptr);
             return launch_status("ddf_fp8_scales (calibration)");
         }
         set_error("calibration runs on float32 networks only");
         return DDF_ERR_UNSUPPORTED;
     }
     auto kern = forward_kernel<P, W, NB, kLdsA, false>;
+    if constexpr (kLdsA) {   // the fused ray assembly exists for the LDS kernels only
+        if (dirs) kern = forward_kernel<P, W, NB, kLdsA, false, true>;
+    }
     const size_t lds = (kLdsA ? L.tiles * tile_bytes(P) : 0) + ((size_t)W * L.depth + 4) * 4 + sizeof(LdsConsts);
     static std::once_flag once;
-    std::call_once(once, [&] { (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes); });
+    std::call_once(once, [&] {
+        (void)hipFuncSetAttribute((const void *)forward_kernel<P, W, NB, kLdsA, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if constexpr (kLdsA)
+            (void)hipFuncSetAttribute((const void *)forward_kernel<P, W, NB, kLdsA, false, true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    });
     const int threads = NB == 2 ? 512 : 256;
     const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
     const int64_t wpb = threads / 64;
     const int per_cu = kLdsA ? 1 : 2;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((ntile + wpb - 1) / wpb, (int64_t)cu_count() * per_cu));
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, (const uint8_t *)blob, L.depth, rays, n,
-                       count_dev, logit, dist, absmax);
+                       count_dev, logit, dist, absmax, dirs);
     return launch_status("ddf_forward");
 }
 
@@ -934,6 +970,23 @@ extern "C" ddf_status ddf_fp8_scales(const ddf_net *net_fp32, const float *param
     hipLaunchKernelGGL(weight_absmax_kernel, dim3(net_fp32->depth + 1), dim3(256), 0, s, params, net_fp32->width,
                        net_fp32->depth, scales_out);
     return launch_status("ddf_fp8_scales");
+}
+
+extern "C" ddf_status ddf_query(const ddf_net *net, const float *orig, const float *dir, int64_t n, float *logit_out,
+                                float *dist_out, ddf_stream stream) {
+    DDF_REQUIRE(net, DDF_ERR_INVALID_ARG, "ddf_query: NULL network");
+    if (ddf_status st = check_shape(net->width, net->depth, net->precision, "ddf_query")) return st;
+    DDF_REQUIRE(n >= 0, DDF_ERR_INVALID_ARG, "ddf_query: negative n");
+    if (n == 0) return DDF_OK;
+    DDF_REQUIRE(net->packed && orig && dir && logit_out && dist_out, DDF_ERR_INVALID_ARG, "ddf_query: NULL array");
+    const NetLayout L = make_layout(net->width, net->depth, net->precision);
+    DDF_REQUIRE(net->width == 128 && net->precision != kFP32 && fits_lds(L), DDF_ERR_UNSUPPORTED,
+                "ddf_query: needs a bf16 or fp8 network whose weights fit in LDS (width 128); use "
+                "ddf_assemble_rays + ddf_forward otherwise");
+    hipStream_t s = as_stream(stream);
+    if (net->precision == kBF16)
+        return launch_forward<kBF16, 128, 2, true>(L, net->packed, orig, n, nullptr, logit_out, dist_out, nullptr, s, dir);
+    return launch_forward<kFP8, 128, 2, true>(L, net->packed, orig, n, nullptr, logit_out, dist_out, nullptr, s, dir);
 }
 
 extern "C" ddf_status ddf_forward(const ddf_net *net, const float *rays, int64_t n, float *logit_out, float *dist_out,

@@ -3,21 +3,16 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "rays_device.hpp"
 
 namespace ddf {
 namespace {
 
-constexpr float kTwoPi = 6.28318530717958647692f;
-constexpr float kBelowTwoPi = 6.28318500518798828125f;   // largest float32 below fl(2 pi)
-
 __global__ void assemble_kernel(const float *__restrict__ orig, const float *__restrict__ dir, int64_t n,
                                 float *__restrict__ rays) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float dx = dir[i], dy = dir[n + i], dz = dir[2 * n + i];
-        const float theta = atan2f(sqrtf(dx * dx + dy * dy), dz);
-        float phi = atan2f(dy, dx);
-        if (phi < 0.f) phi += kTwoPi;
-        if (phi >= kTwoPi) phi = kBelowTwoPi;
+        float theta, phi;
+        dir_angles(dir[i], dir[n + i], dir[2 * n + i], theta, phi);
         rays[i] = orig[i];
         rays[n + i] = orig[n + i];
         rays[2 * n + i] = orig[2 * n + i];

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "rays_device.hpp"
 #include "tuning.hpp"
 #include "mlp_layout.hpp"
 #include "grad_args.hpp"
@@ -91,10 +92,8 @@ __device__ inline float cube_entry(Vec3 o, Vec3 d) {
 __device__ inline void write_query(float *rays5, int64_t stride, int64_t q, Vec3 o, Vec3 d, float t0) {
     const float t = isnan(t0) ? 0.f : t0;
     const Vec3 p = o + t * d;
-    const float theta = atan2f(sqrtf(d.x * d.x + d.y * d.y), d.z);
-    float phi = atan2f(d.y, d.x);
-    if (phi < 0.f) phi += kTwoPi;
-    if (phi >= kTwoPi) phi = kBelowTwoPi;
+    float theta, phi;
+    dir_angles(d.x, d.y, d.z, theta, phi);
     rays5[q] = p.x;
     rays5[stride + q] = p.y;
     rays5[2 * stride + q] = p.z;

@@ -28,7 +28,7 @@ def lib():
 def test_header_declares_the_hot_path():
     names = _declared()
     for required in ("ddf_label_rays", "ddf_forward", "ddf_backward", "ddf_render_wavefront", "ddf_pack_net",
-                     "ddf_train_step", "ddf_assemble_rays"):
+                     "ddf_train_step", "ddf_assemble_rays", "ddf_query", "ddf_set_tuning"):
         assert required in names
 
 
@@ -65,6 +65,13 @@ def test_validation_before_launch(lib):
     net = _lib.DdfNet(128, 4, 1, None)
     assert lib.ddf_forward(ctypes.byref(net), None, 10, None, None, None) == _lib.DDF_ERR_INVALID_ARG
     assert lib.ddf_forward(None, None, 10, None, None, None) == _lib.DDF_ERR_INVALID_ARG
+    # fused query: NULL arrays rejected, n == 0 a no-op, networks beyond LDS or fp32 refused
+    assert lib.ddf_query(ctypes.byref(net), None, None, 10, None, None, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_query(ctypes.byref(net), None, None, 0, None, None, None) == _lib.DDF_OK
+    wide = _lib.DdfNet(256, 4, 1, 1)
+    assert lib.ddf_query(ctypes.byref(wide), 1, 1, 10, 1, 1, None) == _lib.DDF_ERR_UNSUPPORTED
+    f32 = _lib.DdfNet(128, 4, 0, 1)
+    assert lib.ddf_query(ctypes.byref(f32), 1, 1, 10, 1, 1, None) == _lib.DDF_ERR_UNSUPPORTED
     # parameter gradients need a float32 network; fp8 cannot give input gradients
     net = _lib.DdfNet(128, 4, 1, 1)
     assert lib.ddf_backward(ctypes.byref(net), 1, 10, None, None, None, 1, 0, None, 0, None) == _lib.DDF_ERR_UNSUPPORTED

@@ -144,3 +144,26 @@ def test_fp8_scales_not_powers_of_two_give_nan():
         assert np.all(np.isnan(host(out[0]))) and np.all(np.isnan(host(out[1])))
         out = api.Network(cuda(p), width, depth, "fp8", scales=cuda(good))(cuda(rays))
         assert np.all(np.isfinite(host(out[0]))) and np.all(np.isfinite(host(out[1])))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_query_from_directions_equals_assembly_then_forward(prec):
+    """ddf_query (ray assembly fused into the network kernel) gives exactly the outputs of
+    ddf_assemble_rays followed by ddf_forward, ragged tail and NaN rays included."""
+    banner("query from directions (%s 4x128), n=70000" % prec)
+    n = 70000
+    o, d = synthetic.uniform_cube_rays(n, 21)
+    d[:, 17] = np.nan   # a NaN direction gives NaN outputs on both paths
+    p = synthetic.random_params(128, 4, 22)
+    og, dg = cuda(o), cuda(d)
+    scales = api.fp8_scales(cuda(p), 128, 4, api.assemble_rays(og, dg)[:, :4096].contiguous()) if prec == "fp8" else None
+    net = api.Network(cuda(p), 128, 4, prec, scales=scales)
+    l1, d1 = net(api.assemble_rays(og, dg))
+    l2, d2 = net.query(og, dg)
+    assert torch.equal(torch.nan_to_num(l1, nan=7.0), torch.nan_to_num(l2, nan=7.0))
+    assert torch.equal(torch.nan_to_num(d1, nan=7.0), torch.nan_to_num(d2, nan=7.0))
+    assert torch.isnan(l2[17]) and torch.isfinite(l2[:17]).all()
+    # networks that do not fit in LDS are refused
+    wide = api.Network(cuda(synthetic.random_params(256, 2, 23)), 256, 2, "bf16")
+    with pytest.raises(Exception):
+        wide.query(og, dg)
