@@ -9,16 +9,53 @@ namespace ddf {
 constexpr float kFp8Max = 448.0f;
 
 // ------------------------------------------------------------------------------ encoding
+// sin and cos of one float32 argument of moderate size (|v| <= kSinCosFastMax), written from
+// the mathematics: Cody-Waite reduction r = v - j pi/2, j = nearest integer to v 2/pi, with
+// pi/2 split into three float32 parts C1 + C2 + C3 (C1 = fl(pi/2), C2 = fl(pi/2 - C1),
+// C3 = fl(pi/2 - C1 - C2)) applied by fused multiply-adds; the Taylor series of sin to r^9
+// and of cos to r^10 on |r| <= pi/4 (truncation below 2e-9); the quadrant j mod 4 picks and
+// signs the pair.  Absolute error below 7.1e-8 (1.2 float32 ulp of 1) over the range.  A
+// wavefront holding any larger, infinite or NaN argument calls sincosf for all its lanes, so
+// the general reduction costs nothing on the usual inputs (coordinates and angles).
+constexpr float kSinCosFastMax = 1024.f;
+
+__device__ inline void sincos_moderate(float v, float &s, float &c) {
+    if (__builtin_expect(__any(!(fabsf(v) <= kSinCosFastMax)), 0)) {
+        sincosf(v, &s, &c);
+        return;
+    }
+    const float j = __builtin_rintf(v * 0x1.45f306p-1f);   // 2/pi
+    float r = fmaf(-j, 0x1.921fb6p+0f, v);
+    r = fmaf(-j, -0x1.777a5cp-25f, r);
+    r = fmaf(-j, -0x1.ee59dap-50f, r);
+    const float r2 = r * r;
+    float ps = fmaf(r2, 0x1.71de3ap-19f, -0x1.a01a02p-13f);   // 1/9!, -1/7!
+    ps = fmaf(r2, ps, 0x1.111112p-7f);                         // 1/5!
+    ps = fmaf(r2, ps, -0x1.555556p-3f);                        // -1/3!
+    const float sr = fmaf(r * r2, ps, r);
+    float pc = fmaf(r2, -0x1.27e4fcp-22f, 0x1.a01a02p-16f);    // -1/10!, 1/8!
+    pc = fmaf(r2, pc, -0x1.6c16c2p-10f);                       // -1/6!
+    pc = fmaf(r2, pc, 0x1.555556p-5f);                         // 1/4!
+    pc = fmaf(r2, pc, -0.5f);
+    const float cr = fmaf(r2, pc, 1.0f);
+    const int q = (int)j;
+    const bool odd = q & 1;
+    const float so = odd ? cr : sr, co = odd ? sr : cr;
+    s = __uint_as_float(__float_as_uint(so) ^ ((uint32_t)(q & 2) << 30));
+    c = __uint_as_float(__float_as_uint(co) ^ ((uint32_t)((q + 1) & 2) << 30));
+}
+
 // Features of one variable: raw, sin(2^k v), cos(2^k v), k = 0..5.  In float32 mode every
-// frequency calls sincosf (arguments 2^k v are exact); in reduced precision the higher
-// frequencies follow the double-angle recurrence from the k = 0 values.  (The hardware
-// sine was tried for the base frequency: its error, amplified 32x by the recurrence,
-// flipped visibly more bf16 roundings than float32 rounding does.)
+// frequency calls sincosf (arguments 2^k v are exact); in reduced precision the base pair
+// comes from sincos_moderate and the higher frequencies follow the double-angle recurrence.
+// (The hardware sine was tried for the base frequency: its error, amplified 32x by the
+// recurrence, flipped visibly more bf16 roundings than float32 rounding does.)
 template <bool kExact>
 __device__ inline void encode_var(float v, float *f) {
     f[0] = v;
     float s, c;
-    sincosf(v, &s, &c);
+    if constexpr (kExact) sincosf(v, &s, &c);
+    else sincos_moderate(v, s, c);
     f[1] = s;
     f[1 + kNFreq] = c;
 #pragma unroll

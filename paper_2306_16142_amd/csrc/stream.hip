@@ -3,11 +3,13 @@
 //
 // A workgroup evaluates 256 rays at a time and streams the weight tiles through a
 // three-stage LDS ring that all its waves read.  One "phase" is one 32-row M-block of one
-// layer (its K-blocks, plus the bias K-block of a hidden layer).  While the waves multiply
-// phase p, each wave fetches its share of phase p + 2 from L2 into registers and writes it
-// to LDS at the end of the phase; one barrier per phase publishes it.  Every wave reads each
-// weight tile from LDS, and the workgroup reads it from L2 once per 256 rays (the per-wave
-// kernel read it once per 32 or 64).
+// layer (its K-blocks, plus the bias K-block of a hidden layer).  At the start of phase p
+// each wave issues its share of phase p + 2 as loads that write LDS directly
+// (global_load_lds), waits for them at the end of the phase, and one barrier per phase
+// publishes the stage.  The table lookup that locates a phase's tiles is done one phase
+// early, across the previous barrier, so a phase begins with its loads and its MFMA chain.
+// Every wave reads each weight tile from LDS, and the workgroup reads it from L2 once per
+// 256 rays (the per-wave kernel read it once per 32 or 64).
 //
 // Per wave everything else is as in the other network kernels: the Fourier encoding in
 // registers, layer outputs kept in the accumulators and converted into the next layer's B
@@ -98,72 +100,118 @@ struct NetTable {
     int ph[kMaxNets][kMaxPhases][3];   // offset, stride, tiles
 };
 
-// One wave's share of a phase in registers: tiles wave, wave + kWaves, ...  Each lane moves
-// 16 bytes of every tile, so one wave-wide load moves one whole 1 KiB tile.
+// One wave's share of a phase: nothing is held in registers, the loads write LDS directly;
+// only whether the phase exists is kept.
 template <int W>
 struct Stage {
     static constexpr int kMax = (W / 16 + 1 + Geo<W>::kWaves - 1) / Geo<W>::kWaves;
-    i32x4 v[kMax];
     int cnt;   // wave-uniform
 };
 
+// Where one phase's tiles come from: global address of its first tile, byte stride between
+// tiles, tile count, and whether the phase exists (wave-uniform values).
+struct Desc {
+    uint64_t addr;
+    int stride, ks, live;
+};
+
 // The phase pipeline of a workgroup: the current tile's network and phase, the next tile's
-// network (-1: none), and the stage in use.
+// network (-1: none) with both networks' phase counts and blob addresses, the stage in use,
+// and the descriptor of the phase two ahead of the current one (looked up one phase early,
+// so a phase starts its fetch without waiting on the table).
 struct Pipe {
     int cur, q, nxt;
     int stage;   // 0 .. kStages-1
+    int np_cur, np_nxt;
+    uint64_t blob_cur, blob_nxt;
+    Desc d2;
 };
+
+__device__ inline uint64_t uniform_u64(uint64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline void pipe_tiles(Pipe &pp, const NetTable *tab, int cur, int nxt) {
+    pp.cur = cur;
+    pp.nxt = nxt;
+    pp.q = 0;
+    pp.np_cur = __builtin_amdgcn_readfirstlane(tab->nphase[cur]);
+    pp.blob_cur = uniform_u64(tab->blob[cur]);
+    const int nn = nxt >= 0 ? nxt : cur;
+    pp.np_nxt = nxt >= 0 ? __builtin_amdgcn_readfirstlane(tab->nphase[nn]) : 0;
+    pp.blob_nxt = uniform_u64(tab->blob[nn]);
+}
+
+// Phase `ahead` phases after the current one, in two steps: the table read is issued by
+// desc_issue and turned into wave-uniform values by desc_finish (after a wait that the
+// caller has anyway).
+struct DescRaw {
+    int off, stride, ks;   // per lane (all lanes read the same entry)
+    uint64_t blob;
+    int live;
+};
+
+__device__ inline DescRaw desc_issue(const NetTable *tab, const Pipe &pp, int ahead) {
+    int q = pp.q + ahead;
+    const bool nx = q >= pp.np_cur;
+    const int net = nx ? pp.nxt : pp.cur;
+    q = nx ? q - pp.np_cur : q;
+    const int np = nx ? pp.np_nxt : pp.np_cur;
+    DescRaw r;
+    r.live = net >= 0 && q < np;
+    r.blob = nx ? pp.blob_nxt : pp.blob_cur;
+    const int *e = tab->ph[r.live ? net : 0][r.live ? q : 0];
+    r.off = e[0];
+    r.stride = e[1];
+    r.ks = e[2];
+    return r;
+}
+
+__device__ inline Desc desc_finish(const DescRaw &r) {
+    Desc d;
+    d.live = r.live;
+    const int off = __builtin_amdgcn_readfirstlane(r.off);
+    d.stride = __builtin_amdgcn_readfirstlane(r.stride);
+    d.ks = __builtin_amdgcn_readfirstlane(r.ks);
+    d.addr = r.blob + (uint64_t)(int64_t)off;
+    return d;
+}
 
 template <int W>
 __device__ inline lds_u8 *stage_ptr(lds_u8 *ring, int st) {
     return ring + st * (W / 16 + 1) * 1024;
 }
 
-// Fetches this wave's share of the phase `ahead` phases after the current one.  Branch-free
-// over the share: slot i takes tile min(i, ks - 1) and is written at min(i, NKB), so extra
-// slots of a short phase receive copies of its last tile, which nothing reads, and a wave
-// whose share runs past the stage writes the last slot with that slot's own tile.
+// Fetches this wave's share of the phase that `d` describes straight into its LDS stage
+// (global_load_lds, 16 bytes per lane: one instruction moves one whole 1 KiB tile, lane-major,
+// which is the tile's layout).  Branch-free over the share: slot i takes tile min(i, ks - 1),
+// so extra loads of a short phase rewrite its last tile with the same bytes.
 template <int W>
-__device__ inline void stage_fetch(Stage<W> &sg, const NetTable *tab, const Pipe &pp, int ahead, int wave, int lane) {
-    int net = pp.cur, q = pp.q + ahead;
-    const int np = tab->nphase[net];
-    if (q >= np) {
-        q -= np;
-        net = pp.nxt;
-    }
-    const bool live = net >= 0 && q < tab->nphase[net >= 0 ? net : 0];
-    sg.cnt = __builtin_amdgcn_readfirstlane(live ? 1 : 0);
+__device__ inline void stage_fetch(Stage<W> &sg, const Desc &d, lds_u8 *stage, int wave, int lane) {
+    sg.cnt = d.live;
     if (!sg.cnt) return;
-    const int off = __builtin_amdgcn_readfirstlane(tab->ph[net][q][0]);
-    const int stride = __builtin_amdgcn_readfirstlane(tab->ph[net][q][1]);
-    const int ks = __builtin_amdgcn_readfirstlane(tab->ph[net][q][2]);
-    const uint64_t blob = tab->blob[net];
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)blob);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(blob >> 32));
-    gbl_u8 *g = (gbl_u8 *)(((uint64_t)hi << 32) | lo) + off + lane * 16;
+    gbl_u8 *g = (gbl_u8 *)d.addr + lane * 16;
 #pragma unroll
     for (int j = 0; j < Stage<W>::kMax; ++j) {
-        const int i = min(wave + Geo<W>::kWaves * j, ks - 1);
-        sg.v[j] = *reinterpret_cast<const __attribute__((address_space(1))) i32x4 *>(g + i * stride);
+        const int i = min(wave + Geo<W>::kWaves * j, d.ks - 1);
+        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(g + i * d.stride),
+                                         (__attribute__((address_space(3))) void *)(stage + i * 1024), 16, 0, 0);
     }
 }
 
-template <int W>
-__device__ inline void stage_commit(const Stage<W> &sg, lds_u8 *stage, int wave, int lane) {
-    if (!sg.cnt) return;
-#pragma unroll
-    for (int j = 0; j < Stage<W>::kMax; ++j) {
-        const int i = min(wave + Geo<W>::kWaves * j, W / 16);
-        *reinterpret_cast<__attribute__((address_space(3))) i32x4 *>(stage + i * 1024 + lane * 16) = sg.v[j];
-    }
-}
+// The compiler does not track the LDS writes of global_load_lds: wait for them explicitly
+// (vmcnt(0), other counters left alone) before the barrier that publishes the stage.
+__device__ inline void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // End of a phase: publish the fetched share (two phases ahead) and advance.
 template <int W>
-__device__ inline void phase_end(const Stage<W> &sg, lds_u8 *ring, Pipe &pp, int wave, int lane) {
-    const int st2 = pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2;
-    stage_commit<W>(sg, stage_ptr<W>(ring, st2), wave, lane);
+__device__ inline void phase_end(const Stage<W> &sg, lds_u8 *ring, const NetTable *tab, Pipe &pp, int wave, int lane) {
+    const DescRaw nd = desc_issue(tab, pp, 3);   // two ahead of the next phase
+    stage_wait();
     __syncthreads();
+    pp.d2 = desc_finish(nd);
     pp.stage = pp.stage == kStages - 1 ? 0 : pp.stage + 1;
     ++pp.q;
 }
@@ -172,38 +220,38 @@ __device__ inline bf16x8 lds_tile(const lds_u8 *stage, int i, int lane) {
     return *reinterpret_cast<const __attribute__((address_space(3))) bf16x8 *>(stage + i * 1024 + lane * 16);
 }
 
-// A tiles in flight: the first two tiles of the current phase are loaded during the
+// A tiles in flight: the first kAR tiles of the current phase are loaded during the
 // previous phase (its stage was published one barrier earlier), so a phase starts without
-// waiting on LDS.
+// waiting on LDS, and inside a phase each tile is read kAR MFMA steps before its use.
+constexpr int kAR = 4;
 struct ARing {
-    bf16x8 r[2];
+    bf16x8 r[kAR];
 };
 
 // One phase's MFMA chain: KS K-blocks from the stage (the last one the bias block when
-// kBias), A tiles two steps ahead; the last two steps load the next phase's first tiles.
+// kBias); the last kAR steps load the next phase's first tiles.
 template <int W, int KS, bool kBias>
 __device__ __attribute__((always_inline)) inline void phase_mfma(const lds_u8 *st, const lds_u8 *st_next, ARing &ar,
                                                                  const bf16x8 (&bin)[W / 16][Geo<W>::kNB],
                                                                  f32x16 (&acc)[Geo<W>::kNB], int lane, int h) {
     constexpr int kNB = Geo<W>::kNB;
     constexpr int KIN = KS - (kBias ? 1 : 0);
+    static_assert(KS >= kAR, "every phase has at least kAR tiles");
     const bf16x8 one = bias_operand(h);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        const bf16x8 a = ar.r[ks & 1];
-        // every phase has at least two tiles, so the next phase's tiles 0 and 1 exist
-        ar.r[ks & 1] = ks + 2 < KS ? lds_tile(st, ks + 2, lane) : lds_tile(st_next, ks + 2 - KS, lane);
+        const bf16x8 a = ar.r[ks % kAR];
+        ar.r[ks % kAR] = ks + kAR < KS ? lds_tile(st, ks + kAR, lane) : lds_tile(st_next, ks + kAR - KS, lane);
 #pragma unroll
         for (int nb = 0; nb < kNB; ++nb) {
             const bf16x8 b = (kBias && ks == KIN) ? one : bin[ks < KIN ? ks : 0][nb];
             acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, ks == 0 ? f32x16{} : acc[nb], 0, 0, 0);
         }
     }
-    if constexpr (KS % 2 == 1) {   // the next phase's tile 0 landed in slot 1: restore the order
-        const bf16x8 t = ar.r[0];
-        ar.r[0] = ar.r[1];
-        ar.r[1] = t;
-    }
+    // the next phase's tile j landed in slot (KS + j) % kAR: restore the order
+    ARing t = ar;
+#pragma unroll
+    for (int j = 0; j < kAR; ++j) ar.r[j] = t.r[(KS + j) % kAR];
 }
 
 template <int W>
@@ -226,6 +274,9 @@ __device__ inline void relu_mask_out(const f32x16 &y, int l, int mb, int nb, bf1
         wmask[((l * NMB + mb) * kNB + nb) * 64 + lane] = (uint16_t)bits;
     }
     relu_tile_to_bf16(y, mb, nb, bout);
+    // keep the conversion in this phase (interleaved with its MFMA chain) rather than sunk to
+    // the end of the layer, where it would hold every M-block's accumulators live
+    asm volatile("" : "+v"(bout[2 * mb][nb]), "+v"(bout[2 * mb + 1][nb]));
 }
 
 // Forward layer l (all its M-blocks): bin -> bout with ReLU; masks to LDS for gradients.
@@ -240,14 +291,14 @@ __device__ __attribute__((always_inline)) inline void fwd_layer(lds_u8 *ring, co
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) {
         Stage<W> sg;
-        stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+        stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
         phase_mfma<W, KIN + (kBias ? 1 : 0), kBias>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin, acc[mb & 1],
                                                     lane, h);
         if (mb > 0) {
 #pragma unroll
             for (int nb = 0; nb < kNB; ++nb) relu_mask_out<W>(acc[(mb - 1) & 1][nb], l, mb - 1, nb, bout, wmask, lane, kGrad);
         }
-        phase_end<W>(sg, ring, pp, wave, lane);
+        phase_end<W>(sg, ring, tab, pp, wave, lane);
     }
 #pragma unroll
     for (int nb = 0; nb < kNB; ++nb) relu_mask_out<W>(acc[(NMB - 1) & 1][nb], l, NMB - 1, nb, bout, wmask, lane, kGrad);
@@ -265,6 +316,7 @@ __device__ inline void masked_tile_to_bf16(const f32x16 &y, uint32_t bits, int m
     for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int s = 0; s < 8; ++s) b[2 * mb + c][nb][s] = (__bf16)v[8 * c + s];
+    asm volatile("" : "+v"(b[2 * mb][nb]), "+v"(b[2 * mb + 1][nb]));
 }
 
 // Transposed hidden layer l (rows: its inputs): adjoint operands of layer l's outputs ->
@@ -273,8 +325,8 @@ __device__ inline void masked_tile_to_bf16(const f32x16 &y, uint32_t bits, int m
 // first tiles, and the caller still takes part in the fetch and the barrier.
 template <int W>
 __device__ __attribute__((always_inline)) inline void phase_skip(const lds_u8 *st_next, ARing &ar, int lane) {
-    ar.r[0] = lds_tile(st_next, 0, lane);
-    ar.r[1] = lds_tile(st_next, 1, lane);
+#pragma unroll
+    for (int j = 0; j < kAR; ++j) ar.r[j] = lds_tile(st_next, j, lane);
 }
 
 template <int W>
@@ -287,7 +339,7 @@ __device__ __attribute__((always_inline)) inline void bwd_layer(lds_u8 *ring, co
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) {
         Stage<W> sg;
-        stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+        stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
         phase_mfma<W, NKB, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin, acc[mb & 1], lane, h);
         if (mb > 0) {
 #pragma unroll
@@ -295,7 +347,7 @@ __device__ __attribute__((always_inline)) inline void bwd_layer(lds_u8 *ring, co
                 masked_tile_to_bf16<W>(acc[(mb - 1) & 1][nb], wmask[(((l - 1) * NMB + mb - 1) * kNB + nb) * 64 + lane],
                                        mb - 1, nb, bout);
         }
-        phase_end<W>(sg, ring, pp, wave, lane);
+        phase_end<W>(sg, ring, tab, pp, wave, lane);
     }
 #pragma unroll
     for (int nb = 0; nb < kNB; ++nb)
@@ -391,21 +443,19 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
 
     Pipe pp;
     TileWork cw = tile_work(a, t, pre, nk, count);
-    pp.cur = cw.net;
-    pp.q = 0;
-    pp.nxt = t + gridDim.x < ntile ? tile_work(a, t + gridDim.x, pre, nk, count).net : -1;
+    pipe_tiles(pp, tab, cw.net, t + gridDim.x < ntile ? tile_work(a, t + gridDim.x, pre, nk, count).net : -1);
     pp.stage = 0;
     {   // prologue: phases 0 and 1 into stages 0 and 1
         Stage<W> s0, s1;
-        stage_fetch<W>(s0, tab, pp, 0, wave, lane);
-        stage_fetch<W>(s1, tab, pp, 1, wave, lane);
-        stage_commit<W>(s0, stage_ptr<W>(ring, 0), wave, lane);
-        stage_commit<W>(s1, stage_ptr<W>(ring, 1), wave, lane);
+        stage_fetch<W>(s0, desc_finish(desc_issue(tab, pp, 0)), stage_ptr<W>(ring, 0), wave, lane);
+        stage_fetch<W>(s1, desc_finish(desc_issue(tab, pp, 1)), stage_ptr<W>(ring, 1), wave, lane);
+        pp.d2 = desc_finish(desc_issue(tab, pp, 2));
+        stage_wait();
         __syncthreads();
     }
     ARing ar;
-    ar.r[0] = lds_tile(stage_ptr<W>(ring, 0), 0, lane);
-    ar.r[1] = lds_tile(stage_ptr<W>(ring, 0), 1, lane);
+#pragma unroll
+    for (int j = 0; j < kAR; ++j) ar.r[j] = lds_tile(stage_ptr<W>(ring, 0), j, lane);
 
     for (;;) {
         const int depth = __builtin_amdgcn_readfirstlane(tab->depth[pp.cur]);
@@ -451,9 +501,9 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
         f32x16 hacc[kNB];
         {
             Stage<W> sg;
-            stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+            stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
             phase_mfma<W, NKB + 1, true>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b1, hacc, lane, h);
-            phase_end<W>(sg, ring, pp, wave, lane);
+            phase_end<W>(sg, ring, tab, pp, wave, lane);
         }
         float gl[kNB], gd[kNB];
         bool any_hit = false;   // some ray of this wave has logit > 0
@@ -475,9 +525,9 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
                 const int nbwd = (depth - 1) * NMB + kGradRowBlocks0;
                 for (int i = 0; i < nbwd; ++i) {
                     Stage<W> sg;
-                    stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+                    stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
                     phase_skip<W>(nxt_stage<W>(ring, pp), ar, lane);
-                    phase_end<W>(sg, ring, pp, wave, lane);
+                    phase_end<W>(sg, ring, tab, pp, wave, lane);
                 }
             } else {
             // ---- seed: adjoint of the last hidden layer = head rows x seeds, masked -> b0
@@ -521,9 +571,9 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
 #pragma unroll
             for (int mb = 0; mb < kGradRowBlocks0; ++mb) {
                 Stage<W> sg;
-                stage_fetch<W>(sg, tab, pp, 2, wave, lane);
+                stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
                 phase_mfma<W, NKB, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b0, acc0[mb], lane, h);
-                phase_end<W>(sg, ring, pp, wave, lane);
+                phase_end<W>(sg, ring, tab, pp, wave, lane);
             }
             // ---- chain rule through the Fourier features
 #pragma unroll
@@ -551,9 +601,7 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
         t += gridDim.x;
         if (t >= ntile) break;
         cw = tile_work(a, t, pre, nk, count);
-        pp.cur = cw.net;
-        pp.q = 0;
-        pp.nxt = t + gridDim.x < ntile ? tile_work(a, t + gridDim.x, pre, nk, count).net : -1;
+        pipe_tiles(pp, tab, cw.net, t + gridDim.x < ntile ? tile_work(a, t + gridDim.x, pre, nk, count).net : -1);
     }
 }
 
