@@ -116,6 +116,27 @@ def test_forward_full_size_sampled():
     assert np.all(np.isfinite(host(l16)[-100:]))
 
 
+@pytest.mark.parametrize("width,depth", [(128, 4), (256, 6)])
+def test_forward_bf16_large_coordinates(width, depth):
+    """Encoding arguments beyond the fast sin/cos range (|v| > 1024) send their whole wave to
+    the general reduction; the result still matches the emulation like any other ray."""
+    banner("forward bf16 with coordinates beyond the fast sin/cos range: %dx%d" % (depth, width))
+    p = synthetic.random_params(width, depth, 13)
+    rays = _rays(256 + 19, 14)
+    rays[0, 5:40] = rays[0, 5:40] * 3000.0   # rays 5..39: the first wave and part of the second
+    rays[1, 200] = -1500.25
+    net = api.Network(cuda(p), width, depth, "bf16")
+    lg, ds = net(cuda(rays))
+    lg, ds = host(lg), host(ds)
+    el, ed = mlp.forward_bf16(p, width, depth, rays)
+    rl, rd = mlp.forward(p, width, depth, rays)
+    for g, e, r in ((lg, el, rl), (ds, ed, rd)):
+        err = _scaled_err(g, e)
+        own = _scaled_err(e, r)
+        assert np.median(err) < 1e-5
+        assert err.max() <= own.max()
+
+
 def test_forward_edge_cases():
     banner("forward: n = 0, NaN ray")
     p = synthetic.random_params(128, 2, 17)
