@@ -17,11 +17,13 @@ from . import geometry, mlp
 
 
 class MultiScene:
-    def __init__(self, nets, instances, logit_margin=1e-4):
-        """nets: list of (params, width, depth); instances: dicts with R (3x3), T (3), net."""
+    def __init__(self, nets, instances, logit_margin=1e-4, precision="fp64"):
+        """nets: list of (params, width, depth); instances: dicts with R (3x3), T (3), net.
+        precision "bf16": networks evaluated as ``mlp.forward_bf16`` / ``mlp.backward_input_bf16``."""
         self.nets = nets
         self.inst = [(np.asarray(d["R"], np.float64), np.asarray(d["T"], np.float64), int(d["net"])) for d in instances]
         self.margin = logit_margin
+        self.bf16 = precision == "bf16"
 
     def _query_all(self, o, d, want_grad):
         n = o.shape[1]
@@ -35,13 +37,16 @@ class MultiScene:
             q = oo + t0[None] * dd
             th, ph = geometry.angles_from_dirs(dd)
             rays = np.concatenate([q, th[None], ph[None]])
-            logit, dist = mlp.forward(p, w, depth, rays)
+            logit, dist = (mlp.forward_bf16 if self.bf16 else mlp.forward)(p, w, depth, rays)
             t = t0 + dist
             hit = inbox & (logit > 0.0) & (t >= 0.0)
             robust = ~inbox | ((np.abs(logit) > self.margin) & (np.abs(t) > self.margin))
             g = None
             if want_grad:
-                gr, _ = mlp.backward(p, w, depth, rays, np.zeros(n), np.ones(n))
+                if self.bf16:
+                    gr = mlp.backward_input_bf16(p, w, depth, rays, np.zeros(n), np.ones(n))
+                else:
+                    gr, _ = mlp.backward(p, w, depth, rays, np.zeros(n), np.ones(n))
                 g = R @ gr[0:3]
             out.append((hit, t, g, robust))
         return out

@@ -145,11 +145,14 @@ class MeshScene:
 class NetworkScene:
     """Scene backend: the network, queried from the domain-cube entry point."""
 
-    def __init__(self, params, width, depth, logit_margin=1e-4):
+    def __init__(self, params, width, depth, logit_margin=1e-4, precision="fp64"):
+        """precision "bf16": the network is evaluated as ``mlp.forward_bf16`` and its input
+        gradient as ``mlp.backward_input_bf16`` (bfloat16 operands, float64 sums)."""
         self.params = params
         self.width = width
         self.depth = depth
         self.margin = logit_margin
+        self.bf16 = precision == "bf16"
 
     def _query(self, o, d):
         t_in, t_out, inbox = geometry.cube_entry(o, d)
@@ -157,7 +160,8 @@ class NetworkScene:
         q = o + t0[None] * d
         theta, phi = geometry.angles_from_dirs(d)
         rays = np.concatenate([q, theta[None], phi[None]])
-        logit, dist = mlp.forward(self.params, self.width, self.depth, rays)
+        fwd = mlp.forward_bf16 if self.bf16 else mlp.forward
+        logit, dist = fwd(self.params, self.width, self.depth, rays)
         t = t0 + dist
         hit = inbox & (logit > 0.0) & (t >= 0.0)   # a hit needs a non-negative distance
         robust = ~inbox | ((np.abs(logit) > self.margin) & (np.abs(t) > self.margin))
@@ -165,8 +169,11 @@ class NetworkScene:
 
     def intersect(self, o, d, t_max):
         hit, t, rays, robust = self._query(o, d)
-        g, _ = mlp.backward(self.params, self.width, self.depth, rays, np.zeros(rays.shape[1]),
-                            np.ones(rays.shape[1]))
+        n = rays.shape[1]
+        if self.bf16:
+            g = mlp.backward_input_bf16(self.params, self.width, self.depth, rays, np.zeros(n), np.ones(n))
+        else:
+            g, _ = mlp.backward(self.params, self.width, self.depth, rays, np.zeros(n), np.ones(n))
         # a nearly vanishing gradient leaves the normal (and every later bounce) undecided
         gn = np.linalg.norm(g[0:3], axis=0)
         robust = robust & ~(hit & (gn < self.margin * 10.0))

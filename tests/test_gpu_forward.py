@@ -137,6 +137,49 @@ def test_forward_bf16_large_coordinates(width, depth):
         assert err.max() <= own.max()
 
 
+@pytest.mark.parametrize("width,depth,prec", [(128, 1, "fp32"), (128, 1, "bf16"), (256, 1, "bf16"), (256, 3, "bf16")])
+def test_encoding_layout_one_hot(width, depth, prec):
+    """Layout pin of the Fourier encoding (65 features, their order and the packing of layer 0):
+    units 0 and 1 of the first layer copy +feature i and -feature i, later hidden layers pass
+    units 0 and 1 on unchanged, and the distance head takes their difference, so the network
+    outputs exactly feature i, for every i (3 x 256 runs on the streamed kernel, the others on
+    the per-wave kernels).  float32 must match the oracle's encoding to float32 accuracy; bf16
+    must equal the bf16 rounding of it (up to the rare feature whose float32 value sits on the
+    other side of a rounding tie)."""
+    banner("encoding layout one-hot: %dx%d, %s" % (depth, width, prec))
+    n = 1000
+    rays = _rays(n, 21)
+    feat = mlp.encode(rays)   # [65, n]
+    worst = 0.0
+    inexact = 0
+    for i in range(mlp.IN_DIM):
+        W1 = np.zeros((width, mlp.IN_DIM), np.float32)
+        W1[0, i], W1[1, i] = 1.0, -1.0
+        parts = [W1.ravel(), np.zeros(width, np.float32)]
+        for _ in range(depth - 1):
+            Wh = np.zeros((width, width), np.float32)
+            Wh[0, 0], Wh[1, 1] = 1.0, 1.0   # relu(+f_i), relu(-f_i) pass through
+            parts += [Wh.ravel(), np.zeros(width, np.float32)]
+        W2 = np.zeros((2, width), np.float32)
+        W2[0, 0] = 1.0                   # logit = relu(+f_i)
+        W2[1, 0], W2[1, 1] = 1.0, -1.0   # dist = relu(+f_i) - relu(-f_i) = f_i
+        p = np.concatenate(parts + [W2.ravel(), np.zeros(2, np.float32)])
+        net = api.Network(cuda(p), width, depth, prec)
+        lg, ds = net(cuda(rays))
+        ds = host(ds).astype(np.float64)
+        if prec == "fp32":
+            worst = max(worst, np.abs(ds - feat[i]).max())
+        else:
+            ref = mlp.round_bf16(feat[i])
+            ulp = np.abs(mlp.round_bf16(feat[i] * (1 + 2.0 ** -7)) - ref) + 1e-30
+            assert np.all(np.abs(ds - ref) <= ulp * 1.01), i
+            inexact += int(np.sum(ds != ref))
+    if prec == "fp32":
+        assert worst < 2e-6, worst
+    else:
+        assert inexact <= 0.001 * n * mlp.IN_DIM, inexact
+
+
 def test_forward_edge_cases():
     banner("forward: n = 0, NaN ray")
     p = synthetic.random_params(128, 2, 17)

@@ -112,6 +112,53 @@ def test_render_network_bf16_runs_and_is_reproducible():
     assert st[0] == 48 * 32 * 4 and np.all(np.diff(st) <= 0)
 
 
+def _compare_bf16(r, ref, name):
+    """bf16 kernels against the oracle evaluating the same networks in emulated bfloat16
+    (bfloat16 operands, float64 sums): decisions agree where the oracle's margins make them
+    robust; distances, normals and radiance agree up to the kernels' float32 summation order
+    (rare bf16 rounding flips of one activation, as in the forward parity tests).
+
+    Normals: a pre-activation within ~1e-4 of zero can fall on the other side of its ReLU in
+    the kernel, and the gradient then changes by that unit's whole contribution (a 3 x 256
+    render showed one such pixel: its pre-activation was 7e-5, and flipping that single mask
+    in the emulation reproduces the kernel's normal exactly).  So at most 1% of the hit
+    pixels may differ in direction; the rest must agree to a 0.999 cosine."""
+    rob = ref["robust"]
+    dg, dr = host(r.depth), ref["depth"]
+    hit_g, hit_r = np.isfinite(dg), np.isfinite(dr)
+    both = rob & hit_r
+    ng, nr = host(r.normal)[:, both], ref["normal"][:, both]
+    dots = np.sum(ng * nr, axis=0)
+    derr = np.abs(dg[both] - dr[both]) / np.maximum(np.abs(dr[both]), 1.0)
+    rad_g, rad_r = host(r.radiance), ref["radiance"]
+    scale = max(rad_r.max(), 1e-6)
+    rerr = np.abs(rad_g - rad_r)[:, rob] / scale
+    print("%s: robust %.3f, hits %d, depth err p99 %.2e max %.2e, normal dot min %.5f p1 %.5f, radiance err mean %.2e max %.2e"
+          % (name, rob.mean(), both.sum(), np.quantile(derr, 0.99), derr.max(), dots.min(), np.quantile(dots, 0.01),
+             rerr.mean(), rerr.max()), flush=True)
+    assert rob.mean() > 0.8
+    np.testing.assert_array_equal(hit_g[rob], hit_r[rob])
+    assert both.sum() > 0.1 * both.size
+    assert np.quantile(derr, 0.99) < 1e-3 and derr.max() < 2e-2
+    assert np.mean(dots < 0.999) <= 0.01
+    assert rerr.mean() < 1e-3 and rerr.max() < 3e-2
+
+
+@pytest.mark.parametrize("width,depth", [(128, 4), (256, 3)])
+def test_render_network_bf16_matches_emulated_oracle(width, depth):
+    """One bounce through the bf16 kernels: path queries, normals from the streamed kernel's
+    input gradient (only for 32-ray blocks with a hit) and shadow queries."""
+    banner("render network bf16 %dx%d: 32x32 2spp 1 bounce vs emulated-bf16 oracle" % (depth, width))
+    p = _hitting_params(width, depth, 43)
+    net = api.Network(cuda(p), width, depth, "bf16")
+    cfg = synthetic.RenderConfig(32, 32, 2, 1, 1, 3)
+    r = api.Renderer(cfg, net=net)
+    r.render()
+    torch.cuda.synchronize()
+    ref = render.render(render.NetworkScene(p, width, depth, logit_margin=2e-2, precision="bf16"), cfg)
+    _compare_bf16(r, ref, "net %dx%d" % (depth, width))
+
+
 def _multi_setup(prec):
     nets_p = [(_hitting_params(128, 2, 51), 128, 2), (_hitting_params(256, 2, 52), 256, 2), (_hitting_params(128, 3, 53), 128, 3)]
     r = np.array([0.3, -0.1, 0.4, 0.85])
@@ -143,6 +190,21 @@ def test_render_multi_object_fp32_matches_oracle():
         paths, per_net = r.path_stats()
         assert list(paths) == _stats(ref, bounces) or np.all(np.abs(paths - np.array(_stats(ref, bounces))) <= 4)
         assert per_net.shape == (bounces, 3) and per_net[0].sum() > 0
+
+
+def test_render_multi_object_bf16_matches_emulated_oracle():
+    """The persistent multi-network streamed kernel (networks of widths 128 and 256 and
+    different depths in one launch) against the emulated-bf16 oracle, one bounce."""
+    from oracle import multi
+    banner("render multi-object bf16: 3 networks, 4 instances, 24x16 2spp, 1 bounce vs emulated-bf16 oracle")
+    nets_p, inst, nets = _multi_setup("bf16")
+    cfg = synthetic.RenderConfig(24, 16, 2, 1, 1, 5)
+    cfg.camera.eye = (0.0, -7.0, 1.5)
+    r = api.Renderer(cfg, nets=nets, instances=inst)
+    r.render()
+    torch.cuda.synchronize()
+    ref = render.render(multi.MultiScene(nets_p, inst, logit_margin=2e-2, precision="bf16"), cfg)
+    _compare_bf16(r, ref, "multi")
 
 
 def test_render_multi_identity_instance_equals_single_network():
