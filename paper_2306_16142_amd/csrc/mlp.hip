@@ -656,7 +656,12 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
     };
     int64_t tile = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
     if constexpr (kLdsA) load_rays(tile);
+    // Issue priority (bf16 with the weights in LDS): a wave in its MFMA layers outranks a wave
+    // in its encoding and epilogue, and of two waves in their layers the odd one leads, so the
+    // two waves of a SIMD settle into taking turns on the matrix core (measured ~2% faster).
+    const bool odd_wave = (threadIdx.x >> 6) & 1;
     for (; tile < ntile; tile += tstride) {
+        if constexpr (P == kBF16 && kLdsA) __builtin_amdgcn_s_setprio(0);
         const int64_t base = tile * 32 * NB;
         if constexpr (!kLdsA) load_rays(tile);
         float vcur[NB][kInRaw];
@@ -758,6 +763,10 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
             continue;
         }
         // ---- layer 0, then hidden layers two at a time (b1 -> b0 -> b1 ...)
+        if constexpr (P == kBF16 && kLdsA) {
+            if (odd_wave) __builtin_amdgcn_s_setprio(2);
+            else __builtin_amdgcn_s_setprio(1);
+        }
         dense_relu<P, W, NB, K0, kCalib, kCInit>(wsrc, L.layer_tile(0), b0, b1, s_bias, s_c->alpha[0], lane, h, valid_any,
                                           absmax + 3);
         int l = 1;
