@@ -390,6 +390,7 @@ ddf_status launch_grad(const GradArgs &args, hipStream_t s, int grid_cap) {
 
 // Shared with the training driver: grid size used for a given batch (loss partials).
 int64_t grad_grid(int width, int precision, int64_t n) {
+    if (precision == kFP32) return sweep_grid(width, n);   // training runs the LDS sweep
     const int NB = (width == 128 && precision != kFP32) ? 2 : 1;
     const int wpb = NB == 2 ? 8 : 4;
     const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
@@ -401,6 +402,7 @@ ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, h
     const int cap = cu_count_grad() * tuning(DDF_TUNE_GRAD_WG_PER_CU);
     const int w = net->width, p = net->precision;
     if (train) {
+        if (p == kFP32 && !args.g_rays && args.n_nets == 0) return sweep_dispatch(w, args, s);
         if (w == 128) return p == kBF16 ? launch_grad<kBF16, 128, 2, true>(args, s, cap) : launch_grad<kFP32, 128, 1, true>(args, s, cap);
         return p == kBF16 ? launch_grad<kBF16, 256, 1, true>(args, s, cap) : launch_grad<kFP32, 256, 1, true>(args, s, cap);
     }

@@ -49,4 +49,10 @@ int64_t grad_grid(int width, int precision, int64_t n);
 size_t stream_lds_bytes(int width, int depth, int n_nets, bool grad);
 ddf_status stream_dispatch(int width, const GradArgs &args, hipStream_t s);
 
+// float32 training sweep with the layer values of 64 rays in LDS (sweep.hip): one network,
+// parameter-gradient side outputs only (no input gradient); its grid (one loss partial per
+// workgroup) for n rays:
+int64_t sweep_grid(int width, int64_t n);
+ddf_status sweep_dispatch(int width, const GradArgs &args, hipStream_t s);
+
 }  // namespace ddf

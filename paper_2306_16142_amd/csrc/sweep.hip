@@ -1,0 +1,335 @@
+// Training sweep of a float32 network (Sec. V-A training, the hand-written backward): the
+// forward pass with its side outputs, the loss seeds, and the adjoints of every hidden layer,
+// for one network of width 128 or 256.
+//
+// A workgroup of eight waves takes 64 rays at a time and keeps their layer values in LDS
+// ([ray][unit], float32): every wave reads the whole input of a layer from LDS as MFMA B
+// operands (four K-steps per 16-byte read) and produces its own M-blocks (width 256: one
+// 32-row block for both 32-ray halves; width 128: one block for one half), so no wave holds
+// more than one layer's slice in registers.  Weight tiles come from the L2-resident blob
+// (one 256-byte tile per wave and K-step, the layout the per-wave kernels read), ReLU masks
+// go to LDS for the reverse sweep.  The products run over the same tiles and operands in the
+// same order as the per-wave kernel, so the side outputs agree with it bit for bit.
+#include <cmath>
+#include <mutex>
+
+#include "common.hpp"
+#include "grad_args.hpp"
+#include "mlp_device.hpp"
+#include "mlp_layout.hpp"
+
+namespace ddf {
+namespace {
+
+constexpr int kSweepRays = 64;
+constexpr int kSweepWaves = 8;
+constexpr int kSweepLds = 160 * 1024;
+
+template <int W>
+struct SweepGeo {
+    static constexpr int NMB = W / 32;
+    static constexpr int NKB = W / 2;   // float32 K-steps of a hidden layer
+    static constexpr int NBW = W == 256 ? 2 : 1;   // 32-ray blocks per wave
+    static constexpr int XP = W + 4;                // row pitch of the LDS layer values (floats)
+    static_assert(NMB * 2 == kSweepWaves * NBW, "every (M-block, ray block) pair has one wave");
+};
+
+template <int W>
+__host__ __device__ inline size_t sweep_lds_bytes(int depth) {
+    using G = SweepGeo<W>;
+    return (size_t)kSweepRays * G::XP * 4                  // layer values
+           + (size_t)depth * G::NMB * 2 * 64 * 2           // ReLU masks [layer][M-block][ray block][lane]
+           + (size_t)2 * kSweepRays * 4                    // seeds
+           + (size_t)kSweepWaves * 4;                      // loss partials
+}
+
+// One wave's products of a layer: KS K-steps of the tiles t0 + kb * nmb + mb against the
+// layer values in LDS.  kFeat: layer 0 (K-step kb of lane half h reads feature slot
+// 40 h + kb); otherwise K-step kb reads unit 32 (kb / 16) + 8 ((kb % 16) / 4) + 4 h + kb % 4,
+// the contraction order of the packed tiles.
+template <int W, int KS, bool kFeat>
+__device__ __attribute__((always_inline)) inline void sweep_mfma(const uint8_t *blob, int64_t t0, int nmb, int mb,
+                                                                 const float *X, int nb0, int lane,
+                                                                 f32x16 (&acc)[SweepGeo<W>::NBW]) {
+    using G = SweepGeo<W>;
+    constexpr int NBW = G::NBW;
+    static_assert(KS % 4 == 0, "K-steps come in groups of four");
+    const int h = lane >> 5, col = lane & 31;
+    const float *tiles = reinterpret_cast<const float *>(blob) + (t0 + mb) * 64 + lane;
+    const int64_t tstride = (int64_t)nmb * 64;   // floats between consecutive K-steps
+    auto unit = [&](int kb) { return kFeat ? 40 * h + kb : 32 * (kb / 16) + 8 * ((kb % 16) / 4) + 4 * h; };
+    float a_cur[4], a_nxt[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a_cur[q] = tiles[q * tstride];
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) acc[nb] = f32x16{};
+#pragma unroll 4
+    for (int kb = 0; kb < KS; kb += 4) {
+        if (kb + 4 < KS) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a_nxt[q] = tiles[(kb + 4 + q) * tstride];
+        }
+        f32x4 b4[NBW];
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+            b4[nb] = *reinterpret_cast<const f32x4 *>(X + ((nb0 + nb) * 32 + col) * G::XP + unit(kb));
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[q], b4[nb][q], acc[nb], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a_cur[q] = a_nxt[q];
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) {
+    using G = SweepGeo<W>;
+    constexpr int NMB = G::NMB, NKB = G::NKB, NBW = G::NBW, XP = G::XP;
+    constexpr int K0 = layer0_kblocks(kFP32);
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int depth = a.depth;
+    const int64_t n = a.n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int mb = W == 256 ? wave : wave >> 1;   // this wave's M-block
+    const int nb0 = W == 256 ? 0 : (wave & 1);    // and its first ray block
+
+    float *X = reinterpret_cast<float *>(smem);
+    uint16_t *s_mask = reinterpret_cast<uint16_t *>(X + kSweepRays * XP);
+    float *s_seed = reinterpret_cast<float *>(s_mask + depth * NMB * 2 * 64);   // [2][64]
+    float *s_loss = s_seed + 2 * kSweepRays;
+
+    const NetLayout L = make_layout(W, depth, kFP32);
+    const uint8_t *blob = a.blob;
+    const float *bias = reinterpret_cast<const float *>(blob + L.bias_off);
+    const float *head_rows = reinterpret_cast<const float *>(blob + L.head_rows_off);
+    const float *gblob = reinterpret_cast<const float *>(blob + L.grad_off);
+    const float inv_n = a.loss_scalars ? a.loss_scalars[0] : 0.f;
+    const float inv_nhit = a.loss_scalars ? a.loss_scalars[1] : 0.f;
+    float loss_acc = 0.f;
+    const int64_t ntile = (n + kSweepRays - 1) / kSweepRays;
+
+    auto mask_at = [&](int l, int nb) -> uint16_t & { return s_mask[((l * NMB + mb) * 2 + nb) * 64 + lane]; };
+    // D-layout value j of this lane: unit mb * 32 + 8 (j / 4) + 4 h + j % 4 of ray block nb
+
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t base = tile * kSweepRays;
+        // ---- encoding: 64 rays x 5 variables, 13 feature slots each, into X[ray][40 h + slot]
+        for (int t = threadIdx.x; t < kSweepRays * 6; t += blockDim.x) {
+            const int ray = t % kSweepRays, grp = t / kSweepRays;   // grp: 3 h + variable slot group
+            const int hh = grp / 3, g = grp % 3;
+            const int64_t r = base + ray;
+            const bool valid = r < n;
+            float *dst = X + ray * XP + 40 * hh + kFeatPerVar * g;
+            if (hh == 1 && g == 2) {   // the unused slot group of lane half 1, and the pad slot
+#pragma unroll
+                for (int f = 0; f < kFeatPerVar + 1; ++f) dst[f] = 0.f;
+                continue;
+            }
+            const int var = hh ? 3 + g : g;
+            const float x = valid ? a.rays[(int64_t)var * n + r] : 0.f;
+            float feat[kFeatPerVar];
+            encode_var<true>(x, feat);
+#pragma unroll
+            for (int f = 0; f < kFeatPerVar; ++f) {
+                dst[f] = valid ? feat[f] : 0.f;
+                const int c = feature_column(hh, kFeatPerVar * g + f);
+                if (valid && c >= 0) a.ws_gamma[(int64_t)c * n + r] = feat[f];
+            }
+            if (hh == 0 && g == 2) dst[kFeatPerVar] = 0.f;   // pad slot 39 of lane half 0
+        }
+        __syncthreads();
+        // ---- forward: X holds the layer input; every wave reads it, then writes its slice
+        for (int l = 0; l < depth; ++l) {
+            f32x16 acc[NBW];
+            if (l == 0)
+                sweep_mfma<W, K0, true>(blob, L.layer_tile(0), NMB, mb, X, nb0, lane, acc);
+            else
+                sweep_mfma<W, NKB, false>(blob, L.layer_tile(l), NMB, mb, X, nb0, lane, acc);
+            __syncthreads();   // the input is read by every wave before anyone overwrites it
+            float bv[16];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + l * W + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bv[4 * g + i] = b4[i];
+            }
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                const int ray = (nb0 + nb) * 32 + col;
+                const int64_t r = base + ray;
+                float y[16];
+                uint32_t bits = 0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const float z = acc[nb][j] + bv[j];
+                    y[j] = fmaxf(z, 0.f);
+                    bits |= (z > 0.f ? 1u : 0u) << j;
+                }
+                mask_at(l, nb0 + nb) = (uint16_t)bits;
+                if (r < n) {
+                    float *dst = a.ws_h + ((int64_t)l * W + mb * 32 + 4 * h) * n + r;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) dst[(int64_t)(8 * (j / 4) + (j % 4)) * n] = y[j];
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    *reinterpret_cast<f32x4 *>(X + ray * XP + mb * 32 + 8 * g + 4 * h) =
+                        f32x4{y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]};
+            }
+            __syncthreads();
+        }
+        // ---- head (rows 0 and 1 of its one M-block) and loss seeds, by the waves of M-block 0
+        if (mb == 0) {
+            f32x16 hacc[NBW];
+            sweep_mfma<W, NKB, false>(blob, L.head_tile(), 1, 0, X, nb0, lane, hacc);
+            const float hb0 = bias[W * depth], hb1 = bias[W * depth + 1];
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                const int ray = (nb0 + nb) * 32 + col;
+                const int64_t r = base + ray;
+                const bool valid = r < n;
+                const float z = hacc[nb][0] + hb0, dd = hacc[nb][1] + hb1;   // lane half 0 holds rows 0 and 1
+                float gl = 0.f, gd = 0.f;
+                if (a.t_label) {
+                    const float t = valid ? a.t_label[r] : INFINITY;
+                    const float yh = t < INFINITY ? 1.f : 0.f;
+                    const float sig = 1.f / (1.f + expf(-z));
+                    gl = valid ? (sig - yh) * inv_n : 0.f;
+                    const float diff = dd - (yh > 0.f ? t : 0.f);
+                    gd = yh > 0.f ? (diff > 0.f ? inv_nhit : (diff < 0.f ? -inv_nhit : 0.f)) : 0.f;
+                    if (h == 0 && valid)
+                        loss_acc += (fmaxf(z, 0.f) - z * yh + log1pf(expf(-fabsf(z)))) * inv_n + yh * fabsf(diff) * inv_nhit;
+                } else {
+                    gl = (valid && a.g_logit_in) ? a.g_logit_in[r] : 0.f;
+                    gd = (valid && a.g_dist_in) ? a.g_dist_in[r] : 0.f;
+                }
+                if (h == 0) {
+                    if (valid) {
+                        if (a.logit_out) a.logit_out[r] = z;
+                        if (a.dist_out) a.dist_out[r] = dd;
+                        a.ws_delta[(int64_t)depth * W * n + r] = gl;
+                        a.ws_delta[(int64_t)depth * W * n + n + r] = gd;
+                    }
+                    s_seed[ray] = gl;
+                    s_seed[kSweepRays + ray] = gd;
+                }
+            }
+        }
+        __syncthreads();
+        if (a.forward_only) continue;
+        // ---- adjoint of the last hidden layer: head rows times the seeds, masked
+        {
+            float w0[16], w1[16];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const f32x4 a4 = *reinterpret_cast<const f32x4 *>(head_rows + mb * 32 + 8 * g + 4 * h);
+                const f32x4 b4 = *reinterpret_cast<const f32x4 *>(head_rows + W + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    w0[4 * g + i] = a4[i];
+                    w1[4 * g + i] = b4[i];
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                const int ray = (nb0 + nb) * 32 + col;
+                const int64_t r = base + ray;
+                const float gl = s_seed[ray], gd = s_seed[kSweepRays + ray];
+                const uint32_t bits = mask_at(depth - 1, nb0 + nb);
+                float y[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) y[j] = ((bits >> j) & 1u) ? fmaf(gl, w0[j], gd * w1[j]) : 0.f;
+                if (r < n) {
+                    float *dst = a.ws_delta + ((int64_t)(depth - 1) * W + mb * 32 + 4 * h) * n + r;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) dst[(int64_t)(8 * (j / 4) + (j % 4)) * n] = y[j];
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    *reinterpret_cast<f32x4 *>(X + ray * XP + mb * 32 + 8 * g + 4 * h) =
+                        f32x4{y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]};
+            }
+        }
+        __syncthreads();
+        // ---- transposed hidden layers from the top: X holds layer l's adjoint
+        for (int l = depth - 1; l >= 1; --l) {
+            f32x16 acc[NBW];
+            sweep_mfma<W, NKB, false>(reinterpret_cast<const uint8_t *>(gblob), L.grad_layer_tile(l), NMB, mb, X, nb0,
+                                      lane, acc);
+            __syncthreads();
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                const int ray = (nb0 + nb) * 32 + col;
+                const int64_t r = base + ray;
+                const uint32_t bits = mask_at(l - 1, nb0 + nb);
+                float y[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) y[j] = ((bits >> j) & 1u) ? acc[nb][j] : 0.f;
+                if (r < n) {
+                    float *dst = a.ws_delta + ((int64_t)(l - 1) * W + mb * 32 + 4 * h) * n + r;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) dst[(int64_t)(8 * (j / 4) + (j % 4)) * n] = y[j];
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    *reinterpret_cast<f32x4 *>(X + ray * XP + mb * 32 + 8 * g + 4 * h) =
+                        f32x4{y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]};
+            }
+            __syncthreads();
+        }
+    }
+    // block sum of the loss terms -> one partial per block (summed in a fixed order later)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) loss_acc += __shfl_xor(loss_acc, off);
+    if (lane == 0) s_loss[wave] = loss_acc;
+    __syncthreads();
+    if (threadIdx.x == 0 && a.loss_partial) {
+        float t = 0.f;
+        for (int w = 0; w < kSweepWaves; ++w) t += s_loss[w];
+        a.loss_partial[blockIdx.x] = t;
+    }
+}
+
+int cu_count_sweep() {
+    static int cus = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    });
+    return cus;
+}
+
+template <int W>
+ddf_status launch_sweep(const GradArgs &a, hipStream_t s) {
+    auto kern = sweep_kernel<W>;
+    static std::once_flag once;
+    std::call_once(once, [&] { (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kSweepLds); });
+    const size_t lds = sweep_lds_bytes<W>(a.depth);
+    DDF_REQUIRE(lds <= (size_t)kSweepLds, DDF_ERR_UNSUPPORTED, "training sweep: network too deep");
+    hipLaunchKernelGGL(kern, dim3((unsigned)sweep_grid(W, a.n)), dim3(kSweepWaves * 64), lds, s, a);
+    return launch_status("ddf training sweep");
+}
+
+}  // namespace
+
+// Workgroups of the training sweep for n rays (each writes one loss partial): two per CU.
+int64_t sweep_grid(int width, int64_t n) {
+    (void)width;
+    const int64_t tiles = (n + kSweepRays - 1) / kSweepRays;
+    return std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cu_count_sweep() * 2));
+}
+
+// Float32 training sweep of one network (no input gradient): features, activations, adjoints,
+// head seeds and loss partials, as the per-wave gradient kernel writes them.
+ddf_status sweep_dispatch(int width, const GradArgs &a, hipStream_t s) {
+    DDF_REQUIRE(a.n_nets == 0 && !a.g_rays && a.depth >= 1 && a.depth <= 8, DDF_ERR_UNSUPPORTED,
+                "training sweep: one network, no input gradient");
+    return width == 256 ? launch_sweep<256>(a, s) : launch_sweep<128>(a, s);
+}
+
+}  // namespace ddf

@@ -88,16 +88,17 @@ __global__ void sum_partials_kernel(const float *__restrict__ part, int64_t cnt,
 // A: [M][n] adjoints, B: [N][n] layer inputs (rows contiguous over rays).  One workgroup
 // per (128 x 128 output tile, chunk of kChunk rays).  Stages of 32 rays of both operands
 // go through LDS (coalesced 16-byte global loads, rows padded to 36 floats so that the
-// MFMA operand reads are free of bank conflicts), double-buffered; each wave owns a 64 x 64
-// sub-tile (2 x 2 blocks of v_mfma_f32_32x32x2f32).  Lane half h contracts rays 16 h ..
-// 16 h + 15 of a stage (the contraction order only pairs A and B of the same ray).
+// MFMA operand reads are free of bank conflicts), double-buffered; eight waves each own a
+// 32 x 64 sub-tile (1 x 2 blocks of v_mfma_f32_32x32x2f32), two waves per SIMD.  Lane half
+// h contracts rays 16 h .. 16 h + 15 of a stage (the contraction order only pairs A and B of
+// the same ray).  The bias gradient is summed by the first 256 threads (two per row).
 // part[s][M][N] and dbpart[s][M] receive the chunk's sums.
 constexpr int kDwTile = 128;
 constexpr int kDwStep = 32;
 constexpr int kDwPad = 36;
 
 template <bool kVec4>
-__global__ __launch_bounds__(256) void dw_kernel(const float *__restrict__ A, const float *__restrict__ B, int M,
+__global__ __launch_bounds__(512) void dw_kernel(const float *__restrict__ A, const float *__restrict__ B, int M,
                                                  int N, int64_t n, int splits, float *__restrict__ part,
                                                  float *__restrict__ dbpart) {
     __shared__ __attribute__((aligned(16))) float sA[2][kDwTile][kDwPad];
@@ -109,14 +110,14 @@ __global__ __launch_bounds__(256) void dw_kernel(const float *__restrict__ A, co
     const int64_t k0 = (int64_t)s * kChunk;
     const int klen = (int)min<int64_t>(kChunk, n - k0);
     const int nstep = (klen + kDwStep - 1) / kDwStep;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    // global -> register staging: 128 rows x 32 rays per operand = 1024 float4, 4 per thread
-    f32x4 ra[4], rb[4];
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+    // global -> register staging: 128 rows x 32 rays per operand = 1024 float4, 2 per thread
+    f32x4 ra[2], rb[2];
     auto fetch = [&](int st) {
         const int kb = st * kDwStep;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int idx = tid + 256 * r, row = idx >> 3, k4 = (idx & 7) * 4;
+        for (int r = 0; r < 2; ++r) {
+            const int idx = tid + 512 * r, row = idx >> 3, k4 = (idx & 7) * 4;
             const int ma = m0 + row, nb = n0 + row;
             const int kk = kb + k4;
             f32x4 va{0.f, 0.f, 0.f, 0.f}, vb{0.f, 0.f, 0.f, 0.f};
@@ -139,15 +140,15 @@ __global__ __launch_bounds__(256) void dw_kernel(const float *__restrict__ A, co
     };
     auto commit = [&](int buf) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int idx = tid + 256 * r, row = idx >> 3, k4 = (idx & 7) * 4;
+        for (int r = 0; r < 2; ++r) {
+            const int idx = tid + 512 * r, row = idx >> 3, k4 = (idx & 7) * 4;
             *reinterpret_cast<f32x4 *>(&sA[buf][row][k4]) = ra[r];
             *reinterpret_cast<f32x4 *>(&sB[buf][row][k4]) = rb[r];
         }
     };
-    f32x16 acc[2][2];
+    f32x16 acc[1][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 1; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
     float dbs = 0.f;   // bias gradient: thread t sums half a row (row t / 2) of the A tile
@@ -159,21 +160,19 @@ __global__ __launch_bounds__(256) void dw_kernel(const float *__restrict__ A, co
         if (st + 1 < nstep) fetch(st + 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {   // four rays per lane half at a time
-            f32x4 a4[2], b4[2];
+            f32x4 a4[1], b4[2];
+            a4[0] = *reinterpret_cast<const f32x4 *>(&sA[buf][wm + c][16 * h + 4 * q]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                a4[i] = *reinterpret_cast<const f32x4 *>(&sA[buf][wm + 32 * i + c][16 * h + 4 * q]);
-                b4[i] = *reinterpret_cast<const f32x4 *>(&sB[buf][wn + 32 * i + c][16 * h + 4 * q]);
-            }
+            for (int i = 0; i < 2; ++i) b4[i] = *reinterpret_cast<const f32x4 *>(&sB[buf][wn + 32 * i + c][16 * h + 4 * q]);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 1; ++i)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[i][e], b4[j][e], acc[i][j], 0, 0, 0);
         }
-        if (n0 == 0) {
+        if (n0 == 0 && tid < 256) {
             const f32x4 *row = reinterpret_cast<const f32x4 *>(&sA[buf][tid >> 1][16 * (tid & 1)]);
 #pragma unroll
             for (int e = 0; e < 4; ++e) dbs += (row[e][0] + row[e][1]) + (row[e][2] + row[e][3]);
@@ -183,7 +182,7 @@ __global__ __launch_bounds__(256) void dw_kernel(const float *__restrict__ A, co
     }
     float *dst = part + (int64_t)s * M * N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 1; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -192,7 +191,7 @@ __global__ __launch_bounds__(256) void dw_kernel(const float *__restrict__ A, co
                 const int k = n0 + wn + 32 * j + c;
                 if (m < M && k < N) dst[(int64_t)m * N + k] = acc[i][j][q];
             }
-    if (n0 == 0) {
+    if (n0 == 0 && tid < 256) {
         const float t = dbs + __shfl_xor(dbs, 1);
         const int m = m0 + (tid >> 1);
         if ((tid & 1) == 0 && m < M) dbpart[(int64_t)s * M + m] = t;
@@ -297,9 +296,9 @@ ddf_status param_grads(int width, int depth, int64_t n, const TrainWs &w, float 
         const float *B = l == 0 ? w.gamma : w.h + (int64_t)(l - 1) * width * n;
         const unsigned blocks = (unsigned)(((M + kDwTile - 1) / kDwTile) * ((N + kDwTile - 1) / kDwTile) * splits);
         if (n % 4 == 0)
-            hipLaunchKernelGGL(dw_kernel<true>, dim3(blocks), dim3(256), 0, s, A, B, M, N, n, splits, w.part, w.dbpart);
+            hipLaunchKernelGGL(dw_kernel<true>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, w.part, w.dbpart);
         else
-            hipLaunchKernelGGL(dw_kernel<false>, dim3(blocks), dim3(256), 0, s, A, B, M, N, n, splits, w.part, w.dbpart);
+            hipLaunchKernelGGL(dw_kernel<false>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, w.part, w.dbpart);
         if (ddf_status st = launch_status("ddf parameter gradient")) return st;
         const int64_t total = (int64_t)M * N + M;
         hipLaunchKernelGGL(reduce_dw_kernel, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(256), 0, s,
