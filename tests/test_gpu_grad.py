@@ -99,6 +99,29 @@ def test_parameter_gradient_fp32(width, depth, n):
     torch.testing.assert_close(g3, 2 * g2, rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("width,depth,n", [(128, 4, 4096 + 37), (256, 6, 2048 + 5), (256, 1, 50), (128, 8, 64 * 3)])
+def test_parameter_gradient_fp32_training_sweep(width, depth, n):
+    """Parameter gradients without the input gradient run the LDS training sweep: they match
+    the float64 oracle, and equal bit for bit those of the per-wave kernel (which also returns
+    the input gradient), whose products run over the same tiles in the same order."""
+    banner("parameter gradient fp32 (training sweep) %dx%d n=%d" % (depth, width, n))
+    p = synthetic.random_params(width, depth, 37)
+    rays = _away_from_kinks(p, width, depth, _rays(n, 38))
+    n = rays.shape[1]
+    rng = np.random.default_rng(3)
+    gl, gd = rng.normal(size=n).astype(np.float32) / n, rng.normal(size=n).astype(np.float32) / n
+    net = api.Network(cuda(p), width, depth, "fp32")
+    g_none, g_sweep = api.backward(net, cuda(rays), cuda(gl), cuda(gd), want_rays=False, want_params=True)
+    assert g_none is None
+    _, g_wave = api.backward(net, cuda(rays), cuda(gl), cuda(gd), want_rays=True, want_params=True)
+    assert torch.equal(g_sweep, g_wave)
+    _, ref_p = mlp.backward(p, width, depth, rays, gl, gd)
+    gp = host(g_sweep)
+    scale = np.sqrt(np.mean(ref_p ** 2))
+    assert np.max(np.abs(gp - ref_p)) < 1e-5 * np.abs(ref_p).max()
+    assert np.median(np.abs(gp - ref_p) / np.maximum(np.abs(ref_p), scale)) < 1e-5
+
+
 def test_loss_seeds_and_adam():
     banner("loss seeds + adam")
     rng = np.random.default_rng(2)
