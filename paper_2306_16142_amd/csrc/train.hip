@@ -158,8 +158,11 @@ __global__ __launch_bounds__(512) void dw_kernel(const float *__restrict__ A, co
     for (int st = 0; st < nstep; ++st) {
         const int buf = st & 1;
         if (st + 1 < nstep) fetch(st + 1);
+        // a wave whose rows or columns all lie beyond M or N (the head's 2 rows) has no work
+        const bool busy = m0 + wm < M && n0 + wn < N;   // wave-uniform
 #pragma unroll
         for (int q = 0; q < 4; ++q) {   // four rays per lane half at a time
+            if (!busy) break;
             f32x4 a4[1], b4[2];
             a4[0] = *reinterpret_cast<const f32x4 *>(&sA[buf][wm + c][16 * h + 4 * q]);
 #pragma unroll
