@@ -8,8 +8,9 @@
 // 32-row block for both 32-ray halves; width 128: one block for one half), so no wave holds
 // more than one layer's slice in registers.  Weight tiles come from the L2-resident blob
 // (one 256-byte tile per wave and K-step, the layout the per-wave kernels read), ReLU masks
-// go to LDS for the reverse sweep.  The products run over the same tiles and operands in the
-// same order as the per-wave kernel, so the side outputs agree with it bit for bit.
+// go to LDS for the reverse sweep.  The layer products run over the same tiles and operands
+// in the same order as the per-wave kernel; the head's two rows are summed in chunks of 16
+// K-steps spread over all waves, so outputs and seeds agree with it to float32 rounding.
 #include <cmath>
 #include <mutex>
 
@@ -40,6 +41,7 @@ __host__ __device__ inline size_t sweep_lds_bytes(int depth) {
     return (size_t)kSweepRays * G::XP * 4                  // layer values
            + (size_t)depth * G::NMB * 2 * 64 * 2           // ReLU masks [layer][M-block][ray block][lane]
            + (size_t)2 * kSweepRays * 4                    // seeds
+           + (size_t)4 * 2 * 2 * 32 * 4                    // head partial sums [chunk][ray block][row][col]
            + (size_t)kSweepWaves * 4;                      // loss partials
 }
 
@@ -50,14 +52,17 @@ __host__ __device__ inline size_t sweep_lds_bytes(int depth) {
 template <int W, int KS, bool kFeat>
 __device__ __attribute__((always_inline)) inline void sweep_mfma(const uint8_t *blob, int64_t t0, int nmb, int mb,
                                                                  const float *X, int nb0, int lane,
-                                                                 f32x16 (&acc)[SweepGeo<W>::NBW]) {
+                                                                 f32x16 (&acc)[SweepGeo<W>::NBW], int kb0 = 0) {
     using G = SweepGeo<W>;
     constexpr int NBW = G::NBW;
     static_assert(KS % 4 == 0, "K-steps come in groups of four");
     const int h = lane >> 5, col = lane & 31;
-    const float *tiles = reinterpret_cast<const float *>(blob) + (t0 + mb) * 64 + lane;
     const int64_t tstride = (int64_t)nmb * 64;   // floats between consecutive K-steps
-    auto unit = [&](int kb) { return kFeat ? 40 * h + kb : 32 * (kb / 16) + 8 * ((kb % 16) / 4) + 4 * h; };
+    const float *tiles = reinterpret_cast<const float *>(blob) + (t0 + mb) * 64 + lane + kb0 * tstride;
+    auto unit = [&](int kb) {
+        kb += kb0;
+        return kFeat ? 40 * h + kb : 32 * (kb / 16) + 8 * ((kb % 16) / 4) + 4 * h;
+    };
     float a_cur[4], a_nxt[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) a_cur[q] = tiles[q * tstride];
@@ -99,7 +104,8 @@ __global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) 
     float *X = reinterpret_cast<float *>(smem);
     uint16_t *s_mask = reinterpret_cast<uint16_t *>(X + kSweepRays * XP);
     float *s_seed = reinterpret_cast<float *>(s_mask + depth * NMB * 2 * 64);   // [2][64]
-    float *s_loss = s_seed + 2 * kSweepRays;
+    float *s_hpart = s_seed + 2 * kSweepRays;
+    float *s_loss = s_hpart + 4 * 2 * 2 * 32;
 
     const NetLayout L = make_layout(W, depth, kFP32);
     const uint8_t *blob = a.blob;
@@ -181,17 +187,41 @@ __global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) 
             }
             __syncthreads();
         }
-        // ---- head (rows 0 and 1 of its one M-block) and loss seeds, by the waves of M-block 0
-        if (mb == 0) {
+        // ---- head (rows 0 and 1 of its one M-block) in four chunks of its K-steps (width 256:
+        // waves 0-3, each for both ray blocks; width 128: chunk = M-block index, every ray
+        // block); the partial sums meet in LDS (their 2 KiB keep two workgroups per CU at depth
+        // 6) and the waves of M-block 0 add them in chunk order and form the loss seeds
+        constexpr int kChunks = 4, kChunkK = NKB / kChunks;
+        if (W == 128 || wave < kChunks) {
+            const int chunk = W == 256 ? wave : mb;
             f32x16 hacc[NBW];
-            sweep_mfma<W, NKB, false>(blob, L.head_tile(), 1, 0, X, nb0, lane, hacc);
+            sweep_mfma<W, kChunkK, false>(blob, L.head_tile(), 1, 0, X, nb0, lane, hacc, chunk * kChunkK);
+            if (h == 0) {
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) {
+                    float *hp = s_hpart + ((chunk * 2 + nb0 + nb) * 2) * 32 + col;
+                    hp[0] = hacc[nb][0];    // row 0: logit
+                    hp[32] = hacc[nb][1];   // row 1: distance
+                }
+            }
+        }
+        __syncthreads();
+        if (mb == 0) {
             const float hb0 = bias[W * depth], hb1 = bias[W * depth + 1];
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) {
                 const int ray = (nb0 + nb) * 32 + col;
                 const int64_t r = base + ray;
                 const bool valid = r < n;
-                const float z = hacc[nb][0] + hb0, dd = hacc[nb][1] + hb1;   // lane half 0 holds rows 0 and 1
+                float z = 0.f, dd = 0.f;
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) {
+                    const float *hp = s_hpart + ((c * 2 + nb0 + nb) * 2) * 32 + col;
+                    z += hp[0];
+                    dd += hp[32];
+                }
+                z += hb0;
+                dd += hb1;
                 float gl = 0.f, gd = 0.f;
                 if (a.t_label) {
                     const float t = valid ? a.t_label[r] : INFINITY;

@@ -102,8 +102,9 @@ def test_parameter_gradient_fp32(width, depth, n):
 @pytest.mark.parametrize("width,depth,n", [(128, 4, 4096 + 37), (256, 6, 2048 + 5), (256, 1, 50), (128, 8, 64 * 3)])
 def test_parameter_gradient_fp32_training_sweep(width, depth, n):
     """Parameter gradients without the input gradient run the LDS training sweep: they match
-    the float64 oracle, and equal bit for bit those of the per-wave kernel (which also returns
-    the input gradient), whose products run over the same tiles in the same order."""
+    the float64 oracle, and those of the per-wave kernel (which also returns the input
+    gradient; its layer products run over the same tiles in the same order, only the head is
+    summed in another order) to float32 rounding."""
     banner("parameter gradient fp32 (training sweep) %dx%d n=%d" % (depth, width, n))
     p = synthetic.random_params(width, depth, 37)
     rays = _away_from_kinks(p, width, depth, _rays(n, 38))
@@ -114,7 +115,8 @@ def test_parameter_gradient_fp32_training_sweep(width, depth, n):
     g_none, g_sweep = api.backward(net, cuda(rays), cuda(gl), cuda(gd), want_rays=False, want_params=True)
     assert g_none is None
     _, g_wave = api.backward(net, cuda(rays), cuda(gl), cuda(gd), want_rays=True, want_params=True)
-    assert torch.equal(g_sweep, g_wave)
+    gw = host(g_wave)
+    assert np.max(np.abs(host(g_sweep) - gw)) <= 1e-6 * np.abs(gw).max()
     _, ref_p = mlp.backward(p, width, depth, rays, gl, gd)
     gp = host(g_sweep)
     scale = np.sqrt(np.mean(ref_p ** 2))
