@@ -25,8 +25,8 @@ constexpr float kErr = 32.0f * 5.9604645e-8f;   // 32 unit roundoffs of float32
 
 struct alignas(16) TriLds {
     float v0x, v0y, v0z, L;
-    float e1x, e1y, e1z, v0n;
-    float e2x, e2y, e2z, pad;
+    float e1x, e1y, e1z, s;    // s = |v0| + L (the triangle's part of the bound's scale)
+    float e2x, e2y, e2z, kL;   // kL = 32 eps L
 };
 
 // Float64 Moller-Trumbore from the float32 corners; returns the accepted t or NaN.
@@ -104,8 +104,8 @@ __global__ __launch_bounds__(kLabelThreads) void label_kernel(
             const float l2 = t.e2x * t.e2x + t.e2y * t.e2y + t.e2z * t.e2z;
             const float l3 = fx * fx + fy * fy + fz * fz;
             t.L = sqrtf(fmaxf(l1, fmaxf(l2, l3))) * 1.0001f;
-            t.v0n = sqrtf(t.v0x * t.v0x + t.v0y * t.v0y + t.v0z * t.v0z) * 1.0001f;
-            t.pad = 0.f;
+            t.s = sqrtf(t.v0x * t.v0x + t.v0y * t.v0y + t.v0z * t.v0z) * 1.0001f + t.L;
+            t.kL = kErr * t.L;
             s_tri[threadIdx.x] = t;
         }
         __syncthreads();
@@ -115,34 +115,38 @@ __global__ __launch_bounds__(kLabelThreads) void label_kernel(
             const float px = dy * T.e2z - dz * T.e2y;
             const float py = dz * T.e2x - dx * T.e2z;
             const float pz = dx * T.e2y - dy * T.e2x;
-            float D = T.e1x * px + T.e1y * py + T.e1z * pz;
+            const float D0 = T.e1x * px + T.e1y * py + T.e1z * pz;
             const float sx = ox - T.v0x, sy = oy - T.v0y, sz = oz - T.v0z;
-            float U = sx * px + sy * py + sz * pz;
             const float qx = sy * T.e1z - sz * T.e1y;
             const float qy = sz * T.e1x - sx * T.e1z;
             const float qz = sx * T.e1y - sy * T.e1x;
-            float V = dx * qx + dy * qy + dz * qz;
-            float Tq = T.e2x * qx + T.e2y * qy + T.e2z * qz;
-            if (D < 0.f) {
-                D = -D;
-                U = -U;
-                V = -V;
-                Tq = -Tq;
-            }
-            const float S = onorm + T.v0n + T.L;
-            const float B = kErr * S * T.L * dnorm;
-            const float BT = kErr * S * T.L * T.L;
+            // the two-sided test on |det|: flip the signs of all four quantities with det's
+            const uint32_t sgn = __float_as_uint(D0) & 0x80000000u;
+            const float D = __uint_as_float(__float_as_uint(D0) ^ sgn);
+            const float U = __uint_as_float(__float_as_uint(sx * px + sy * py + sz * pz) ^ sgn);
+            const float V = __uint_as_float(__float_as_uint(dx * qx + dy * qy + dz * qz) ^ sgn);
+            const float Tq = __uint_as_float(__float_as_uint(T.e2x * qx + T.e2y * qy + T.e2z * qz) ^ sgn);
+            const float st = (onorm + T.s) * T.kL;   // 32 eps (|o| + |v0| + L) L
+            const float B = st * dnorm;
+            const float BT = st * T.L;
+            // sure miss (no lane of the wave needs more: the common case, one branch per wave)
+            const bool small = D <= 2.f * B;
+            const float lo = t_min * D, blo = BT + abs_tmin * B;
+            const float hi = tmax_inf ? INFINITY : t_max * D, bhi = BT + abs_tmax * B;
+            // (bitwise | and & keep this straight-line: no branch per comparison)
+            const bool miss_small = (fabsf(U) > 4.f * B) | (fabsf(V) > 4.f * B);
+            const bool miss_big = (U < -B) | (V < -B) | (U + V > D + 3.f * B) | (Tq <= lo - blo) |
+                                  ((!tmax_inf) & (Tq >= hi + bhi));
+            const bool miss = (small & miss_small) | ((!small) & miss_big);
+            if (__builtin_expect(!__any(!miss), 1)) continue;
             int decision;   // 0 sure miss, 1 sure hit, 2 undecided
-            if (D <= 2.f * B) {
-                decision = (fabsf(U) > 4.f * B || fabsf(V) > 4.f * B) ? 0 : 2;
+            if (miss) {
+                decision = 0;
+            } else if (small) {
+                decision = 2;
             } else {
-                const float lo = t_min * D, blo = BT + abs_tmin * B;
-                const float hi = tmax_inf ? INFINITY : t_max * D, bhi = BT + abs_tmax * B;
-                const bool miss = U < -B || V < -B || U + V > D + 3.f * B || Tq <= lo - blo ||
-                                  (!tmax_inf && Tq >= hi + bhi);
-                const bool hit = U > B && V > B && U + V < D - 3.f * B && Tq > lo + blo &&
-                                 (tmax_inf || Tq < hi - bhi);
-                decision = miss ? 0 : (hit ? 1 : 2);
+                const bool hit = U > B && V > B && U + V < D - 3.f * B && Tq > lo + blo && (tmax_inf || Tq < hi - bhi);
+                decision = hit ? 1 : 2;
             }
             if (decision == 0) continue;
             float t;
