@@ -52,6 +52,8 @@ __device__ __noinline__ double mt_fp64(const float *__restrict__ tris, int64_t m
 
 // Output slot q reads ray idx[q] (or q) from [3][stride] arrays; only q < n (or *count_dev)
 // are processed.  Blocks past the count exit before touching LDS.
+// kTmaxInf: t_max is +inf (labels), so the far bound needs no test.
+template <bool kTmaxInf>
 __global__ __launch_bounds__(kLabelThreads) void label_kernel(
     const float *__restrict__ orig, const float *__restrict__ dir, int64_t stride, const int *__restrict__ idx,
     const int *__restrict__ count_dev, const float *__restrict__ tris, int64_t m, float t_min, float t_max,
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(kLabelThreads) void label_kernel(
     const bool active = ray < n && finite;
     const float onorm = sqrtf(ox * ox + oy * oy + oz * oz);
     const float dnorm = sqrtf(dx * dx + dy * dy + dz * dz);
-    const bool tmax_inf = isinf(t_max);
+    constexpr bool tmax_inf = kTmaxInf;
     const float abs_tmin = fabsf(t_min), abs_tmax = tmax_inf ? 0.f : fabsf(t_max);
 
     float best_t = INFINITY;
@@ -133,12 +135,14 @@ __global__ __launch_bounds__(kLabelThreads) void label_kernel(
             const bool small = D <= 2.f * B;
             const float lo = t_min * D, blo = BT + abs_tmin * B;
             const float hi = tmax_inf ? INFINITY : t_max * D, bhi = BT + abs_tmax * B;
-            // (bitwise | and & keep this straight-line: no branch per comparison)
-            const bool miss_small = (fabsf(U) > 4.f * B) | (fabsf(V) > 4.f * B);
-            const bool miss_big = (U < -B) | (V < -B) | (U + V > D + 3.f * B) | (Tq <= lo - blo) |
-                                  ((!tmax_inf) & (Tq >= hi + bhi));
-            const bool miss = (small & miss_small) | ((!small) & miss_big);
-            if (__builtin_expect(!__any(!miss), 1)) continue;
+            // every comparison as a wave-wide lane mask (scalar ORs, no per-lane branch)
+            const uint64_t m_small = __ballot(small);
+            const uint64_t ms = __ballot(fabsf(U) > 4.f * B) | __ballot(fabsf(V) > 4.f * B);
+            uint64_t mb = __ballot(U < -B) | __ballot(V < -B) | __ballot(U + V > D + 3.f * B) | __ballot(Tq <= lo - blo);
+            if constexpr (!kTmaxInf) mb |= __ballot(Tq >= hi + bhi);
+            const uint64_t miss_mask = (m_small & ms) | (~m_small & mb);
+            if (__builtin_expect((__ballot(1) & ~miss_mask) == 0, 1)) continue;
+            const bool miss = (miss_mask >> __lane_id()) & 1u;
             int decision;   // 0 sure miss, 1 sure hit, 2 undecided
             if (miss) {
                 decision = 0;
@@ -192,7 +196,8 @@ extern "C" ddf_status ddf_label_rays(const float *orig, const float *dir, int64_
     DDF_REQUIRE(m < (int64_t)1 << 31, DDF_ERR_UNSUPPORTED, "ddf_label_rays: more than 2^31 triangles");
     const int64_t blocks = (n + kLabelThreads - 1) / kLabelThreads;
     DDF_REQUIRE(blocks < (int64_t)1 << 31, DDF_ERR_UNSUPPORTED, "ddf_label_rays: too many rays");
-    hipLaunchKernelGGL(label_kernel, dim3((unsigned)blocks), dim3(kLabelThreads), 0, as_stream(stream), orig, dir,
+    hipLaunchKernelGGL(std::isinf(t_max) ? label_kernel<true> : label_kernel<false>, dim3((unsigned)blocks),
+                       dim3(kLabelThreads), 0, as_stream(stream), orig, dir,
                        n, (const int *)nullptr, (const int *)nullptr, tris, m, t_min, t_max, t_out, tri_out, crossings);
     return launch_status("ddf_label_rays");
 }
@@ -203,7 +208,8 @@ ddf_status label_queue(const float *orig, const float *dir, int64_t stride, cons
                        const float *tris, int64_t m, float t_min, float t_max, float *t_out, int32_t *tri_out,
                        hipStream_t s) {
     const int64_t blocks = (stride + kLabelThreads - 1) / kLabelThreads;
-    hipLaunchKernelGGL(label_kernel, dim3((unsigned)blocks), dim3(kLabelThreads), 0, s, orig, dir, stride, idx,
+    hipLaunchKernelGGL(std::isinf(t_max) ? label_kernel<true> : label_kernel<false>, dim3((unsigned)blocks),
+                       dim3(kLabelThreads), 0, s, orig, dir, stride, idx,
                        count_dev, tris, m, t_min, t_max, t_out, tri_out, (uint32_t *)nullptr);
     return launch_status("ddf labeller (queue)");
 }
