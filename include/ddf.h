@@ -197,6 +197,19 @@ ddf_status ddf_train_step(const ddf_net *net, float *params, float *adam_m, floa
                           float *loss_out, float *g_params, void *ws, size_t ws_bytes,
                           ddf_stream stream);
 
+/* The same training step for a batch whose workspace would be too large: the n rays are
+ * swept in column ranges of `chunk` rays, each recomputing its forward pass and keeping its
+ * activations only in a workspace of ddf_train_workspace_size(width, depth, chunk) bytes
+ * (memory independent of n).  The loss and its seeds use the whole batch's normalisation
+ * (1 / n, 1 / hits), so the gradient is that of the full batch, summed over chunks in a
+ * fixed order (equal to ddf_train_step's up to float32 summation order); then one Adam
+ * update and repack.  rays [5][n] and t_label [n] as in ddf_train_step; chunk >= 1
+ * (values above n mean one chunk). */
+ddf_status ddf_train_step_chunked(const ddf_net *net, float *params, float *adam_m, float *adam_v,
+                                  int64_t step, float lr, const float *rays, const float *t_label,
+                                  int64_t n, int64_t chunk, float *loss_out, float *g_params, void *ws,
+                                  size_t ws_bytes, ddf_stream stream);
+
 /* ---------------------------------------------------------------- renderer
  * Wavefront path tracer of Fig. 1 in which the nearest-hit search is either the
  * brute-force triangle search (backend MESH) or the network (backend NET): the

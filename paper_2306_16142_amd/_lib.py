@@ -63,6 +63,8 @@ SIGNATURES = {
     "ddf_render_wavefront": [ctypes.POINTER(DdfScene), ctypes.POINTER(DdfRenderParams), c_p, c_p, c_p, c_p, c_p, c_sz,
                              c_p],
     "ddf_train_step": [ctypes.POINTER(DdfNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64, c_p, c_p, c_p, c_sz, c_p],
+    "ddf_train_step_chunked": [ctypes.POINTER(DdfNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64, c_i64, c_p, c_p,
+                               c_p, c_sz, c_p],
     "ddf_set_tuning": [c_i32, c_i32],
     "ddf_get_tuning": [c_i32, ctypes.POINTER(c_i32)],
 }

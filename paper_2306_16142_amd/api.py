@@ -151,7 +151,10 @@ class Trainer:
     The packed network ``net`` is rewritten after every step; ``params`` is updated in place.
     """
 
-    def __init__(self, params, width, depth, batch, lr=1e-3):
+    def __init__(self, params, width, depth, batch, lr=1e-3, chunk=None):
+        """``chunk``: sweep batches in column ranges of this many rays (workspace sized for
+        ``chunk`` instead of ``batch``; the forward pass is recomputed per chunk)."""
+        self.chunk = chunk
         self.net = Network(params, width, depth, "fp32")
         self.params = params
         self.m = torch.zeros_like(params)
@@ -160,13 +163,19 @@ class Trainer:
         self.loss = torch.zeros(1, device=params.device, dtype=torch.float32)
         self.lr = lr
         self.step_count = 0
-        self.ws = torch.empty(train_workspace_bytes(width, depth, batch), device=params.device, dtype=torch.uint8)
+        self.ws = torch.empty(train_workspace_bytes(width, depth, chunk if chunk else batch), device=params.device,
+                              dtype=torch.uint8)
 
     def step(self, rays, t_label):
         _dev(rays, torch.float32, "rays", 5)
         _dev(t_label, torch.float32, "t_label")
         self.step_count += 1
         n = rays.shape[1]
+        if self.chunk:
+            _lib.call("ddf_train_step_chunked", ctypes.byref(self.net.desc), _p(self.params), _p(self.m), _p(self.v),
+                      self.step_count, self.lr, _p(rays), _p(t_label), n, self.chunk, _p(self.loss), _p(self.g),
+                      _p(self.ws), self.ws.numel(), _stream())
+            return self.loss
         _lib.call("ddf_train_step", ctypes.byref(self.net.desc), _p(self.params), _p(self.m), _p(self.v),
                   self.step_count, self.lr, _p(rays), _p(t_label), n, _p(self.loss), _p(self.g), _p(self.ws),
                   self.ws.numel(), _stream())

@@ -13,6 +13,8 @@ struct GradArgs {
     int depth;                   // single network: depth; multi: the largest depth of the group
     const float *rays;           // [5][n]
     int64_t n;                   // row length of every [k][n] array
+    int64_t ray_stride;          // training sweep only: row length of `rays` when it is a column
+                                 // range of a longer batch (0: n)
     const int *count_dev;        // single network: only the first *count_dev rays (NULL: all n)
     const float *g_logit_in;     // seeds (NULL = 0)
     const float *g_dist_in;

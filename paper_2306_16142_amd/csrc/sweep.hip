@@ -96,6 +96,7 @@ __global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) 
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     const int depth = a.depth;
     const int64_t n = a.n;
+    const int64_t rstride = a.ray_stride ? a.ray_stride : n;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = lane >> 5, col = lane & 31;
     const int mb = W == 256 ? wave : wave >> 1;   // this wave's M-block
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) 
                 continue;
             }
             const int var = hh ? 3 + g : g;
-            const float x = valid ? a.rays[(int64_t)var * n + r] : 0.f;
+            const float x = valid ? a.rays[(int64_t)var * rstride + r] : 0.f;
             float feat[kFeatPerVar];
             encode_var<true>(x, feat);
 #pragma unroll

@@ -71,7 +71,7 @@ void launch_loss_scalars(const float *t_label, int64_t n, unsigned int *part, fl
     hipLaunchKernelGGL(loss_scalars_kernel, dim3(1), dim3(256), 0, s, part, blocks, n, scalars, count);
 }
 
-__global__ void sum_partials_kernel(const float *__restrict__ part, int64_t cnt, float *out) {
+__global__ void sum_partials_kernel(const float *__restrict__ part, int64_t cnt, float *out, bool accumulate) {
     __shared__ float red[256];
     float s = 0.f;
     for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) s += part[i];
@@ -81,7 +81,7 @@ __global__ void sum_partials_kernel(const float *__restrict__ part, int64_t cnt,
         if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = red[0];
+    if (threadIdx.x == 0) *out = accumulate ? *out + red[0] : red[0];
 }
 
 // ------------------------------------------------------------------------------ dW = A B^T
@@ -382,7 +382,7 @@ extern "C" ddf_status ddf_loss_seeds(const float *logit, const float *dist, cons
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(loss_seeds_kernel, dim3(blocks), dim3(256), 0, s, logit, dist, t_label, n, scalars, g_logit,
                        g_dist, part);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, part, (int64_t)blocks, loss_out);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, part, (int64_t)blocks, loss_out, false);
     return launch_status("ddf_loss_seeds");
 }
 
@@ -397,6 +397,25 @@ extern "C" ddf_status ddf_adam_step(float *params, const float *grads, float *m,
 
 extern "C" ddf_status ddf_pack_net(const float *params, int32_t width, int32_t depth, int32_t precision,
                                    const float *scales, void *packed, ddf_stream stream);
+
+namespace ddf {
+namespace {
+// Adam on the flat parameters (float32 layers of the network) and repacking of `net`.
+ddf_status adam_and_repack(const ddf_net *net, float *params, float *adam_m, float *adam_v, const float *g_params,
+                           int64_t step, float lr, ddf_stream stream) {
+    int64_t count = 0;
+    int in = kInDim;
+    for (int l = 0; l <= net->depth; ++l) {
+        const int out = l == net->depth ? 2 : net->width;
+        count += (int64_t)out * in + out;
+        in = net->width;
+    }
+    if (ddf_status st = ddf_adam_step(params, g_params, adam_m, adam_v, count, step, lr, 0.9f, 0.999f, 1e-8f, stream))
+        return st;
+    return ddf_pack_net(params, net->width, net->depth, net->precision, nullptr, const_cast<void *>(net->packed), stream);
+}
+}  // namespace
+}  // namespace ddf
 
 extern "C" ddf_status ddf_train_step(const ddf_net *net, float *params, float *adam_m, float *adam_v, int64_t step,
                                      float lr, const float *rays, const float *t_label, int64_t n, float *loss_out,
@@ -425,18 +444,50 @@ extern "C" ddf_status ddf_train_step(const ddf_net *net, float *params, float *a
     a.ws_delta = w.delta;
     a.loss_partial = w.loss_part;
     if (ddf_status st = grad_dispatch(net, a, true, s)) return st;
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, w.loss_part, grid, loss_out);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, w.loss_part, grid, loss_out, false);
     if (ddf_status st = param_grads(net->width, net->depth, n, w, g_params, false, s)) return st;
-    int64_t count = 0;
-    {
-        int in = kInDim;
-        for (int l = 0; l <= net->depth; ++l) {
-            const int out = l == net->depth ? 2 : net->width;
-            count += (int64_t)out * in + out;
-            in = net->width;
-        }
+    return adam_and_repack(net, params, adam_m, adam_v, g_params, step, lr, stream);
+}
+
+extern "C" ddf_status ddf_train_step_chunked(const ddf_net *net, float *params, float *adam_m, float *adam_v,
+                                             int64_t step, float lr, const float *rays, const float *t_label,
+                                             int64_t n, int64_t chunk, float *loss_out, float *g_params, void *ws,
+                                             size_t ws_bytes, ddf_stream stream) {
+    if (ddf_status st = check_net(net, "ddf_train_step_chunked", true)) return st;
+    DDF_REQUIRE(params && adam_m && adam_v && rays && t_label && loss_out && g_params && n > 0 && chunk > 0 &&
+                    step >= 1,
+                DDF_ERR_INVALID_ARG, "ddf_train_step_chunked: bad argument");
+    chunk = std::min(chunk, n);
+    const TrainWs need = train_ws(net->width, net->depth, chunk, nullptr);
+    DDF_REQUIRE(ws && ws_bytes >= need.bytes, DDF_ERR_WORKSPACE,
+                "ddf_train_step_chunked: workspace of %zu bytes needed", need.bytes);
+    DDF_REQUIRE(grad_grid(net->width, net->precision, chunk) <= 4096, DDF_ERR_UNSUPPORTED,
+                "ddf_train_step_chunked: grid too large");
+    hipStream_t s = as_stream(stream);
+    const TrainWs w = train_ws(net->width, net->depth, chunk, ws);
+    // the loss normalisation (1 / N, 1 / hits) of the whole batch, then every chunk's sweep
+    // (its forward pass recomputed, its activations only in the chunk workspace) adds its
+    // loss and parameter gradient in chunk order
+    launch_loss_scalars(t_label, n, reinterpret_cast<unsigned int *>(w.loss_part), w.scalars, w.count, s);
+    if (ddf_status st = launch_status("ddf_train_step_chunked")) return st;
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        const int64_t m = std::min(chunk, n - c0);
+        GradArgs a{};
+        a.blob = (const uint8_t *)net->packed;
+        a.depth = net->depth;
+        a.rays = rays + c0;
+        a.ray_stride = n;
+        a.n = m;
+        a.t_label = t_label + c0;
+        a.loss_scalars = w.scalars;
+        a.ws_gamma = w.gamma;
+        a.ws_h = w.h;
+        a.ws_delta = w.delta;
+        a.loss_partial = w.loss_part;
+        if (ddf_status st = sweep_dispatch(net->width, a, s)) return st;
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, w.loss_part,
+                           grad_grid(net->width, net->precision, m), loss_out, c0 > 0);
+        if (ddf_status st = param_grads(net->width, net->depth, m, w, g_params, c0 > 0, s)) return st;
     }
-    if (ddf_status st = ddf_adam_step(params, g_params, adam_m, adam_v, count, step, lr, 0.9f, 0.999f, 1e-8f, stream))
-        return st;
-    return ddf_pack_net(params, net->width, net->depth, net->precision, nullptr, const_cast<void *>(net->packed), stream);
+    return adam_and_repack(net, params, adam_m, adam_v, g_params, step, lr, stream);
 }

@@ -28,7 +28,8 @@ def lib():
 def test_header_declares_the_hot_path():
     names = _declared()
     for required in ("ddf_label_rays", "ddf_forward", "ddf_backward", "ddf_render_wavefront", "ddf_pack_net",
-                     "ddf_train_step", "ddf_assemble_rays", "ddf_query", "ddf_set_tuning"):
+                     "ddf_train_step", "ddf_train_step_chunked", "ddf_assemble_rays", "ddf_query",
+                     "ddf_set_tuning"):
         assert required in names
 
 
@@ -77,6 +78,17 @@ def test_validation_before_launch(lib):
     assert lib.ddf_backward(ctypes.byref(net), 1, 10, None, None, None, 1, 0, None, 0, None) == _lib.DDF_ERR_UNSUPPORTED
     net = _lib.DdfNet(128, 4, 2, 1)
     assert lib.ddf_backward(ctypes.byref(net), 1, 10, None, None, 1, None, 0, None, 0, None) == _lib.DDF_ERR_UNSUPPORTED
+    # chunked training step: float32 only, chunk >= 1, workspace sized for one chunk
+    f32 = _lib.DdfNet(128, 4, 0, 1)
+    bf = _lib.DdfNet(128, 4, 1, 1)
+    big = 1 << 40
+    assert lib.ddf_train_step_chunked(ctypes.byref(bf), 1, 1, 1, 1, 1e-3, 1, 1, 1000, 100, 1, 1, 1, big, None) == \
+        _lib.DDF_ERR_UNSUPPORTED
+    assert lib.ddf_train_step_chunked(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 1000, 0, 1, 1, 1, big, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_train_step_chunked(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 1000, 100, 1, 1, 1, 16, None) == \
+        _lib.DDF_ERR_WORKSPACE
+    assert b"workspace" in lib.ddf_last_error()
     # fp8 packing needs scales, the others must not get any
     assert lib.ddf_pack_net(1, 128, 4, 2, None, 1, None) == _lib.DDF_ERR_INVALID_ARG
     assert lib.ddf_pack_net(1, 128, 4, 1, 1, 1, None) == _lib.DDF_ERR_INVALID_ARG

@@ -181,6 +181,36 @@ def test_train_step_matches_oracle():
     assert np.max(_rel(host(lg2), lref)) < 1e-4
 
 
+@pytest.mark.parametrize("width,depth,n,chunk", [(128, 4, 4096 + 100, 1000), (256, 3, 3000, 64 * 7 + 5)])
+def test_chunked_train_step_equals_full_batch(width, depth, n, chunk):
+    """A batch swept in column ranges (each recomputing its forward pass in a workspace sized
+    for one range) gives the full batch's loss and gradient: the seeds use the whole batch's
+    normalisation, only the float32 summation order differs."""
+    banner("chunked train step %dx%d n=%d chunk=%d" % (depth, width, n, chunk))
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    o, d, _ = synthetic.training_rays(v, f, n, 5)
+    from oracle import geometry
+    t = geometry.nearest_hit(o, d, tris)["t"].astype(np.float32)
+    rays = cuda(rays5_from(o, d))
+    p = synthetic.xavier_params(width, depth, 4)
+    full = api.Trainer(cuda(p), width, depth, n)
+    part = api.Trainer(cuda(p), width, depth, n, chunk=chunk)
+    assert part.ws.numel() < full.ws.numel()
+    lf = host(full.step(rays, cuda(t)))[0]
+    lp = host(part.step(rays, cuda(t)))[0]
+    assert abs(lp - lf) <= 1e-6 * abs(lf)
+    gf, gp = host(full.g), host(part.g)
+    assert np.max(np.abs(gp - gf)) <= 1e-5 * np.abs(gf).max()
+    # the first Adam step moves by lr * sign(g): signs of near-zero components may differ
+    moved_f, moved_p = host(full.params) - p, host(part.params) - p
+    assert np.mean(np.abs(moved_f - moved_p) < 1e-6) > 0.999
+    # a second step runs on the repacked network
+    lf2 = host(full.step(rays, cuda(t)))[0]
+    lp2 = host(part.step(rays, cuda(t)))[0]
+    assert abs(lp2 - lf2) <= 1e-3 * abs(lf2)
+
+
 def test_autograd_function_matches_backward():
     banner("autograd.Function")
     width, depth, n = 128, 2, 512
