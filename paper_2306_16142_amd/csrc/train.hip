@@ -201,19 +201,31 @@ __global__ __launch_bounds__(512) void dw_kernel(const float *__restrict__ A, co
     }
 }
 
-// g[W block] (+)= sum_s part[s], g[b block] (+)= sum_s dbpart[s]  (fixed summation order)
+// g[W block] (+)= sum_s part[s], g[b block] (+)= sum_s dbpart[s]  (fixed summation order).
+// Four lanes share an element: lane q sums the splits q, q + 4, q + 8, ... and lane 0 of the
+// group adds the four sums in lane order, so more loads are in flight per element.
+constexpr int kReduceLanes = 4;   // the shuffles below take four partial sums
 __global__ void reduce_dw_kernel(const float *__restrict__ part, const float *__restrict__ dbpart, int M, int N,
                                  int splits, float *__restrict__ g, bool accumulate) {
     const int64_t total = (int64_t)M * N + M;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int q = threadIdx.x % kReduceLanes;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kReduceLanes);
+    // every lane runs the same number of iterations (the shuffles need the whole wave)
+    for (int64_t e0 = (int64_t)blockIdx.x * (blockDim.x / kReduceLanes); e0 < total; e0 += stride) {
+        const int64_t e = e0 + threadIdx.x / kReduceLanes;
         float s = 0.f;
         if (e < (int64_t)M * N) {
-            for (int k = 0; k < splits; ++k) s += part[(int64_t)k * M * N + e];
-        } else {
+            for (int k = q; k < splits; k += kReduceLanes) s += part[(int64_t)k * M * N + e];
+        } else if (e < total) {
             const int64_t m = e - (int64_t)M * N;
-            for (int k = 0; k < splits; ++k) s += dbpart[(int64_t)k * M + m];
+            for (int k = q; k < splits; k += kReduceLanes) s += dbpart[(int64_t)k * M + m];
         }
-        g[e] = accumulate ? g[e] + s : s;
+        const int lead = (threadIdx.x & 63) & ~(kReduceLanes - 1);
+        const float s0 = __shfl(s, lead), s1 = __shfl(s, lead + 1), s2 = __shfl(s, lead + 2), s3 = __shfl(s, lead + 3);
+        if (q == 0 && e < total) {
+            const float t = ((s0 + s1) + s2) + s3;
+            g[e] = accumulate ? g[e] + t : t;
+        }
     }
 }
 
@@ -304,7 +316,7 @@ ddf_status param_grads(int width, int depth, int64_t n, const TrainWs &w, float 
             hipLaunchKernelGGL(dw_kernel<false>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, w.part, w.dbpart);
         if (ddf_status st = launch_status("ddf parameter gradient")) return st;
         const int64_t total = (int64_t)M * N + M;
-        hipLaunchKernelGGL(reduce_dw_kernel, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(256), 0, s,
+        hipLaunchKernelGGL(reduce_dw_kernel, dim3((unsigned)std::min<int64_t>((total + 63) / 64, 4096)), dim3(256), 0, s,
                            w.part, w.dbpart, M, N, splits, g_params + off, accumulate);
         if (ddf_status st = launch_status("ddf parameter gradient reduction")) return st;
         off += total;
