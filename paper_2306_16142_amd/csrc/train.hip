@@ -99,7 +99,7 @@ constexpr int kDwPad = 36;
 
 template <bool kVec4>
 __global__ __launch_bounds__(512) void dw_kernel(const float *__restrict__ A, const float *__restrict__ B, int M,
-                                                 int N, int64_t n, int splits, float *__restrict__ part,
+                                                 int N, int64_t n, int splits, int chunk, float *__restrict__ part,
                                                  float *__restrict__ dbpart) {
     __shared__ __attribute__((aligned(16))) float sA[2][kDwTile][kDwPad];
     __shared__ __attribute__((aligned(16))) float sB[2][kDwTile][kDwPad];
@@ -107,8 +107,8 @@ __global__ __launch_bounds__(512) void dw_kernel(const float *__restrict__ A, co
     const int ntn = (N + kDwTile - 1) / kDwTile;
     const int s = blockIdx.x % splits, tile = blockIdx.x / splits;
     const int m0 = (tile / ntn) * kDwTile, n0 = (tile % ntn) * kDwTile;
-    const int64_t k0 = (int64_t)s * kChunk;
-    const int klen = (int)min<int64_t>(kChunk, n - k0);
+    const int64_t k0 = (int64_t)s * chunk;
+    const int klen = (int)min<int64_t>(chunk, n - k0);
     const int nstep = (klen + kDwStep - 1) / kDwStep;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
     // global -> register staging: 128 rows x 32 rays per operand = 1024 float4, 2 per thread
@@ -293,8 +293,9 @@ TrainWs train_ws(int width, int depth, int64_t n, void *base) {
     w.loss_part = reinterpret_cast<float *>(take(4096 * 4));
     w.scalars = reinterpret_cast<float *>(take(16));
     w.count = reinterpret_cast<unsigned int *>(take(16));
-    w.part = reinterpret_cast<float *>(take((size_t)splits * width * maxN * 4));
-    w.dbpart = reinterpret_cast<float *>(take((size_t)splits * width * 4));
+    // partials for up to twice the splits (layers of few output tiles use half-size chunks)
+    w.part = reinterpret_cast<float *>(take((size_t)2 * splits * width * maxN * 4));
+    w.dbpart = reinterpret_cast<float *>(take((size_t)2 * splits * width * 4));
     w.bytes = off;
     return w;
 }
@@ -302,18 +303,24 @@ TrainWs train_ws(int width, int depth, int64_t n, void *base) {
 // Parameter gradients of all layers from the stored features / activations / adjoints.
 ddf_status param_grads(int width, int depth, int64_t n, const TrainWs &w, float *g_params, bool accumulate,
                        hipStream_t s) {
-    const int splits = (int)((n + kChunk - 1) / kChunk);
     int64_t off = 0;
     for (int l = 0; l <= depth; ++l) {
         const int M = l == depth ? 2 : width;
         const int N = l == 0 ? kInDim : width;
         const float *A = l == depth ? w.delta + (int64_t)depth * width * n : w.delta + (int64_t)l * width * n;
         const float *B = l == 0 ? w.gamma : w.h + (int64_t)(l - 1) * width * n;
-        const unsigned blocks = (unsigned)(((M + kDwTile - 1) / kDwTile) * ((N + kDwTile - 1) / kDwTile) * splits);
+        const int tiles = ((M + kDwTile - 1) / kDwTile) * ((N + kDwTile - 1) / kDwTile);
+        // layers of fewer than four output tiles (layer 0, the head, width 128) split the rays
+        // twice as finely, so that they still occupy every CU
+        const int chunk = tiles >= 4 ? kChunk : kChunk / 2;
+        const int splits = (int)((n + chunk - 1) / chunk);
+        const unsigned blocks = (unsigned)(tiles * splits);
         if (n % 4 == 0)
-            hipLaunchKernelGGL(dw_kernel<true>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, w.part, w.dbpart);
+            hipLaunchKernelGGL(dw_kernel<true>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, chunk, w.part,
+                               w.dbpart);
         else
-            hipLaunchKernelGGL(dw_kernel<false>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, w.part, w.dbpart);
+            hipLaunchKernelGGL(dw_kernel<false>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, chunk, w.part,
+                               w.dbpart);
         if (ddf_status st = launch_status("ddf parameter gradient")) return st;
         const int64_t total = (int64_t)M * N + M;
         hipLaunchKernelGGL(reduce_dw_kernel, dim3((unsigned)std::min<int64_t>((total + 63) / 64, 4096)), dim3(256), 0, s,
