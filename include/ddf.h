@@ -109,8 +109,9 @@ ddf_status ddf_assemble_rays(const float *orig, const float *dir, int64_t n, flo
                                            that is width 128); default 2 */
 #define DDF_TUNE_CULL_RAYS_PER_BLOCK 1  /* rays per block of the multi-object instance culling:
                                            power of two in [256, 16384]; default 2048 */
-#define DDF_TUNE_GRAD_WG_PER_CU 2       /* workgroups per CU of the float32 gradient kernel: 1, 2 or
-                                           4; default 2 */
+#define DDF_TUNE_GRAD_WG_PER_CU 2       /* workgroups per CU of the per-wave gradient kernel (input
+                                           gradients; the float32 training sweep sizes its own
+                                           grid): 1, 2 or 4; default 2 */
 #define DDF_TUNE_COUNT 3
 ddf_status ddf_set_tuning(int32_t knob, int32_t value);
 ddf_status ddf_get_tuning(int32_t knob, int32_t *value);
