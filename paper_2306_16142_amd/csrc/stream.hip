@@ -1,12 +1,12 @@
 // Network query and input gradient (Sec. IV-A query, Eq. 3 normals) for bf16 networks whose
 // packed weights do not fit in one CU's LDS: width 256, or width 128 deeper than four layers.
 //
-// A workgroup evaluates 256 rays at a time and streams the weight tiles through a
-// three-stage LDS ring that all its waves read.  One "phase" is one 32-row M-block of one
-// layer (its K-blocks, plus the bias K-block of a hidden layer).  At the start of phase p
-// each wave issues its share of phase p + 2 as loads that write LDS directly
-// (global_load_lds), waits for them at the end of the phase, and one barrier per phase
-// publishes the stage.  The table lookup that locates a phase's tiles is done one phase
+// A workgroup evaluates 256 rays at a time and streams the weight tiles through an LDS ring
+// that all its waves read.  One "phase" is one 32-row M-block of one layer (its K-blocks,
+// plus the bias K-block of a hidden layer).  At the start of phase p each wave issues its
+// share of phase p + 2 as loads that write LDS directly (global_load_lds) and waits for them
+// before the next barrier, which publishes the stages: at width 128 one barrier per phase
+// (three stages), at width 256 one per pair of phases (four stages).  The table lookup that locates a phase's tiles is done one phase
 // early, across the previous barrier, so a phase begins with its loads and its MFMA chain.
 // Every wave reads each weight tile from LDS, and the workgroup reads it from L2 once per
 // 256 rays (the per-wave kernel read it once per 32 or 64).
@@ -36,7 +36,13 @@ struct Geo {
     static constexpr int kNB = W == 256 ? 1 : 2;
 };
 constexpr int kRaysPerTile = 256;
-constexpr int kStages = 3;
+// Width 256 runs its phases in pairs between barriers with a four-stage ring; width 128 (whose
+// two workgroups per CU need the smaller ring) one phase per barrier with three stages.
+template <int W>
+struct Ring {
+    static constexpr bool kPair = W == 256;
+    static constexpr int kStages = kPair ? 4 : 3;
+};
 constexpr int kMaxStreamLds = 160 * 1024;
 constexpr int kMaxPhases = 8 * 8 + 1 + 7 * 8 + kGradRowBlocks0;   // width 256, depth 8, gradient
 
@@ -121,7 +127,7 @@ struct Desc {
 // so a phase starts its fetch without waiting on the table).
 struct Pipe {
     int cur, q, nxt;
-    int stage;   // 0 .. kStages-1
+    int stage;   // 0 .. stages - 1
     int np_cur, np_nxt;
     uint64_t blob_cur, blob_nxt;
     Desc d2;
@@ -205,14 +211,29 @@ __device__ inline void stage_fetch(Stage<W> &sg, const Desc &d, lds_u8 *stage, i
 // (vmcnt(0), other counters left alone) before the barrier that publishes the stage.
 __device__ inline void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// End of a phase: publish the fetched share (two phases ahead) and advance.
+// Start of a phase: issue this wave's loads of the phase two ahead (into the stage that the
+// phase two back used) and the table read for the phase after that.
 template <int W>
-__device__ inline void phase_end(const Stage<W> &sg, lds_u8 *ring, const NetTable *tab, Pipe &pp, int wave, int lane) {
-    const DescRaw nd = desc_issue(tab, pp, 3);   // two ahead of the next phase
-    stage_wait();
-    __syncthreads();
+__device__ inline DescRaw phase_begin(Stage<W> &sg, lds_u8 *ring, const NetTable *tab, const Pipe &pp, int wave,
+                                      int lane) {
+    stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, (pp.stage + 2) % Ring<W>::kStages), wave, lane);
+    if constexpr (Ring<W>::kPair) return desc_issue(tab, pp, 3);
+    return DescRaw{};   // single mode reads the table at the end of the phase (fewer live registers)
+}
+
+// End of a phase.  With `bar` the barrier waits for this wave's loads and publishes the next
+// stages; in pair mode only the second phase of a pair (or a lone phase) has one, so every
+// phase is still separated by a barrier from the phase two before it, whose stage its loads
+// overwrite, and its own stage was loaded and published before it starts.
+template <int W>
+__device__ inline void phase_end(const DescRaw &nd_begin, const NetTable *tab, Pipe &pp, bool bar) {
+    const DescRaw nd = Ring<W>::kPair ? nd_begin : desc_issue(tab, pp, 3);
+    if (bar) {
+        stage_wait();
+        __syncthreads();
+    }
     pp.d2 = desc_finish(nd);
-    pp.stage = pp.stage == kStages - 1 ? 0 : pp.stage + 1;
+    pp.stage = pp.stage == Ring<W>::kStages - 1 ? 0 : pp.stage + 1;
     ++pp.q;
 }
 
@@ -229,8 +250,9 @@ struct ARing {
 };
 
 // One phase's MFMA chain: KS K-blocks from the stage (the last one the bias block when
-// kBias); the last kAR steps load the next phase's first tiles.
-template <int W, int KS, bool kBias>
+// kBias).  kHaveFirst: the ring holds tiles 0 .. kAR - 1 already (else they are read here);
+// kNext: the last kAR steps load the next phase's first tiles (its stage is published).
+template <int W, int KS, bool kBias, bool kHaveFirst = true, bool kNext = true>
 __device__ __attribute__((always_inline)) inline void phase_mfma(const lds_u8 *st, const lds_u8 *st_next, ARing &ar,
                                                                  const bf16x8 (&bin)[W / 16][Geo<W>::kNB],
                                                                  f32x16 (&acc)[Geo<W>::kNB], int lane, int h) {
@@ -238,20 +260,26 @@ __device__ __attribute__((always_inline)) inline void phase_mfma(const lds_u8 *s
     constexpr int KIN = KS - (kBias ? 1 : 0);
     static_assert(KS >= kAR, "every phase has at least kAR tiles");
     const bf16x8 one = bias_operand(h);
+    if constexpr (!kHaveFirst) {
+#pragma unroll
+        for (int j = 0; j < kAR; ++j) ar.r[j] = lds_tile(st, j, lane);
+    }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const bf16x8 a = ar.r[ks % kAR];
-        ar.r[ks % kAR] = ks + kAR < KS ? lds_tile(st, ks + kAR, lane) : lds_tile(st_next, ks + kAR - KS, lane);
+        if (ks + kAR < KS) ar.r[ks % kAR] = lds_tile(st, ks + kAR, lane);
+        else if (kNext) ar.r[ks % kAR] = lds_tile(st_next, ks + kAR - KS, lane);
 #pragma unroll
         for (int nb = 0; nb < kNB; ++nb) {
             const bf16x8 b = (kBias && ks == KIN) ? one : bin[ks < KIN ? ks : 0][nb];
             acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, ks == 0 ? f32x16{} : acc[nb], 0, 0, 0);
         }
     }
-    // the next phase's tile j landed in slot (KS + j) % kAR: restore the order
-    ARing t = ar;
+    if constexpr (kNext) {   // the next phase's tile j landed in slot (KS + j) % kAR: restore the order
+        ARing t = ar;
 #pragma unroll
-    for (int j = 0; j < kAR; ++j) ar.r[j] = t.r[(KS + j) % kAR];
+        for (int j = 0; j < kAR; ++j) ar.r[j] = t.r[(KS + j) % kAR];
+    }
 }
 
 template <int W>
@@ -260,7 +288,7 @@ __device__ inline const lds_u8 *cur_stage(lds_u8 *ring, const Pipe &pp) {
 }
 template <int W>
 __device__ inline const lds_u8 *nxt_stage(lds_u8 *ring, const Pipe &pp) {
-    return stage_ptr<W>(ring, pp.stage == kStages - 1 ? 0 : pp.stage + 1);
+    return stage_ptr<W>(ring, pp.stage == Ring<W>::kStages - 1 ? 0 : pp.stage + 1);
 }
 
 template <int W>
@@ -291,14 +319,21 @@ __device__ __attribute__((always_inline)) inline void fwd_layer(lds_u8 *ring, co
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) {
         Stage<W> sg;
-        stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
-        phase_mfma<W, KIN + (kBias ? 1 : 0), kBias>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin, acc[mb & 1],
-                                                    lane, h);
+        const DescRaw nd = phase_begin<W>(sg, ring, tab, pp, wave, lane);
+        if (!Ring<W>::kPair)
+            phase_mfma<W, KIN + (kBias ? 1 : 0), kBias>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin,
+                                                        acc[mb & 1], lane, h);
+        else if (mb & 1)   // second of a pair (the loop is unrolled: mb is a constant here)
+            phase_mfma<W, KIN + (kBias ? 1 : 0), kBias, true, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar,
+                                                                     bin, acc[mb & 1], lane, h);
+        else
+            phase_mfma<W, KIN + (kBias ? 1 : 0), kBias, false, true>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar,
+                                                                     bin, acc[mb & 1], lane, h);
         if (mb > 0) {
 #pragma unroll
             for (int nb = 0; nb < kNB; ++nb) relu_mask_out<W>(acc[(mb - 1) & 1][nb], l, mb - 1, nb, bout, wmask, lane, kGrad);
         }
-        phase_end<W>(sg, ring, tab, pp, wave, lane);
+        phase_end<W>(nd, tab, pp, !Ring<W>::kPair || (mb & 1));
     }
 #pragma unroll
     for (int nb = 0; nb < kNB; ++nb) relu_mask_out<W>(acc[(NMB - 1) & 1][nb], l, NMB - 1, nb, bout, wmask, lane, kGrad);
@@ -339,15 +374,22 @@ __device__ __attribute__((always_inline)) inline void bwd_layer(lds_u8 *ring, co
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) {
         Stage<W> sg;
-        stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
-        phase_mfma<W, NKB, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin, acc[mb & 1], lane, h);
+        const DescRaw nd = phase_begin<W>(sg, ring, tab, pp, wave, lane);
+        if (!Ring<W>::kPair)
+            phase_mfma<W, NKB, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin, acc[mb & 1], lane, h);
+        else if (mb & 1)
+            phase_mfma<W, NKB, false, true, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin, acc[mb & 1],
+                                                   lane, h);
+        else
+            phase_mfma<W, NKB, false, false, true>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, bin, acc[mb & 1],
+                                                   lane, h);
         if (mb > 0) {
 #pragma unroll
             for (int nb = 0; nb < kNB; ++nb)
                 masked_tile_to_bf16<W>(acc[(mb - 1) & 1][nb], wmask[(((l - 1) * NMB + mb - 1) * kNB + nb) * 64 + lane],
                                        mb - 1, nb, bout);
         }
-        phase_end<W>(sg, ring, tab, pp, wave, lane);
+        phase_end<W>(nd, tab, pp, !Ring<W>::kPair || (mb & 1));
     }
 #pragma unroll
     for (int nb = 0; nb < kNB; ++nb)
@@ -400,7 +442,7 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
 
     // LDS: weight ring | network tables | ReLU masks [wave][depth][NMB][kNB][64] | head rows
     lds_u8 *ring = (lds_u8 *)smem;
-    NetTable *tab = reinterpret_cast<NetTable *>(smem + kStages * (NKB + 1) * 1024);
+    NetTable *tab = reinterpret_cast<NetTable *>(smem + Ring<W>::kStages * (NKB + 1) * 1024);
     uint16_t *s_mask = reinterpret_cast<uint16_t *>(tab + 1);
     float *s_head = reinterpret_cast<float *>(s_mask + (kGrad ? kWaves * dmax * NMB * kNB * 64 : 0));
     uint16_t *wmask = s_mask + wave * dmax * NMB * kNB * 64;
@@ -453,9 +495,11 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
         stage_wait();
         __syncthreads();
     }
-    ARing ar;
+    ARing ar;   // in pair mode the first phase follows a barrier and fills it itself
+    if constexpr (!Ring<W>::kPair) {
 #pragma unroll
-    for (int j = 0; j < kAR; ++j) ar.r[j] = lds_tile(stage_ptr<W>(ring, 0), j, lane);
+        for (int j = 0; j < kAR; ++j) ar.r[j] = lds_tile(stage_ptr<W>(ring, 0), j, lane);
+    }
 
     for (;;) {
         const int depth = __builtin_amdgcn_readfirstlane(tab->depth[pp.cur]);
@@ -500,10 +544,14 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
         // ---- head: logit and distance in rows 0 and 1 of lane half 0
         f32x16 hacc[kNB];
         {
-            Stage<W> sg;
-            stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
-            phase_mfma<W, NKB + 1, true>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b1, hacc, lane, h);
-            phase_end<W>(sg, ring, tab, pp, wave, lane);
+            Stage<W> sg;   // in pair mode a lone phase
+            const DescRaw nd = phase_begin<W>(sg, ring, tab, pp, wave, lane);
+            if constexpr (Ring<W>::kPair)
+                phase_mfma<W, NKB + 1, true, false, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b1, hacc,
+                                                           lane, h);
+            else
+                phase_mfma<W, NKB + 1, true>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b1, hacc, lane, h);
+            phase_end<W>(nd, tab, pp, true);
         }
         float gl[kNB], gd[kNB];
         bool any_hit = false;   // some ray of this wave has logit > 0
@@ -522,12 +570,14 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
             // walks the phases (fetch, ring, barrier) and writes no gradient
             const bool active = !a.grad_hits_only || any_hit;   // wave-uniform
             if (!active) {
-                const int nbwd = (depth - 1) * NMB + kGradRowBlocks0;
+                // (the barriers of the active waves: in pair mode pairs in the hidden layers, then
+                // a pair and a lone phase in the transposed layer 0)
+                const int nh = (depth - 1) * NMB, nbwd = nh + kGradRowBlocks0;
                 for (int i = 0; i < nbwd; ++i) {
                     Stage<W> sg;
-                    stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
-                    phase_skip<W>(nxt_stage<W>(ring, pp), ar, lane);
-                    phase_end<W>(sg, ring, tab, pp, wave, lane);
+                    const DescRaw nd = phase_begin<W>(sg, ring, tab, pp, wave, lane);
+                    if constexpr (!Ring<W>::kPair) phase_skip<W>(nxt_stage<W>(ring, pp), ar, lane);
+                    phase_end<W>(nd, tab, pp, !Ring<W>::kPair || (i < nh ? (i & 1) == 1 : i != nh));
                 }
             } else {
             // ---- seed: adjoint of the last hidden layer = head rows x seeds, masked -> b0
@@ -569,11 +619,22 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
             // ---- transposed layer 0: adjoints of this lane's feature slots
             f32x16 acc0[kGradRowBlocks0][kNB];
 #pragma unroll
-            for (int mb = 0; mb < kGradRowBlocks0; ++mb) {
+            for (int mb = 0; mb < kGradRowBlocks0; ++mb) {   // in pair mode: a pair, then a lone phase
+                static_assert(kGradRowBlocks0 == 3, "transposed layer 0: three M-blocks");
                 Stage<W> sg;
-                stage_fetch<W>(sg, pp.d2, stage_ptr<W>(ring, pp.stage >= kStages - 2 ? pp.stage + 2 - kStages : pp.stage + 2), wave, lane);
-                phase_mfma<W, NKB, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b0, acc0[mb], lane, h);
-                phase_end<W>(sg, ring, tab, pp, wave, lane);
+                const DescRaw nd = phase_begin<W>(sg, ring, tab, pp, wave, lane);
+                if (!Ring<W>::kPair)
+                    phase_mfma<W, NKB, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b0, acc0[mb], lane, h);
+                else if (mb == 0)
+                    phase_mfma<W, NKB, false, false, true>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b0, acc0[mb],
+                                                           lane, h);
+                else if (mb == 1)
+                    phase_mfma<W, NKB, false, true, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b0, acc0[mb],
+                                                           lane, h);
+                else
+                    phase_mfma<W, NKB, false, false, false>(cur_stage<W>(ring, pp), nxt_stage<W>(ring, pp), ar, b0,
+                                                            acc0[mb], lane, h);
+                phase_end<W>(nd, tab, pp, !Ring<W>::kPair || mb != 0);
             }
             // ---- chain rule through the Fourier features
 #pragma unroll
@@ -641,7 +702,8 @@ size_t stream_lds_bytes(int width, int depth, int n_nets, bool grad) {
     const int nmb = width / 32, nkb = width / 16;
     const int waves = width == 256 ? Geo<256>::kWaves : Geo<128>::kWaves;
     const int nb = width == 256 ? Geo<256>::kNB : Geo<128>::kNB;
-    size_t b = (size_t)kStages * (nkb + 1) * 1024 + sizeof(NetTable);
+    const int stages = width == 256 ? Ring<256>::kStages : Ring<128>::kStages;
+    size_t b = (size_t)stages * (nkb + 1) * 1024 + sizeof(NetTable);
     if (grad) b += (size_t)waves * depth * nmb * nb * 64 * 2 + (size_t)n_nets * 2 * width * 4;
     return b;
 }
