@@ -63,16 +63,19 @@ __device__ __attribute__((always_inline)) inline void sweep_mfma(const uint8_t *
         kb += kb0;
         return kFeat ? 40 * h + kb : 32 * (kb / 16) + 8 * ((kb % 16) / 4) + 4 * h;
     };
-    float a_cur[4], a_nxt[4];
+    constexpr int kG = 4;   // groups of four K-steps of weight tiles in flight (L2 latency)
+    float a[kG][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a_cur[q] = tiles[q * tstride];
+    for (int g = 0; g < kG - 1; ++g)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[g][q] = 4 * g < KS ? tiles[(4 * g + q) * tstride] : 0.f;
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) acc[nb] = f32x16{};
 #pragma unroll 4
     for (int kb = 0; kb < KS; kb += 4) {
-        if (kb + 4 < KS) {
+        if (kb + 4 * (kG - 1) < KS) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) a_nxt[q] = tiles[(kb + 4 + q) * tstride];
+            for (int q = 0; q < 4; ++q) a[kG - 1][q] = tiles[(kb + 4 * (kG - 1) + q) * tstride];
         }
         f32x4 b4[NBW];
 #pragma unroll
@@ -82,9 +85,11 @@ __device__ __attribute__((always_inline)) inline void sweep_mfma(const uint8_t *
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[q], b4[nb][q], acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][q], b4[nb][q], acc[nb], 0, 0, 0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a_cur[q] = a_nxt[q];
+        for (int g = 0; g + 1 < kG; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[g][q] = a[g + 1][q];
     }
 }
 
