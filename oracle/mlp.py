@@ -128,17 +128,36 @@ def round_e4m3(x):
     return np.sign(f) * q
 
 
+def split_bf16(x):
+    """``x`` (a float32 value) as ``hi + lo`` with both parts bfloat16.
+
+    hi = bf16(x); lo = bf16(x - hi), where x - hi is exact in float32 (hi is x with
+    its low mantissa bits rounded off).  hi + lo keeps 16 significant bits of x.
+    """
+    x32 = np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+    hi = round_bf16(x32)
+    return hi, round_bf16(x32 - hi)
+
+
 def forward_bf16(params, width, depth, rays):
     """Forward with every layer's operands rounded to bfloat16 and float64 sums.
 
     Weights and layer inputs (the encoding and each hidden activation) are
     rounded to bfloat16; products and sums are exact-ish (float64, standing in
-    for the kernel's float32 accumulation); the bias is added unrounded.
+    for the kernel's float32 accumulation); the bias is added unrounded.  The
+    head's two weight rows are carried as a sum of two bfloat16 values: the
+    rounded row plus the rounded remainder (``split_bf16``), since a rounding
+    error there moves the outputs directly rather than through later layers.
     """
     layers = unpack(params, width, depth)
     h = round_bf16(encode(rays))
     for l, (W, b) in enumerate(layers):
-        z = round_bf16(W) @ h + b[:, None]
+        if l < depth:
+            Wq = round_bf16(W)
+        else:
+            hi, lo = split_bf16(W)
+            Wq = hi + lo
+        z = Wq @ h + b[:, None]
         if l < depth:
             h = round_bf16(np.maximum(z, 0.0))
         else:

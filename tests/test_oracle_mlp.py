@@ -189,6 +189,23 @@ def test_round_bf16_matches_torch_cast():
     np.testing.assert_array_equal(ours, ref)
 
 
+def test_split_bf16_two_terms():
+    """hi + lo reproduces values of up to 16 significant bits exactly; both parts are bfloat16
+    and hi is the plain bfloat16 rounding; in general hi + lo is within 2^-16 relative."""
+    rng = np.random.default_rng(3)
+    m = rng.integers(1 << 15, 1 << 16, size=4096).astype(np.float64)
+    x = m * 2.0 ** rng.integers(-30, 10, size=m.size) * rng.choice([-1.0, 1.0], size=m.size)
+    hi, lo = mlp.split_bf16(x)
+    np.testing.assert_array_equal(hi + lo, x)
+    np.testing.assert_array_equal(mlp.round_bf16(hi), hi)
+    np.testing.assert_array_equal(mlp.round_bf16(lo), lo)
+    np.testing.assert_array_equal(hi, torch.from_numpy(x).float().bfloat16().double().numpy())
+    y = rng.standard_normal(4096).astype(np.float32).astype(np.float64)
+    hi, lo = mlp.split_bf16(y)
+    assert np.all(np.abs(hi + lo - y) <= 2.0 ** -16 * np.abs(y))
+    assert np.all(np.abs(lo) <= 2.0 ** -8 * np.abs(y))
+
+
 def test_round_e4m3_matches_torch_cast():
     rng = np.random.default_rng(4)
     x = np.concatenate([rng.normal(size=20000) * 10 ** rng.uniform(-4, 3, 20000),
@@ -213,6 +230,15 @@ def test_emulated_precisions_exact_on_representable_inputs():
     p = mlp.pack(layers)
     ref = mlp.forward(p, width, depth, rays)
     np.testing.assert_array_equal(mlp.forward_bf16(p, width, depth, rays), ref)
+    # head weights with 9 to 16 significant bits: not bfloat16, but the sum of two; the
+    # emulation stays exact only if it keeps the remainder of the head rows
+    head = layers[2][0].copy()
+    layers[2][0][:] = head * (1.0 + 2.0 ** -10) + np.sign(head) * 2.0 ** -14
+    p = mlp.pack(layers)
+    ref = mlp.forward(p, width, depth, rays)
+    assert np.any(mlp.round_bf16(layers[2][0]) != layers[2][0])
+    np.testing.assert_array_equal(mlp.forward_bf16(p, width, depth, rays), ref)
+    layers[2][0][:] = head
     # e4m3 keeps 3 mantissa bits: signed permutations scaled by powers of two keep every
     # layer input representable
     for l, (W, b) in enumerate(layers):
