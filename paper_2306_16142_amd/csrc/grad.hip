@@ -220,9 +220,10 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
             }
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                // rows 0 (logit) and 1 (distance) live in lanes 0..31; share them with the upper half
-                const float z = __shfl(acc[nb][0], col) + hb0;
-                const float dd = __shfl(acc[nb][1], col) + hb1;
+                // rows 0 (logit) and 1 (distance) live in lanes 0..31, plus rows 2 and 3 (the bf16
+                // remainders of the head rows, zero in float32); share them with the upper half
+                const float z = __shfl(acc[nb][0] + acc[nb][2], col) + hb0;
+                const float dd = __shfl(acc[nb][1] + acc[nb][3], col) + hb1;
                 const int64_t r = base + nb * 32 + col;
                 if (h == 0 && valid[nb]) {
                     if (a.logit_out) a.logit_out[r] = z;

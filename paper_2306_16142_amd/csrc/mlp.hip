@@ -70,7 +70,13 @@ __device__ inline float forward_weight(const float *params, const NetLayout &L, 
     const int kb = (int)(t / nmb), mb = (int)(t % nmb);
     const int h = lane / 32;
     const int m = mb * 32 + (lane % 32);
-    if (l == depth && m >= 2) return 0.f;
+    if (l == depth && m >= 2) {
+        // bf16 head: rows 2 and 3 carry what rounding rows 0 and 1 to bf16 left over (exact
+        // in float32; rounded to bf16 when stored), so each output is the sum of two rows
+        if (prec != kBF16 || m >= 4 || kb >= L.nkb) return 0.f;
+        const float w = weight_at(params, width, depth, l, m - 2, prev_unit(prec, kb, h, s));
+        return w - (float)(__bf16)w;
+    }
     // bf16 bias split into hi + lo (see bias_kblocks)
     auto bias_part = [&](int part) {
         const float b = bias_at(params, width, depth, l, m);
@@ -546,8 +552,9 @@ __device__ __attribute__((always_inline)) inline void head_out(const uint8_t *ws
         for (int nb = 0; nb < NB; ++nb) {
             const int64_t r = base + nb * 32 + col;
             if (r < n) {
-                logit_out[r] = (nan_ray[nb] || bad) ? NAN : fmaf(acc[nb][0], alpha, c0);
-                dist_out[r] = (nan_ray[nb] || bad) ? NAN : fmaf(acc[nb][1], alpha, c1);
+                // rows 2 and 3: the bf16 remainders of the head rows (zero in float32)
+                logit_out[r] = (nan_ray[nb] || bad) ? NAN : fmaf(acc[nb][0] + acc[nb][2], alpha, c0);
+                dist_out[r] = (nan_ray[nb] || bad) ? NAN : fmaf(acc[nb][1] + acc[nb][3], alpha, c1);
             }
         }
     }

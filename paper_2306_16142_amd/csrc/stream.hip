@@ -558,7 +558,8 @@ __global__ __launch_bounds__(Geo<W>::kWaves * 64, 2) void stream_kernel(GradArgs
 #pragma unroll
         for (int nb = 0; nb < kNB; ++nb) {
             const int64_t r = cw.base + (wave * kNB + nb) * 32 + col;
-            const float z = __shfl(hacc[nb][0], col), dd = __shfl(hacc[nb][1], col);
+            // rows 2 and 3 hold the bf16 remainders of the head rows 0 and 1
+            const float z = __shfl(hacc[nb][0] + hacc[nb][2], col), dd = __shfl(hacc[nb][1] + hacc[nb][3], col);
             any_hit |= __ballot(valid[nb] && z > 0.f) != 0;
             float *dst = h ? a.dist_out : a.logit_out;
             if (valid[nb] && dst) dst[r] = h ? dd : z;

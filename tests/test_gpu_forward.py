@@ -67,6 +67,30 @@ def test_forward_bf16_matches_emulation(width, depth, n):
         assert _scaled_err(g, r).mean() <= 1.1 * own.mean() + 1e-6
 
 
+@pytest.mark.parametrize("width,depth,n", [(128, 4, 8192 + 3), (256, 6, 4096 + 17)])
+def test_forward_bf16_keeps_head_remainder(width, depth, n):
+    """bf16 head rows travel as two bf16 rows (the rounded row and its rounded remainder).
+    With every other weight bf16-representable the kernel must sit far closer to that
+    emulation than to one with plainly rounded head rows (the LDS-resident kernel at
+    width 128, the streamed kernel at 256)."""
+    banner("forward bf16 head remainder: %dx%d, n=%d" % (depth, width, n))
+    layers = mlp.unpack(synthetic.random_params(width, depth, 17), width, depth)
+    for W, _ in layers[:-1]:
+        W[:] = mlp.round_bf16(W)
+    p = mlp.pack(layers).astype(np.float32)
+    rays = _rays(n, 18)
+    net = api.Network(cuda(p), width, depth, "bf16")
+    lg, ds = net(cuda(rays))
+    lg, ds = host(lg), host(ds)
+    el, ed = mlp.forward_bf16(p, width, depth, rays)
+    layers[-1][0][:] = mlp.round_bf16(layers[-1][0])
+    nl, nd = mlp.forward_bf16(mlp.pack(layers), width, depth, rays)   # remainder dropped
+    for out, emu, plain in ((lg, el, nl), (ds, ed, nd)):
+        shift = np.median(np.abs(plain - emu))
+        assert shift > 0
+        assert np.median(np.abs(out - emu)) < 0.1 * shift
+
+
 @pytest.mark.parametrize("width,depth", [(128, 4), (256, 3)])
 def test_fp8_scales_and_forward_match_emulation(width, depth):
     banner("forward fp8: %dx%d" % (depth, width))
