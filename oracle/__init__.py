@@ -18,6 +18,8 @@ Modules:
   respect to the input point), Adam, normals (Eq. 3).
 * ``render``   -- counter-based random numbers (SplitMix64) and the path tracer
   of Fig. 1 with a mesh or a network backend.
+* ``dataset``  -- the informative training-data sampler of Sec. V-B
+  (Eqs. 8-12): face points, direction samples, marching, infinite samples.
 * ``multi``    -- rigid instances of several networks (Sec. VII, scenes as
   future work).
 

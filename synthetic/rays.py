@@ -89,3 +89,17 @@ def training_rays(v, f, n, seed):
     anchored[:n_s] = True
     oo, dd = _soa(o, d)
     return oo, dd, anchored
+
+
+def dataset_uniforms(m, s_fc, s_dr, seed):
+    """Uniforms of the face-point and direction samplers, float32 in [0, 1).
+
+    Returns ``face_uv`` [2, m * s_fc] (column f * s_fc + j: the (a, b) pair of
+    point j of face f) and ``dir_uv`` [2, m * s_dr] (column f * s_dr + j: the
+    (a, b) pair of direction j of face f).  Draw order: face pairs, then direction
+    pairs, each row-major over (column, component).
+    """
+    rng = np.random.default_rng(seed)
+    face_uv = np.ascontiguousarray(rng.random((m * s_fc, 2), dtype=np.float32).T)
+    dir_uv = np.ascontiguousarray(rng.random((m * s_dr, 2), dtype=np.float32).T)
+    return face_uv, dir_uv
