@@ -12,7 +12,8 @@
  *   - the ground-truth labels from ray shooting against the triangle mesh by a
  *     linear search over all triangles (Sec. I, Sec. VI-B) with the odd-even
  *     inside rule (Sec. V-B);
- *   - the path tracer whose nearest-hit search the field replaces (Fig. 1).
+ *   - the path tracer whose nearest-hit search the field replaces (Fig. 1);
+ *   - the informative training-data sampler built on the ray shooting (Sec. V-B).
  *
  * Conventions common to every entry point
  *   Memory    Every array argument is DEVICE memory owned by the caller unless the
@@ -97,6 +98,48 @@ ddf_status ddf_label_rays(const float *orig, const float *dir, int64_t n,
  * into [0, 2 pi) (0 on the z axis).  orig, dir [3][n].  In place is not allowed. */
 ddf_status ddf_assemble_rays(const float *orig, const float *dir, int64_t n, float *rays_out,
                              ddf_stream stream);
+
+/* ---------------------------------------------------------------- training-data sampler
+ * The informative sampler of Sec. V-B (Eqs. 8-12, Fig. 2) on top of the labeller.
+ * For each face f in face_first .. face_first + n_faces - 1 (of the m triangles):
+ *   s_fc points (1 - a - b) p0 + a p1 + b p2 (Eq. 8), (a, b) folded to (1 - a, 1 - b)
+ *     when a + b > 1 (decided exactly), from face_uv [2][m * s_fc] (column f * s_fc + j);
+ *   s_dr directions of polar angle a pi and azimuth 2 b pi (Eq. 9; Eq. 1 for the
+ *     vector), from dir_uv [2][m * s_dr] (column f * s_dr + j), shared by the face's points.
+ * Pair (point, direction) i = (f - face_first) * s_fc * s_dr + point * s_dr + direction.
+ * A pair is kept when its ray meets no triangle at t > eps (eps steps over the point's own
+ * face; on a closed mesh a ray into the solid always meets another face, so this also drops
+ * what the odd-even rule calls inside) and the point lies inside the cube [-1, 1]^3.
+ * A kept ray is marched to where it leaves the cube, t_k = k t_exit / s_p, k = 1..s_p, and at
+ * q = p + t_k d it yields, in this order:
+ *   (q, -d; t_k)      looking back at the face point (Eq. 10);
+ *   (q,  d; +inf)     looking on along the ray (Eq. 11);
+ *   (q, polar + pi/2; +inf) and (q, polar - pi/2; +inf), each only when that ray meets no
+ *                     triangle (Eq. 12).
+ * Samples are ordered by pair, then k, then the order above (deterministic).
+ *   rays_out  [5][cap] (qx, qy, qz, theta, phi), theta in [0, pi], phi in [0, 2 pi), row
+ *             stride cap; t_out [cap] labels (+inf: no hit); pair_out [cap] source pair
+ *             index, or NULL.  Samples beyond cap are counted but not written.
+ *   count_out device int64: the number of samples (may exceed cap).
+ *   ws        ddf_dataset_workspace_size bytes (device, caller-owned).
+ * Random numbers are inputs (uniforms in [0, 1)), so a seed fixes the dataset.
+ * Errors: INVALID_ARG for s_fc, s_dr or s_p < 1, eps < 0 or not finite, a face range
+ * beyond m, cap < 0, NULL arrays that are needed; UNSUPPORTED when
+ * n_faces * s_fc * s_dr * s_p reaches 2^29; WORKSPACE when ws is too small.
+ * n_faces == 0 writes count 0 and nothing else. */
+typedef struct {
+    int32_t s_fc;        /* points per face (Eq. 8) */
+    int32_t s_dr;        /* directions per face (Eq. 9) */
+    int32_t s_p;         /* marching steps per kept ray (Eq. 10) */
+    float eps;           /* offset over the own face for the kept test (scene units) */
+    int64_t face_first;  /* first sampled face */
+    int64_t n_faces;     /* number of sampled faces (every triangle is still intersected) */
+} ddf_dataset_params;
+
+ddf_status ddf_dataset_workspace_size(const ddf_dataset_params *p, size_t *bytes);
+ddf_status ddf_sample_dataset(const float *tris, int64_t m, const ddf_dataset_params *p, const float *face_uv,
+                              const float *dir_uv, float *rays_out, float *t_out, int32_t *pair_out, int64_t cap,
+                              int64_t *count_out, void *ws, size_t ws_bytes, ddf_stream stream);
 
 /* ---------------------------------------------------------------- launch tuning
  * Process-wide launch-shape knobs.  They decide how work is spread over the GPU and

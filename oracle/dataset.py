@@ -99,7 +99,7 @@ def sample_angles(theta0, theta1, kind):
     return t, np.where(flip, _wrap_azimuth(theta1 + PI), theta1)
 
 
-def sample_dataset(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, face_first=0, n_faces=None):
+def sample_dataset(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, face_first=0, n_faces=None, amb_tol=1e-6):
     """The sampler of Sec. V-B over faces ``face_first .. face_first + n_faces - 1``.
 
     ``tris`` [9, m] float32 corners (every triangle is intersected); ``face_uv``
@@ -111,7 +111,8 @@ def sample_dataset(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, face_first=0, n_
     [P] (the kept / dropped decision is not decided by the geometry: see
     ``geometry.nearest_hit``), ``perp_free`` [P, s_p, 2] and ``perp_ambiguous``
     [P, s_p, 2] (False where the pair is dropped), and the per-pair ``origin``,
-    ``theta0``, ``theta1``, ``t_exit``.
+    ``theta0``, ``theta1``, ``t_exit``.  ``amb_tol`` is passed to the ambiguity test of
+    ``geometry.nearest_hit``.
     """
     v0, _, _ = geometry.triangles_from_soup(tris)
     m = v0.shape[1]
@@ -128,7 +129,7 @@ def sample_dataset(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, face_first=0, n_
     d = geometry.dirs_from_angles(th0, th1)
     inside = np.all(np.abs(o) < 1.0, axis=0)
     t_exit = np.where(inside, cube_exit(o, d), 0.0)
-    fwd = geometry.nearest_hit(o, d, tris, t_min=eps)
+    fwd = geometry.nearest_hit(o, d, tris, t_min=eps, amb_tol=amb_tol)
     keep = (fwd["tri"] < 0) & (t_exit > 0.0)
     fwd_amb = fwd["ambiguous"]
 
@@ -143,7 +144,7 @@ def sample_dataset(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, face_first=0, n_
     perp_free = np.zeros((P, s_p, 2), dtype=bool)
     perp_amb = np.zeros((P, s_p, 2), dtype=bool)
     for s, sign in enumerate((1.0, -1.0)):
-        h = geometry.nearest_hit(qf, sign * dpf, tris, t_min=0.0)
+        h = geometry.nearest_hit(qf, sign * dpf, tris, t_min=0.0, amb_tol=amb_tol)
         perp_free[kept, :, s] = (h["tri"] < 0).reshape(len(kept), s_p)
         perp_amb[kept, :, s] = h["ambiguous"].reshape(len(kept), s_p)
 

@@ -44,6 +44,11 @@ class DdfRenderParams(ctypes.Structure):
 
 BACKEND_MESH, BACKEND_NET, BACKEND_MULTI = 0, 1, 2
 
+
+class DdfDatasetParams(ctypes.Structure):
+    _fields_ = [("s_fc", c_i32), ("s_dr", c_i32), ("s_p", c_i32), ("eps", c_f), ("face_first", c_i64),
+                ("n_faces", c_i64)]
+
 # name -> argument types (every entry point returns ddf_status unless listed in _RESTYPE)
 SIGNATURES = {
     "ddf_abi_version": [],
@@ -67,6 +72,9 @@ SIGNATURES = {
                                c_p, c_sz, c_p],
     "ddf_set_tuning": [c_i32, c_i32],
     "ddf_get_tuning": [c_i32, ctypes.POINTER(c_i32)],
+    "ddf_dataset_workspace_size": [ctypes.POINTER(DdfDatasetParams), ctypes.POINTER(c_sz)],
+    "ddf_sample_dataset": [c_p, c_i64, ctypes.POINTER(DdfDatasetParams), c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
+                           c_sz, c_p],
 }
 # launch-shape knobs (DDF_TUNE_* in ddf.h)
 TUNE_KNOBS = {"stream_wg_per_cu": 0, "cull_rays_per_block": 1, "grad_wg_per_cu": 2}

@@ -54,6 +54,39 @@ def assemble_rays(orig, dirs, out=None):
     return out
 
 
+class DatasetSampler:
+    """The training-data sampler of Sec. V-B (``ddf_sample_dataset``) with its workspace and
+    output buffers allocated once (capacity: every possible sample, 4 per marching step)."""
+
+    def __init__(self, tris, s_fc, s_dr, s_p, eps=1e-4, face_first=0, n_faces=None, device="cuda"):
+        _dev(tris, torch.float32, "tris", 9)
+        self.tris, self.m = tris, tris.shape[1]
+        n_faces = self.m - face_first if n_faces is None else n_faces
+        self.params = _lib.DdfDatasetParams(s_fc, s_dr, s_p, eps, face_first, n_faces)
+        b = ctypes.c_size_t(0)
+        _lib.call("ddf_dataset_workspace_size", ctypes.byref(self.params), ctypes.byref(b))
+        self.ws = torch.empty(max(b.value, 1), device=tris.device, dtype=torch.uint8)
+        self.cap = 4 * n_faces * s_fc * s_dr * s_p
+        self.rays = torch.empty((5, self.cap), device=tris.device, dtype=torch.float32)
+        self.t = torch.empty(self.cap, device=tris.device, dtype=torch.float32)
+        self.pair = torch.empty(self.cap, device=tris.device, dtype=torch.int32)
+        self.count = torch.zeros(1, device=tris.device, dtype=torch.int64)
+
+    def run(self, face_uv, dir_uv, pairs=True):
+        """Enqueue one sampling pass; the sample count lands in ``self.count`` (device)."""
+        _dev(face_uv, torch.float32, "face_uv", 2)
+        _dev(dir_uv, torch.float32, "dir_uv", 2)
+        _lib.call("ddf_sample_dataset", _p(self.tris), self.m, ctypes.byref(self.params), _p(face_uv), _p(dir_uv),
+                  _p(self.rays), _p(self.t), _p(self.pair) if pairs else None, self.cap, _p(self.count),
+                  _p(self.ws), self.ws.numel(), _stream())
+
+    def __call__(self, face_uv, dir_uv):
+        """Sample and return (rays [5][N], t [N], pair [N]) views of the output buffers."""
+        self.run(face_uv, dir_uv)
+        n = int(self.count.item())
+        return self.rays[:, :n], self.t[:n], self.pair[:n]
+
+
 def packed_bytes(width, depth, precision):
     b = ctypes.c_size_t(0)
     _lib.call("ddf_packed_bytes", width, depth, PRECISIONS[precision], ctypes.byref(b))

@@ -29,7 +29,7 @@ def test_header_declares_the_hot_path():
     names = _declared()
     for required in ("ddf_label_rays", "ddf_forward", "ddf_backward", "ddf_render_wavefront", "ddf_pack_net",
                      "ddf_train_step", "ddf_train_step_chunked", "ddf_assemble_rays", "ddf_query",
-                     "ddf_set_tuning"):
+                     "ddf_set_tuning", "ddf_sample_dataset", "ddf_dataset_workspace_size"):
         assert required in names
 
 
@@ -92,6 +92,39 @@ def test_validation_before_launch(lib):
     # fp8 packing needs scales, the others must not get any
     assert lib.ddf_pack_net(1, 128, 4, 2, None, 1, None) == _lib.DDF_ERR_INVALID_ARG
     assert lib.ddf_pack_net(1, 128, 4, 1, 1, 1, None) == _lib.DDF_ERR_INVALID_ARG
+
+
+def test_dataset_sampler_validation(lib):
+    from paper_2306_16142_amd import _lib
+    P = _lib.DdfDatasetParams
+    b = ctypes.c_size_t(0)
+    assert lib.ddf_dataset_workspace_size(ctypes.byref(P(10, 10, 10, 1e-4, 0, 20480)), ctypes.byref(b)) == _lib.DDF_OK
+    # pair data, perpendicular rays (origin, direction, t, triangle) and two scans, at least
+    pairs = 20480 * 100
+    assert b.value >= pairs * 36 + 2 * pairs * 10 * 32 + 2 * pairs * 10 * 4
+    assert lib.ddf_dataset_workspace_size(None, ctypes.byref(b)) == _lib.DDF_ERR_INVALID_ARG
+    for bad in (P(0, 1, 1, 1e-4, 0, 1), P(1, 0, 1, 1e-4, 0, 1), P(1, 1, 0, 1e-4, 0, 1), P(1, 1, 1, -1.0, 0, 1),
+                P(1, 1, 1, math.nan, 0, 1), P(1, 1, 1, 1e-4, -1, 1), P(1, 1, 1, 1e-4, 0, -1)):
+        assert lib.ddf_dataset_workspace_size(ctypes.byref(bad), ctypes.byref(b)) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_dataset_workspace_size(ctypes.byref(P(64, 64, 64, 1e-4, 0, 1 << 20)), ctypes.byref(b)) == \
+        _lib.DDF_ERR_UNSUPPORTED
+    ok = P(2, 2, 2, 1e-4, 0, 4)
+    # face range beyond the mesh, NULL count, NULL outputs with capacity, negative capacity
+    assert lib.ddf_sample_dataset(1, 3, ctypes.byref(ok), 1, 1, 1, 1, None, 8, 1, 1, 1 << 40, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    assert b"beyond" in lib.ddf_last_error()
+    assert lib.ddf_sample_dataset(1, 4, ctypes.byref(ok), 1, 1, 1, 1, None, 8, None, 1, 1 << 40, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_sample_dataset(1, 4, ctypes.byref(ok), 1, 1, None, None, None, 8, 1, 1, 1 << 40, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_sample_dataset(1, 4, ctypes.byref(ok), 1, 1, 1, 1, None, -1, 1, 1, 1 << 40, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    # NULL triangles or uniforms, too small a workspace
+    assert lib.ddf_sample_dataset(None, 4, ctypes.byref(ok), 1, 1, 1, 1, None, 8, 1, 1, 1 << 40, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_sample_dataset(1, 4, ctypes.byref(ok), 1, 1, 1, 1, None, 8, 1, 1, 16, None) == \
+        _lib.DDF_ERR_WORKSPACE
+    assert b"workspace" in lib.ddf_last_error()
 
 
 def test_workspace_sizes(lib):

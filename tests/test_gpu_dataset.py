@@ -1,0 +1,163 @@
+"""GPU parity of ddf_sample_dataset (the training-data sampler of Sec. V-B, Eqs. 8-12) against
+the float64 dataset oracle.
+
+Kept / dropped decisions and perpendicular-ray decisions must agree exactly wherever the
+geometry decides them: the oracle marks rays near a triangle edge, near grazing or near t_min
+as ambiguous, and rays within 1e-3 of their own face's plane are left out too (the kernel's
+float32 face point lies up to an ulp off the face, which such a ray can meet beyond eps).
+Samples of pairs decided on both sides must match in order, position, angles and label."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import dataset, geometry
+from paper_2306_16142_amd import _lib, api
+
+from gpu_common import banner, cuda, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, face_first=0, n_faces=None):
+    sampler = api.DatasetSampler(cuda(tris), s_fc, s_dr, s_p, eps, face_first, n_faces)
+    rays, t, pair = sampler(cuda(face_uv), cuda(dir_uv))
+    torch.cuda.synchronize()
+    return host(rays), host(t), host(pair)
+
+
+def _phi_diff(a, b):
+    d = np.abs(a - b)
+    return np.minimum(d, 2 * np.pi - d)
+
+
+def _compare(tris, ref, got, s_fc, s_dr, s_p, face_first=0):
+    rays, t, pair = got
+    P = ref["keep"].size
+    # every GPU sample is well formed, in pair order, 2-4 per marching step of a kept pair
+    assert np.all(np.diff(pair) >= 0)
+    assert rays[3].min() >= 0 and rays[3].max() <= np.float32(np.pi)
+    assert rays[4].min() >= 0 and rays[4].max() < np.float32(2 * np.pi)
+    per_pair = np.bincount(pair, minlength=P)
+    kept_gpu = per_pair > 0
+    assert np.all((per_pair[kept_gpu] >= 2 * s_p) & (per_pair[kept_gpu] <= 4 * s_p))
+    # decisions fixed by the geometry agree exactly
+    n = geometry.face_normals(tris)
+    face = face_first + np.arange(P) // (s_fc * s_dr)
+    d = geometry.dirs_from_angles(ref["theta0"], ref["theta1"])
+    graze = np.abs(np.sum(d * n[:, face], 0)) < 1e-3
+    sure = ~ref["fwd_ambiguous"] & ~graze
+    np.testing.assert_array_equal(kept_gpu[sure], ref["keep"][sure])
+    assert sure.mean() > 0.98
+    # samples of pairs kept on both sides whose perpendicular decisions are sure
+    perp_sure = ~ref["perp_ambiguous"].any(axis=(1, 2))
+    both = sure & ref["keep"] & kept_gpu & perp_sure
+    assert both.sum() > 0.9 * (sure & ref["keep"]).sum()
+    g_lo, g_hi = np.searchsorted(pair, np.arange(P)), np.searchsorted(pair, np.arange(P), side="right")
+    r_lo, r_hi = np.searchsorted(ref["pair"], np.arange(P)), np.searchsorted(ref["pair"], np.arange(P), side="right")
+    idx = np.flatnonzero(both)
+    np.testing.assert_array_equal(g_hi[idx] - g_lo[idx], r_hi[idx] - r_lo[idx])
+    gsel = np.concatenate([np.arange(g_lo[i], g_hi[i]) for i in idx])
+    rsel = np.concatenate([np.arange(r_lo[i], r_hi[i]) for i in idx])
+    gr, rr = rays[:, gsel].astype(np.float64), ref["rays"][:, rsel]
+    np.testing.assert_allclose(gr[:3], rr[:3], atol=4e-6)
+    np.testing.assert_allclose(gr[3], rr[3], atol=2e-6)
+    assert _phi_diff(gr[4], rr[4]).max() < 2e-6
+    gt, rt = t[gsel].astype(np.float64), ref["t"][rsel]
+    np.testing.assert_array_equal(np.isinf(gt), np.isinf(rt))
+    fin = np.isfinite(rt)
+    np.testing.assert_allclose(gt[fin], rt[fin], rtol=2e-6, atol=2e-6)
+    return kept_gpu.mean(), t.size
+
+
+def test_dataset_icosphere():
+    banner("dataset: icosphere 320 tris, s_fc 3, s_dr 8, s_p 6 (seed 21)")
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    s_fc, s_dr, s_p, eps = 3, 8, 6, 1e-4
+    face_uv, dir_uv = synthetic.dataset_uniforms(f.shape[0], s_fc, s_dr, 21)
+    ref = dataset.sample_dataset(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, amb_tol=1e-5)
+    kept, n = _compare(tris, ref, _gpu(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps), s_fc, s_dr, s_p)
+    assert 0.4 < kept < 0.6   # convex: the outward half of the directions
+
+
+def test_dataset_torus_face_range():
+    banner("dataset: torus 384 tris, faces 37..236, s_fc 4, s_dr 6, s_p 5 (seed 22)")
+    v, f = synthetic.torus(0.55, 0.22, 16, 12)
+    tris = synthetic.tri_soup(v, f)
+    s_fc, s_dr, s_p, eps = 4, 6, 5, 1e-4
+    face_uv, dir_uv = synthetic.dataset_uniforms(f.shape[0], s_fc, s_dr, 22)
+    ref = dataset.sample_dataset(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, 37, 200, amb_tol=1e-5)
+    kept, _ = _compare(tris, ref, _gpu(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, 37, 200), s_fc, s_dr, s_p, 37)
+    assert 0.2 < kept < 0.5   # concave: some outward rays meet the ring
+
+
+def test_dataset_single_step_and_tiny():
+    banner("dataset: two-triangle quad, s_fc 1, s_dr 1, s_p 1 (seed 23)")
+    v = np.array([[-0.5, -0.5, 0.1], [0.5, -0.5, 0.1], [0.5, 0.5, 0.1], [-0.5, 0.5, 0.1]])
+    tris = synthetic.tri_soup(v, np.array([[0, 1, 2], [0, 2, 3]]))
+    face_uv, dir_uv = synthetic.dataset_uniforms(2, 1, 1, 23)
+    ref = dataset.sample_dataset(tris, face_uv, dir_uv, 1, 1, 1, 1e-4)
+    got = _gpu(tris, face_uv, dir_uv, 1, 1, 1, 1e-4)
+    assert got[1].size == ref["t"].size
+    _compare(tris, ref, got, 1, 1, 1)
+
+
+def test_dataset_capacity_and_empty():
+    banner("dataset: capacity below the sample count, NULL pair output, empty face range")
+    v, f = synthetic.icosphere(1, 0.8)
+    tris = cuda(synthetic.tri_soup(v, f))
+    m = f.shape[0]
+    s_fc, s_dr, s_p = 2, 4, 3
+    fu, du = [cuda(a) for a in synthetic.dataset_uniforms(m, s_fc, s_dr, 24)]
+    full = api.DatasetSampler(tris, s_fc, s_dr, s_p, 1e-4)
+    rays, t, pair = [x.clone() for x in full(fu, du)]
+    total = t.numel()
+    assert total > 100
+    p = _lib.DdfDatasetParams(s_fc, s_dr, s_p, 1e-4, 0, m)
+    cap = total // 3
+    out_r = torch.full((5, cap), -7.0, device="cuda")
+    out_t = torch.full((cap,), -7.0, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = full.ws
+    _lib.call("ddf_sample_dataset", tris.data_ptr(), m, ctypes.byref(p), fu.data_ptr(), du.data_ptr(),
+              out_r.data_ptr(), out_t.data_ptr(), None, cap, cnt.data_ptr(), ws.data_ptr(), ws.numel(), None)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == total
+    assert torch.equal(out_r, rays[:, :cap]) and torch.equal(out_t, t[:cap])
+    # an empty face range writes a zero count and nothing else
+    p0 = _lib.DdfDatasetParams(s_fc, s_dr, s_p, 1e-4, 5, 0)
+    cnt.fill_(123)
+    _lib.call("ddf_sample_dataset", tris.data_ptr(), m, ctypes.byref(p0), fu.data_ptr(), du.data_ptr(),
+              out_r.data_ptr(), out_t.data_ptr(), None, cap, cnt.data_ptr(), None, 0, None)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == 0
+    # a second run of the same sampler reproduces the first bit for bit
+    rays2, t2, pair2 = full(fu, du)
+    assert torch.equal(rays2, rays) and torch.equal(t2, t) and torch.equal(pair2, pair)
+
+
+def test_dataset_full_size_sampled():
+    """The 20,480-triangle training mesh with s_fc = s_dr = s_p = 10 (2,048,000 pairs), in the
+    launch configuration the benchmark times; the oracle recomputes the pairs of faces 0-7
+    against all triangles."""
+    banner("dataset: 20480-tri training mesh, s_fc = s_dr = s_p = 10 (seed 25), oracle on faces 0-7")
+    v, f = synthetic.training_mesh(1)
+    tris = synthetic.tri_soup(v, f)
+    m = f.shape[0]
+    s = 10
+    face_uv, dir_uv = synthetic.dataset_uniforms(m, s, s, 25)
+    rays, t, pair = _gpu(tris, face_uv, dir_uv, s, s, s, 1e-4)
+    P = m * s * s
+    kept = np.zeros(P, dtype=bool)
+    kept[np.unique(pair)] = True
+    assert 0.25 < kept.mean() < 0.6
+    # the label column: finite labels exactly on the back samples, one per marching step
+    finite = np.isfinite(t)
+    assert finite.sum() == kept.sum() * s and np.all(t[finite] > 0)
+    nf = 8
+    ref = dataset.sample_dataset(tris, face_uv, dir_uv, s, s, s, 1e-4, 0, nf, amb_tol=1e-5)
+    sel = pair < nf * s * s
+    _compare(tris, ref, (rays[:, sel], t[sel], pair[sel]), s, s, s)
