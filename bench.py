@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--icosphere-train-steps", type=int, default=1500)
     ap.add_argument("--render-train-steps", type=int, default=5000)
     ap.add_argument("--multi-train-steps", type=int, default=100)
+    ap.add_argument("--dataset-s", type=int, default=10, help="s_fc = s_dr = s_p of the dataset sampler workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -120,6 +121,45 @@ def train_network(torch, api, dev, v, f, tris, width, depth, seed, steps, n_rays
         tr.step(*batches[i % nb])
     torch.cuda.synchronize()
     return params, {"steps": steps, "loss_first": first, "loss_last": float(tr.loss)}
+
+
+def bench_dataset(args, torch, api, dev):
+    """Training-data sampler of Sec. V-B (Eqs. 8-12) on the 20,480-triangle mesh."""
+    import synthetic
+    from oracle import dataset
+    v, f = synthetic.training_mesh(1)
+    tris_np = synthetic.tri_soup(v, f)
+    tris = torch.from_numpy(tris_np).to(dev)
+    m, s, eps = f.shape[0], args.dataset_s, 1e-4
+    fu_np, du_np = synthetic.dataset_uniforms(m, s, s, 25)
+    fu, du = torch.from_numpy(fu_np).to(dev), torch.from_numpy(du_np).to(dev)
+    smp = api.DatasetSampler(tris, s, s, s, eps)
+    smp.run(fu, du)
+    torch.cuda.synchronize()
+    timer = event_timer(torch)
+    for _ in range(3):
+        timer.start()
+        smp.run(fu, du)
+        timer.stop()
+    torch.cuda.synchronize()
+    ms = timer.mean_ms()
+    n = int(smp.count.item())
+    kept = int(torch.isfinite(smp.t[:n]).sum().item()) // s   # one finite label per marching step
+    pairs = m * s * s
+    rays = pairs + 2 * kept * s                               # pair rays + perpendicular rays
+    out = {"workload": "20,480-triangle mesh, s_fc = s_dr = s_p = %d (%d pairs), eps %g" % (s, pairs, eps),
+           "ms": ms, "samples": n, "samples_per_s": n / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
+           "kept_fraction": kept / pairs, "labeller_rays": rays,
+           "ray_triangle_tests_per_s": rays * m / (ms * 1e-3)}
+    if not args.quick:
+        # the float64 oracle on the host: the pairs of faces 0 and 1, against every triangle
+        t0 = time.perf_counter()
+        ref = dataset.sample_dataset(tris_np, fu_np, du_np, s, s, s, eps, 0, 2)
+        cpu_s = time.perf_counter() - t0
+        out["oracle"] = {"pairs_per_s": ref["keep"].size / cpu_s, "samples_per_s": ref["t"].size / cpu_s,
+                         "sample": "faces 0-1 (%d pairs), %.1f s" % (ref["keep"].size, cpu_s)}
+    del smp
+    return {"dataset": out}
 
 
 def bench_label_train_render(args, torch, api, dev):
@@ -402,6 +442,7 @@ def main():
     if not args.quick:
         extra.update(bench_label_train_render(args, torch, api, dev))
         extra.update(bench_multi(args, torch, api, dev))
+        extra.update(bench_dataset(args, torch, api, dev))
     if not args.quick:
         # the float64 oracle on the host cores, bounded sample of the same query workload
         from oracle import mlp
