@@ -20,6 +20,8 @@ Modules:
   of Fig. 1 with a mesh or a network backend.
 * ``dataset``  -- the informative training-data sampler of Sec. V-B
   (Eqs. 8-12): face points, direction samples, marching, infinite samples.
+* ``udf``      -- the unsigned distance field as the minimum of the field over
+  a direction set (Sec. III-A, Eq. 5).
 * ``multi``    -- rigid instances of several networks (Sec. VII, scenes as
   future work).
 
