@@ -123,6 +123,33 @@ def train_network(torch, api, dev, v, f, tris, width, depth, seed, steps, n_rays
     return params, {"steps": steps, "loss_first": first, "loss_last": float(tr.loss)}
 
 
+def bench_udf(args, torch, api, dev, net, radius):
+    """Unsigned distance field (Eq. 5) of the icosphere network on a 32^3 grid x 512 directions."""
+    import synthetic
+    x_np = synthetic.grid_points(32)
+    _, d_np = synthetic.uniform_cube_rays(512, 38)
+    x, d = torch.from_numpy(x_np).to(dev), torch.from_numpy(d_np).to(dev)
+    n, nd = x.shape[1], d.shape[1]
+    ws = torch.empty(api.udf_workspace_bytes(n, nd), device=dev, dtype=torch.uint8)
+    u, a = api.udf(net, x, d, workspace=ws)
+    torch.cuda.synchronize()
+    timer = event_timer(torch)
+    for _ in range(5):
+        timer.start()
+        api.udf(net, x, d, out=u, arg=a, workspace=ws)
+        timer.stop()
+    torch.cuda.synchronize()
+    ms = timer.mean_ms()
+    uh = u.cpu().numpy()
+    fin = np.isfinite(uh)
+    # the icosphere's own unsigned distance, for context on the network's fit
+    true_u = np.abs(np.linalg.norm(x_np.astype(np.float64), axis=0) - radius)
+    return {"udf": {"workload": "32^3 grid points x 512 directions, bf16 4 x 128 icosphere network",
+                    "ms": ms, "points_per_s": n / (ms * 1e-3), "queries_per_s": n * nd / (ms * 1e-3),
+                    "finite_fraction": float(fin.mean()),
+                    "abs_err_vs_icosphere_udf_mean": float(np.abs(uh[fin] - true_u[fin]).mean())}}
+
+
 def bench_dataset(args, torch, api, dev):
     """Training-data sampler of Sec. V-B (Eqs. 8-12) on the 20,480-triangle mesh."""
     import synthetic
@@ -443,6 +470,7 @@ def main():
         extra.update(bench_label_train_render(args, torch, api, dev))
         extra.update(bench_multi(args, torch, api, dev))
         extra.update(bench_dataset(args, torch, api, dev))
+        extra.update(bench_udf(args, torch, api, dev, nets["bf16"], 0.8))
     if not args.quick:
         # the float64 oracle on the host cores, bounded sample of the same query workload
         from oracle import mlp

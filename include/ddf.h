@@ -13,7 +13,8 @@
  *     linear search over all triangles (Sec. I, Sec. VI-B) with the odd-even
  *     inside rule (Sec. V-B);
  *   - the path tracer whose nearest-hit search the field replaces (Fig. 1);
- *   - the informative training-data sampler built on the ray shooting (Sec. V-B).
+ *   - the informative training-data sampler built on the ray shooting (Sec. V-B);
+ *   - the unsigned distance field as the minimum of the field over directions (Eq. 5).
  *
  * Conventions common to every entry point
  *   Memory    Every array argument is DEVICE memory owned by the caller unless the
@@ -140,6 +141,25 @@ ddf_status ddf_dataset_workspace_size(const ddf_dataset_params *p, size_t *bytes
 ddf_status ddf_sample_dataset(const float *tris, int64_t m, const ddf_dataset_params *p, const float *face_uv,
                               const float *dir_uv, float *rays_out, float *t_out, int32_t *pair_out, int64_t cap,
                               int64_t *count_out, void *ws, size_t ws_bytes, ddf_stream stream);
+
+/* ---------------------------------------------------------------- unsigned distance field
+ * UDF(x) = min over a direction set of phi(x, theta) (Sec. III-A, Eq. 5), with phi the
+ * network's distance where logit > 0 and +inf where it reports a miss (a NaN distance counts
+ * as a miss).
+ *   points   [3][n_points] query points (network inputs as given: inside the domain).
+ *   dirs     [3][n_dirs] unit directions, turned into the network's angles as
+ *            ddf_assemble_rays does.
+ *   udf_out  [n_points] the minimum, +inf where every direction misses (or n_dirs == 0).
+ *   arg_out  [n_points] the lowest direction index reaching it, -1 where none; or NULL.
+ *   ws       workspace; ddf_udf_workspace_size gives the size for one pass over up to
+ *            2^24 queries; a smaller workspace (at least one point's queries) is used in
+ *            chunks of points, with the same results.
+ * Any network ddf_forward accepts.  Errors: INVALID_ARG for negative sizes, NULL arrays that
+ * are needed; UNSUPPORTED for unsupported networks or n_dirs >= 2^31; WORKSPACE when ws
+ * cannot hold one point's queries.  n_points == 0 is a no-op. */
+ddf_status ddf_udf_workspace_size(int64_t n_points, int64_t n_dirs, size_t *bytes);
+ddf_status ddf_udf(const ddf_net *net, const float *points, int64_t n_points, const float *dirs, int64_t n_dirs,
+                   float *udf_out, int32_t *arg_out, void *ws, size_t ws_bytes, ddf_stream stream);
 
 /* ---------------------------------------------------------------- launch tuning
  * Process-wide launch-shape knobs.  They decide how work is spread over the GPU and

@@ -54,6 +54,28 @@ def assemble_rays(orig, dirs, out=None):
     return out
 
 
+def udf_workspace_bytes(n_points, n_dirs):
+    b = ctypes.c_size_t(0)
+    _lib.call("ddf_udf_workspace_size", n_points, n_dirs, ctypes.byref(b))
+    return b.value
+
+
+def udf(net, points, dirs, out=None, arg=None, workspace=None):
+    """Unsigned distance field (Eq. 5): the minimum over the unit directions ``dirs`` [3][d]
+    of the network's distance from each of ``points`` [3][n] (misses: +inf).  Returns
+    (udf [n], argmin direction [n] int32, -1 where every direction misses)."""
+    _dev(points, torch.float32, "points", 3)
+    _dev(dirs, torch.float32, "dirs", 3)
+    n, d = points.shape[1], dirs.shape[1]
+    out = torch.empty(n, device=points.device, dtype=torch.float32) if out is None else out
+    arg = torch.empty(n, device=points.device, dtype=torch.int32) if arg is None else arg
+    if workspace is None:
+        workspace = torch.empty(max(udf_workspace_bytes(n, d), 1), device=points.device, dtype=torch.uint8)
+    _lib.call("ddf_udf", ctypes.byref(net.desc), _p(points), n, _p(dirs), d, _p(out), _p(arg), _p(workspace),
+              workspace.numel(), _stream())
+    return out, arg
+
+
 class DatasetSampler:
     """The training-data sampler of Sec. V-B (``ddf_sample_dataset``) with its workspace and
     output buffers allocated once (capacity: every possible sample, 4 per marching step)."""

@@ -103,3 +103,10 @@ def dataset_uniforms(m, s_fc, s_dr, seed):
     face_uv = np.ascontiguousarray(rng.random((m * s_fc, 2), dtype=np.float32).T)
     dir_uv = np.ascontiguousarray(rng.random((m * s_dr, 2), dtype=np.float32).T)
     return face_uv, dir_uv
+
+
+def grid_points(n_side, half=0.95):
+    """Regular grid of n_side^3 points in [-half, half]^3, float32 [3, n_side^3] (x fastest)."""
+    c = np.linspace(-half, half, n_side)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    return np.ascontiguousarray(np.stack([x.ravel(), y.ravel(), z.ravel()]).astype(np.float32))

@@ -29,7 +29,7 @@ def test_header_declares_the_hot_path():
     names = _declared()
     for required in ("ddf_label_rays", "ddf_forward", "ddf_backward", "ddf_render_wavefront", "ddf_pack_net",
                      "ddf_train_step", "ddf_train_step_chunked", "ddf_assemble_rays", "ddf_query",
-                     "ddf_set_tuning", "ddf_sample_dataset", "ddf_dataset_workspace_size"):
+                     "ddf_set_tuning", "ddf_sample_dataset", "ddf_dataset_workspace_size", "ddf_udf", "ddf_udf_workspace_size"):
         assert required in names
 
 
@@ -124,6 +124,24 @@ def test_dataset_sampler_validation(lib):
         _lib.DDF_ERR_INVALID_ARG
     assert lib.ddf_sample_dataset(1, 4, ctypes.byref(ok), 1, 1, 1, 1, None, 8, 1, 1, 16, None) == \
         _lib.DDF_ERR_WORKSPACE
+    assert b"workspace" in lib.ddf_last_error()
+
+
+def test_udf_validation(lib):
+    from paper_2306_16142_amd import _lib
+    b = ctypes.c_size_t(0)
+    assert lib.ddf_udf_workspace_size(1000, 100, ctypes.byref(b)) == _lib.DDF_OK and b.value >= 1000 * 100 * 28
+    assert lib.ddf_udf_workspace_size(1 << 20, 512, ctypes.byref(b)) == _lib.DDF_OK
+    assert b.value < (1 << 24) * 29 + 8 * 512 + 1024   # one pass holds at most 2^24 queries
+    assert lib.ddf_udf_workspace_size(-1, 100, ctypes.byref(b)) == _lib.DDF_ERR_INVALID_ARG
+    net = _lib.DdfNet(128, 4, 1, 1)
+    assert lib.ddf_udf(None, 1, 10, 1, 10, 1, None, 1, 1 << 30, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_udf(ctypes.byref(_lib.DdfNet(96, 4, 1, 1)), 1, 10, 1, 10, 1, None, 1, 1 << 30, None) == \
+        _lib.DDF_ERR_UNSUPPORTED
+    assert lib.ddf_udf(ctypes.byref(net), None, 10, 1, 10, 1, None, 1, 1 << 30, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_udf(ctypes.byref(net), 1, -1, 1, 10, 1, None, 1, 1 << 30, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_udf(ctypes.byref(net), 1, 0, None, 10, None, None, None, 0, None) == _lib.DDF_OK
+    assert lib.ddf_udf(ctypes.byref(net), 1, 10, 1, 10, 1, None, 1, 64, None) == _lib.DDF_ERR_WORKSPACE
     assert b"workspace" in lib.ddf_last_error()
 
 
