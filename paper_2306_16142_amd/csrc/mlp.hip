@@ -281,16 +281,55 @@ __device__ __attribute__((always_inline)) inline void dense_fp8(const uint8_t *w
     fp8_schedule<0, NSTEP, KIN, NMB, NB, kAhead>();
 }
 
+// Unsigned distance field epilogue (Eq. 5): the queries of one 32-ray block (lanes 0..31 hold
+// ray r's logit z and distance d; lanes 32..63 pass valid = false) are point-major, query
+// r = point * nd + direction.  Each hit becomes a 64-bit key (the distance's bits in an
+// order-preserving form, then the direction index), lanes of one point take their minimum by
+// a segmented suffix scan, and the first lane of each point meets the other blocks in one
+// atomic minimum, so the smallest distance wins and, among equal ones, the lowest direction.
+// A miss (z <= 0) and a NaN or +inf distance give no key.
+// r / nd for 0 <= r < 2^31 without a division: with 2^(l-1) < nd <= 2^l and
+// m = ceil(2^(31+l) / nd) (at most 32 bits), r / nd = (r m) >> (31 + l) exactly (the round-up
+// method of Granlund and Montgomery, 1994).
+struct UdfDiv {
+    uint32_t m;
+    int sh, nd;
+};
+__device__ inline UdfDiv udf_div_make(int nd) {
+    const int l = nd > 1 ? 32 - __clz(nd - 1) : 0;
+    return {(uint32_t)(((1ull << (31 + l)) + (uint64_t)nd - 1) / (uint64_t)nd), 31 + l, nd};
+}
+__device__ inline int udf_div(const UdfDiv &q, int r) { return (int)(((uint64_t)(uint32_t)r * q.m) >> q.sh); }
+
+__device__ inline void udf_block_min(float z, float d, bool valid, int64_t r, const UdfDiv &q,
+                                     unsigned long long *keys, int col) {
+    const int nd = q.nd;
+    const bool hit = valid && z > 0.f && d < INFINITY;
+    const int p = valid ? udf_div(q, (int)r) : -1;
+    const uint32_t u = __float_as_uint(d);
+    const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    unsigned long long key = hit ? ((unsigned long long)ord << 32) | (uint32_t)((int)r - p * nd) : ~0ull;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+        const unsigned long long other = __shfl_down(key, off, 32);
+        const int po = __shfl_down(p, off, 32);
+        if (col + off < 32 && po == p && other < key) key = other;
+    }
+    const int prev = __shfl_up(p, 1, 32);
+    if (p >= 0 && (col == 0 || prev != p) && key != ~0ull) atomicMin(keys + p, key);
+}
+
 // fp8 head with the weights in LDS: rows 0 (logit) and 1 (distance), bias as the start
 // value, the power-of-two s_w s_a in the MFMA scale.  Lanes of half 0 hold both rows; the
 // distance moves to half 1 so that every lane stores one value (no divergent branch near
 // the matrix ops).
-template <int W, int NB>
+template <int W, int NB, bool kUdf = false>
 __device__ __attribute__((always_inline)) inline void head_fp8(const uint8_t *wsrc, int64_t th,
                                                                const i32x8 (&bin)[W / 64][NB], const float *bias,
                                                                int aexp, bool bad, int lane, int h, int col,
                                                                int64_t base, int64_t n, const bool (&nan_ray)[NB],
-                                                               float *logit_out, float *dist_out) {
+                                                               float *logit_out, float *dist_out, UdfDiv udq = {},
+                                                               unsigned long long *udf_keys = nullptr) {
     __builtin_amdgcn_sched_barrier(0);
     const f32x4 hb = *reinterpret_cast<const f32x4 *>(bias);   // logit, distance biases, 0, 0
     const float keep = (float)(1 - h);
@@ -307,10 +346,14 @@ __device__ __attribute__((always_inline)) inline void head_fp8(const uint8_t *ws
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const float d = __shfl(acc[nb][1], col);
-        const float v = h ? d : acc[nb][0];
         const int64_t r = base + nb * 32 + col;
-        float *dst = h ? dist_out : logit_out;
-        if (r < n) dst[r] = (nan_ray[nb] || bad) ? NAN : v;
+        if constexpr (kUdf) {
+            udf_block_min(acc[nb][0], d, h == 0 && r < n && !nan_ray[nb] && !bad, r, udq, udf_keys, col);
+        } else {
+            const float v = h ? d : acc[nb][0];
+            float *dst = h ? dist_out : logit_out;
+            if (r < n) dst[r] = (nan_ray[nb] || bad) ? NAN : v;
+        }
     }
 }
 
@@ -515,12 +558,13 @@ __device__ __attribute__((always_inline)) inline void dense_relu_inplace(
 }
 
 // Head: rows 0 (logit) and 1 (distance) of one 32-row MFMA block, written by lanes 0..31.
-template <int P, int W, int NB, bool kCInit = false>
+template <int P, int W, int NB, bool kCInit = false, bool kUdf = false>
 __device__ __attribute__((always_inline)) inline void head_out(const uint8_t *wsrc, int64_t th,
                                                                const typename OpOf<P>::T (&bin)[W / k_per_block(P)][NB],
                                                                const float *bias, float alpha, bool bad, int lane, int h,
                                                                int col, int64_t base, int64_t n, const bool (&nan_ray)[NB],
-                                                               float *logit_out, float *dist_out) {
+                                                               float *logit_out, float *dist_out, UdfDiv udq = {},
+                                                               unsigned long long *udf_keys = nullptr) {
     using Op = typename OpOf<P>::T;
     constexpr int NKB = W / k_per_block(P);
     f32x16 start{};
@@ -547,6 +591,15 @@ __device__ __attribute__((always_inline)) inline void head_out(const uint8_t *ws
         for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma<P>(a, one, acc[nb]);
         c0 = c1 = 0.f;
     }
+    if constexpr (kUdf) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int64_t r = base + nb * 32 + col;
+            udf_block_min(fmaf(acc[nb][0] + acc[nb][2], alpha, c0), fmaf(acc[nb][1] + acc[nb][3], alpha, c1),
+                          h == 0 && r < n && !nan_ray[nb] && !bad, r, udq, udf_keys, col);
+        }
+        return;
+    }
     if (h == 0) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
@@ -564,11 +617,15 @@ __device__ __attribute__((always_inline)) inline void head_out(const uint8_t *ws
 // kCalib: record per-layer input absmax (fp8 calibration) instead of writing outputs.
 // kOD: the inputs are origins [3][stride] (`rays`) and unit directions [3][stride] (`dirs`),
 // assembled into the 5-value query in registers (one kernel for ray assembly and query).
-template <int P, int W, int NB, bool kLdsA, bool kCalib, bool kOD = false>
+// kUdf: the queries are the grid of `stride` points [3][stride] (`rays`) x `nd` directions
+// given as angles [2][nd] (`dirs`), query r = point * nd + direction; instead of writing
+// outputs each point's minimum hit distance goes to udf_keys (Eq. 5, see udf_block_min).
+template <int P, int W, int NB, bool kLdsA, bool kCalib, bool kOD = false, bool kUdf = false>
 __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
     const uint8_t *__restrict__ blob, int depth, const float *__restrict__ rays, int64_t stride,
     const int *__restrict__ count_dev, float *__restrict__ logit_out, float *__restrict__ dist_out,
-    unsigned int *__restrict__ absmax, const float *__restrict__ dirs = nullptr) {
+    unsigned int *__restrict__ absmax, const float *__restrict__ dirs = nullptr, int nd = 0,
+    unsigned long long *__restrict__ udf_keys = nullptr) {
     using Op = typename OpOf<P>::T;
     constexpr int KB = k_per_block(P);
     constexpr int NKB = W / KB;
@@ -635,7 +692,9 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
     const int wpb = blockDim.x >> 6;
     // rays are rows of length `stride`; the first `n` are evaluated (n from the device when
     // a queue produced them)
-    const int64_t n = count_dev ? min<int64_t>(*count_dev, stride) : stride;
+    const int64_t n = kUdf ? stride * nd : count_dev ? min<int64_t>(*count_dev, stride) : stride;
+    UdfDiv udq{};
+    if constexpr (kUdf) udq = udf_div_make(nd);
     const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
 
     // With the weights in LDS the rays of the next tile are loaded while this one is computed
@@ -655,6 +714,12 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
                 vnext[nb][3] = r < n ? dirs[r] : 0.f;
                 vnext[nb][4] = r < n ? dirs[stride + r] : 0.f;
                 dz_next[nb] = r < n ? dirs[2 * stride + r] : 1.f;
+            } else if constexpr (kUdf) {
+                const int p = r < n ? udf_div(udq, (int)r) : 0, j = r < n ? (int)r - p * nd : 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) vnext[nb][c] = r < n ? rays[(int64_t)c * stride + p] : 0.f;
+                vnext[nb][3] = r < n ? dirs[j] : 0.f;
+                vnext[nb][4] = r < n ? dirs[nd + j] : 0.f;
             } else {
 #pragma unroll
                 for (int j = 0; j < kInRaw; ++j) vnext[nb][j] = r < n ? rays[(int64_t)j * stride + r] : 0.f;
@@ -750,11 +815,11 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
             }
             if (l < depth) {
                 dense_fp8<W, NB, NKB>(wsrc, L.layer_tile(l), b1, b0, s_bias + l * W, s_c->aexp[l], lane, h);
-                head_fp8<W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->aexp[depth], bad, lane, h, col, base,
-                                n, nan_ray, logit_out, dist_out);
+                head_fp8<W, NB, kUdf>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->aexp[depth], bad, lane, h,
+                                      col, base, n, nan_ray, logit_out, dist_out, udq, udf_keys);
             } else {
-                head_fp8<W, NB>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->aexp[depth], bad, lane, h, col, base,
-                                n, nan_ray, logit_out, dist_out);
+                head_fp8<W, NB, kUdf>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->aexp[depth], bad, lane, h,
+                                      col, base, n, nan_ray, logit_out, dist_out, udq, udf_keys);
             }
             continue;
         }
@@ -765,8 +830,9 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
                 dense_relu_inplace<P, W, NB, NKB, kCalib>(wsrc, L.layer_tile(l), b0, s_bias + l * W, s_c->alpha[l], lane,
                                                            h, valid_any, absmax + 2 * (l + 1) + 1);
             if constexpr (!kCalib)
-                head_out<P, W, NB>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
-                                   nan_ray, logit_out, dist_out);
+                head_out<P, W, NB, false, kUdf>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth],
+                                                s_c->bad != 0, lane, h, col, base, n, nan_ray, logit_out, dist_out, udq,
+                                                udf_keys);
             continue;
         }
         // ---- layer 0, then hidden layers two at a time (b1 -> b0 -> b1 ...)
@@ -790,11 +856,11 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
         if constexpr (kCalib) continue;
         // ---- head: rows 0 (logit) and 1 (distance) of one 32-row block
         if (last_in_b0)
-            head_out<P, W, NB, kCInit>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
-                               nan_ray, logit_out, dist_out);
+            head_out<P, W, NB, kCInit, kUdf>(wsrc, L.head_tile(), b0, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0,
+                                             lane, h, col, base, n, nan_ray, logit_out, dist_out, udq, udf_keys);
         else
-            head_out<P, W, NB, kCInit>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0, lane, h, col, base, n,
-                               nan_ray, logit_out, dist_out);
+            head_out<P, W, NB, kCInit, kUdf>(wsrc, L.head_tile(), b1, s_bias + W * depth, s_c->alpha[depth], s_c->bad != 0,
+                                             lane, h, col, base, n, nan_ray, logit_out, dist_out, udq, udf_keys);
     }
 }
 
@@ -856,10 +922,11 @@ int cu_count() {
     return cus;
 }
 
+// udf_keys (weights in LDS only): the UDF grid of n points x nd directions (angles in `dirs`).
 template <int P, int W, int NB, bool kLdsA>
 ddf_status launch_forward(const NetLayout &L, const void *blob, const float *rays, int64_t n, const int *count_dev,
                           float *logit, float *dist, unsigned int *absmax, hipStream_t stream,
-                          const float *dirs = nullptr) {
+                          const float *dirs = nullptr, int nd = 0, unsigned long long *udf_keys = nullptr) {
     if (absmax) {
         if constexpr (P == kFP32 && !kLdsA) {
             auto kc = forward_kernel<P, W, NB, kLdsA, true>;
@@ -867,32 +934,37 @@ ddf_status launch_forward(const NetLayout &L, const void *blob, const float *ray
             const size_t lds = ((size_t)W * L.depth + 4) * 4 + sizeof(LdsConsts);
             hipLaunchKernelGGL(kc, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 32 * NB * 4 - 1) / (32 * NB * 4), 512))),
                                dim3(threads), lds, stream, (const uint8_t *)blob, L.depth, rays, n, count_dev, logit, dist, absmax,
-                               (const float *)nullptr);
+                               (const float *)nullptr, 0, (unsigned long long *)nullptr);
             return launch_status("ddf_fp8_scales (calibration)");
         }
         set_error("calibration runs on float32 networks only");
         return DDF_ERR_UNSUPPORTED;
     }
     auto kern = forward_kernel<P, W, NB, kLdsA, false>;
-    if constexpr (kLdsA) {   // the fused ray assembly exists for the LDS kernels only
-        if (dirs) kern = forward_kernel<P, W, NB, kLdsA, false, true>;
+    if constexpr (kLdsA) {   // the fused ray assembly and the fused UDF exist for the LDS kernels only
+        if (udf_keys) kern = forward_kernel<P, W, NB, kLdsA, false, false, true>;
+        else if (dirs) kern = forward_kernel<P, W, NB, kLdsA, false, true>;
     }
     const size_t lds = (kLdsA ? L.tiles * tile_bytes(P) : 0) + ((size_t)W * L.depth + 4) * 4 + sizeof(LdsConsts);
     static std::once_flag once;
     std::call_once(once, [&] {
         (void)hipFuncSetAttribute((const void *)forward_kernel<P, W, NB, kLdsA, false>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-        if constexpr (kLdsA)
+        if constexpr (kLdsA) {
             (void)hipFuncSetAttribute((const void *)forward_kernel<P, W, NB, kLdsA, false, true>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+            (void)hipFuncSetAttribute((const void *)forward_kernel<P, W, NB, kLdsA, false, false, true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        }
     });
     const int threads = NB == 2 ? 512 : 256;
-    const int64_t ntile = (n + 32 * NB - 1) / (32 * NB);
+    const int64_t nq = udf_keys ? n * nd : n;   // queries
+    const int64_t ntile = (nq + 32 * NB - 1) / (32 * NB);
     const int64_t wpb = threads / 64;
     const int per_cu = kLdsA ? 1 : 2;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((ntile + wpb - 1) / wpb, (int64_t)cu_count() * per_cu));
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, (const uint8_t *)blob, L.depth, rays, n,
-                       count_dev, logit, dist, absmax, dirs);
+                       count_dev, logit, dist, absmax, dirs, nd, udf_keys);
     return launch_status("ddf_forward");
 }
 
@@ -945,6 +1017,24 @@ ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, co
     if (net->precision == kBF16) return launch_forward<kBF16, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
     if (net->precision == kFP8) return launch_forward<kFP8, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
     return launch_forward<kFP32, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
+}
+
+// Fused UDF (Eq. 5): networks whose weights fit in LDS (width 128, bf16 or fp8) and grids of
+// fewer than 2^31 queries.
+bool udf_fused_ok(const ddf_net *net, int64_t np, int64_t nd) {
+    const NetLayout L = make_layout(net->width, net->depth, net->precision);
+    return net->width == 128 && net->precision != kFP32 && fits_lds(L) && np * nd < ((int64_t)1 << 31);
+}
+
+// keys [np] must hold ~0 on entry; ang is [2][nd].
+ddf_status udf_fused_launch(const ddf_net *net, const float *points, int64_t np, const float *ang, int64_t nd,
+                            unsigned long long *keys, hipStream_t s) {
+    const NetLayout L = make_layout(net->width, net->depth, net->precision);
+    if (net->precision == kBF16)
+        return launch_forward<kBF16, 128, 2, true>(L, net->packed, points, np, nullptr, nullptr, nullptr, nullptr, s, ang,
+                                                   (int)nd, keys);
+    return launch_forward<kFP8, 128, 2, true>(L, net->packed, points, np, nullptr, nullptr, nullptr, nullptr, s, ang,
+                                              (int)nd, keys);
 }
 
 }  // namespace ddf

@@ -11,6 +11,10 @@
 //   min      one wave per point: each lane scans a strided share of the directions in
 //            ascending order, then a wave reduction keeps the smallest distance and, among
 //            equal ones, the lowest direction index
+// For networks whose weights fit in LDS the grid, the network and the minimum are one kernel
+// (the forward kernel's UDF form: each 32-query block reduces its points' hits to 64-bit keys
+// and meets the other blocks in an atomic minimum), then the keys are decoded; the answers
+// are the same, since the minimum and its tie rule do not depend on the order.
 #include <climits>
 #include <cmath>
 
@@ -18,6 +22,11 @@
 #include "rays_device.hpp"
 
 namespace ddf {
+
+bool udf_fused_ok(const ddf_net *net, int64_t np, int64_t nd);
+ddf_status udf_fused_launch(const ddf_net *net, const float *points, int64_t np, const float *ang, int64_t nd,
+                            unsigned long long *keys, hipStream_t s);
+
 namespace {
 
 constexpr int64_t kUdfMaxQueries = (int64_t)1 << 24;   // queries per chunk the size query plans for
@@ -82,10 +91,30 @@ __global__ __launch_bounds__(kUdfWaves * 64) void udf_min_kernel(const float *__
 
 inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
+__global__ void udf_keys_init_kernel(unsigned long long *__restrict__ keys, int64_t np) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) keys[i] = ~0ull;
+}
+
+// Key = order-preserving bits of the distance (high word), direction index (low word);
+// ~0 = every direction missed.
+__global__ void udf_keys_decode_kernel(const unsigned long long *__restrict__ keys, int64_t np,
+                                       float *__restrict__ udf_out, int32_t *__restrict__ arg_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const unsigned long long k = keys[i];
+    const uint32_t ord = (uint32_t)(k >> 32);
+    const uint32_t u = (ord & 0x80000000u) ? (ord & 0x7fffffffu) : ~ord;
+    udf_out[i] = k == ~0ull ? INFINITY : __uint_as_float(u);
+    if (arg_out) arg_out[i] = k == ~0ull ? -1 : (int32_t)(uint32_t)k;
+}
+
 // Workspace for chunks of `chunk` points: angles [2][nd] | rays [5][chunk nd] | logit | dist,
 // each 256-byte aligned (the three alignments of the per-query arrays are the 768 bytes).
 size_t udf_fixed_bytes(int64_t nd) { return align256(8 * nd) + 3 * 256; }
 size_t udf_bytes(int64_t chunk, int64_t nd) { return udf_fixed_bytes(nd) + (size_t)28 * chunk * nd; }
+// The fused form: angles [2][nd] | keys [np].
+size_t udf_fused_bytes(int64_t np, int64_t nd) { return align256(8 * nd) + align256(8 * np); }
 
 }  // namespace
 }  // namespace ddf
@@ -99,7 +128,7 @@ extern "C" ddf_status ddf_udf_workspace_size(int64_t n_points, int64_t n_dirs, s
         return DDF_OK;
     }
     const int64_t chunk = std::min<int64_t>(n_points, std::max<int64_t>(1, kUdfMaxQueries / n_dirs));
-    *bytes = udf_bytes(chunk, n_dirs);
+    *bytes = std::max(udf_bytes(chunk, n_dirs), udf_fused_bytes(n_points, n_dirs));
     return DDF_OK;
 }
 
@@ -117,6 +146,16 @@ extern "C" ddf_status ddf_udf(const ddf_net *net, const float *points, int64_t n
     if (n_dirs == 0) {   // the minimum over no direction: +inf, argument -1
         hipLaunchKernelGGL(udf_min_kernel, dim3(blocks_for(n_points, kUdfWaves)), dim3(kUdfWaves * 64), 0, s,
                            (const float *)nullptr, (const float *)nullptr, (int64_t)0, n_points, udf_out, arg_out);
+        return launch_status("ddf_udf");
+    }
+    if (udf_fused_ok(net, n_points, n_dirs) && ws && ws_bytes >= udf_fused_bytes(n_points, n_dirs)) {
+        float *ang = (float *)ws;
+        auto *keys = (unsigned long long *)((uint8_t *)ws + align256(8 * n_dirs));
+        hipLaunchKernelGGL(udf_keys_init_kernel, dim3(blocks_for(n_points, 256)), dim3(256), 0, s, keys, n_points);
+        hipLaunchKernelGGL(udf_angles_kernel, dim3(blocks_for(n_dirs, 256)), dim3(256), 0, s, dirs, n_dirs, ang);
+        if (ddf_status st = udf_fused_launch(net, points, n_points, ang, n_dirs, keys, s)) return st;
+        hipLaunchKernelGGL(udf_keys_decode_kernel, dim3(blocks_for(n_points, 256)), dim3(256), 0, s, keys, n_points,
+                           udf_out, arg_out);
         return launch_status("ddf_udf");
     }
     const size_t fixed = udf_fixed_bytes(n_dirs);

@@ -73,11 +73,11 @@ def test_udf_bf16_matches_emulation(width, depth):
 
 
 def test_udf_chunks_and_edges():
-    banner("udf: workspace chunking, no directions, no points")
+    banner("udf: workspace chunking (fp32, unfused), no directions, no points")
     width, depth = 128, 2
     p = synthetic.random_params(width, depth, 35)
     x, d = _inputs(37, 50, 36)
-    net = api.Network(cuda(p), width, depth, "bf16")
+    net = api.Network(cuda(p), width, depth, "fp32")
     xg, dg = cuda(x), cuda(d)
     u1, a1 = [t.clone() for t in api.udf(net, xg, dg)]
     # a workspace for five points' queries: eight chunks, bit-identical results
@@ -85,12 +85,45 @@ def test_udf_chunks_and_edges():
     u2, a2 = api.udf(net, xg, dg, workspace=ws)
     torch.cuda.synchronize()
     assert torch.equal(u1, u2) and torch.equal(a1, a2)
-    # no directions: +inf and -1 everywhere
-    u3, a3 = api.udf(net, xg, torch.empty((3, 0), device="cuda"))
+    # no directions: +inf and -1 everywhere; no points: nothing (fused and unfused networks)
+    for prec in ("fp32", "bf16"):
+        net = api.Network(cuda(p), width, depth, prec)
+        u3, a3 = api.udf(net, xg, torch.empty((3, 0), device="cuda"))
+        torch.cuda.synchronize()
+        assert torch.isinf(u3).all() and (a3 == -1).all()
+        u4, _ = api.udf(net, torch.empty((3, 0), device="cuda"), dg)
+        assert u4.numel() == 0
+
+
+@pytest.mark.parametrize("prec,n_points,n_dirs", [("bf16", 333, 70), ("bf16", 50, 7), ("fp8", 129, 96)])
+def test_udf_fused_equals_forward_then_minimum(prec, n_points, n_dirs):
+    """4 x 128 bf16 / fp8 networks take the fused kernel (grid, network and minimum in one
+    launch); its answer equals, bit for bit, the minimum over ddf_forward's outputs for the
+    same grid assembled by ddf_assemble_rays (the same angle code), ties to the lowest index."""
+    banner("udf fused %s: %d points x %d dirs" % (prec, n_points, n_dirs))
+    width, depth = 128, 4
+    p = synthetic.random_params(width, depth, 41)
+    x, d = _inputs(n_points, n_dirs, 42)
+    pg, xg, dg = cuda(p), cuda(x), cuda(d)
+    if prec == "fp8":
+        co, cd = synthetic.uniform_cube_rays(1 << 14, 4)
+        calib = api.assemble_rays(cuda(co), cuda(cd))
+        net = api.Network(pg, width, depth, "fp8",
+                          scales=api.fp8_scales(pg, width, depth, calib, api.Network(pg, width, depth, "fp32")))
+    else:
+        net = api.Network(pg, width, depth, prec)
+    u, a = api.udf(net, xg, dg)
+    og = xg.repeat_interleave(n_dirs, dim=1).contiguous()
+    og_d = dg.repeat(1, n_points).contiguous()
+    lg, ds = net(api.assemble_rays(og, og_d))
     torch.cuda.synchronize()
-    assert torch.isinf(u3).all() and (a3 == -1).all()
-    u4, _ = api.udf(net, torch.empty((3, 0), device="cuda"), dg)
-    assert u4.numel() == 0
+    L, Dd = lg.view(n_points, n_dirs), ds.view(n_points, n_dirs)
+    masked = torch.where((L > 0) & (Dd < float("inf")), Dd, torch.full_like(Dd, float("inf")))
+    ref_u = masked.min(dim=1).values
+    ref_a = torch.where(torch.isinf(ref_u), torch.full_like(ref_u, -1, dtype=torch.int64),
+                        masked.argmin(dim=1)).to(torch.int32)
+    assert torch.isfinite(ref_u).float().mean() > 0.3
+    assert torch.equal(u, ref_u) and torch.equal(a, ref_a)
 
 
 def test_udf_full_size_sampled():
