@@ -240,6 +240,32 @@ def loss_and_seeds(logit, dist, hit, t):
     return bce + l1, g_logit, g_dist
 
 
+def paper_loss_and_seeds(dist, t, kind, delta=1.0):
+    """The paper's losses on the distance output alone (Sec. IV-A Eq. 6, Sec. V-A Eq. 7).
+
+    kind "clamp" (Eq. 7): mean over the N rays of |c(t) - c(d)|, c(x) = min(delta,
+    max(-delta, x)); a miss (t = +inf) clamps to delta.  kind "squish" (Eq. 6, reading:
+    the absolute value of the difference, sigma = tanh): mean of |tanh(t) - tanh(d)|, with
+    tanh(+inf) = 1.  Returns ``(loss, g_dist)``: g_dist = sign(c(d) - c(t)) c'(d) / N with
+    sign(0) = 0 and c' the derivative (1 strictly inside the clamp window, 0 outside and
+    on its edges; 1 - tanh^2 for the squish).  The logit gets no gradient.
+    Pinned by closed-form values and central finite differences in the tests.
+    """
+    d = np.asarray(dist, dtype=np.float64)
+    tt = np.asarray(t, dtype=np.float64)
+    n = d.size
+    if kind == "clamp":
+        cd, ct = np.clip(d, -delta, delta), np.clip(tt, -delta, delta)
+        dc = ((d > -delta) & (d < delta)).astype(np.float64)
+    elif kind == "squish":
+        cd, ct = np.tanh(d), np.tanh(tt)
+        dc = 1.0 - cd * cd
+    else:
+        raise ValueError("kind must be 'clamp' or 'squish'")
+    loss = np.abs(ct - cd).mean() if n else 0.0
+    return loss, np.sign(cd - ct) * dc / n
+
+
 def backward(params, width, depth, rays, g_logit, g_dist):
     """Reverse-mode gradient of sum(g_logit * logit + g_dist * dist).
 

@@ -342,3 +342,36 @@ def test_pow2_scale_edges():
         s = mlp.pow2_scale(a)
         assert np.log2(s) == np.round(np.log2(s))
         assert 224.0 < a / s <= 448.0
+
+
+def test_paper_losses_closed_form_and_differences():
+    """Eq. 7 clamp and Eq. 6 squish losses: hand-computed values, then central differences of
+    the loss against the seeds away from the clamp edges and from d = c(t)."""
+    d = np.array([0.5, -2.0, 0.2, 3.0])
+    t = np.array([np.inf, 0.1, 0.2, np.inf])
+    loss, g = mlp.paper_loss_and_seeds(d, t, "clamp", 1.0)
+    # |1 - 0.5| + |0.1 - (-1)| + 0 + |1 - 1| over 4
+    assert abs(loss - (0.5 + 1.1 + 0.0 + 0.0) / 4) < 1e-15
+    np.testing.assert_array_equal(g, [-0.25, 0.0, 0.0, 0.0])
+    loss, g = mlp.paper_loss_and_seeds(d, t, "squish")
+    want = (abs(1 - np.tanh(0.5)) + abs(np.tanh(0.1) - np.tanh(-2.0)) + 0 + abs(1 - np.tanh(3.0))) / 4
+    assert abs(loss - want) < 1e-15
+    np.testing.assert_allclose(g, [-(1 - np.tanh(0.5) ** 2) / 4, -(1 - np.tanh(-2.0) ** 2) / 4, 0.0,
+                                   -(1 - np.tanh(3.0) ** 2) / 4], rtol=1e-14)
+    rng = np.random.default_rng(8)
+    n = 200
+    d = rng.normal(size=n) * 1.5
+    t = np.where(rng.random(n) < 0.5, rng.uniform(0, 2, n), np.inf)
+    h = 1e-6
+    for kind, delta in (("clamp", 0.8), ("squish", 1.0)):
+        _, g = mlp.paper_loss_and_seeds(d, t, kind, delta)
+        for i in range(0, n, 7):
+            c_t = min(t[i], delta) if kind == "clamp" else np.tanh(t[i])
+            c_d = np.clip(d[i], -delta, delta) if kind == "clamp" else np.tanh(d[i])
+            if kind == "clamp" and (abs(abs(d[i]) - delta) < 1e-3 or abs(c_d - c_t) < 1e-3):
+                continue
+            dp, dm = d.copy(), d.copy()
+            dp[i] += h
+            dm[i] -= h
+            fd = (mlp.paper_loss_and_seeds(dp, t, kind, delta)[0] - mlp.paper_loss_and_seeds(dm, t, kind, delta)[0]) / (2 * h)
+            assert abs(fd - g[i]) < 1e-7, (kind, i, fd, g[i])
