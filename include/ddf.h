@@ -274,6 +274,38 @@ ddf_status ddf_train_step_chunked(const ddf_net *net, float *params, float *adam
                                   int64_t n, int64_t chunk, float *loss_out, float *g_params, void *ws,
                                   size_t ws_bytes, ddf_stream stream);
 
+/* Training losses (the default is the one above):
+ *   DDF_LOSS_BCE_L1  binary cross-entropy on the hit logit + L1 on hit distances (1:1);
+ *   DDF_LOSS_CLAMP   the clamp loss of Eq. 7 (Sec. V-A) on the distance output alone:
+ *                    |c(t) - c(dist)| / n with c the two-sided clamp at `delta` (> 0,
+ *                    finite); a miss (t = +inf) clamps to delta;
+ *   DDF_LOSS_SQUISH  the squish loss of Eq. 6 (Sec. IV-A) on the distance alone, read with
+ *                    the absolute value and sigma = tanh: |tanh(t) - tanh(dist)| / n,
+ *                    tanh(+inf) = 1 (delta unused).
+ * With the clamp and squish losses g_logit is 0 and g_dist = sign(c(dist) - c(t)) c'(dist) / n
+ * (c' = 1 strictly inside the clamp window and 0 outside or on its edges; 1 - tanh^2). */
+#define DDF_LOSS_BCE_L1 0
+#define DDF_LOSS_CLAMP 1
+#define DDF_LOSS_SQUISH 2
+typedef struct {
+    int32_t kind;   /* DDF_LOSS_* */
+    float delta;    /* clamp window of DDF_LOSS_CLAMP */
+} ddf_loss;
+
+/* ddf_loss_seeds with a chosen loss (`loss` NULL: DDF_LOSS_BCE_L1).  Errors as
+ * ddf_loss_seeds, plus INVALID_ARG for an unknown kind or a clamp without a finite delta > 0. */
+ddf_status ddf_loss_seeds_ex(const float *logit, const float *dist, const float *t_label, int64_t n,
+                             const ddf_loss *loss, float *g_logit, float *g_dist, float *loss_out, void *ws,
+                             size_t ws_bytes, ddf_stream stream);
+
+/* The training step with a chosen loss: chunk == 0 is ddf_train_step, chunk >= 1 is
+ * ddf_train_step_chunked (same workspace rules); `loss` NULL: DDF_LOSS_BCE_L1.  Errors as
+ * those two, plus INVALID_ARG for a bad loss or a negative chunk. */
+ddf_status ddf_train_step_ex(const ddf_net *net, float *params, float *adam_m, float *adam_v, int64_t step,
+                             float lr, const float *rays, const float *t_label, int64_t n, int64_t chunk,
+                             const ddf_loss *loss, float *loss_out, float *g_params, void *ws, size_t ws_bytes,
+                             ddf_stream stream);
+
 /* ---------------------------------------------------------------- renderer
  * Wavefront path tracer of Fig. 1 in which the nearest-hit search is either the
  * brute-force triangle search (backend MESH) or the network (backend NET): the

@@ -45,6 +45,13 @@ class DdfRenderParams(ctypes.Structure):
 BACKEND_MESH, BACKEND_NET, BACKEND_MULTI = 0, 1, 2
 
 
+class DdfLoss(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("delta", c_f)]
+
+
+LOSSES = {"bce_l1": 0, "clamp": 1, "squish": 2}
+
+
 class DdfDatasetParams(ctypes.Structure):
     _fields_ = [("s_fc", c_i32), ("s_dr", c_i32), ("s_p", c_i32), ("eps", c_f), ("face_first", c_i64),
                 ("n_faces", c_i64)]
@@ -72,6 +79,9 @@ SIGNATURES = {
                                c_p, c_sz, c_p],
     "ddf_set_tuning": [c_i32, c_i32],
     "ddf_get_tuning": [c_i32, ctypes.POINTER(c_i32)],
+    "ddf_loss_seeds_ex": [c_p, c_p, c_p, c_i64, ctypes.POINTER(DdfLoss), c_p, c_p, c_p, c_p, c_sz, c_p],
+    "ddf_train_step_ex": [ctypes.POINTER(DdfNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64, c_i64,
+                          ctypes.POINTER(DdfLoss), c_p, c_p, c_p, c_sz, c_p],
     "ddf_udf_workspace_size": [c_i64, c_i64, ctypes.POINTER(c_sz)],
     "ddf_udf": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_sz, c_p],
     "ddf_dataset_workspace_size": [ctypes.POINTER(DdfDatasetParams), ctypes.POINTER(c_sz)],

@@ -184,15 +184,22 @@ def backward(net, rays, g_logit=None, g_dist=None, want_rays=True, want_params=F
     return g_rays, g_params
 
 
-def loss_seeds(logit, dist, t_label):
-    """BCE (hit) + L1 (distance over hits) loss and its seeds: returns (loss [1], g_logit, g_dist)."""
+def _loss_desc(loss, delta):
+    return _lib.DdfLoss(_lib.LOSSES[loss], delta)
+
+
+def loss_seeds(logit, dist, t_label, loss="bce_l1", delta=1.0):
+    """A training loss and its seeds: returns (loss [1], g_logit, g_dist).  ``loss``: "bce_l1"
+    (BCE on the hit + L1 on hit distances), "clamp" (Eq. 7, window ``delta``) or "squish"
+    (Eq. 6 with tanh)."""
     n = logit.numel()
     g_logit, g_dist = torch.empty_like(logit), torch.empty_like(dist)
-    loss = torch.empty(1, device=logit.device, dtype=torch.float32)
+    out = torch.empty(1, device=logit.device, dtype=torch.float32)
     ws = torch.empty(4160, device=logit.device, dtype=torch.uint8)
-    _lib.call("ddf_loss_seeds", _p(logit), _p(dist), _p(t_label), n, _p(g_logit), _p(g_dist), _p(loss), _p(ws),
-              ws.numel(), _stream())
-    return loss, g_logit, g_dist
+    desc = _loss_desc(loss, delta)
+    _lib.call("ddf_loss_seeds_ex", _p(logit), _p(dist), _p(t_label), n, ctypes.byref(desc), _p(g_logit), _p(g_dist),
+              _p(out), _p(ws), ws.numel(), _stream())
+    return out, g_logit, g_dist
 
 
 def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -206,10 +213,12 @@ class Trainer:
     The packed network ``net`` is rewritten after every step; ``params`` is updated in place.
     """
 
-    def __init__(self, params, width, depth, batch, lr=1e-3, chunk=None):
+    def __init__(self, params, width, depth, batch, lr=1e-3, chunk=None, loss="bce_l1", delta=1.0):
         """``chunk``: sweep batches in column ranges of this many rays (workspace sized for
-        ``chunk`` instead of ``batch``; the forward pass is recomputed per chunk)."""
+        ``chunk`` instead of ``batch``; the forward pass is recomputed per chunk).  ``loss``:
+        "bce_l1" (default), "clamp" (Eq. 7, window ``delta``) or "squish" (Eq. 6, tanh)."""
         self.chunk = chunk
+        self.loss_desc = _loss_desc(loss, delta)
         self.net = Network(params, width, depth, "fp32")
         self.params = params
         self.m = torch.zeros_like(params)
@@ -226,14 +235,9 @@ class Trainer:
         _dev(t_label, torch.float32, "t_label")
         self.step_count += 1
         n = rays.shape[1]
-        if self.chunk:
-            _lib.call("ddf_train_step_chunked", ctypes.byref(self.net.desc), _p(self.params), _p(self.m), _p(self.v),
-                      self.step_count, self.lr, _p(rays), _p(t_label), n, self.chunk, _p(self.loss), _p(self.g),
-                      _p(self.ws), self.ws.numel(), _stream())
-            return self.loss
-        _lib.call("ddf_train_step", ctypes.byref(self.net.desc), _p(self.params), _p(self.m), _p(self.v),
-                  self.step_count, self.lr, _p(rays), _p(t_label), n, _p(self.loss), _p(self.g), _p(self.ws),
-                  self.ws.numel(), _stream())
+        _lib.call("ddf_train_step_ex", ctypes.byref(self.net.desc), _p(self.params), _p(self.m), _p(self.v),
+                  self.step_count, self.lr, _p(rays), _p(t_label), n, self.chunk or 0, ctypes.byref(self.loss_desc),
+                  _p(self.loss), _p(self.g), _p(self.ws), self.ws.numel(), _stream())
         return self.loss
 
 

@@ -231,14 +231,12 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void grad_kernel(GradArgs a) {
                 }
                 if (kTrain && a.t_label) {
                     const float t = valid[nb] ? a.t_label[r] : INFINITY;
-                    const float y = t < INFINITY ? 1.f : 0.f;
-                    const float sig = 1.f / (1.f + expf(-z));
-                    gl[nb] = valid[nb] ? (sig - y) * inv_n : 0.f;
-                    const float diff = dd - (y > 0.f ? t : 0.f);
-                    gd[nb] = y > 0.f ? (diff > 0.f ? inv_nhit : (diff < 0.f ? -inv_nhit : 0.f)) : 0.f;
+                    float g0, g1;
+                    const float term = ray_loss(z, dd, t, inv_n, inv_nhit, a.loss, g0, g1);
+                    gl[nb] = valid[nb] ? g0 : 0.f;
+                    gd[nb] = valid[nb] ? g1 : 0.f;
                     if (h == 0 && valid[nb]) {
-                        loss_acc += (fmaxf(z, 0.f) - z * y + log1pf(expf(-fabsf(z)))) * inv_n +
-                                    y * fabsf(diff) * inv_nhit;
+                        loss_acc += term;
                         a.ws_delta[(int64_t)depth * W * n + r] = gl[nb];
                         a.ws_delta[(int64_t)depth * W * n + n + r] = gd[nb];
                     }

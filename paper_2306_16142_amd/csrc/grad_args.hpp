@@ -3,6 +3,7 @@
 #include <cstdint>
 
 #include "common.hpp"
+#include "loss_device.hpp"
 
 namespace ddf {
 
@@ -20,6 +21,7 @@ struct GradArgs {
     const float *g_dist_in;
     const float *t_label;        // training: label distance, +inf = miss (NULL: seeds from g_*_in)
     const float *loss_scalars;   // training: {1 / N, 1 / n_hit}
+    LossSpec loss;               // training: which loss forms the seeds (zero: BCE + L1)
     float *logit_out;            // optional
     float *dist_out;             // optional
     float *g_rays;               // optional [5][n]

@@ -231,13 +231,11 @@ __global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) 
                 float gl = 0.f, gd = 0.f;
                 if (a.t_label) {
                     const float t = valid ? a.t_label[r] : INFINITY;
-                    const float yh = t < INFINITY ? 1.f : 0.f;
-                    const float sig = 1.f / (1.f + expf(-z));
-                    gl = valid ? (sig - yh) * inv_n : 0.f;
-                    const float diff = dd - (yh > 0.f ? t : 0.f);
-                    gd = yh > 0.f ? (diff > 0.f ? inv_nhit : (diff < 0.f ? -inv_nhit : 0.f)) : 0.f;
-                    if (h == 0 && valid)
-                        loss_acc += (fmaxf(z, 0.f) - z * yh + log1pf(expf(-fabsf(z)))) * inv_n + yh * fabsf(diff) * inv_nhit;
+                    float g0, g1;
+                    const float term = ray_loss(z, dd, t, inv_n, inv_nhit, a.loss, g0, g1);
+                    gl = valid ? g0 : 0.f;
+                    gd = valid ? g1 : 0.f;
+                    if (h == 0 && valid) loss_acc += term;
                 } else {
                     gl = (valid && a.g_logit_in) ? a.g_logit_in[r] : 0.f;
                     gd = (valid && a.g_dist_in) ? a.g_dist_in[r] : 0.f;

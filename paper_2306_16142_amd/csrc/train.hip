@@ -246,17 +246,16 @@ __global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, 
 // ------------------------------------------------------------------------------ loss seeds
 __global__ void loss_seeds_kernel(const float *__restrict__ logit, const float *__restrict__ dist,
                                   const float *__restrict__ t_label, int64_t n, const float *__restrict__ scalars,
-                                  float *__restrict__ g_logit, float *__restrict__ g_dist, float *__restrict__ part) {
+                                  LossSpec ls, float *__restrict__ g_logit, float *__restrict__ g_dist,
+                                  float *__restrict__ part) {
     __shared__ float red[256];
     const float inv_n = scalars[0], inv_nhit = scalars[1];
     float acc = 0.f;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float z = logit[i], d = dist[i], t = t_label[i];
-        const float y = t < INFINITY ? 1.f : 0.f;
-        const float diff = d - (y > 0.f ? t : 0.f);
-        g_logit[i] = (1.f / (1.f + expf(-z)) - y) * inv_n;
-        g_dist[i] = y > 0.f ? (diff > 0.f ? inv_nhit : (diff < 0.f ? -inv_nhit : 0.f)) : 0.f;
-        acc += (fmaxf(z, 0.f) - z * y + log1pf(expf(-fabsf(z)))) * inv_n + y * fabsf(diff) * inv_nhit;
+        float gl, gd;
+        acc += ray_loss(logit[i], dist[i], t_label[i], inv_n, inv_nhit, ls, gl, gd);
+        g_logit[i] = gl;
+        g_dist[i] = gd;
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -386,9 +385,28 @@ extern "C" ddf_status ddf_backward(const ddf_net *net, const float *rays, int64_
     return param_grads(net->width, net->depth, n, w, g_params, (flags & 1u) != 0, s);
 }
 
-extern "C" ddf_status ddf_loss_seeds(const float *logit, const float *dist, const float *t_label, int64_t n,
-                                     float *g_logit, float *g_dist, float *loss_out, void *ws, size_t ws_bytes,
-                                     ddf_stream stream) {
+namespace ddf {
+namespace {
+ddf_status check_loss(const ddf_loss *loss, LossSpec *out, const char *who) {
+    if (!loss) {
+        *out = LossSpec{0, 0.f};
+        return DDF_OK;
+    }
+    DDF_REQUIRE(loss->kind >= DDF_LOSS_BCE_L1 && loss->kind <= DDF_LOSS_SQUISH, DDF_ERR_INVALID_ARG,
+                "%s: unknown loss kind %d", who, loss->kind);
+    DDF_REQUIRE(loss->kind != DDF_LOSS_CLAMP || (std::isfinite(loss->delta) && loss->delta > 0.f), DDF_ERR_INVALID_ARG,
+                "%s: the clamp loss needs a finite delta > 0", who);
+    *out = LossSpec{loss->kind, loss->delta};
+    return DDF_OK;
+}
+}  // namespace
+}  // namespace ddf
+
+extern "C" ddf_status ddf_loss_seeds_ex(const float *logit, const float *dist, const float *t_label, int64_t n,
+                                        const ddf_loss *loss, float *g_logit, float *g_dist, float *loss_out, void *ws,
+                                        size_t ws_bytes, ddf_stream stream) {
+    LossSpec ls;
+    if (ddf_status st = check_loss(loss, &ls, "ddf_loss_seeds")) return st;
     DDF_REQUIRE(n > 0 && logit && dist && t_label && g_logit && g_dist && loss_out, DDF_ERR_INVALID_ARG,
                 "ddf_loss_seeds: bad argument");
     DDF_REQUIRE(ws && ws_bytes >= 1024 * 4 + 64, DDF_ERR_WORKSPACE, "ddf_loss_seeds: workspace of %d bytes needed",
@@ -399,10 +417,16 @@ extern "C" ddf_status ddf_loss_seeds(const float *logit, const float *dist, cons
     unsigned int *count = reinterpret_cast<unsigned int *>(scalars + 4);
     launch_loss_scalars(t_label, n, reinterpret_cast<unsigned int *>(part), scalars, count, s);
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
-    hipLaunchKernelGGL(loss_seeds_kernel, dim3(blocks), dim3(256), 0, s, logit, dist, t_label, n, scalars, g_logit,
+    hipLaunchKernelGGL(loss_seeds_kernel, dim3(blocks), dim3(256), 0, s, logit, dist, t_label, n, scalars, ls, g_logit,
                        g_dist, part);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, part, (int64_t)blocks, loss_out, false);
     return launch_status("ddf_loss_seeds");
+}
+
+extern "C" ddf_status ddf_loss_seeds(const float *logit, const float *dist, const float *t_label, int64_t n,
+                                     float *g_logit, float *g_dist, float *loss_out, void *ws, size_t ws_bytes,
+                                     ddf_stream stream) {
+    return ddf_loss_seeds_ex(logit, dist, t_label, n, nullptr, g_logit, g_dist, loss_out, ws, ws_bytes, stream);
 }
 
 extern "C" ddf_status ddf_adam_step(float *params, const float *grads, float *m, float *v, int64_t count, int64_t step,
@@ -436,9 +460,11 @@ ddf_status adam_and_repack(const ddf_net *net, float *params, float *adam_m, flo
 }  // namespace
 }  // namespace ddf
 
-extern "C" ddf_status ddf_train_step(const ddf_net *net, float *params, float *adam_m, float *adam_v, int64_t step,
-                                     float lr, const float *rays, const float *t_label, int64_t n, float *loss_out,
-                                     float *g_params, void *ws, size_t ws_bytes, ddf_stream stream) {
+namespace ddf {
+namespace {
+ddf_status train_step_whole(const ddf_net *net, float *params, float *adam_m, float *adam_v, int64_t step, float lr,
+                            const float *rays, const float *t_label, int64_t n, LossSpec ls, float *loss_out,
+                            float *g_params, void *ws, size_t ws_bytes, ddf_stream stream) {
     if (ddf_status st = check_net(net, "ddf_train_step", true)) return st;
     DDF_REQUIRE(params && adam_m && adam_v && rays && t_label && loss_out && g_params && n > 0 && step >= 1,
                 DDF_ERR_INVALID_ARG, "ddf_train_step: bad argument");
@@ -458,6 +484,7 @@ extern "C" ddf_status ddf_train_step(const ddf_net *net, float *params, float *a
     a.n = n;
     a.t_label = t_label;
     a.loss_scalars = w.scalars;
+    a.loss = ls;
     a.ws_gamma = w.gamma;
     a.ws_h = w.h;
     a.ws_delta = w.delta;
@@ -467,11 +494,21 @@ extern "C" ddf_status ddf_train_step(const ddf_net *net, float *params, float *a
     if (ddf_status st = param_grads(net->width, net->depth, n, w, g_params, false, s)) return st;
     return adam_and_repack(net, params, adam_m, adam_v, g_params, step, lr, stream);
 }
+}  // namespace
+}  // namespace ddf
 
-extern "C" ddf_status ddf_train_step_chunked(const ddf_net *net, float *params, float *adam_m, float *adam_v,
-                                             int64_t step, float lr, const float *rays, const float *t_label,
-                                             int64_t n, int64_t chunk, float *loss_out, float *g_params, void *ws,
-                                             size_t ws_bytes, ddf_stream stream) {
+extern "C" ddf_status ddf_train_step(const ddf_net *net, float *params, float *adam_m, float *adam_v, int64_t step,
+                                     float lr, const float *rays, const float *t_label, int64_t n, float *loss_out,
+                                     float *g_params, void *ws, size_t ws_bytes, ddf_stream stream) {
+    return train_step_whole(net, params, adam_m, adam_v, step, lr, rays, t_label, n, LossSpec{0, 0.f}, loss_out,
+                            g_params, ws, ws_bytes, stream);
+}
+
+namespace ddf {
+namespace {
+ddf_status train_step_chunks(const ddf_net *net, float *params, float *adam_m, float *adam_v, int64_t step, float lr,
+                             const float *rays, const float *t_label, int64_t n, int64_t chunk, LossSpec ls,
+                             float *loss_out, float *g_params, void *ws, size_t ws_bytes, ddf_stream stream) {
     if (ddf_status st = check_net(net, "ddf_train_step_chunked", true)) return st;
     DDF_REQUIRE(params && adam_m && adam_v && rays && t_label && loss_out && g_params && n > 0 && chunk > 0 &&
                     step >= 1,
@@ -499,6 +536,7 @@ extern "C" ddf_status ddf_train_step_chunked(const ddf_net *net, float *params, 
         a.n = m;
         a.t_label = t_label + c0;
         a.loss_scalars = w.scalars;
+        a.loss = ls;
         a.ws_gamma = w.gamma;
         a.ws_h = w.h;
         a.ws_delta = w.delta;
@@ -509,4 +547,28 @@ extern "C" ddf_status ddf_train_step_chunked(const ddf_net *net, float *params, 
         if (ddf_status st = param_grads(net->width, net->depth, m, w, g_params, c0 > 0, s)) return st;
     }
     return adam_and_repack(net, params, adam_m, adam_v, g_params, step, lr, stream);
+}
+}  // namespace
+}  // namespace ddf
+
+extern "C" ddf_status ddf_train_step_chunked(const ddf_net *net, float *params, float *adam_m, float *adam_v,
+                                             int64_t step, float lr, const float *rays, const float *t_label,
+                                             int64_t n, int64_t chunk, float *loss_out, float *g_params, void *ws,
+                                             size_t ws_bytes, ddf_stream stream) {
+    return train_step_chunks(net, params, adam_m, adam_v, step, lr, rays, t_label, n, chunk, LossSpec{0, 0.f}, loss_out,
+                             g_params, ws, ws_bytes, stream);
+}
+
+extern "C" ddf_status ddf_train_step_ex(const ddf_net *net, float *params, float *adam_m, float *adam_v, int64_t step,
+                                        float lr, const float *rays, const float *t_label, int64_t n, int64_t chunk,
+                                        const ddf_loss *loss, float *loss_out, float *g_params, void *ws,
+                                        size_t ws_bytes, ddf_stream stream) {
+    LossSpec ls;
+    if (ddf_status st = check_loss(loss, &ls, "ddf_train_step_ex")) return st;
+    DDF_REQUIRE(chunk >= 0, DDF_ERR_INVALID_ARG, "ddf_train_step_ex: negative chunk");
+    if (chunk == 0)
+        return train_step_whole(net, params, adam_m, adam_v, step, lr, rays, t_label, n, ls, loss_out, g_params, ws,
+                                ws_bytes, stream);
+    return train_step_chunks(net, params, adam_m, adam_v, step, lr, rays, t_label, n, chunk, ls, loss_out, g_params,
+                             ws, ws_bytes, stream);
 }

@@ -29,7 +29,7 @@ def test_header_declares_the_hot_path():
     names = _declared()
     for required in ("ddf_label_rays", "ddf_forward", "ddf_backward", "ddf_render_wavefront", "ddf_pack_net",
                      "ddf_train_step", "ddf_train_step_chunked", "ddf_assemble_rays", "ddf_query",
-                     "ddf_set_tuning", "ddf_sample_dataset", "ddf_dataset_workspace_size", "ddf_udf", "ddf_udf_workspace_size"):
+                     "ddf_set_tuning", "ddf_sample_dataset", "ddf_dataset_workspace_size", "ddf_udf", "ddf_udf_workspace_size", "ddf_loss_seeds_ex", "ddf_train_step_ex"):
         assert required in names
 
 
@@ -143,6 +143,25 @@ def test_udf_validation(lib):
     assert lib.ddf_udf(ctypes.byref(net), 1, 0, None, 10, None, None, None, 0, None) == _lib.DDF_OK
     assert lib.ddf_udf(ctypes.byref(net), 1, 10, 1, 10, 1, None, 1, 64, None) == _lib.DDF_ERR_WORKSPACE
     assert b"workspace" in lib.ddf_last_error()
+
+
+def test_paper_loss_validation(lib):
+    from paper_2306_16142_amd import _lib
+    L = _lib.DdfLoss
+    big = 1 << 20
+    for bad in (L(3, 1.0), L(-1, 1.0), L(1, 0.0), L(1, -1.0), L(1, math.inf), L(1, math.nan)):
+        assert lib.ddf_loss_seeds_ex(1, 1, 1, 10, ctypes.byref(bad), 1, 1, 1, 1, big, None) == _lib.DDF_ERR_INVALID_ARG
+    assert b"loss" in lib.ddf_last_error() or b"delta" in lib.ddf_last_error()
+    f32 = _lib.DdfNet(128, 4, 0, 1)
+    assert lib.ddf_train_step_ex(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 100, 0, ctypes.byref(L(7, 1.0)), 1, 1, 1,
+                                 1 << 40, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_train_step_ex(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 100, -1, None, 1, 1, 1, 1 << 40, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    # the squish loss ignores delta; the default loss is taken for NULL
+    assert lib.ddf_loss_seeds_ex(None, 1, 1, 10, ctypes.byref(L(2, math.nan)), 1, 1, 1, 1, big, None) == \
+        _lib.DDF_ERR_INVALID_ARG   # (NULL logit)
+    assert lib.ddf_train_step_ex(ctypes.byref(_lib.DdfNet(128, 4, 1, 1)), 1, 1, 1, 1, 1e-3, 1, 1, 100, 0, None, 1, 1,
+                                 1, 1 << 40, None) == _lib.DDF_ERR_UNSUPPORTED
 
 
 def test_workspace_sizes(lib):

@@ -224,3 +224,49 @@ def test_autograd_function_matches_backward():
     ref_r, ref_p = mlp.backward(p, width, depth, host(rays.detach()), np.full(n, 0.5), 2 * ds)
     assert np.quantile(_rel(host(rays.grad), ref_r), 0.99) < 1e-4
     assert np.median(_rel(host(pg.grad), ref_p)) < 1e-4
+
+
+@pytest.mark.parametrize("loss,delta", [("clamp", 0.7), ("squish", 1.0)])
+def test_paper_loss_seeds(loss, delta):
+    """ddf_loss_seeds_ex with the clamp loss (Eq. 7) and the squish loss (Eq. 6, tanh) against
+    the oracle: no logit gradient, distance seeds sign(c(d) - c(t)) c'(d) / N."""
+    banner("loss seeds: %s (delta %g)" % (loss, delta))
+    rng = np.random.default_rng(12)
+    n = 20000 + 3
+    z = rng.normal(size=n).astype(np.float32)
+    d = (rng.normal(size=n) * 1.2).astype(np.float32)
+    t = np.where(rng.random(n) < 0.5, rng.uniform(0, 2, n), np.inf).astype(np.float32)
+    out, gl, gd = api.loss_seeds(cuda(z), cuda(d), cuda(t), loss=loss, delta=delta)
+    rl, rgd = mlp.paper_loss_and_seeds(d, t, loss, delta)
+    assert abs(host(out)[0] - rl) < 1e-5 * abs(rl)
+    assert not host(gl).any()
+    # 1 - tanh(d)^2 cancels in float32 where |d| is large: its absolute error is about two
+    # float32 ulps of 1, i.e. 2.4e-7 / N in the seed
+    np.testing.assert_allclose(host(gd), rgd, rtol=1e-5, atol=2.4e-7 / n)
+
+
+@pytest.mark.parametrize("loss,delta,chunk", [("clamp", 0.5, 0), ("squish", 1.0, 0), ("clamp", 0.5, 1500)])
+def test_train_step_paper_loss(loss, delta, chunk):
+    """A training step with the paper's loss (whole batch and in chunks) against the oracle's
+    seeds pushed through its backward pass."""
+    banner("train step %s delta %g chunk %d, 128x4 batch 4096" % (loss, delta, chunk))
+    width, depth, n = 128, 4, 4096
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    o, d, _ = synthetic.training_rays(v, f, n, 5)
+    from oracle import geometry
+    t = geometry.nearest_hit(o, d, tris)["t"].astype(np.float32)
+    rays = rays5_from(o, d)
+    p = synthetic.xavier_params(width, depth, 2)
+    tr = api.Trainer(cuda(p), width, depth, n, lr=1e-3, chunk=chunk or None, loss=loss, delta=delta)
+    out = host(tr.step(cuda(rays), cuda(t)))[0]
+    lg, ds = mlp.forward(p, width, depth, rays)
+    rl, sd = mlp.paper_loss_and_seeds(ds, t, loss, delta)
+    _, gref = mlp.backward(p, width, depth, rays, np.zeros(n), sd)
+    assert abs(out - rl) < 1e-5 * abs(rl)
+    g = host(tr.g)
+    scale = np.sqrt(np.mean(gref ** 2))
+    assert np.median(np.abs(g - gref) / np.maximum(np.abs(gref), scale)) < 1e-4
+    # the logit head's parameters (the head's first row and bias) get no gradient
+    head_w = slice(g.size - 2 * width - 2, g.size - width - 2)
+    assert not g[head_w].any() and g[-2] == 0.0
