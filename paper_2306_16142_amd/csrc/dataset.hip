@@ -11,8 +11,10 @@
 //   labeller    the pair rays, t_min = eps (the offset that steps over the own face)
 //   scan        kept flags -> positions (deterministic: block sums, one scan of the block
 //               sums, block-local scans), then the kept pair list
-//   perp        one thread per (kept pair, marching step): the two perpendicular rays
-//   labeller    the perpendicular rays, count read from the device
+//   perp        one thread per (kept pair, marching step): the line through the marching
+//               point along the polar perpendicular
+//   labeller    both rays of each line in one test per triangle (line form of the labeller),
+//               count read from the device
 //   scan        samples per (kept pair, step): 2 + free perpendiculars -> output positions
 //   emit        one thread per (kept pair, step): its 2-4 samples at their positions
 // Counts stay on the device, so the call never synchronises the host.
@@ -25,6 +27,8 @@ namespace ddf {
 ddf_status label_queue(const float *orig, const float *dir, int64_t stride, const int *idx, const int *count_dev,
                        const float *tris, int64_t m, float t_min, float t_max, float *t_out, int32_t *tri_out,
                        hipStream_t s);
+ddf_status line_queue(const float *orig, const float *dir, int64_t stride, const int *count_dev, const float *tris,
+                      int64_t m, int32_t *side_out, hipStream_t s);
 
 namespace {
 
@@ -38,13 +42,14 @@ constexpr int kTopThreads = 1024;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Workspace carve-up for P pairs and s_p steps (U = P * s_p units, 2U perpendicular rays).
+// Workspace carve-up for P pairs and s_p steps (U = P * s_p units = perpendicular lines, each
+// with a + and a - side).
 struct DsWs {
     float *o, *d, *t_exit, *th0, *th1, *t_fwd;
     int32_t *tri_fwd;
     int *cnt, *pos, *acc_idx, *bsum, *counts;   // counts: [0] kept, [1] units, [2] perp rays, [3] samples
-    float *po, *pd, *pt;
-    int32_t *ptri;
+    float *po, *pd;
+    int32_t *ptri;                              // [2U]: a hit triangle of each side, -1 = none
     size_t bytes;
 };
 
@@ -71,9 +76,8 @@ DsWs carve(int64_t P, int64_t s_p, uint8_t *base) {
     w.acc_idx = (int *)take(P * 4);
     w.bsum = (int *)take((nblk + 1) * 4);
     w.counts = (int *)take(4 * 4);
-    w.po = (float *)take(3 * R * 4);
-    w.pd = (float *)take(3 * R * 4);
-    w.pt = (float *)take(R * 4);
+    w.po = (float *)take(3 * U * 4);
+    w.pd = (float *)take(3 * U * 4);
     w.ptri = (int32_t *)take(R * 4);
     w.bytes = off;
     return w;
@@ -251,11 +255,12 @@ __device__ inline void march_point(const float *__restrict__ o, const float *__r
     for (int c = 0; c < 3; ++c) q[c] = o[c * P + i] + tk * d[c * P + i];
 }
 
-// Unit u = kept slot * s_p + (k - 1): its point and the two rays at polar angle +- pi/2.
+// Unit u = kept slot * s_p + (k - 1): its point and the line along polar angle + pi/2 (its
+// - side is the ray at - pi/2).
 __global__ void ds_perp_kernel(const int *__restrict__ acc_idx, const int *__restrict__ counts, int s_p, int64_t P,
                                const float *__restrict__ o, const float *__restrict__ d,
                                const float *__restrict__ t_exit, const float *__restrict__ th0,
-                               const float *__restrict__ th1, int64_t R, float *__restrict__ po,
+                               const float *__restrict__ th1, int64_t U, float *__restrict__ po,
                                float *__restrict__ pd) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= counts[1]) return;
@@ -269,10 +274,8 @@ __global__ void ds_perp_kernel(const int *__restrict__ acc_idx, const int *__res
     const float dp[3] = {c0 * c1, c0 * s1, -s0};   // d(theta0 + pi/2, theta1)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        po[c * R + 2 * u] = q[c];
-        po[c * R + 2 * u + 1] = q[c];
-        pd[c * R + 2 * u] = dp[c];
-        pd[c * R + 2 * u + 1] = -dp[c];
+        po[c * U + u] = q[c];
+        pd[c * U + u] = dp[c];
     }
 }
 
@@ -394,8 +397,8 @@ extern "C" ddf_status ddf_sample_dataset(const float *tris, int64_t m, const ddf
     scan(w.cnt, P, nullptr, w.pos, w.bsum, w.counts, 0, s_p, 2 * s_p, nullptr, s);
     hipLaunchKernelGGL(ds_compact_kernel, dim3(blocks_for(P, 256)), dim3(256), 0, s, w.cnt, w.pos, P, w.acc_idx);
     hipLaunchKernelGGL(ds_perp_kernel, dim3(blocks_for(U, 256)), dim3(256), 0, s, w.acc_idx, w.counts, s_p, P, w.o,
-                       w.d, w.t_exit, w.th0, w.th1, R, w.po, w.pd);
-    r = label_queue(w.po, w.pd, R, nullptr, w.counts + 2, tris, m, 0.f, INFINITY, w.pt, w.ptri, s);
+                       w.d, w.t_exit, w.th0, w.th1, U, w.po, w.pd);
+    r = line_queue(w.po, w.pd, U, w.counts + 1, tris, m, w.ptri, s);
     if (r != DDF_OK) return r;
     hipLaunchKernelGGL(ds_unit_count_kernel, dim3(blocks_for(U, 256)), dim3(256), 0, s, w.ptri, w.counts, w.cnt);
     // counts[3] = samples

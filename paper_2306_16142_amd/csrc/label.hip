@@ -50,6 +50,30 @@ __device__ __noinline__ double mt_fp64(const float *__restrict__ tris, int64_t m
     return NAN;
 }
 
+// Corner v0, edges, longest edge and the bound's scale of triangle i, for the LDS tile.
+__device__ inline TriLds stage_triangle(const float *__restrict__ tris, int64_t m, int64_t i) {
+    TriLds t;
+    t.v0x = tris[i];
+    t.v0y = tris[m + i];
+    t.v0z = tris[2 * m + i];
+    const float v1x = tris[3 * m + i], v1y = tris[4 * m + i], v1z = tris[5 * m + i];
+    const float v2x = tris[6 * m + i], v2y = tris[7 * m + i], v2z = tris[8 * m + i];
+    t.e1x = v1x - t.v0x;
+    t.e1y = v1y - t.v0y;
+    t.e1z = v1z - t.v0z;
+    t.e2x = v2x - t.v0x;
+    t.e2y = v2y - t.v0y;
+    t.e2z = v2z - t.v0z;
+    const float fx = v2x - v1x, fy = v2y - v1y, fz = v2z - v1z;
+    const float l1 = t.e1x * t.e1x + t.e1y * t.e1y + t.e1z * t.e1z;
+    const float l2 = t.e2x * t.e2x + t.e2y * t.e2y + t.e2z * t.e2z;
+    const float l3 = fx * fx + fy * fy + fz * fz;
+    t.L = sqrtf(fmaxf(l1, fmaxf(l2, l3))) * 1.0001f;
+    t.s = sqrtf(t.v0x * t.v0x + t.v0y * t.v0y + t.v0z * t.v0z) * 1.0001f + t.L;
+    t.kL = kErr * t.L;
+    return t;
+}
+
 // Output slot q reads ray idx[q] (or q) from [3][stride] arrays; only q < n (or *count_dev)
 // are processed.  Blocks past the count exit before touching LDS.
 // kTmaxInf: t_max is +inf (labels), so the far bound needs no test.
@@ -87,29 +111,7 @@ __global__ __launch_bounds__(kLabelThreads) void label_kernel(
     for (int64_t base = 0; base < m; base += kLabelTile) {
         const int cnt = (int)min<int64_t>(kLabelTile, m - base);
         __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            const int64_t i = base + threadIdx.x;
-            TriLds t;
-            t.v0x = tris[i];
-            t.v0y = tris[m + i];
-            t.v0z = tris[2 * m + i];
-            const float v1x = tris[3 * m + i], v1y = tris[4 * m + i], v1z = tris[5 * m + i];
-            const float v2x = tris[6 * m + i], v2y = tris[7 * m + i], v2z = tris[8 * m + i];
-            t.e1x = v1x - t.v0x;
-            t.e1y = v1y - t.v0y;
-            t.e1z = v1z - t.v0z;
-            t.e2x = v2x - t.v0x;
-            t.e2y = v2y - t.v0y;
-            t.e2z = v2z - t.v0z;
-            const float fx = v2x - v1x, fy = v2y - v1y, fz = v2z - v1z;
-            const float l1 = t.e1x * t.e1x + t.e1y * t.e1y + t.e1z * t.e1z;
-            const float l2 = t.e2x * t.e2x + t.e2y * t.e2y + t.e2z * t.e2z;
-            const float l3 = fx * fx + fy * fy + fz * fz;
-            t.L = sqrtf(fmaxf(l1, fmaxf(l2, l3))) * 1.0001f;
-            t.s = sqrtf(t.v0x * t.v0x + t.v0y * t.v0y + t.v0z * t.v0z) * 1.0001f + t.L;
-            t.kL = kErr * t.L;
-            s_tri[threadIdx.x] = t;
-        }
+        if ((int)threadIdx.x < cnt) s_tri[threadIdx.x] = stage_triangle(tris, m, base + threadIdx.x);
         __syncthreads();
         if (!active) continue;
         for (int k = 0; k < cnt; ++k) {
@@ -179,6 +181,89 @@ __global__ __launch_bounds__(kLabelThreads) void label_kernel(
     if (cross_out) cross_out[ray] = cross;
 }
 
+// Any hit on both rays of a line: from `orig` along +dir and along -dir (t > 0 on each side),
+// with one Moller-Trumbore test per triangle.  For -dir the float32 quantities are exactly
+// those of +dir with det and t*det negated (so u, v and |det| agree and t changes sign), and
+// the float64 re-evaluation negates exactly too, so each side's decision equals the one the
+// labeller takes for that ray on its own (t_min = 0, t_max = +inf).
+// side_out[2 q] and [2 q + 1]: the index of a triangle hit on the + and - side (the first
+// met, not the nearest), -1 where that side meets nothing; lines q < *count_dev (or stride)
+// read [3][stride] arrays.
+__global__ __launch_bounds__(kLabelThreads) void line_kernel(const float *__restrict__ orig,
+                                                             const float *__restrict__ dir, int64_t stride,
+                                                             const int *__restrict__ count_dev,
+                                                             const float *__restrict__ tris, int64_t m,
+                                                             int32_t *__restrict__ side_out) {
+    __shared__ TriLds s_tri[kLabelTile];
+    const int64_t n = count_dev ? min<int64_t>(*count_dev, stride) : stride;
+    if ((int64_t)blockIdx.x * kLabelThreads >= n) return;
+    const int64_t ray = (int64_t)blockIdx.x * kLabelThreads + threadIdx.x;
+    float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f;
+    if (ray < n) {
+        ox = orig[ray];
+        oy = orig[stride + ray];
+        oz = orig[2 * stride + ray];
+        dx = dir[ray];
+        dy = dir[stride + ray];
+        dz = dir[2 * stride + ray];
+    }
+    const bool finite = isfinite(ox) && isfinite(oy) && isfinite(oz) && isfinite(dx) && isfinite(dy) &&
+                        isfinite(dz) && (dx != 0.f || dy != 0.f || dz != 0.f);
+    const bool active = ray < n && finite;
+    const float onorm = sqrtf(ox * ox + oy * oy + oz * oz);
+    const float dnorm = sqrtf(dx * dx + dy * dy + dz * dz);
+    int32_t hit_p = -1, hit_m = -1;
+    for (int64_t base = 0; base < m; base += kLabelTile) {
+        const int cnt = (int)min<int64_t>(kLabelTile, m - base);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) s_tri[threadIdx.x] = stage_triangle(tris, m, base + threadIdx.x);
+        __syncthreads();
+        if (!active) continue;
+        for (int k = 0; k < cnt; ++k) {
+            const TriLds T = s_tri[k];
+            const float px = dy * T.e2z - dz * T.e2y;
+            const float py = dz * T.e2x - dx * T.e2z;
+            const float pz = dx * T.e2y - dy * T.e2x;
+            const float D0 = T.e1x * px + T.e1y * py + T.e1z * pz;
+            const float sx = ox - T.v0x, sy = oy - T.v0y, sz = oz - T.v0z;
+            const float qx = sy * T.e1z - sz * T.e1y;
+            const float qy = sz * T.e1x - sx * T.e1z;
+            const float qz = sx * T.e1y - sy * T.e1x;
+            const uint32_t sgn = __float_as_uint(D0) & 0x80000000u;
+            const float D = __uint_as_float(__float_as_uint(D0) ^ sgn);
+            const float U = __uint_as_float(__float_as_uint(sx * px + sy * py + sz * pz) ^ sgn);
+            const float V = __uint_as_float(__float_as_uint(dx * qx + dy * qy + dz * qz) ^ sgn);
+            const float Tq = __uint_as_float(__float_as_uint(T.e2x * qx + T.e2y * qy + T.e2z * qz) ^ sgn);
+            const float st = (onorm + T.s) * T.kL;
+            const float B = st * dnorm;
+            const float BT = st * T.L;
+            // sure miss of both sides: the line passes outside the triangle (no test on t)
+            const bool small = D <= 2.f * B;
+            const uint64_t m_small = __ballot(small);
+            const uint64_t ms = __ballot(fabsf(U) > 4.f * B) | __ballot(fabsf(V) > 4.f * B);
+            const uint64_t mb = __ballot(U < -B) | __ballot(V < -B) | __ballot(U + V > D + 3.f * B);
+            const uint64_t miss_mask = (m_small & ms) | (~m_small & mb);
+            if (__builtin_expect((__ballot(1) & ~miss_mask) == 0, 1)) continue;
+            if ((miss_mask >> __lane_id()) & 1u) continue;
+            if (hit_p >= 0 && hit_m >= 0) continue;
+            const int32_t idx = (int32_t)(base + k);
+            const bool inside = !small && U > B && V > B && U + V < D - 3.f * B;
+            if (inside && Tq > BT) {
+                if (hit_p < 0) hit_p = idx;
+            } else if (inside && Tq < -BT) {
+                if (hit_m < 0) hit_m = idx;
+            } else {   // undecided: each side in float64 from the same float32 inputs
+                if (hit_p < 0 && !isnan(mt_fp64(tris, m, idx, ox, oy, oz, dx, dy, dz, 0.0, INFINITY))) hit_p = idx;
+                if (hit_m < 0 && !isnan(mt_fp64(tris, m, idx, ox, oy, oz, -dx, -dy, -dz, 0.0, INFINITY)))
+                    hit_m = idx;
+            }
+        }
+    }
+    if (ray >= n) return;
+    side_out[2 * ray] = hit_p;
+    side_out[2 * ray + 1] = hit_m;
+}
+
 }  // namespace
 }  // namespace ddf
 
@@ -203,6 +288,15 @@ extern "C" ddf_status ddf_label_rays(const float *orig, const float *dir, int64_
 }
 
 namespace ddf {
+// Both sides of each line q < *count_dev of [3][stride] arrays (see line_kernel).
+ddf_status line_queue(const float *orig, const float *dir, int64_t stride, const int *count_dev, const float *tris,
+                      int64_t m, int32_t *side_out, hipStream_t s) {
+    const int64_t blocks = (stride + kLabelThreads - 1) / kLabelThreads;
+    hipLaunchKernelGGL(line_kernel, dim3((unsigned)blocks), dim3(kLabelThreads), 0, s, orig, dir, stride, count_dev, tris,
+                       m, side_out);
+    return launch_status("ddf labeller (lines)");
+}
+
 // Labeller over a queue: slot q < *count_dev reads ray idx[q] of [3][stride] arrays.
 ddf_status label_queue(const float *orig, const float *dir, int64_t stride, const int *idx, const int *count_dev,
                        const float *tris, int64_t m, float t_min, float t_max, float *t_out, int32_t *tri_out,

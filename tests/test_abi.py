@@ -99,9 +99,9 @@ def test_dataset_sampler_validation(lib):
     P = _lib.DdfDatasetParams
     b = ctypes.c_size_t(0)
     assert lib.ddf_dataset_workspace_size(ctypes.byref(P(10, 10, 10, 1e-4, 0, 20480)), ctypes.byref(b)) == _lib.DDF_OK
-    # pair data, perpendicular rays (origin, direction, t, triangle) and two scans, at least
+    # pair data, perpendicular lines (origin, direction, a flag per side) and two scans, at least
     pairs = 20480 * 100
-    assert b.value >= pairs * 36 + 2 * pairs * 10 * 32 + 2 * pairs * 10 * 4
+    assert b.value >= pairs * 36 + pairs * 10 * (24 + 8 + 8)
     assert lib.ddf_dataset_workspace_size(None, ctypes.byref(b)) == _lib.DDF_ERR_INVALID_ARG
     for bad in (P(0, 1, 1, 1e-4, 0, 1), P(1, 0, 1, 1e-4, 0, 1), P(1, 1, 0, 1e-4, 0, 1), P(1, 1, 1, -1.0, 0, 1),
                 P(1, 1, 1, math.nan, 0, 1), P(1, 1, 1, 1e-4, -1, 1), P(1, 1, 1, 1e-4, 0, -1)):
