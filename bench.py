@@ -346,8 +346,9 @@ def bench_multi(args, torch, api, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the hot path runs on a single MI355X here "
-              "(--gpus %d requested). See DESIGN.md for how it would shard." % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus %d requested): every ray is independent, so the "
+              "path would shard by rays, one process per GPU, with no collective in the query or render "
+              "loops; that multi-GPU launch is not built." % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 
