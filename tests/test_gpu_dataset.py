@@ -161,3 +161,40 @@ def test_dataset_full_size_sampled():
     ref = dataset.sample_dataset(tris, face_uv, dir_uv, s, s, s, 1e-4, 0, nf, amb_tol=1e-5)
     sel = pair < nf * s * s
     _compare(tris, ref, (rays[:, sel], t[sel], pair[sel]), s, s, s)
+
+
+def _restrict(ref, P):
+    """The oracle's result for pairs 0 .. P - 1 only (per-pair arrays cut, samples filtered)."""
+    out = {k: ref[k][:P] for k in ("keep", "fwd_ambiguous", "perp_free", "perp_ambiguous", "theta0", "theta1",
+                                   "t_exit")}
+    out["origin"] = ref["origin"][:, :P]
+    sel = ref["pair"] < P
+    out["rays"] = ref["rays"][:, sel]
+    for k in ("t", "pair", "kind"):
+        out[k] = ref[k][sel]
+    return out
+
+
+def test_dataset_degenerate_triangles():
+    """Zero-area triangles (a repeated corner, collinear corners) appended to a closed mesh: no
+    ray ever meets them (det = 0), so the regular faces' samples agree with the oracle as
+    usual (the degenerate faces' own pairs have no face normal to screen grazing rays with,
+    so they are left out of the comparison)."""
+    banner("dataset: icosphere with 6 degenerate triangles appended (seed 26)")
+    v, f = synthetic.icosphere(1, 0.8)
+    rng = np.random.default_rng(26)
+    deg = []
+    for _ in range(3):
+        a, b = rng.uniform(-0.5, 0.5, 3), rng.uniform(-0.5, 0.5, 3)
+        deg.append(np.concatenate([a, a, b]))                 # repeated corner
+        deg.append(np.concatenate([a, (a + b) / 2, b]))       # collinear corners
+    tris = np.concatenate([synthetic.tri_soup(v, f), np.array(deg, dtype=np.float32).T], axis=1)
+    s_fc, s_dr, s_p, eps = 2, 5, 3, 1e-4
+    face_uv, dir_uv = synthetic.dataset_uniforms(tris.shape[1], s_fc, s_dr, 26)
+    ref = dataset.sample_dataset(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps, amb_tol=1e-5)
+    rays, t, pair = _gpu(tris, face_uv, dir_uv, s_fc, s_dr, s_p, eps)
+    P_reg = f.shape[0] * s_fc * s_dr
+    sel = pair < P_reg
+    kept, _ = _compare(tris[:, :f.shape[0]], _restrict(ref, P_reg), (rays[:, sel], t[sel], pair[sel]), s_fc, s_dr,
+                       s_p)
+    assert 0.4 < kept < 0.6   # the degenerate triangles inside the sphere block nothing

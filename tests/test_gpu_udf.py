@@ -143,3 +143,22 @@ def test_udf_full_size_sampled():
     assert np.mean(np.isfinite(ref_u) == np.isfinite(u[idx])) >= 0.95
     err = np.abs(u[idx][fin] - ref_u[fin]) / np.maximum(1.0, np.abs(ref_u[fin]))
     assert np.median(err) < 2e-3
+
+
+def test_udf_nan_points_are_misses():
+    """A point with a NaN coordinate gives NaN network outputs, which no direction counts as a
+    hit: +inf and -1, on the fused (bf16) and the unfused (fp32) path alike."""
+    banner("udf: NaN points")
+    p = synthetic.random_params(128, 2, 43)
+    x, d = _inputs(70, 40, 44)
+    x[1, 5] = np.nan
+    x[0, 66] = np.nan
+    for prec in ("bf16", "fp32"):
+        net = api.Network(cuda(p), 128, 2, prec)
+        u, a = api.udf(net, cuda(x), cuda(d))
+        u, a = host(u), host(a)
+        assert np.isinf(u[[5, 66]]).all() and (a[[5, 66]] == -1).all()
+        ok = np.ones(70, bool)
+        ok[[5, 66]] = False
+        ref_u, _ = udf.udf(udf.network_field(p, 128, 2, "bf16" if prec == "bf16" else "fp64"), x[:, ok], d)
+        assert np.mean(np.isfinite(u[ok]) == np.isfinite(ref_u)) >= 0.95
