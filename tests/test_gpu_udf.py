@@ -162,3 +162,46 @@ def test_udf_nan_points_are_misses():
         ok[[5, 66]] = False
         ref_u, _ = udf.udf(udf.network_field(p, 128, 2, "bf16" if prec == "bf16" else "fp64"), x[:, ok], d)
         assert np.mean(np.isfinite(u[ok]) == np.isfinite(ref_u)) >= 0.95
+
+
+def test_sampler_and_udf_graph_replay_matches_eager():
+    """ddf_sample_dataset and the fused ddf_udf captured into one HIP graph: every replay, with
+    eager work and synchronisations between replays, equals the eager results bit for bit
+    (no host synchronisation and no memset inside either call)."""
+    banner("graph replay: dataset sampler (icosphere 80 tris) + fused udf (bf16 4x128)")
+    v, f = synthetic.icosphere(1, 0.8)
+    tris = cuda(synthetic.tri_soup(v, f))
+    fu, du = [cuda(a) for a in synthetic.dataset_uniforms(f.shape[0], 2, 4, 45)]
+    sampler = api.DatasetSampler(tris, 2, 4, 3, 1e-4)
+    p = synthetic.random_params(128, 4, 46)
+    net = api.Network(cuda(p), 128, 4, "bf16")
+    x, d = _inputs(300, 64, 47)
+    xg, dg = cuda(x), cuda(d)
+    ws = torch.empty(api.udf_workspace_bytes(300, 64), device="cuda", dtype=torch.uint8)
+    u = torch.empty(300, device="cuda")
+    a = torch.empty(300, device="cuda", dtype=torch.int32)
+
+    def work():
+        sampler.run(fu, du)
+        api.udf(net, xg, dg, out=u, arg=a, workspace=ws)
+
+    work()   # eager, also keeps one-time launch setup outside the capture
+    torch.cuda.synchronize()
+    n = int(sampler.count.item())
+    ref = [sampler.rays[:, :n].clone(), sampler.t[:n].clone(), sampler.pair[:n].clone(), u.clone(), a.clone()]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        work()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        sampler.rays.fill_(-1.0)
+        u.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(sampler.count.item()) == n
+        got = [sampler.rays[:, :n], sampler.t[:n], sampler.pair[:n], u, a]
+        for r_, g_ in zip(ref, got):
+            assert torch.equal(r_, g_), rep
+        work()   # eager work between replays
+        torch.cuda.synchronize()
