@@ -270,3 +270,39 @@ def test_train_step_paper_loss(loss, delta, chunk):
     # the logit head's parameters (the head's first row and bias) get no gradient
     head_w = slice(g.size - 2 * width - 2, g.size - width - 2)
     assert not g[head_w].any() and g[-2] == 0.0
+
+
+@pytest.mark.parametrize("chunk", [None, 1500])
+def test_train_step_graph_replay_matches_eager(chunk):
+    """A training step captured into a HIP graph: four replays equal four eager steps bit for
+    bit (parameters, Adam moments, loss).  Adam's step number is a host argument, so both
+    sides run step 2 four times; eager forward queries run between the replays."""
+    banner("train step graph replay, 128x4 batch 4096, chunk %s" % chunk)
+    width, depth, n = 128, 4, 4096
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    o, d, _ = synthetic.training_rays(v, f, n, 7)
+    from oracle import geometry
+    t = cuda(geometry.nearest_hit(o, d, tris)["t"].astype(np.float32))
+    rays = cuda(rays5_from(o, d))
+    p = synthetic.xavier_params(width, depth, 3)
+    eager = api.Trainer(cuda(p), width, depth, n, chunk=chunk)
+    graph = api.Trainer(cuda(p), width, depth, n, chunk=chunk)
+    for tr in (eager, graph):   # step 1, eager on both (one-time launch setup outside the capture)
+        tr.step(rays, t)
+    torch.cuda.synchronize()
+    graph.step_count = 1
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        graph.step(rays, t)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        eager.step_count = 1
+        eager.step(rays, t)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(eager.params, graph.params), rep
+        assert torch.equal(eager.m, graph.m) and torch.equal(eager.v, graph.v), rep
+        assert torch.equal(eager.loss, graph.loss), rep
+        eager.net.forward(rays)   # eager work between replays
+        torch.cuda.synchronize()
