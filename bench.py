@@ -154,6 +154,23 @@ def bench_udf(args, torch, api, dev, net, radius):
                     "abs_err_vs_icosphere_udf_mean_all": float(np.abs(uh[fin] - true_u[fin]).mean())}}
 
 
+def bench_eikonal(torch, api, dev, net, o_g, d_g, rays):
+    """How far the trained network is from the directed Eikonal equation (Sec. III-A, Eq. 2):
+    along its own ray the distance falls at unit rate, grad_x phi . d = -1 where the ray hits.
+    The input gradient of the distance comes from ddf_backward; sampled rays, hits only."""
+    idx = torch.arange(0, rays.shape[1], max(1, rays.shape[1] // 65536), device=dev)[:65536]
+    sub = rays[:, idx].contiguous()
+    logit, _ = net(sub)
+    g_rays, _ = api.backward(net, sub, None, torch.ones(sub.shape[1], device=dev))
+    d = d_g[:, idx]
+    d = d / d.norm(dim=0, keepdim=True)
+    r = (g_rays[:3] * d).sum(dim=0) + 1.0
+    hit = logit > 0
+    ra = r[hit].abs()
+    return {"rays": int(hit.sum()), "abs_residual_mean": float(ra.mean()), "abs_residual_median": float(ra.median()),
+            "fraction_below_0.1": float((ra < 0.1).float().mean())}
+
+
 def bench_dataset(args, torch, api, dev):
     """Training-data sampler of Sec. V-B (Eqs. 8-12) on the 20,480-triangle mesh."""
     import synthetic
@@ -476,6 +493,7 @@ def main():
         extra.update(bench_multi(args, torch, api, dev))
         extra.update(bench_dataset(args, torch, api, dev))
         extra.update(bench_udf(args, torch, api, dev, nets["bf16"], 0.8))
+        extra["eikonal_fp32"] = bench_eikonal(torch, api, dev, nets["fp32"], o_g, d_g, rays)
     if not args.quick:
         # the float64 oracle on the host cores, bounded sample of the same query workload
         from oracle import mlp
