@@ -266,6 +266,27 @@ def paper_loss_and_seeds(dist, t, kind, delta=1.0):
     return loss, np.sign(cd - ct) * dc / n
 
 
+def eikonal_loss_and_seeds(dist_a, dist_b, t, h, lam):
+    """Directed Eikonal penalty (Sec. III-A, Eq. 2) with the derivative along the ray taken as
+    a forward difference: r = (phi(x + h d) - phi(x)) / h + 1, which Eq. 2 makes 0.
+
+    dist_a, dist_b: the network's distances at x and at x + h d (same direction); the penalty
+    lam / N * sum r^2 runs over the N rays, counting those whose label is a hit farther than h
+    (t finite, t > h: x + h d is still in front of the surface).  Returns (loss, g_a, g_b) with
+    g_a = -2 lam r / (N h), g_b = +2 lam r / (N h) on counted rays, 0 elsewhere.
+    Pinned by an analytic plane field (r = 0 exactly) and central differences in the tests.
+    """
+    a = np.asarray(dist_a, dtype=np.float64)
+    b = np.asarray(dist_b, dtype=np.float64)
+    tt = np.asarray(t, dtype=np.float64)
+    n = a.size
+    on = np.isfinite(tt) & (tt > h)
+    r = np.where(on, (b - a) / h + 1.0, 0.0)
+    loss = lam * np.sum(r * r) / n if n else 0.0
+    g = 2.0 * lam * r / (n * h)
+    return loss, -g, g
+
+
 def backward(params, width, depth, rays, g_logit, g_dist):
     """Reverse-mode gradient of sum(g_logit * logit + g_dist * dist).
 

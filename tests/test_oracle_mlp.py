@@ -375,3 +375,38 @@ def test_paper_losses_closed_form_and_differences():
             dm[i] -= h
             fd = (mlp.paper_loss_and_seeds(dp, t, kind, delta)[0] - mlp.paper_loss_and_seeds(dm, t, kind, delta)[0]) / (2 * h)
             assert abs(fd - g[i]) < 1e-7, (kind, i, fd, g[i])
+
+
+def test_eikonal_penalty_plane_field_and_differences():
+    """Eq. 2 on an analytic field: for the plane z = 0 seen from above, phi(x, d) = -x_z / d_z
+    for d_z < 0, and phi(x + h d) - phi(x) = -h exactly, so the residual vanishes; then
+    central differences of the penalty against its seeds."""
+    rng = np.random.default_rng(9)
+    n, h = 500, 0.05
+    x = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(0.2, 1, n)])
+    d = rng.normal(size=(3, n))
+    d[2] = -np.abs(d[2]) - 0.2
+    d /= np.linalg.norm(d, axis=0)
+    phi = lambda p: -p[2] / d[2]
+    t = phi(x)
+    loss, ga, gb = mlp.eikonal_loss_and_seeds(phi(x), phi(x + h * d), t, h, 0.3)
+    assert loss < 1e-24 and np.abs(ga).max() < 1e-12
+    # rays whose label is a miss or closer than h do not count
+    a = rng.normal(size=n)
+    b = a - h + rng.normal(size=n) * 0.01
+    t = np.where(rng.random(n) < 0.3, np.inf, rng.uniform(0, 0.1, n))
+    loss, ga, gb = mlp.eikonal_loss_and_seeds(a, b, t, h, 0.3)
+    off = ~(np.isfinite(t) & (t > h))
+    assert not ga[off].any() and not gb[off].any()
+    eps = 1e-6
+    for i in range(0, n, 23):
+        ap, am = a.copy(), a.copy()
+        ap[i] += eps
+        am[i] -= eps
+        fd = (mlp.eikonal_loss_and_seeds(ap, b, t, h, 0.3)[0] - mlp.eikonal_loss_and_seeds(am, b, t, h, 0.3)[0]) / (2 * eps)
+        assert abs(fd - ga[i]) < 1e-7
+        bp, bm = b.copy(), b.copy()
+        bp[i] += eps
+        bm[i] -= eps
+        fd = (mlp.eikonal_loss_and_seeds(a, bp, t, h, 0.3)[0] - mlp.eikonal_loss_and_seeds(a, bm, t, h, 0.3)[0]) / (2 * eps)
+        assert abs(fd - gb[i]) < 1e-7
