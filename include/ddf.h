@@ -306,6 +306,24 @@ ddf_status ddf_train_step_ex(const ddf_net *net, float *params, float *adam_m, f
                              const ddf_loss *loss, float *loss_out, float *g_params, void *ws, size_t ws_bytes,
                              ddf_stream stream);
 
+/* A training step with the directed Eikonal penalty of Eq. 2 (Sec. III-A): along its own ray
+ * the field falls at unit rate (grad_x phi . d = -1 where the ray hits).  The derivative is
+ * taken as a forward difference along the ray, r = (phi(x + h d) - phi(x)) / h + 1, and the
+ * loss is `loss`'s (NULL: DDF_LOSS_BCE_L1) on the rays plus lambda / n * sum r^2 over rays
+ * whose label is a hit farther than h.  The batch is doubled internally (the rays at their
+ * origins and moved by h along their unit direction), so the gradient needs first-order
+ * passes only: forward of both halves, seeds, one parameter-gradient sweep, Adam, repack.
+ *   orig, dir [3][n] origins and directions (any non-zero length; normalised for the move);
+ *   t_label [n] labels (+inf = miss); loss_out: device scalar (both terms, before the update);
+ *   ws: ddf_eikonal_workspace_size(width, depth, n) bytes.
+ * Float32 networks only.  Errors: INVALID_ARG for a bad argument, h <= 0 or not finite,
+ * lambda < 0 or not finite, a bad loss; WORKSPACE when ws is too small. */
+ddf_status ddf_eikonal_workspace_size(int32_t width, int32_t depth, int64_t n, size_t *bytes);
+ddf_status ddf_train_step_eikonal(const ddf_net *net, float *params, float *adam_m, float *adam_v, int64_t step,
+                                  float lr, const float *orig, const float *dir, const float *t_label, int64_t n,
+                                  float h, float lambda, const ddf_loss *loss, float *loss_out, float *g_params,
+                                  void *ws, size_t ws_bytes, ddf_stream stream);
+
 /* ---------------------------------------------------------------- renderer
  * Wavefront path tracer of Fig. 1 in which the nearest-hit search is either the
  * brute-force triangle search (backend MESH) or the network (backend NET): the

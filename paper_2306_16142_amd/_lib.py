@@ -82,6 +82,9 @@ SIGNATURES = {
     "ddf_loss_seeds_ex": [c_p, c_p, c_p, c_i64, ctypes.POINTER(DdfLoss), c_p, c_p, c_p, c_p, c_sz, c_p],
     "ddf_train_step_ex": [ctypes.POINTER(DdfNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64, c_i64,
                           ctypes.POINTER(DdfLoss), c_p, c_p, c_p, c_sz, c_p],
+    "ddf_eikonal_workspace_size": [c_i32, c_i32, c_i64, ctypes.POINTER(c_sz)],
+    "ddf_train_step_eikonal": [ctypes.POINTER(DdfNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_p, c_i64, c_f, c_f,
+                               ctypes.POINTER(DdfLoss), c_p, c_p, c_p, c_sz, c_p],
     "ddf_udf_workspace_size": [c_i64, c_i64, ctypes.POINTER(c_sz)],
     "ddf_udf": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_sz, c_p],
     "ddf_dataset_workspace_size": [ctypes.POINTER(DdfDatasetParams), ctypes.POINTER(c_sz)],

@@ -241,6 +241,24 @@ class Trainer:
         return self.loss
 
 
+    def step_eikonal(self, orig, dirs, t_label, h=0.02, lam=0.1):
+        """One step with the directed Eikonal penalty of Eq. 2 added (forward difference along
+        each ray with step ``h``, weight ``lam``): rays given as origins + directions."""
+        _dev(orig, torch.float32, "orig", 3)
+        _dev(dirs, torch.float32, "dirs", 3)
+        _dev(t_label, torch.float32, "t_label")
+        n = orig.shape[1]
+        b = ctypes.c_size_t(0)
+        _lib.call("ddf_eikonal_workspace_size", self.net.width, self.net.depth, n, ctypes.byref(b))
+        if getattr(self, "eik_ws", None) is None or self.eik_ws.numel() < b.value:
+            self.eik_ws = torch.empty(b.value, device=orig.device, dtype=torch.uint8)
+        self.step_count += 1
+        _lib.call("ddf_train_step_eikonal", ctypes.byref(self.net.desc), _p(self.params), _p(self.m), _p(self.v),
+                  self.step_count, self.lr, _p(orig), _p(dirs), _p(t_label), n, h, lam, ctypes.byref(self.loss_desc),
+                  _p(self.loss), _p(self.g), _p(self.eik_ws), self.eik_ws.numel(), _stream())
+        return self.loss
+
+
 class DDFQuery(torch.autograd.Function):
     """torch.autograd wrapper: forward = ddf_forward, backward = ddf_backward (float32 network)."""
 

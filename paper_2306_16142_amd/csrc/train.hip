@@ -17,6 +17,7 @@
 #include "mlp_device.hpp"
 #include "mlp_layout.hpp"
 #include "grad_args.hpp"
+#include "rays_device.hpp"
 
 namespace ddf {
 
@@ -571,4 +572,137 @@ extern "C" ddf_status ddf_train_step_ex(const ddf_net *net, float *params, float
                                 ws_bytes, stream);
     return train_step_chunks(net, params, adam_m, adam_v, step, lr, rays, t_label, n, chunk, ls, loss_out, g_params,
                              ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------------------------------------ directed Eikonal
+// Training with the directed Eikonal penalty of Eq. 2 (Sec. III-A): along its own ray the
+// field falls at unit rate.  The derivative along the ray is taken as a forward difference,
+// r = (phi(x + h d) - phi(x)) / h + 1, so the step needs first-order gradients only: the batch
+// is doubled (rays at x and at x + h d), both halves go through the network, the seeds are the
+// chosen loss's on the first half plus the penalty's on both, and one backward sweep over the
+// doubled batch gives the parameter gradient.
+namespace ddf {
+namespace {
+
+// rays [5][2n]: columns 0..n-1 at the origins, n..2n-1 moved by h along the unit direction.
+__global__ void eikonal_pairs_kernel(const float *__restrict__ orig, const float *__restrict__ dir, int64_t n, float h,
+                                     float *__restrict__ rays) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float dx = dir[i], dy = dir[n + i], dz = dir[2 * n + i];
+    float theta, phi;
+    dir_angles(dx, dy, dz, theta, phi);
+    const float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+    const float d[3] = {dx * inv, dy * inv, dz * inv};
+    const int64_t m = 2 * n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float o = orig[c * n + i];
+        rays[c * m + i] = o;
+        rays[c * m + n + i] = fmaf(h, d[c], o);
+    }
+    rays[3 * m + i] = rays[3 * m + n + i] = theta;
+    rays[4 * m + i] = rays[4 * m + n + i] = phi;
+}
+
+// Adds the penalty's seeds to g_dist[0..n), writes them to g_dist[n..2n) (g_logit there 0),
+// and one partial of lam / n * sum r^2 per block.
+__global__ void eikonal_seeds_kernel(const float *__restrict__ dist, const float *__restrict__ t_label, int64_t n,
+                                     float h, float lam, float *__restrict__ g_logit, float *__restrict__ g_dist,
+                                     float *__restrict__ part) {
+    __shared__ float red[256];
+    const float inv_n = 1.f / (float)n;
+    float acc = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float t = t_label[i];
+        const bool on = t < INFINITY && t > h;
+        const float r = on ? (dist[n + i] - dist[i]) / h + 1.f : 0.f;
+        const float g = 2.f * lam * r * inv_n / h;
+        g_dist[i] -= g;
+        g_dist[n + i] = g;
+        g_logit[n + i] = 0.f;
+        acc += lam * r * r * inv_n;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Workspace: rays [5][2n] | logit, dist, g_logit, g_dist [2n] | loss scratch | backward workspace.
+struct EikWs {
+    float *rays, *logit, *dist, *g_logit, *g_dist, *loss_ws;
+    void *bws;
+    size_t bws_bytes, bytes;
+};
+
+EikWs eik_ws(int width, int depth, int64_t n, void *base) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    EikWs w{};
+    uint8_t *b = (uint8_t *)base;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        uint8_t *p = b ? b + off : nullptr;
+        off += al(bytes);
+        return p;
+    };
+    const int64_t m = 2 * n;
+    w.rays = (float *)take(5 * m * 4);
+    w.logit = (float *)take(m * 4);
+    w.dist = (float *)take(m * 4);
+    w.g_logit = (float *)take(m * 4);
+    w.g_dist = (float *)take(m * 4);
+    w.loss_ws = (float *)take(1024 * 4 + 64);
+    w.bws_bytes = train_ws(width, depth, m, nullptr).bytes;
+    w.bws = take(w.bws_bytes);
+    w.bytes = off;
+    return w;
+}
+
+}  // namespace
+}  // namespace ddf
+
+extern "C" ddf_status ddf_eikonal_workspace_size(int32_t width, int32_t depth, int64_t n, size_t *bytes) {
+    DDF_REQUIRE(bytes && n >= 0, DDF_ERR_INVALID_ARG, "ddf_eikonal_workspace_size: bad argument");
+    *bytes = eik_ws(width, depth, n, nullptr).bytes;
+    return DDF_OK;
+}
+
+extern "C" ddf_status ddf_train_step_eikonal(const ddf_net *net, float *params, float *adam_m, float *adam_v,
+                                             int64_t step, float lr, const float *orig, const float *dir,
+                                             const float *t_label, int64_t n, float h, float lambda,
+                                             const ddf_loss *loss, float *loss_out, float *g_params, void *ws,
+                                             size_t ws_bytes, ddf_stream stream) {
+    if (ddf_status st = check_net(net, "ddf_train_step_eikonal", true)) return st;
+    LossSpec ls;
+    if (ddf_status st = check_loss(loss, &ls, "ddf_train_step_eikonal")) return st;
+    DDF_REQUIRE(params && adam_m && adam_v && orig && dir && t_label && loss_out && g_params && n > 0 && step >= 1,
+                DDF_ERR_INVALID_ARG, "ddf_train_step_eikonal: bad argument");
+    DDF_REQUIRE(std::isfinite(h) && h > 0.f && std::isfinite(lambda) && lambda >= 0.f, DDF_ERR_INVALID_ARG,
+                "ddf_train_step_eikonal: need a finite h > 0 and lambda >= 0");
+    const EikWs need = eik_ws(net->width, net->depth, n, nullptr);
+    DDF_REQUIRE(ws && ws_bytes >= need.bytes, DDF_ERR_WORKSPACE,
+                "ddf_train_step_eikonal: workspace of %zu bytes needed", need.bytes);
+    const EikWs w = eik_ws(net->width, net->depth, n, ws);
+    hipStream_t s = as_stream(stream);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(eikonal_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, orig, dir, n, h,
+                       w.rays);
+    if (ddf_status st = launch_status("ddf_train_step_eikonal")) return st;
+    if (ddf_status st = ddf_forward(net, w.rays, 2 * n, w.logit, w.dist, stream)) return st;
+    if (ddf_status st = ddf_loss_seeds_ex(w.logit, w.dist, t_label, n, loss, w.g_logit, w.g_dist, loss_out,
+                                          w.loss_ws, 1024 * 4 + 64, stream))
+        return st;
+    const unsigned eb = std::min<unsigned>(blocks, 1024);
+    hipLaunchKernelGGL(eikonal_seeds_kernel, dim3(eb), dim3(256), 0, s, w.dist, t_label, n, h, lambda, w.g_logit,
+                       w.g_dist, w.loss_ws);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, w.loss_ws, (int64_t)eb, loss_out, true);
+    if (ddf_status st = launch_status("ddf_train_step_eikonal")) return st;
+    if (ddf_status st = ddf_backward(net, w.rays, 2 * n, w.g_logit, w.g_dist, nullptr, g_params, 0u, w.bws,
+                                     w.bws_bytes, stream))
+        return st;
+    return adam_and_repack(net, params, adam_m, adam_v, g_params, step, lr, stream);
 }

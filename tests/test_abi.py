@@ -29,7 +29,7 @@ def test_header_declares_the_hot_path():
     names = _declared()
     for required in ("ddf_label_rays", "ddf_forward", "ddf_backward", "ddf_render_wavefront", "ddf_pack_net",
                      "ddf_train_step", "ddf_train_step_chunked", "ddf_assemble_rays", "ddf_query",
-                     "ddf_set_tuning", "ddf_sample_dataset", "ddf_dataset_workspace_size", "ddf_udf", "ddf_udf_workspace_size", "ddf_loss_seeds_ex", "ddf_train_step_ex"):
+                     "ddf_set_tuning", "ddf_sample_dataset", "ddf_dataset_workspace_size", "ddf_udf", "ddf_udf_workspace_size", "ddf_loss_seeds_ex", "ddf_train_step_ex", "ddf_train_step_eikonal", "ddf_eikonal_workspace_size"):
         assert required in names
 
 
@@ -162,6 +162,21 @@ def test_paper_loss_validation(lib):
         _lib.DDF_ERR_INVALID_ARG   # (NULL logit)
     assert lib.ddf_train_step_ex(ctypes.byref(_lib.DdfNet(128, 4, 1, 1)), 1, 1, 1, 1, 1e-3, 1, 1, 100, 0, None, 1, 1,
                                  1, 1 << 40, None) == _lib.DDF_ERR_UNSUPPORTED
+
+
+def test_eikonal_step_validation(lib):
+    from paper_2306_16142_amd import _lib
+    b = ctypes.c_size_t(0)
+    assert lib.ddf_eikonal_workspace_size(128, 4, 1000, ctypes.byref(b)) == _lib.DDF_OK and b.value > 2000 * 4 * 9
+    f32 = _lib.DdfNet(128, 4, 0, 1)
+    args = lambda h, lam, ws: (ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 1, 100, h, lam, None, 1, 1, 1, ws, None)
+    assert lib.ddf_train_step_eikonal(*args(0.0, 0.1, 1 << 40)) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_train_step_eikonal(*args(math.nan, 0.1, 1 << 40)) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_train_step_eikonal(*args(0.01, -1.0, 1 << 40)) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_train_step_eikonal(*args(0.01, 0.1, 16)) == _lib.DDF_ERR_WORKSPACE
+    bf = _lib.DdfNet(128, 4, 1, 1)
+    assert lib.ddf_train_step_eikonal(ctypes.byref(bf), 1, 1, 1, 1, 1e-3, 1, 1, 1, 100, 0.01, 0.1, None, 1, 1, 1,
+                                      1 << 40, None) == _lib.DDF_ERR_UNSUPPORTED
 
 
 def test_workspace_sizes(lib):

@@ -306,3 +306,39 @@ def test_train_step_graph_replay_matches_eager(chunk):
         assert torch.equal(eager.loss, graph.loss), rep
         eager.net.forward(rays)   # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("loss,h,lam", [("bce_l1", 0.02, 0.1), ("clamp", 0.05, 0.5)])
+def test_train_step_eikonal_matches_oracle(loss, h, lam):
+    """The directed Eikonal training step (Eq. 2 as a forward difference along each ray) against
+    the oracle: primary loss seeds on the rays, the penalty's seeds on the rays and on their
+    moved copies, one backward pass of the doubled batch."""
+    banner("train step eikonal: %s h=%g lam=%g, 128x4 batch 4096" % (loss, h, lam))
+    width, depth, n = 128, 4, 4096
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    o, d, _ = synthetic.training_rays(v, f, n, 9)
+    from oracle import geometry
+    t = geometry.nearest_hit(o, d, tris)["t"].astype(np.float32)
+    p = synthetic.xavier_params(width, depth, 4)
+    tr = api.Trainer(cuda(p), width, depth, n, lr=1e-3, loss=loss, delta=0.5)
+    out = host(tr.step_eikonal(cuda(o), cuda(d), cuda(t), h=h, lam=lam))[0]
+    # oracle: the rays at x and at x + h d (moved in float32 like the kernel), angles of d
+    ra = rays5_from(o, d)
+    dn = (d / np.linalg.norm(d, axis=0)).astype(np.float32)
+    rb = ra.copy()
+    rb[:3] = (o.astype(np.float32) + np.float32(h) * dn).astype(np.float32)
+    la, da = mlp.forward(p, width, depth, ra)
+    _, db = mlp.forward(p, width, depth, rb)
+    if loss == "bce_l1":
+        l0, gl, gd = mlp.loss_and_seeds(la, da, t < np.inf, t)
+    else:
+        l0, gd = mlp.paper_loss_and_seeds(da, t, loss, 0.5)
+        gl = np.zeros(n)
+    le, ga, gb = mlp.eikonal_loss_and_seeds(da, db, t, h, lam)
+    rays2 = np.concatenate([ra, rb], axis=1)
+    _, gref = mlp.backward(p, width, depth, rays2, np.concatenate([gl, np.zeros(n)]), np.concatenate([gd + ga, gb]))
+    assert le > 0 and abs(out - (l0 + le)) < 1e-4 * abs(l0 + le)
+    g = host(tr.g)
+    scale = np.sqrt(np.mean(gref ** 2))
+    assert np.median(np.abs(g - gref) / np.maximum(np.abs(gref), scale)) < 1e-3
