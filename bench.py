@@ -171,6 +171,57 @@ def bench_eikonal(torch, api, dev, net, o_g, d_g, rays):
             "fraction_below_0.1": float((ra < 0.1).float().mean())}
 
 
+def bench_eikonal_training(args, torch, api, dev, steps=1500, lam=1.0, h=0.02, batch=65536):
+    """The 4 x 128 icosphere network trained with and without the directed Eikonal penalty
+    (Eq. 2, forward difference with step h): residual |grad_x phi . d + 1|, distance error and
+    hit agreement on held-out rays, and the time per step."""
+    import synthetic
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = torch.from_numpy(synthetic.tri_soup(v, f)).to(dev)
+
+    def labelled(n, seed):
+        o, d, _ = synthetic.training_rays(v, f, n, seed)
+        og, dg = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+        t, _, cr = api.label_rays(og, dg, tris)
+        k = (cr % 2) == 0
+        og, dg, t = og[:, k].contiguous(), dg[:, k].contiguous(), t[k].contiguous()
+        return og, dg, t, api.assemble_rays(og, dg)
+
+    og, dg, t, rays = labelled(1 << 20, 1)
+    ho, hd, ht, hrays = labelled(1 << 16, 7)
+    nb = rays.shape[1] // batch
+    out = {}
+    for name, weight in (("plain", 0.0), ("eikonal", lam)):
+        tr = api.Trainer(torch.from_numpy(synthetic.xavier_params(128, 4, 0)).to(dev), 128, 4, batch)
+        timer = event_timer(torch)
+        for s in range(steps):
+            sl = slice((s % nb) * batch, (s % nb + 1) * batch)
+            batch_args = ((og[:, sl].contiguous(), dg[:, sl].contiguous(), t[sl].contiguous()) if weight
+                          else (rays[:, sl].contiguous(), t[sl].contiguous()))
+            if s == steps - 20:
+                torch.cuda.synchronize()
+            if s >= steps - 20:
+                timer.start()
+            if weight:
+                tr.step_eikonal(*batch_args, h=h, lam=weight)
+            else:
+                tr.step(*batch_args)
+            if s >= steps - 20:
+                timer.stop()
+        torch.cuda.synchronize()
+        lg, ds = tr.net(hrays)
+        g, _ = api.backward(tr.net, hrays, None, torch.ones(hrays.shape[1], device=dev))
+        r = ((g[:3] * (hd / hd.norm(dim=0, keepdim=True))).sum(0) + 1).abs()
+        hit = (lg > 0) & torch.isfinite(ht)
+        out[name] = {"lambda": weight, "eikonal_abs_residual_mean": float(r[hit].mean()),
+                     "dist_abs_err_mean_hits": float((ds[hit] - ht[hit]).abs().mean()),
+                     "hit_agreement": float(((lg > 0) == torch.isfinite(ht)).float().mean()),
+                     "ms_per_step": timer.mean_ms()}
+    out["workload"] = "4 x 128 fp32, icosphere labels, batch %d, %d Adam steps, h = %g; held-out rays" % (
+        batch, steps, h)
+    return {"eikonal_training": out}
+
+
 def bench_dataset(args, torch, api, dev):
     """Training-data sampler of Sec. V-B (Eqs. 8-12) on the 20,480-triangle mesh."""
     import synthetic
@@ -494,6 +545,7 @@ def main():
         extra.update(bench_dataset(args, torch, api, dev))
         extra.update(bench_udf(args, torch, api, dev, nets["bf16"], 0.8))
         extra["eikonal_fp32"] = bench_eikonal(torch, api, dev, nets["fp32"], o_g, d_g, rays)
+        extra.update(bench_eikonal_training(args, torch, api, dev))
     if not args.quick:
         # the float64 oracle on the host cores, bounded sample of the same query workload
         from oracle import mlp
