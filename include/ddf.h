@@ -14,7 +14,9 @@
  *     inside rule (Sec. V-B);
  *   - the path tracer whose nearest-hit search the field replaces (Fig. 1);
  *   - the informative training-data sampler built on the ray shooting (Sec. V-B);
- *   - the unsigned distance field as the minimum of the field over directions (Eq. 5).
+ *   - the unsigned distance field as the minimum of the field over directions (Eq. 5);
+ *   - training with the paper's clamp / squish losses (Eqs. 6-7) and the directed Eikonal
+ *     property of the field (Eq. 2) as a penalty.
  *
  * Conventions common to every entry point
  *   Memory    Every array argument is DEVICE memory owned by the caller unless the
