@@ -94,3 +94,30 @@ def test_assemble_rays_matches_oracle_angles():
     dph = np.minimum(dph, 2 * np.pi - dph)
     assert dph.max() < 1e-6
     assert np.all((r[4] >= 0) & (r[4] < 2 * np.pi))
+
+
+def test_label_exact_ties_go_to_the_lowest_index():
+    banner("label: coincident and coplanar triangles, ties across triangle tiles")
+    rng = np.random.default_rng(11)
+    m = 700
+    # filler triangles far away (z = 5), then copies of one plane z = 0 at indices that span tiles
+    far = np.array([5, 5, 5, 6, 5, 5, 5, 6, 5], dtype=np.float32)
+    tris = np.repeat(far[:, None], m, axis=1)
+    a = np.array([0, 0, 0, 1, 0, 0, 0, 1, 0], dtype=np.float32)
+    b = np.array([-1, -1, 0, 2, -1, 0, -1, 2, 0], dtype=np.float32)
+    for i, t in ((600, a), (3, b), (300, a), (299, b)):
+        tris[:, i] = t
+    # rays straight down onto points inside both triangles, with dyadic coordinates (t exact)
+    n = 257
+    o = np.zeros((3, n), dtype=np.float32)
+    o[0] = rng.integers(1, 16, n) / 64.0
+    o[1] = rng.integers(1, 16, n) / 64.0
+    o[2] = rng.integers(1, 8, n) / 4.0
+    d = np.zeros((3, n), dtype=np.float32)
+    d[2] = -1.0
+    t, tri, cr = api.label_rays(cuda(o), cuda(d), cuda(tris))
+    t, tri, cr = host(t), host(tri), host(cr)
+    np.testing.assert_array_equal(t, o[2])
+    assert np.all(tri == 3) and np.all(cr == 4)
+    ref = geometry.nearest_hit(o, d, tris)
+    np.testing.assert_array_equal(ref["tri"], tri)
