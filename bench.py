@@ -54,6 +54,29 @@ def committed_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
+def progress(msg):
+    """One line per workload on stderr (the JSON result line is the only stdout output)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for l in open("/proc/cpuinfo"):
+            if l.startswith("model name"):
+                return l.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def issued_flop_per_query(width, depth, precision):
+    """MFMA work the kernel issues per query: layer 0's 65 features padded to the operand's
+    K slots (80 in bf16, 128 in fp8), and the head's one 32-row output block (two rows used)."""
+    k0 = {"bf16": 80, "fp8": 128}[precision]
+    macs = k0 * width + (depth - 1) * width * width + 32 * width
+    return 2 * macs
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +91,8 @@ def parse():
     ap.add_argument("--render-train-steps", type=int, default=5000)
     ap.add_argument("--multi-train-steps", type=int, default=100)
     ap.add_argument("--dataset-s", type=int, default=10, help="s_fc = s_dr = s_p of the dataset sampler workload")
+    ap.add_argument("--save-params", default=None,
+                    help="write the in-run trained 4 x 128 icosphere network's float32 parameters to this .npy file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -438,9 +463,12 @@ def main():
     # the labeller, the training recipe of the 20k-triangle workload, fixed step count)
     ico_v, ico_f = synthetic.icosphere(2, 0.8)
     ico_tris = torch.from_numpy(synthetic.tri_soup(ico_v, ico_f)).to(dev)
+    progress("training the icosphere network")
     p_g, train_info = train_network(torch, api, dev, ico_v, ico_f, ico_tris, W, D, seed=0,
                                     steps=0 if args.quick else args.icosphere_train_steps)
     p = p_g.cpu().numpy()
+    if args.save_params:
+        np.save(args.save_params, p)
     rays = torch.empty((5, n), device=dev)
     logit = torch.empty(n, device=dev)
     dist = torch.empty(n, device=dev)
@@ -469,6 +497,7 @@ def main():
 
     results = {}
     for prec in (["bf16"] if args.quick else ["bf16", "fp32", "fp8"]):
+        progress("precision workload, %s" % prec)
         net = nets[prec]
         steps = args.steps if prec != "fp32" else max(3, args.steps // 4)
         # cold: first call after packing (the paper notes the first render is slower)
@@ -533,17 +562,23 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": 32 * n,
                      "kernel": "forward_kernel<bf16,128,2,lds> with ray assembly fused (ddf_query)",
-                     "algorithmic_flop_per_query": flop_per_query(W, D)},
+                     "algorithmic_flop_per_query": flop_per_query(W, D),
+                     "issued_flop_per_query": issued_flop_per_query(W, D, "bf16")},
     }
     extra = {k: v for k, v in results.items() if k != "bf16"}
     extra["icosphere_training"] = train_info
     extra["bf16"] = {k: v for k, v in bf.items() if k not in ("queries_per_s",)}
 
     if not args.quick:
+        progress("labeller, training and render workloads")
         extra.update(bench_label_train_render(args, torch, api, dev))
+        progress("multi-object render")
         extra.update(bench_multi(args, torch, api, dev))
+        progress("training-data sampler")
         extra.update(bench_dataset(args, torch, api, dev))
+        progress("unsigned distance field")
         extra.update(bench_udf(args, torch, api, dev, nets["bf16"], 0.8))
+        progress("Eikonal residual and Eikonal training")
         extra["eikonal_fp32"] = bench_eikonal(torch, api, dev, nets["fp32"], o_g, d_g, rays)
         extra.update(bench_eikonal_training(args, torch, api, dev))
     if not args.quick:
@@ -559,7 +594,10 @@ def main():
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
         line["cpu_baseline"] = {"value": ns / cpu_s, "unit": "queries/s", "cores": threads, "kind": "oracle",
                                 "sample": "float64 NumPy forward of the first 2^22 rays of the batch, in chunks "
-                                          "of 2^19 (%.1f s)" % cpu_s}
+                                          "of 2^19 (%.1f s)" % cpu_s,
+                                "cores_note": "BLAS threads used by the oracle's matrix products",
+                                "os_cpu_count": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+                                "cpu_model": cpu_model()}
     line["extra"] = extra
     print(json.dumps(line))
 

@@ -186,7 +186,7 @@ class NetworkScene:
         return hit & (t < t_max), robust
 
 
-def render(scene, cfg):
+def render(scene, cfg, pixels=None):
     """Render ``cfg`` (a ``synthetic.RenderConfig``) with a scene backend.
 
     Returns a dict: ``radiance`` [3, H, W] (mean over samples), ``depth`` [H, W]
@@ -194,11 +194,18 @@ def render(scene, cfg):
     on a miss), ``robust`` [H, W] (every query of every sample of the pixel was
     decided away from its threshold), and ``active`` per bounce (number of
     paths that entered the bounce).
+
+    ``pixels``: optional flat pixel indices (row * W + column).  Only those pixels
+    are traced (every path is independent, so each one is traced exactly as in the
+    whole frame) and the per-pixel arrays come back as [3, len] / [len] in that
+    order; ``active`` then counts the paths of those pixels only.
     """
     W, H, S = cfg.width, cfg.height, cfg.spp
-    P = W * H * S
+    pix = np.arange(W * H, dtype=np.int64) if pixels is None else np.asarray(pixels, dtype=np.int64)
+    npx = pix.size
+    P = npx * S
     pid = np.arange(P, dtype=np.int64)
-    pixel = pid // S
+    pixel = pix[pid // S]
     sample = pid % S
     keys = path_keys(cfg.seed, pixel, sample)
     o, d = camera_rays(cfg, pixel, sample, keys)
@@ -267,12 +274,13 @@ def render(scene, cfg):
             alive[idx[die]] = False
             keep = idx[~die]
             thr[:, keep] /= q[~die][None]
-    rad = L.reshape(3, H * W, S).mean(axis=2).reshape(3, H, W)
+    shape = (H, W) if pixels is None else (npx,)
+    rad = L.reshape(3, npx, S).mean(axis=2).reshape((3,) + shape)
     first = pid % S == 0
     return {
         "radiance": rad,
-        "depth": depth0[first].reshape(H, W),
-        "normal": normal0[:, first].reshape(3, H, W),
-        "robust": robust.reshape(H * W, S).all(axis=1).reshape(H, W),
+        "depth": depth0[first].reshape(shape),
+        "normal": normal0[:, first].reshape((3,) + shape),
+        "robust": robust.reshape(npx, S).all(axis=1).reshape(shape),
         "active": active,
     }

@@ -278,3 +278,74 @@ def test_autotune_knobs_keep_results_identical(tmp_path):
     finally:
         api.set_tuning("stream_wg_per_cu", 2)
         api.set_tuning("cull_rays_per_block", 2048)
+
+
+def test_render_mesh_full_frame_sampled_pixels():
+    """The full-render shape (1920 x 1080, 4 bounces, Russian roulette after bounce 2) at 8
+    samples per pixel: the automatic sample chunk takes all 8 samples at once, 16.6 million
+    paths per chunk, so every grid-stride loop of the render kernels runs several rounds.  A
+    64 x 64 crop across the silhouette and 4,096 pixels spread over the frame are compared per
+    pixel with the oracle tracing the same paths (the mesh backend: the icosphere)."""
+    banner("render mesh: icosphere 1920x1080 8spp 4 bounces, sampled pixels vs the oracle")
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    cfg = synthetic.full_render(spp=8)
+    W, H = cfg.width, cfg.height
+    r = api.Renderer(cfg, tris=cuda(tris))
+    r.render()
+    torch.cuda.synchronize()
+    paths = host(r.stats)
+    assert paths[0] == W * H * cfg.spp and np.all(np.diff(paths) <= 0) and paths[-1] > 0
+    rows, cols = np.meshgrid(np.arange(100, 164), np.arange(928, 992), indexing="ij")   # top silhouette
+    crop = (rows * W + cols).ravel()
+    spread = np.random.default_rng(8).choice(W * H, 4096, replace=False)
+    pix = np.concatenate([crop, spread])
+    ref = render.render(render.MeshScene(tris, amb_tol=1e-4), cfg, pixels=pix)
+    rob = ref["robust"]
+    assert rob.mean() > 0.9
+    rad_g = host(r.radiance).reshape(3, -1)[:, pix]
+    scale = max(ref["radiance"].max(), 1e-6)
+    assert np.abs(rad_g - ref["radiance"])[:, rob].max() <= 1e-4 * scale
+    dg, dr = host(r.depth).ravel()[pix], ref["depth"]
+    np.testing.assert_array_equal(np.isfinite(dg)[rob], np.isfinite(dr)[rob])
+    both = rob & np.isfinite(dr)
+    assert 0.2 * pix.size < both.sum() < 0.9 * pix.size   # the crop and the spread see hits and misses
+    np.testing.assert_allclose(dg[both], dr[both], rtol=1e-4, atol=1e-5)
+    ng = host(r.normal).reshape(3, -1)[:, pix][:, both]
+    assert np.min(np.sum(ng * ref["normal"][:, both], axis=0)) > 1 - 1e-3
+    lit = rob & (ref["radiance"].max(axis=0) > 0)
+    assert lit.sum() > 0.1 * pix.size
+
+
+def test_render_mesh_full_frame_multi_bounce_sampled_pixels():
+    """The full-render shape on the 20,480-triangle training mesh (three tori and a sphere,
+    concave, so paths bounce and reach the Russian roulette after bounce 2) at 2 samples per
+    pixel: 4.1 million paths in one chunk.  A 64 x 16 crop across a torus edge (background,
+    shadowed and lit surface) and 256 spread pixels are compared per pixel with the oracle."""
+    banner("render mesh: 20480-triangle mesh 1920x1080 2spp 4 bounces, sampled pixels vs the oracle")
+    v, f = synthetic.training_mesh(1)
+    tris = synthetic.tri_soup(v, f)
+    cfg = synthetic.full_render(spp=2)
+    W, H = cfg.width, cfg.height
+    r = api.Renderer(cfg, tris=cuda(tris))
+    r.render()
+    torch.cuda.synchronize()
+    paths = host(r.stats)
+    assert paths[0] == W * H * cfg.spp and np.all(np.diff(paths) <= 0) and paths[3] > 0
+    rows, cols = np.meshgrid(np.arange(168, 184), np.arange(430, 494), indexing="ij")
+    pix = np.concatenate([(rows * W + cols).ravel(), np.random.default_rng(9).choice(W * H, 256, replace=False)])
+    ref = render.render(render.MeshScene(tris, amb_tol=1e-4), cfg, pixels=pix)
+    assert ref["active"][3] > 0   # some sampled paths reach the last bounce
+    rob = ref["robust"]
+    assert rob.mean() > 0.9
+    rad_g = host(r.radiance).reshape(3, -1)[:, pix]
+    scale = max(ref["radiance"].max(), 1e-6)
+    assert np.abs(rad_g - ref["radiance"])[:, rob].max() <= 1e-4 * scale
+    dg, dr = host(r.depth).ravel()[pix], ref["depth"]
+    np.testing.assert_array_equal(np.isfinite(dg)[rob], np.isfinite(dr)[rob])
+    both = rob & np.isfinite(dr)
+    assert both.sum() > 0.3 * pix.size
+    np.testing.assert_allclose(dg[both], dr[both], rtol=1e-4, atol=1e-5)
+    ng = host(r.normal).reshape(3, -1)[:, pix][:, both]
+    assert np.min(np.sum(ng * ref["normal"][:, both], axis=0)) > 1 - 1e-3
+    assert (rob & (ref["radiance"].max(axis=0) > 0)).sum() > 50

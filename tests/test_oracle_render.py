@@ -171,3 +171,21 @@ def test_multi_rigid_motion_of_the_whole_scene_leaves_the_image_unchanged():
     M = synthetic.scenes._rotation_from_quaternion(q / np.linalg.norm(q))
     _moved_render(nets, inst, M, np.array([0.5, -1.0, 2.0]), 1)
     _moved_render(nets, inst, np.eye(3), np.array([0.5, -1.0, 2.0]), 3)
+
+
+def test_pixel_subset_equals_whole_frame():
+    """Tracing only listed pixels gives those pixels' values of the whole frame bit for bit
+    (paths are independent and every random number is keyed by pixel and sample), with
+    jitter, several bounces and Russian roulette."""
+    v, f = synthetic.icosphere(1, 0.8)
+    cfg = synthetic.RenderConfig(20, 14, 3, 4, 1, 5)
+    scene = render.MeshScene(synthetic.tri_soup(v, f))
+    whole = render.render(scene, cfg)
+    pix = np.array([279, 0, 141, 150, 151, 37, 200, 141])   # any order, repeats allowed
+    part = render.render(scene, cfg, pixels=pix)
+    r, c = pix // cfg.width, pix % cfg.width
+    np.testing.assert_array_equal(part["radiance"], whole["radiance"][:, r, c])
+    np.testing.assert_array_equal(part["depth"], whole["depth"][r, c])
+    np.testing.assert_array_equal(part["normal"], whole["normal"][:, r, c])
+    np.testing.assert_array_equal(part["robust"], whole["robust"][r, c])
+    assert whole["radiance"][:, r, c].max() > 0 and np.isfinite(whole["depth"][r, c]).any()
