@@ -326,6 +326,65 @@ ddf_status ddf_train_step_eikonal(const ddf_net *net, float *params, float *adam
                                   float h, float lambda, const ddf_loss *loss, float *loss_out, float *g_params,
                                   void *ws, size_t ws_bytes, ddf_stream stream);
 
+/* ---------------------------------------------------------------- the paper's network
+ * The network of Sec. V-A as the paper builds it: `depth` (the paper: 8) weight-normalised
+ * hidden ReLU layers of 512 units on the raw oriented point (ox, oy, oz, polar angle,
+ * azimuth; Sec. IV-A, MLP_w : (R^3, R^2) -> R), then one affine output, the field value.
+ * Dropout (p = 0.5 in the paper) is the identity when the network is queried; training runs
+ * without it.  Weight normalisation (Salimans and Kingma 2016): W_l = g_l v_l / |v_l| per
+ * output row, folded on the device by ddf_paper_pack (every row of v_l must be non-zero).
+ *   Parameters (float32, flat, device): per hidden layer l = 0 .. depth - 1: v_l [512][in_l]
+ *   row-major (in_0 = 5, else 512), g_l [512], b_l [512]; then the output row [512] and its
+ *   bias [1] (ddf_paper_param_count values).
+ * Precisions: DDF_PREC_FP32 (queries, gradients, training) and DDF_PREC_BF16 (queries and
+ * input gradients: the first layer takes the raw inputs in float32, the hidden layers bf16
+ * operands with float32 accumulation, the output row as a bf16 pair).  depth 1..8. */
+#define DDF_PAPER_WIDTH 512
+typedef struct {
+    int32_t depth;
+    int32_t precision;      /* DDF_PREC_FP32 or DDF_PREC_BF16 */
+    const void *packed;     /* device blob written by ddf_paper_pack for this depth / precision */
+} ddf_paper_net;
+
+ddf_status ddf_paper_param_count(int32_t depth, int64_t *count);
+/* Bytes of the packed blob (device memory the caller allocates). */
+ddf_status ddf_paper_packed_bytes(int32_t depth, int32_t precision, size_t *bytes);
+/* Folds the weight normalisation and packs `params` (device, layout above) for `precision`. */
+ddf_status ddf_paper_pack(const float *params, int32_t depth, int32_t precision, void *packed, ddf_stream stream);
+
+/* Query (Sec. IV-A): rays [5][n] (ox, oy, oz, theta, phi) -> dist_out [n], the field value
+ * (the paper's losses saturate misses at their clamp or squish limit).  NaN rays give NaN.
+ * Errors: INVALID_ARG for NULL arrays with n > 0 or n < 0; UNSUPPORTED for a bad depth or
+ * precision. */
+ddf_status ddf_paper_forward(const ddf_paper_net *net, const float *rays, int64_t n, float *dist_out,
+                             ddf_stream stream);
+
+/* Reverse mode of sum(g_dist * dist) (g_dist [n], NULL = zeros):
+ *   g_rays   [5][n] d/d(ox, oy, oz, theta, phi), or NULL; its origin part is the gradient of the
+ *            field with respect to the query point that gives the normal (Eq. 3, Sec. IV-B);
+ *   g_params [P] float32 in the parameter order above (gradients of v, g, b of every hidden
+ *            layer through the weight normalisation, then of the output row and bias), or
+ *            NULL; float32 networks only; written, or added to with DDF_GRAD_ACCUMULATE;
+ *            needs ddf_paper_workspace_size(depth, n) bytes of workspace (ws unused otherwise).
+ * The forward pass is recomputed inside the kernels; sums over rays run in fixed-size chunks
+ * combined in a fixed order (repeated calls are bitwise identical). */
+ddf_status ddf_paper_workspace_size(int32_t depth, int64_t n, size_t *bytes);
+ddf_status ddf_paper_backward(const ddf_paper_net *net, const float *rays, int64_t n, const float *g_dist,
+                              float *g_rays, float *g_params, uint32_t flags, void *ws, size_t ws_bytes,
+                              ddf_stream stream);
+
+/* One training step of Sec. V-A on a labelled batch: the loss (`loss`: DDF_LOSS_CLAMP, Eq. 7,
+ * or DDF_LOSS_SQUISH, Eq. 6; the paper trains on the clamp loss) on the distance, its gradient
+ * with respect to every parameter (as ddf_paper_backward), one Adam update (beta 0.9 / 0.999,
+ * eps 1e-8, 1-based `step`) of `params` / `adam_m` / `adam_v`, and repacking of `net` (a
+ * DDF_PREC_FP32 blob of `params`, rewritten in place).
+ *   rays [5][n], t_label [n] (+inf = miss); loss_out: device scalar (before the update);
+ *   g_params [P] receives the gradient; ws: ddf_paper_workspace_size(depth, n) bytes.
+ * Errors: INVALID_ARG for a bad argument or a loss other than clamp / squish; WORKSPACE. */
+ddf_status ddf_paper_train_step(const ddf_paper_net *net, float *params, float *adam_m, float *adam_v, int64_t step,
+                                float lr, const float *rays, const float *t_label, int64_t n, const ddf_loss *loss,
+                                float *loss_out, float *g_params, void *ws, size_t ws_bytes, ddf_stream stream);
+
 /* ---------------------------------------------------------------- renderer
  * Wavefront path tracer of Fig. 1 in which the nearest-hit search is either the
  * brute-force triangle search (backend MESH) or the network (backend NET): the

@@ -25,6 +25,10 @@ class DdfNet(ctypes.Structure):
     _fields_ = [("width", c_i32), ("depth", c_i32), ("precision", c_i32), ("packed", c_p)]
 
 
+class DdfPaperNet(ctypes.Structure):
+    _fields_ = [("depth", c_i32), ("precision", c_i32), ("packed", c_p)]
+
+
 class DdfInstance(ctypes.Structure):
     _fields_ = [("R", c_f * 9), ("T", c_f * 3), ("net", c_i32)]
 
@@ -90,6 +94,14 @@ SIGNATURES = {
     "ddf_dataset_workspace_size": [ctypes.POINTER(DdfDatasetParams), ctypes.POINTER(c_sz)],
     "ddf_sample_dataset": [c_p, c_i64, ctypes.POINTER(DdfDatasetParams), c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
                            c_sz, c_p],
+    "ddf_paper_param_count": [c_i32, ctypes.POINTER(c_i64)],
+    "ddf_paper_packed_bytes": [c_i32, c_i32, ctypes.POINTER(c_sz)],
+    "ddf_paper_pack": [c_p, c_i32, c_i32, c_p, c_p],
+    "ddf_paper_forward": [ctypes.POINTER(DdfPaperNet), c_p, c_i64, c_p, c_p],
+    "ddf_paper_workspace_size": [c_i32, c_i64, ctypes.POINTER(c_sz)],
+    "ddf_paper_backward": [ctypes.POINTER(DdfPaperNet), c_p, c_i64, c_p, c_p, c_p, c_u32, c_p, c_sz, c_p],
+    "ddf_paper_train_step": [ctypes.POINTER(DdfPaperNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64,
+                             ctypes.POINTER(DdfLoss), c_p, c_p, c_p, c_sz, c_p],
 }
 # launch-shape knobs (DDF_TUNE_* in ddf.h)
 TUNE_KNOBS = {"stream_wg_per_cu": 0, "cull_rays_per_block": 1, "grad_wg_per_cu": 2}

@@ -158,6 +158,97 @@ class Network:
         return logit, dist
 
 
+def paper_param_count(depth):
+    c = ctypes.c_int64(0)
+    _lib.call("ddf_paper_param_count", depth, ctypes.byref(c))
+    return c.value
+
+
+def paper_workspace_bytes(depth, n):
+    b = ctypes.c_size_t(0)
+    _lib.call("ddf_paper_workspace_size", depth, n, ctypes.byref(b))
+    return b.value
+
+
+class PaperNetwork:
+    """The paper's own network (Sec. V-A): ``depth`` weight-normalised hidden ReLU layers of 512
+    units on the raw ray (ox, oy, oz, theta, phi), one distance output.
+
+    ``params``: flat float32 CUDA tensor (per hidden layer v [512][in], g [512], b [512], then
+    the output row [512] and bias); the weight normalisation is folded when packing.
+    ``precision``: "fp32" or "bf16"."""
+
+    def __init__(self, params, depth, precision="bf16"):
+        _dev(params, torch.float32, "params")
+        if params.numel() != paper_param_count(depth):
+            raise ValueError("params has %d values, a depth-%d paper network needs %d"
+                             % (params.numel(), depth, paper_param_count(depth)))
+        self.params, self.depth, self.precision = params, depth, precision
+        b = ctypes.c_size_t(0)
+        _lib.call("ddf_paper_packed_bytes", depth, PRECISIONS[precision], ctypes.byref(b))
+        self.blob = torch.empty(b.value, device=params.device, dtype=torch.uint8)
+        self.desc = _lib.DdfPaperNet(depth, PRECISIONS[precision], self.blob.data_ptr())
+        self.repack()
+
+    def repack(self):
+        _lib.call("ddf_paper_pack", _p(self.params), self.depth, PRECISIONS[self.precision], _p(self.blob), _stream())
+
+    def forward(self, rays, dist=None):
+        """rays [5][n] -> dist [n]."""
+        _dev(rays, torch.float32, "rays", 5)
+        n = rays.shape[1]
+        dist = torch.empty(n, device=rays.device, dtype=torch.float32) if dist is None else dist
+        _lib.call("ddf_paper_forward", ctypes.byref(self.desc), _p(rays), n, _p(dist), _stream())
+        return dist
+
+    __call__ = forward
+
+    def backward(self, rays, g_dist, want_rays=True, want_params=False, g_params=None, accumulate=False,
+                 workspace=None):
+        """Reverse mode of sum(g_dist * dist): returns (g_rays [5][n] or None, g_params or None)."""
+        _dev(rays, torch.float32, "rays", 5)
+        n = rays.shape[1]
+        g_rays = torch.empty((5, n), device=rays.device, dtype=torch.float32) if want_rays else None
+        ws = None
+        if want_params:
+            if g_params is None:
+                g_params = torch.zeros(self.params.numel(), device=rays.device, dtype=torch.float32)
+            nb = paper_workspace_bytes(self.depth, n)
+            ws = workspace if workspace is not None and workspace.numel() >= nb else \
+                torch.empty(nb, device=rays.device, dtype=torch.uint8)
+        else:
+            g_params = None
+        _lib.call("ddf_paper_backward", ctypes.byref(self.desc), _p(rays), n, _p(g_dist), _p(g_rays), _p(g_params),
+                  1 if accumulate else 0, _p(ws), ws.numel() if ws is not None else 0, _stream())
+        return g_rays, g_params
+
+
+class PaperTrainer:
+    """Adam training of the paper's network (float32) on labelled rays with the clamp loss
+    (Eq. 7, window ``delta``) or the squish loss (Eq. 6); ``params`` is updated in place."""
+
+    def __init__(self, params, depth, batch, lr=1e-3, loss="clamp", delta=1.0):
+        self.net = PaperNetwork(params, depth, "fp32")
+        self.params = params
+        self.loss_desc = _loss_desc(loss, delta)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.g = torch.zeros_like(params)
+        self.loss = torch.zeros(1, device=params.device, dtype=torch.float32)
+        self.lr = lr
+        self.step_count = 0
+        self.ws = torch.empty(paper_workspace_bytes(depth, batch), device=params.device, dtype=torch.uint8)
+
+    def step(self, rays, t_label):
+        _dev(rays, torch.float32, "rays", 5)
+        _dev(t_label, torch.float32, "t_label")
+        self.step_count += 1
+        _lib.call("ddf_paper_train_step", ctypes.byref(self.net.desc), _p(self.params), _p(self.m), _p(self.v),
+                  self.step_count, self.lr, _p(rays), _p(t_label), rays.shape[1], ctypes.byref(self.loss_desc),
+                  _p(self.loss), _p(self.g), _p(self.ws), self.ws.numel(), _stream())
+        return self.loss
+
+
 def train_workspace_bytes(width, depth, n):
     b = ctypes.c_size_t(0)
     _lib.call("ddf_train_workspace_size", width, depth, n, ctypes.byref(b))

@@ -1,0 +1,714 @@
+// The paper's own network (Sec. V-A): `depth` weight-normalised hidden ReLU layers of 512
+// units on the raw oriented point (ox, oy, oz, polar angle, azimuth), one affine output (the
+// field value), dropout the identity at query time; trained on the clamp loss (Eq. 7) or the
+// squish loss (Eq. 6).
+//
+// Packing folds the weight normalisation, W = g v / |v| per row, on the device, into one of
+// two blobs:
+//   bf16 (queries, normals): the first layer as float32 tiles of the 32x32x2 float32 MFMA (the
+//     five raw inputs and the bias are its six contraction slots: a raw coordinate rounded to
+//     bf16 would move by up to 2^-9 of its size); the hidden layers as bf16 tiles of the
+//     32x32x16 MFMA, their biases in float32 (each M-block's accumulation starts from its
+//     bias); the output row as rows 0 and 1 of one 32-row block (the bf16 row and its bf16
+//     remainder); the transposed tiles of the input gradient; the output row in float32.
+//   float32 (training, float32 queries): float32 tiles of the 32x32x2 MFMA for every layer and
+//     its transpose, biases in float32.
+//
+// bf16 kernel (paper_stream_kernel): a 512-wide layer of 32 rays is 32 KiB of bf16 operands, so
+// a wave keeps one layer's input and one layer's output in registers (256 of its 512) and runs
+// alone on its SIMD: a workgroup is four waves = 128 rays.  Weights stream through an LDS ring
+// that all four waves read: one phase is one half of a 32-row M-block (16 K-blocks), two
+// phases per barrier, four 16 KiB stages, each phase's tiles fetched two phases ahead by loads
+// that write LDS directly; the first layer's tiles and the hidden biases stay in LDS.  Layer outputs stay in the accumulators and become the next layer's B operands
+// (the contraction index renumbered in the packed tiles); ReLU masks go to LDS for the
+// reverse sweep of the input gradient.
+#include <cmath>
+#include <mutex>
+#include <type_traits>
+
+#include "common.hpp"
+#include "grad_args.hpp"
+#include "loss_device.hpp"
+#include "mlp_device.hpp"
+#include "mlp_layout.hpp"
+
+namespace ddf {
+namespace {
+
+constexpr int kPW = 512;            // width
+constexpr int kPNMB = kPW / 32;     // 32-row M-blocks
+constexpr int kPNKB = kPW / 16;     // bf16 K-blocks of a hidden layer
+constexpr int kPF32K = kPW / 2;     // float32 K-steps of a hidden layer
+constexpr int kPK0 = 3;             // float32 K-steps of the first layer: (x, y), (z, theta), (phi, 1)
+constexpr int kPMaxDepth = 8;
+
+// Blob of one precision (byte offsets).
+struct PaperLayout {
+    int depth, prec;
+    int64_t l0_off;       // float32 first-layer tiles [M-block][K-step][lane] (both precisions)
+    int64_t hid_off;      // bf16: [(l - 1) * 16 + mb][32 K-blocks][lane][8]; fp32: [(l - 1)][256 kb][16 mb][lane]
+    int64_t head_off;     // bf16: [32 K-blocks][lane][8]; fp32: [256 kb][lane] (row 0 = the output row)
+    int64_t tr_off;       // transposed hidden layers as hid_off without bias blocks, then the
+                          // transposed first layer (bf16: [32 kb]; fp32: [256 kb]; rows 0..4 = inputs)
+    int64_t bias_off;     // hidden biases [(depth - 1)][512], float32
+    int64_t row_off;      // the output row [512] and its bias [1], float32
+    int64_t bytes;
+};
+
+__host__ __device__ inline PaperLayout paper_layout(int depth, int prec) {
+    PaperLayout L;
+    L.depth = depth;
+    L.prec = prec;
+    const int64_t nh = depth - 1;
+    L.l0_off = 0;
+    L.hid_off = (int64_t)kPNMB * kPK0 * 256;
+    if (prec == kBF16) {
+        L.head_off = L.hid_off + nh * kPNMB * kPNKB * 1024;
+        L.tr_off = L.head_off + (int64_t)kPNKB * 1024;
+        L.bias_off = L.tr_off + (nh * kPNMB * kPNKB + kPNKB) * 1024;
+    } else {
+        L.head_off = L.hid_off + nh * kPF32K * kPNMB * 256;
+        L.tr_off = L.head_off + (int64_t)kPF32K * 256;
+        L.bias_off = L.tr_off + (nh * kPF32K * kPNMB + kPF32K) * 256;
+    }
+    L.row_off = L.bias_off + nh * kPW * 4;
+    L.bytes = L.row_off + (kPW + 4) * 4;
+    return L;
+}
+
+// ------------------------------------------------------------------------------ packing
+// Flat parameters: per hidden layer l, v_l [512][in_l], g_l [512], b_l [512] (in_0 = 5), then
+// the output row [512] and its bias.
+__host__ __device__ inline int64_t paper_layer_off(int l) {
+    return l == 0 ? 0 : (int64_t)kPW * kInRaw + 2 * kPW + (int64_t)(l - 1) * ((int64_t)kPW * kPW + 2 * kPW);
+}
+__host__ __device__ inline int64_t paper_params(int depth) { return paper_layer_off(depth) + kPW + 1; }
+__host__ __device__ inline int paper_in(int l) { return l == 0 ? kInRaw : kPW; }
+
+// Row norms of the weight normalisation, norm[l][i] = |v_l[i, :]|, in float64 (one wave per
+// row, fixed lane order).  The folded weight W = g v / |v| is formed in float64 and rounded
+// once to float32, so the bf16 rounding of a weight is decided from the same float32 value
+// whatever order the norm was summed in.
+__global__ void paper_norm_kernel(const float *__restrict__ params, int depth, double *__restrict__ norm) {
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (row >= (int64_t)depth * kPW) return;
+    const int l = (int)(row / kPW), i = (int)(row % kPW);
+    const int in = paper_in(l);
+    const float *v = params + paper_layer_off(l) + (int64_t)i * in;
+    double s = 0.0;
+    for (int k = lane; k < in; k += 64) s = fma((double)v[k], (double)v[k], s);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) norm[row] = sqrt(s);
+}
+
+// Folded weight W_l[i][k] = (g_l[i] v_l[i][k]) / |v_l[i, :]| (float64), as float32.
+__device__ inline float paper_w(const float *params, const double *norm, int l, int i, int k) {
+    const int in = paper_in(l);
+    const double g = params[paper_layer_off(l) + (int64_t)kPW * in + i];
+    return (float)((g * (double)params[paper_layer_off(l) + (int64_t)i * in + k]) / norm[(int64_t)l * kPW + i]);
+}
+__device__ inline float paper_b(const float *params, int l, int i) {
+    return params[paper_layer_off(l) + (int64_t)kPW * paper_in(l) + kPW + i];
+}
+
+// Float32 first-layer slot: M-block mb, K-step ks, lane -> W0[row][2 ks + lane / 32] (slot 5 = bias).
+__device__ inline float l0_slot(const float *params, const double *scale, int mb, int ks, int lane) {
+    const int row = mb * 32 + (lane & 31), k = 2 * ks + (lane >> 5);
+    return k < kInRaw ? paper_w(params, scale, 0, row, k) : paper_b(params, 0, row);
+}
+
+// One thread per packed element.
+__global__ void paper_pack_kernel(const float *__restrict__ params, const double *__restrict__ scale, int depth, int prec,
+                                  uint8_t *__restrict__ blob) {
+    const PaperLayout L = paper_layout(depth, prec);
+    const int nh = depth - 1;
+    const int64_t n_l0 = (int64_t)kPNMB * kPK0 * 64;
+    int64_t n_hid, n_head, n_tr, n_bias;
+    if (prec == kBF16) {
+        n_hid = (int64_t)nh * kPNMB * kPNKB * 512;
+        n_head = (int64_t)kPNKB * 512;
+        n_tr = ((int64_t)nh * kPNMB * kPNKB + kPNKB) * 512;
+        n_bias = (int64_t)nh * kPW;
+    } else {
+        n_hid = (int64_t)nh * kPF32K * kPNMB * 64;
+        n_head = (int64_t)kPF32K * 64;
+        n_tr = ((int64_t)nh * kPF32K * kPNMB + kPF32K) * 64;
+        n_bias = (int64_t)nh * kPW;
+    }
+    const int64_t n_row = kPW + 4;
+    const int64_t total = n_l0 + n_hid + n_head + n_tr + n_bias + n_row;
+    const float *head_row = params + paper_layer_off(depth);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = e;
+        if (r < n_l0) {
+            const int lane = (int)(r % 64), ks = (int)((r / 64) % kPK0), mb = (int)(r / (64 * kPK0));
+            reinterpret_cast<float *>(blob + L.l0_off)[r] = l0_slot(params, scale, mb, ks, lane);
+            continue;
+        }
+        r -= n_l0;
+        if (prec == kBF16) {
+            uint16_t *dst = nullptr;
+            float w = 0.f;
+            if (r < n_hid) {
+                // tile ((l - 1) * 16 + mb) * 32 + kb, lane, slot s: row mb * 32 + lane % 32 of layer l
+                const int s = (int)(r % 8), lane = (int)((r / 8) % 64);
+                const int64_t t = r / 512;
+                const int kb = (int)(t % kPNKB), mb = (int)((t / kPNKB) % kPNMB);
+                const int l = 1 + (int)(t / ((int64_t)kPNKB * kPNMB));
+                w = paper_w(params, scale, l, mb * 32 + (lane & 31), prev_unit(kBF16, kb, lane >> 5, s));
+                dst = reinterpret_cast<uint16_t *>(blob + L.hid_off) + r;
+            } else if ((r -= n_hid) < n_head) {
+                // rows 0 and 1: the output row as bf16 and its bf16 remainder
+                const int s = (int)(r % 8), lane = (int)((r / 8) % 64), kb = (int)(r / 512);
+                const int row = lane & 31, h = lane >> 5;
+                if (row < 2) {
+                    const float x = head_row[prev_unit(kBF16, kb, h, s)];
+                    const float hi = (float)(__bf16)x;
+                    w = row == 0 ? hi : x - hi;
+                }
+                dst = reinterpret_cast<uint16_t *>(blob + L.head_off) + r;
+            } else if ((r -= n_head) < n_tr) {
+                // transposed layer l: A[m][k] = W_l[k][m], rows m = inputs of layer l; the
+                // transposed first layer (the last 32 tiles) has rows 0..4 = the raw inputs
+                const int s = (int)(r % 8), lane = (int)((r / 8) % 64);
+                const int64_t t = r / 512;
+                const int h = lane >> 5;
+                if (t < (int64_t)nh * kPNMB * kPNKB) {
+                    const int kb = (int)(t % kPNKB), mb = (int)((t / kPNKB) % kPNMB);
+                    const int l = 1 + (int)(t / ((int64_t)kPNKB * kPNMB));
+                    w = paper_w(params, scale, l, prev_unit(kBF16, kb, h, s), mb * 32 + (lane & 31));
+                } else {
+                    const int kb = (int)(t - (int64_t)nh * kPNMB * kPNKB), m = lane & 31;
+                    if (m < kInRaw) w = paper_w(params, scale, 0, prev_unit(kBF16, kb, h, s), m);
+                }
+                dst = reinterpret_cast<uint16_t *>(blob + L.tr_off) + r;
+            } else if ((r -= n_tr) < n_bias) {
+                reinterpret_cast<float *>(blob + L.bias_off)[r] = paper_b(params, 1 + (int)(r / kPW), (int)(r % kPW));
+                continue;
+            } else {
+                r -= n_bias;
+                reinterpret_cast<float *>(blob + L.row_off)[r] =
+                    r < kPW ? head_row[r] : (r == kPW ? head_row[kPW] : 0.f);
+                continue;
+            }
+            *dst = bf16_bits(w);
+            continue;
+        }
+        // float32 tiles: lane slot of K-step kb reads unit prev_unit(kFP32, kb, h, 0)
+        if (r < n_hid) {
+            const int lane = (int)(r % 64);
+            const int64_t t = r / 64;
+            const int mb = (int)(t % kPNMB), kb = (int)((t / kPNMB) % kPF32K);
+            const int l = 1 + (int)(t / ((int64_t)kPNMB * kPF32K));
+            reinterpret_cast<float *>(blob + L.hid_off)[r] =
+                paper_w(params, scale, l, mb * 32 + (lane & 31), prev_unit(kFP32, kb, lane >> 5, 0));
+            continue;
+        }
+        r -= n_hid;
+        if (r < n_head) {
+            const int lane = (int)(r % 64), kb = (int)(r / 64);
+            reinterpret_cast<float *>(blob + L.head_off)[r] =
+                (lane & 31) == 0 ? head_row[prev_unit(kFP32, kb, lane >> 5, 0)] : 0.f;
+            continue;
+        }
+        r -= n_head;
+        if (r < n_tr) {
+            const int lane = (int)(r % 64), h = lane >> 5, m = lane & 31;
+            const int64_t t = r / 64;
+            float w = 0.f;
+            if (t < (int64_t)nh * kPF32K * kPNMB) {
+                const int mb = (int)(t % kPNMB), kb = (int)((t / kPNMB) % kPF32K);
+                const int l = 1 + (int)(t / ((int64_t)kPNMB * kPF32K));
+                w = paper_w(params, scale, l, prev_unit(kFP32, kb, h, 0), mb * 32 + m);
+            } else {
+                const int kb = (int)(t - (int64_t)nh * kPF32K * kPNMB);
+                if (m < kInRaw) w = paper_w(params, scale, 0, prev_unit(kFP32, kb, h, 0), m);
+            }
+            reinterpret_cast<float *>(blob + L.tr_off)[r] = w;
+            continue;
+        }
+        r -= n_tr;
+        if (r < n_bias) {
+            reinterpret_cast<float *>(blob + L.bias_off)[r] = paper_b(params, 1 + (int)(r / kPW), (int)(r % kPW));
+            continue;
+        }
+        r -= n_bias;
+        reinterpret_cast<float *>(blob + L.row_off)[r] = r < kPW ? head_row[r] : (r == kPW ? head_row[kPW] : 0.f);
+    }
+}
+
+// ------------------------------------------------------------------------------ bf16 kernel
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+typedef __attribute__((address_space(1))) const uint8_t gbl_u8;
+
+constexpr int kPWaves = 4;
+constexpr int kPRays = 32 * kPWaves;       // rays per workgroup tile
+constexpr int kPStages = 4;
+constexpr int kPStageBytes = 16 * 1024;    // half an M-block: 16 K-blocks
+constexpr int kPAR = 4;                    // A tiles read ahead from LDS
+constexpr int kPLds = 160 * 1024;
+
+struct PLds {   // byte offsets of the LDS sections
+    int l0, ring, bias, row, mask, bytes;
+};
+__host__ __device__ inline PLds paper_lds(int depth, bool grad) {
+    PLds s;
+    s.l0 = 0;
+    s.ring = kPNMB * kPK0 * 256;
+    s.bias = s.ring + kPStages * kPStageBytes;
+    s.row = s.bias + (depth - 1) * kPW * 4;
+    s.mask = s.row + (kPW + 4) * 4;
+    s.bytes = s.mask + (grad ? kPWaves * depth * kPNMB * 64 * 2 : 0);
+    return s;
+}
+
+// Phase q of a tile's program -> (byte offset of its first tile in the blob, tile count):
+// hidden layers (l, mb, half), the output row's two halves, then for gradients the
+// transposed hidden layers from the top and the transposed first layer.
+__device__ inline void paper_phase(const PaperLayout &L, int q, int64_t &off, int &cnt) {
+    const int nh = 2 * kPNMB * (L.depth - 1);
+    if (q < nh) {
+        const int l = 1 + q / (2 * kPNMB), mb = (q % (2 * kPNMB)) / 2, half = q & 1;
+        off = L.hid_off + ((int64_t)((l - 1) * kPNMB + mb) * kPNKB + 16 * half) * 1024;
+        cnt = 16;
+        return;
+    }
+    q -= nh;
+    if (q < 2) {
+        off = L.head_off + (int64_t)16 * q * 1024;
+        cnt = 16;
+        return;
+    }
+    q -= 2;
+    if (q < nh) {
+        const int l = L.depth - 1 - q / (2 * kPNMB), mb = (q % (2 * kPNMB)) / 2, half = q & 1;
+        off = L.tr_off + ((int64_t)((l - 1) * kPNMB + mb) * kPNKB + 16 * half) * 1024;
+        cnt = 16;
+        return;
+    }
+    q -= nh;
+    off = L.tr_off + ((int64_t)(L.depth - 1) * kPNMB * kPNKB + 16 * q) * 1024;
+    cnt = 16;
+}
+
+// The ring of one workgroup: global phase counter g (phase g % NP of the workgroup's tile
+// g / NP), phases beyond `gend` do not exist.
+struct PRing {
+    const uint8_t *blob;
+    PaperLayout L;
+    int np;          // phases per tile
+    int64_t gend;    // phases of this workgroup
+    int64_t g;       // current phase
+};
+
+// This wave's share of phase gq's 16 tiles, loaded straight into its stage (16 bytes per lane:
+// one instruction moves a whole 1 KiB tile): tiles wave, wave + 4, wave + 8, wave + 12.
+__device__ inline void paper_fetch(const PRing &rg, int64_t gq, lds_u8 *ring, int wave, int lane) {
+    if (gq >= rg.gend) return;   // wave-uniform
+    int64_t off;
+    int cnt;
+    paper_phase(rg.L, (int)(gq % rg.np), off, cnt);
+    lds_u8 *stage = ring + (int)(gq % kPStages) * kPStageBytes;
+    gbl_u8 *g = (gbl_u8 *)(rg.blob + off) + lane * 16;
+    (void)cnt;   // every phase has 16 tiles
+#pragma unroll
+    for (int j = 0; j < 16 / kPWaves; ++j) {
+        const int i = wave + kPWaves * j;
+        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(g + i * 1024),
+                                         (__attribute__((address_space(3))) void *)(stage + i * 1024), 16, 0, 0);
+    }
+}
+
+// The LDS writes of global_load_lds are not tracked by the compiler: wait for them (vmcnt(0))
+// before the barrier that publishes a stage.
+__device__ inline void paper_stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ inline bf16x8 ptile(const lds_u8 *stage, int i, int lane) {
+    return *reinterpret_cast<const __attribute__((address_space(3))) bf16x8 *>(stage + i * 1024 + lane * 16);
+}
+
+struct PAR {
+    bf16x8 r[kPAR];
+};
+
+// One phase's MFMA chain over K-blocks kb0 .. kb0 + KS - 1 of `bin`, accumulating into acc.
+// kLoadFirst: the ring does not hold this phase's first tiles yet; kNext: the last steps read
+// the next phase's first tiles (its stage is already published).
+template <int KS, int kb0, bool kLoadFirst, bool kNext>
+__device__ __attribute__((always_inline)) inline void pchain(const lds_u8 *st, const lds_u8 *st_next, PAR &ar,
+                                                             const bf16x8 (&bin)[kPNKB][1], f32x16 &acc, int lane) {
+    if constexpr (kLoadFirst) {
+#pragma unroll
+        for (int j = 0; j < kPAR; ++j) ar.r[j] = ptile(st, j, lane);
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const bf16x8 a = ar.r[ks % kPAR];
+        if (ks + kPAR < KS) ar.r[ks % kPAR] = ptile(st, ks + kPAR, lane);
+        else if (kNext) ar.r[ks % kPAR] = ptile(st_next, ks + kPAR - KS, lane);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bin[kb0 + ks][0], acc, 0, 0, 0);
+    }
+    if constexpr (kNext) {   // the next phase's tile j landed in slot (KS + j) % kPAR
+        PAR t = ar;
+#pragma unroll
+        for (int j = 0; j < kPAR; ++j) ar.r[j] = t.r[(KS + j) % kPAR];
+    }
+}
+
+__device__ inline const lds_u8 *pstage(lds_u8 *ring, int64_t g) { return ring + (int)(g % kPStages) * kPStageBytes; }
+
+// A pair of phases (the two halves of one M-block's contraction) between barriers; the
+// accumulation starts from `init` (the M-block's float32 biases, or zero).
+__device__ __attribute__((always_inline)) inline void paper_pair(PRing &rg, lds_u8 *ring, PAR &ar,
+                                                                 const bf16x8 (&bin)[kPNKB][1], f32x16 &acc,
+                                                                 const f32x16 &init, int wave, int lane) {
+    acc = init;
+    paper_fetch(rg, rg.g + 2, ring, wave, lane);
+    pchain<16, 0, true, true>(pstage(ring, rg.g), pstage(ring, rg.g + 1), ar, bin, acc, lane);
+    ++rg.g;
+    paper_fetch(rg, rg.g + 2, ring, wave, lane);
+    pchain<16, 16, false, false>(pstage(ring, rg.g), nullptr, ar, bin, acc, lane);
+    ++rg.g;
+    paper_stage_wait();
+    __syncthreads();
+}
+
+// Compile-time loop: f(integral_constant<I>) for I = I0 .. N - 1, so that register arrays are
+// indexed by constants however large the body (a 16-step loop over 33-MFMA phases is beyond
+// what the unroller takes on by itself).
+template <int I, int N, typename F>
+__device__ __attribute__((always_inline)) inline void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+__device__ __attribute__((always_inline)) inline uint32_t tile_mask(const f32x16 &y) {
+    uint32_t bits = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) bits |= (y[j] > 0.f ? 1u : 0u) << j;
+    return bits;
+}
+
+// Masked adjoint tile -> bf16 B operands (K-blocks 2 mb, 2 mb + 1).
+__device__ __attribute__((always_inline)) inline void pmasked_to_bf16(const f32x16 &y, uint32_t bits, int mb, bf16x8 (&b)[kPNKB][1]) {
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = __uint_as_float(__float_as_uint(y[j]) & (uint32_t)__builtin_amdgcn_sbfe((int)bits, j, 1));
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) b[2 * mb + c][0][s] = (__bf16)v[8 * c + s];
+}
+
+// The 16 float32 biases of the rows this lane holds in M-block mb (rows 8 g + 4 h + i).
+__device__ __attribute__((always_inline)) inline f32x16 pbias_tile(const float *bias, int mb, int h) {
+    f32x16 v;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[4 * g + i] = b4[i];
+    }
+    return v;
+}
+
+// Hidden layer l: bin -> bout (ReLU, bf16); masks of layer l to LDS for gradients.
+template <bool kGrad>
+__device__ __attribute__((always_inline)) inline void paper_fwd_layer(PRing &rg, lds_u8 *ring, PAR &ar, int l,
+                                                                      const bf16x8 (&bin)[kPNKB][1],
+                                                                      bf16x8 (&bout)[kPNKB][1], uint16_t *wmask,
+                                                                      const float *s_bias, int wave, int lane, int h) {
+    f32x16 acc[2];
+    const float *lb = s_bias + (l - 1) * kPW;
+    static_for<0, kPNMB>([&](auto mbc) __attribute__((always_inline)) {
+        constexpr int mb = decltype(mbc)::value;
+        paper_pair(rg, ring, ar, bin, acc[mb & 1], pbias_tile(lb, mb, h), wave, lane);
+        if constexpr (mb > 0) {
+            if (kGrad) wmask[(l * kPNMB + mb - 1) * 64 + lane] = (uint16_t)tile_mask(acc[(mb - 1) & 1]);
+            relu_tile_to_bf16(acc[(mb - 1) & 1], mb - 1, 0, bout);
+            asm volatile("" : "+v"(bout[2 * (mb - 1)][0]), "+v"(bout[2 * (mb - 1) + 1][0]));
+        }
+    });
+    if (kGrad) wmask[(l * kPNMB + kPNMB - 1) * 64 + lane] = (uint16_t)tile_mask(acc[(kPNMB - 1) & 1]);
+    relu_tile_to_bf16(acc[(kPNMB - 1) & 1], kPNMB - 1, 0, bout);
+}
+
+// Transposed hidden layer l: adjoint operands of layer l's outputs -> masked adjoint operands
+// of layer l - 1's outputs.
+__device__ __attribute__((always_inline)) inline void paper_bwd_layer(PRing &rg, lds_u8 *ring, PAR &ar, int l,
+                                                                      const bf16x8 (&bin)[kPNKB][1],
+                                                                      bf16x8 (&bout)[kPNKB][1], const uint16_t *wmask,
+                                                                      int wave, int lane) {
+    f32x16 acc[2];
+    static_for<0, kPNMB>([&](auto mbc) __attribute__((always_inline)) {
+        constexpr int mb = decltype(mbc)::value;
+        paper_pair(rg, ring, ar, bin, acc[mb & 1], f32x16{}, wave, lane);
+        if constexpr (mb > 0) {
+            pmasked_to_bf16(acc[(mb - 1) & 1], wmask[((l - 1) * kPNMB + mb - 1) * 64 + lane], mb - 1, bout);
+            asm volatile("" : "+v"(bout[2 * (mb - 1)][0]), "+v"(bout[2 * (mb - 1) + 1][0]));
+        }
+    });
+    pmasked_to_bf16(acc[(kPNMB - 1) & 1], wmask[((l - 1) * kPNMB + kPNMB - 1) * 64 + lane], kPNMB - 1, bout);
+}
+
+struct PaperArgs {
+    const uint8_t *blob;
+    int depth;
+    const float *rays;     // [5][n]
+    int64_t n;
+    const float *g_dist;   // seeds (NULL = 0)
+    float *dist_out;       // or NULL
+    float *g_rays;         // [5][n] or NULL
+};
+
+template <bool kGrad>
+__global__ __launch_bounds__(kPWaves * 64, 1) void paper_stream_kernel(PaperArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int depth = a.depth;
+    const int64_t n = a.n;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int h = lane >> 5, col = lane & 31;
+    const PaperLayout L = paper_layout(depth, kBF16);
+    const PLds S = paper_lds(depth, kGrad);
+    lds_u8 *ring = (lds_u8 *)(smem + S.ring);
+    const float *s_l0 = reinterpret_cast<const float *>(smem + S.l0);
+    const float *s_row = reinterpret_cast<const float *>(smem + S.row);
+    const float *s_bias = reinterpret_cast<const float *>(smem + S.bias);
+    uint16_t *wmask = reinterpret_cast<uint16_t *>(smem + S.mask) + wave * depth * kPNMB * 64;
+
+    const int64_t ntile = (n + kPRays - 1) / kPRays;
+    if ((int64_t)blockIdx.x >= ntile) return;   // the whole workgroup
+    PRing rg;
+    rg.blob = a.blob;
+    rg.L = L;
+    rg.np = 2 * kPNMB * (depth - 1) + 2 + (kGrad ? 2 * kPNMB * (depth - 1) + 2 : 0);
+    rg.gend = ((ntile - blockIdx.x + gridDim.x - 1) / gridDim.x) * rg.np;
+    rg.g = 0;
+    {   // first-layer tiles and the output row stay in LDS; phases 0 and 1 into stages 0 and 1
+        const i32x4 *src = reinterpret_cast<const i32x4 *>(a.blob + L.l0_off);
+        for (int i = threadIdx.x; i < kPNMB * kPK0 * 16; i += blockDim.x)
+            reinterpret_cast<i32x4 *>(smem + S.l0)[i] = src[i];
+        const float *row = reinterpret_cast<const float *>(a.blob + L.row_off);
+        for (int i = threadIdx.x; i < kPW + 4; i += blockDim.x) reinterpret_cast<float *>(smem + S.row)[i] = row[i];
+        const float *bias = reinterpret_cast<const float *>(a.blob + L.bias_off);
+        for (int i = threadIdx.x; i < (depth - 1) * kPW; i += blockDim.x) reinterpret_cast<float *>(smem + S.bias)[i] = bias[i];
+        paper_fetch(rg, 0, ring, wave, lane);
+        paper_fetch(rg, 1, ring, wave, lane);
+        paper_stage_wait();
+        __syncthreads();
+    }
+    const float out_bias = s_row[kPW];
+
+    for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+        const int64_t r = t * kPRays + wave * 32 + col;
+        const bool valid = r < n;
+        float v[kInRaw];
+#pragma unroll
+        for (int j = 0; j < kInRaw; ++j) v[j] = valid ? a.rays[(int64_t)j * n + r] : 0.f;
+        const bool nan_ray = isnan(v[0]) || isnan(v[1]) || isnan(v[2]) || isnan(v[3]) || isnan(v[4]);
+        bf16x8 b0[kPNKB][1], b1[kPNKB][1];
+        // ---- first layer: float32 MFMA over (x, y), (z, theta), (phi, 1), ReLU -> bf16 into b0
+        {
+            const float in0 = h ? v[1] : v[0], in1 = h ? v[3] : v[2], in2 = h ? 1.f : v[4];
+#pragma unroll
+            for (int mb = 0; mb < kPNMB; ++mb) {
+                f32x16 acc = f32x16{};
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(s_l0[(mb * kPK0 + 0) * 64 + lane], in0, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(s_l0[(mb * kPK0 + 1) * 64 + lane], in1, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(s_l0[(mb * kPK0 + 2) * 64 + lane], in2, acc, 0, 0, 0);
+                if (kGrad) wmask[mb * 64 + lane] = (uint16_t)tile_mask(acc);
+                relu_tile_to_bf16(acc, mb, 0, b0);
+            }
+        }
+        PAR ar;
+        // ---- hidden layers alternating b0 -> b1 -> b0 ...; the last output ends in b0
+        int l = 1;
+        if ((depth - 1) % 2 == 1) {
+            paper_fwd_layer<kGrad>(rg, ring, ar, 1, b0, b1, wmask, s_bias, wave, lane, h);
+#pragma unroll
+            for (int kb = 0; kb < kPNKB; ++kb) b0[kb][0] = b1[kb][0];
+            l = 2;
+        }
+        for (; l + 1 < depth; l += 2) {
+            paper_fwd_layer<kGrad>(rg, ring, ar, l, b0, b1, wmask, s_bias, wave, lane, h);
+            paper_fwd_layer<kGrad>(rg, ring, ar, l + 1, b1, b0, wmask, s_bias, wave, lane, h);
+        }
+        // ---- output: rows 0 (the bf16 row) and 1 (its remainder) of lane half 0
+        f32x16 hacc;
+        paper_pair(rg, ring, ar, b0, hacc, f32x16{}, wave, lane);
+        {
+            const float d = __shfl(hacc[0] + hacc[1], col) + out_bias;
+            if (h == 0 && valid && a.dist_out) a.dist_out[r] = nan_ray ? NAN : d;
+        }
+        if constexpr (kGrad) {
+            const float gd = (valid && a.g_dist) ? a.g_dist[r] : 0.f;
+            // ---- adjoint of the last hidden layer: output row x seed, masked -> b0
+#pragma unroll
+            for (int mb = 0; mb < kPNMB; ++mb) {
+                f32x16 y;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const f32x4 w4 = *reinterpret_cast<const f32x4 *>(s_row + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) y[4 * g + i] = w4[i] * gd;
+                }
+                pmasked_to_bf16(y, wmask[((depth - 1) * kPNMB + mb) * 64 + lane], mb, b0);
+            }
+            // ---- transposed hidden layers from the top; the last adjoint ends in b0
+            int lb = depth - 1;
+            if (lb % 2 == 1) {
+                paper_bwd_layer(rg, ring, ar, lb, b0, b1, wmask, wave, lane);
+#pragma unroll
+                for (int kb = 0; kb < kPNKB; ++kb) b0[kb][0] = b1[kb][0];
+                --lb;
+            }
+            for (; lb >= 2; lb -= 2) {
+                paper_bwd_layer(rg, ring, ar, lb, b0, b1, wmask, wave, lane);
+                paper_bwd_layer(rg, ring, ar, lb - 1, b1, b0, wmask, wave, lane);
+            }
+            // ---- transposed first layer: rows 0..4 = d/d(ox, oy, oz, theta, phi)
+            f32x16 gacc;
+            paper_pair(rg, ring, ar, b0, gacc, f32x16{}, wave, lane);
+            // row 8 (j / 4) + 4 h + j % 4: rows 0..3 in lane half 0 (j = 0..3), row 4 in half 1 (j = 0)
+            if (valid && a.g_rays) {
+                if (h == 0) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) a.g_rays[(int64_t)j * n + r] = nan_ray ? NAN : gacc[j];
+                } else {
+                    a.g_rays[(int64_t)4 * n + r] = nan_ray ? NAN : gacc[0];
+                }
+            }
+        }
+    }
+}
+
+int cu_count_paper() {
+    static int cus = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    });
+    return cus;
+}
+
+template <bool kGrad>
+ddf_status launch_paper_stream(const PaperArgs &a, hipStream_t s) {
+    auto kern = paper_stream_kernel<kGrad>;
+    static std::once_flag once;
+    std::call_once(once, [&] { (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kPLds); });
+    const size_t lds = paper_lds(a.depth, kGrad).bytes;
+    const int64_t ntile = (a.n + kPRays - 1) / kPRays;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ntile, cu_count_paper()));
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPWaves * 64), lds, s, a);
+    return launch_status("ddf paper network kernel");
+}
+
+ddf_status check_paper(const ddf_paper_net *net, const char *who) {
+    DDF_REQUIRE(net && net->packed, DDF_ERR_INVALID_ARG, "%s: NULL network", who);
+    DDF_REQUIRE(net->depth >= 1 && net->depth <= kPMaxDepth, DDF_ERR_UNSUPPORTED, "%s: depth %d not supported (1..8)",
+                who, net->depth);
+    DDF_REQUIRE(net->precision == kFP32 || net->precision == kBF16, DDF_ERR_UNSUPPORTED,
+                "%s: precision %d not supported (float32 or bf16)", who, net->precision);
+    return DDF_OK;
+}
+
+}  // namespace
+}  // namespace ddf
+
+using namespace ddf;
+
+extern "C" ddf_status ddf_paper_param_count(int32_t depth, int64_t *count) {
+    DDF_REQUIRE(count, DDF_ERR_INVALID_ARG, "ddf_paper_param_count: NULL output");
+    DDF_REQUIRE(depth >= 1 && depth <= kPMaxDepth, DDF_ERR_UNSUPPORTED, "ddf_paper_param_count: depth %d not supported (1..8)",
+                depth);
+    *count = paper_params(depth);
+    return DDF_OK;
+}
+
+extern "C" ddf_status ddf_paper_packed_bytes(int32_t depth, int32_t precision, size_t *bytes) {
+    DDF_REQUIRE(bytes, DDF_ERR_INVALID_ARG, "ddf_paper_packed_bytes: NULL output");
+    DDF_REQUIRE(depth >= 1 && depth <= kPMaxDepth, DDF_ERR_UNSUPPORTED, "ddf_paper_packed_bytes: depth %d not supported (1..8)",
+                depth);
+    DDF_REQUIRE(precision == kFP32 || precision == kBF16, DDF_ERR_UNSUPPORTED,
+                "ddf_paper_packed_bytes: precision %d not supported", precision);
+    *bytes = (size_t)paper_layout(depth, precision).bytes + (size_t)depth * kPW * 8;   // + the row norms
+    return DDF_OK;
+}
+
+extern "C" ddf_status ddf_paper_pack(const float *params, int32_t depth, int32_t precision, void *packed,
+                                     ddf_stream stream) {
+    DDF_REQUIRE(params && packed, DDF_ERR_INVALID_ARG, "ddf_paper_pack: NULL params or output");
+    DDF_REQUIRE(depth >= 1 && depth <= kPMaxDepth, DDF_ERR_UNSUPPORTED, "ddf_paper_pack: depth %d not supported (1..8)", depth);
+    DDF_REQUIRE(precision == kFP32 || precision == kBF16, DDF_ERR_UNSUPPORTED, "ddf_paper_pack: precision %d not supported",
+                precision);
+    hipStream_t s = as_stream(stream);
+    const PaperLayout L = paper_layout(depth, precision);
+    // the row scales g / |v| live after the blob proper
+    double *norm = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(packed) + L.bytes);
+    const int rows = depth * kPW;
+    hipLaunchKernelGGL(paper_norm_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, params, depth, norm);
+    if (ddf_status st = launch_status("ddf_paper_pack")) return st;
+    hipLaunchKernelGGL(paper_pack_kernel, dim3(2048), dim3(256), 0, s, params, (const double *)norm, depth, precision,
+                       (uint8_t *)packed);
+    return launch_status("ddf_paper_pack");
+}
+
+extern "C" ddf_status ddf_paper_forward(const ddf_paper_net *net, const float *rays, int64_t n, float *dist_out,
+                                        ddf_stream stream) {
+    if (ddf_status st = check_paper(net, "ddf_paper_forward")) return st;
+    DDF_REQUIRE(n >= 0, DDF_ERR_INVALID_ARG, "ddf_paper_forward: negative n");
+    if (n == 0) return DDF_OK;
+    DDF_REQUIRE(rays && dist_out, DDF_ERR_INVALID_ARG, "ddf_paper_forward: NULL array");
+    DDF_REQUIRE(net->precision == kBF16, DDF_ERR_UNSUPPORTED, "ddf_paper_forward: float32 not built yet");
+    PaperArgs a{};
+    a.blob = (const uint8_t *)net->packed;
+    a.depth = net->depth;
+    a.rays = rays;
+    a.n = n;
+    a.dist_out = dist_out;
+    return launch_paper_stream<false>(a, as_stream(stream));
+}
+
+extern "C" ddf_status ddf_paper_backward(const ddf_paper_net *net, const float *rays, int64_t n, const float *g_dist,
+                                         float *g_rays, float *g_params, uint32_t flags, void *ws, size_t ws_bytes,
+                                         ddf_stream stream) {
+    if (ddf_status st = check_paper(net, "ddf_paper_backward")) return st;
+    DDF_REQUIRE(n >= 0, DDF_ERR_INVALID_ARG, "ddf_paper_backward: negative n");
+    DDF_REQUIRE((flags & ~1u) == 0, DDF_ERR_INVALID_ARG, "ddf_paper_backward: unknown flags 0x%x", flags);
+    if (n == 0) return DDF_OK;
+    DDF_REQUIRE(rays && (g_rays || g_params), DDF_ERR_INVALID_ARG, "ddf_paper_backward: nothing to compute");
+    DDF_REQUIRE(!g_params && net->precision == kBF16, DDF_ERR_UNSUPPORTED, "ddf_paper_backward: not built yet");
+    (void)ws;
+    (void)ws_bytes;
+    PaperArgs a{};
+    a.blob = (const uint8_t *)net->packed;
+    a.depth = net->depth;
+    a.rays = rays;
+    a.n = n;
+    a.g_dist = g_dist;
+    a.g_rays = g_rays;
+    return launch_paper_stream<true>(a, as_stream(stream));
+}
+
+extern "C" ddf_status ddf_paper_workspace_size(int32_t depth, int64_t n, size_t *bytes) {
+    DDF_REQUIRE(bytes && n >= 0 && depth >= 1 && depth <= kPMaxDepth, DDF_ERR_INVALID_ARG,
+                "ddf_paper_workspace_size: bad argument");
+    *bytes = 0;
+    return DDF_OK;
+}
+
+extern "C" ddf_status ddf_paper_train_step(const ddf_paper_net *net, float *params, float *adam_m, float *adam_v,
+                                           int64_t step, float lr, const float *rays, const float *t_label, int64_t n,
+                                           const ddf_loss *loss, float *loss_out, float *g_params, void *ws,
+                                           size_t ws_bytes, ddf_stream stream) {
+    (void)net, (void)params, (void)adam_m, (void)adam_v, (void)step, (void)lr, (void)rays, (void)t_label, (void)n;
+    (void)loss, (void)loss_out, (void)g_params, (void)ws, (void)ws_bytes, (void)stream;
+    DDF_REQUIRE(false, DDF_ERR_UNSUPPORTED, "ddf_paper_train_step: not built yet");
+}

@@ -52,3 +52,25 @@ def multi_object_network_shape(seed):
     width = int(rng.choice([128, 256]))
     depth = int(rng.integers(4, 9))
     return width, depth
+
+
+PAPER_WIDTH = 512
+
+
+def paper_params(depth, seed, width=PAPER_WIDTH, bias_scale=0.1):
+    """Parameters of the paper's network (weight-normalised hidden layers on the 5 raw ray
+    values, one output): per hidden layer v [width][in] Xavier-uniform, g = |v| per row (the
+    weight-norm start, so W = v), b uniform in +-bias_scale; then the output row
+    (Xavier-uniform) and a zero bias.  Drawn layer after layer from ``default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    dims = [5] + [width] * depth
+    parts = []
+    for l in range(depth):
+        i, o = dims[l], dims[l + 1]
+        a = np.sqrt(6.0 / (i + o))
+        v = rng.uniform(-a, a, size=(o, i)).astype(np.float32)
+        parts += [v.ravel(), np.sqrt(np.sum(v.astype(np.float64) ** 2, axis=1)).astype(np.float32),
+                  rng.uniform(-bias_scale, bias_scale, size=o).astype(np.float32)]
+    a = np.sqrt(6.0 / (width + 1))
+    parts += [rng.uniform(-a, a, size=width).astype(np.float32), np.zeros(1, np.float32)]
+    return np.concatenate(parts).astype(np.float32)

@@ -214,7 +214,7 @@ def test_train_step_matches_oracle():
     g = host(tr.g)
     scale = np.sqrt(np.mean(gref ** 2))
     assert np.median(np.abs(g - gref) / np.maximum(np.abs(gref), scale)) < 1e-5
-    banner("  worst per-layer gradient error %.3g" % _per_layer_close(g, gref, width, depth, 2e-4))
+    banner("  worst per-layer gradient error %.3g" % _per_layer_close(g, gref, width, depth, 1e-5))
     # the first Adam step moves every parameter by lr * sign(g) (up to eps): compare moves
     moved = host(pg) - p
     ref_moved = pnew - p
@@ -315,7 +315,7 @@ def test_train_step_paper_loss(loss, delta, chunk):
     g = host(tr.g)
     scale = np.sqrt(np.mean(gref ** 2))
     assert np.median(np.abs(g - gref) / np.maximum(np.abs(gref), scale)) < 1e-5
-    banner("  worst per-layer gradient error %.3g" % _per_layer_close(g, gref, width, depth, 2e-4))
+    banner("  worst per-layer gradient error %.3g" % _per_layer_close(g, gref, width, depth, 1e-5))
     # the logit head's parameters (the head's first row and bias) get no gradient
     head_w = slice(g.size - 2 * width - 2, g.size - width - 2)
     assert not g[head_w].any() and g[-2] == 0.0
@@ -364,8 +364,8 @@ def test_train_step_eikonal_matches_oracle(loss, h, lam):
     moved copies, one backward pass of the doubled batch.  With lam = 100 the penalty's seeds
     set the gradient almost alone, so the moved half of the batch is checked by itself.
     The seeds divide float32 distance differences by h (an error of ~1e-6 of the distance
-    becomes ~5e-5 of the residual at h = 0.02), so the per-layer bound is 1e-3, and the
-    penalty-dominated case takes h = 0.1."""
+    becomes ~5e-5 of the residual at h = 0.02), so the per-layer bound is 5e-4 (measured: up
+    to 5e-5), and the penalty-dominated case takes h = 0.1."""
     banner("train step eikonal: %s h=%g lam=%g, 128x4 batch 4096" % (loss, h, lam))
     width, depth, n = 128, 4, 4096
     v, f = synthetic.icosphere(2, 0.8)
@@ -401,4 +401,4 @@ def test_train_step_eikonal_matches_oracle(loss, h, lam):
     g = host(tr.g)
     scale = np.sqrt(np.mean(gref ** 2))
     assert np.median(np.abs(g - gref) / np.maximum(np.abs(gref), scale)) < 1e-4
-    banner("  worst per-layer gradient error %.3g" % _per_layer_close(g, gref, width, depth, 1e-3))
+    banner("  worst per-layer gradient error %.3g" % _per_layer_close(g, gref, width, depth, 5e-4))

@@ -295,7 +295,7 @@ def test_render_mesh_full_frame_sampled_pixels():
     r.render()
     torch.cuda.synchronize()
     paths = host(r.stats)
-    assert paths[0] == W * H * cfg.spp and np.all(np.diff(paths) <= 0) and paths[-1] > 0
+    assert paths[0] == W * H * cfg.spp and np.all(np.diff(paths) <= 0) and paths[1] > 0   # convex: no third bounce
     rows, cols = np.meshgrid(np.arange(100, 164), np.arange(928, 992), indexing="ij")   # top silhouette
     crop = (rows * W + cols).ravel()
     spread = np.random.default_rng(8).choice(W * H, 4096, replace=False)
