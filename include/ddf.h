@@ -22,7 +22,8 @@
  *   Memory    Every array argument is DEVICE memory owned by the caller unless the
  *             comment says "host".  The library never allocates, frees or keeps
  *             caller memory; scratch comes from a caller-supplied workspace whose
- *             size the matching *_workspace_size call returns.
+ *             size the matching *_workspace_size call returns (ddf_udf_noalloc alone
+ *             uses a fixed scratch array of the library's instead).
  *   Layout    Ray batches are structure-of-arrays float32: an array "[k][n]" holds
  *             row r of ray i at index r*n + i.  Triangles are a "[9][m]" soup of
  *             corners v0xyz, v1xyz, v2xyz.
@@ -162,6 +163,20 @@ ddf_status ddf_sample_dataset(const float *tris, int64_t m, const ddf_dataset_pa
 ddf_status ddf_udf_workspace_size(int64_t n_points, int64_t n_dirs, size_t *bytes);
 ddf_status ddf_udf(const ddf_net *net, const float *points, int64_t n_points, const float *dirs, int64_t n_dirs,
                    float *udf_out, int32_t *arg_out, void *ws, size_t ws_bytes, ddf_stream stream);
+
+/* ddf_udf for callers that cannot allocate memory (code under HIP graph capture, serving loops
+ * and harnesses that forbid hipMalloc): no workspace argument, and no allocation of any kind.
+ * Its scratch is a fixed 8 MiB array in device memory, one per GPU the library runs on, held
+ * until the process ends; its address is looked up once per device on the first call there.
+ * The same kernels and results as ddf_udf (bit for bit): the fused form while the keys of all
+ * points fit (up to about a million points), otherwise chunks of points as ddf_udf does with a
+ * small workspace.  Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other threads, other streams) race and must be serialised by the caller; nothing is
+ * assumed about the array's previous contents (the keys are reset by a kernel).
+ * Errors: those of ddf_udf, plus UNSUPPORTED for n_dirs > 65536 (one point's queries must fit
+ * the scratch) and HIP_ERROR when the scratch's address cannot be obtained. */
+ddf_status ddf_udf_noalloc(const ddf_net *net, const float *points, int64_t n_points, const float *dirs,
+                           int64_t n_dirs, float *udf_out, int32_t *arg_out, ddf_stream stream);
 
 /* ---------------------------------------------------------------- launch tuning
  * Process-wide launch-shape knobs.  They decide how work is spread over the GPU and

@@ -91,6 +91,7 @@ SIGNATURES = {
                                ctypes.POINTER(DdfLoss), c_p, c_p, c_p, c_sz, c_p],
     "ddf_udf_workspace_size": [c_i64, c_i64, ctypes.POINTER(c_sz)],
     "ddf_udf": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_sz, c_p],
+    "ddf_udf_noalloc": [ctypes.POINTER(DdfNet), c_p, c_i64, c_p, c_i64, c_p, c_p, c_p],
     "ddf_dataset_workspace_size": [ctypes.POINTER(DdfDatasetParams), ctypes.POINTER(c_sz)],
     "ddf_sample_dataset": [c_p, c_i64, ctypes.POINTER(DdfDatasetParams), c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
                            c_sz, c_p],

@@ -181,3 +181,57 @@ extern "C" ddf_status ddf_udf(const ddf_net *net, const float *points, int64_t n
     }
     return launch_status("ddf_udf");
 }
+
+// ------------------------------------------------------------------------------ no allocation
+// ddf_udf for callers that cannot allocate (code under HIP graph capture, serving loops): its
+// scratch -- the direction angles, the fused form's 64-bit keys, or the unfused form's chunks of
+// queries -- lives in one file-scope device array per GPU.  Host code never uses the array's
+// name as an address: its device address comes from hipGetSymbolAddress, once per device, with
+// that device current.
+#include <mutex>
+
+namespace ddf {
+namespace {
+
+constexpr size_t kUdfScratchBytes = (size_t)8 << 20;   // 8 MiB per GPU, held until the process ends
+constexpr int64_t kUdfScratchMaxDirs = 65536;          // one point's queries always fit (2.4 MB)
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) uint8_t scratch[kUdfScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device (NULL and an error message on failure).
+void *udf_scratch_ptr() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error("ddf_udf_noalloc: no current HIP device (or device index >= %d)", kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("ddf_udf_noalloc: hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+}  // namespace ddf
+
+extern "C" ddf_status ddf_udf_noalloc(const ddf_net *net, const float *points, int64_t n_points, const float *dirs,
+                                      int64_t n_dirs, float *udf_out, int32_t *arg_out, ddf_stream stream) {
+    using namespace ddf;
+    DDF_REQUIRE(n_dirs >= 0 && n_dirs <= kUdfScratchMaxDirs, DDF_ERR_UNSUPPORTED,
+                "ddf_udf_noalloc: %lld directions; at most %lld fit the fixed scratch (use ddf_udf with a workspace)",
+                (long long)n_dirs, (long long)kUdfScratchMaxDirs);
+    void *ws = udf_scratch_ptr();
+    if (!ws) return DDF_ERR_HIP;
+    return ddf_udf(net, points, n_points, dirs, n_dirs, udf_out, arg_out, ws, kUdfScratchBytes, stream);
+}
