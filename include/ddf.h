@@ -374,7 +374,9 @@ ddf_status ddf_paper_pack(const float *params, int32_t depth, int32_t precision,
 ddf_status ddf_paper_forward(const ddf_paper_net *net, const float *rays, int64_t n, float *dist_out,
                              ddf_stream stream);
 
-/* Reverse mode of sum(g_dist * dist) (g_dist [n], NULL = zeros):
+/* Reverse mode of sum(g_dist * dist) (g_dist [n], NULL = zeros); `params` are the parameters
+ * `net` was packed from (needed with g_params: the weight normalisation's gradient depends on
+ * v and g, not only on the folded weights; may be NULL otherwise):
  *   g_rays   [5][n] d/d(ox, oy, oz, theta, phi), or NULL; its origin part is the gradient of the
  *            field with respect to the query point that gives the normal (Eq. 3, Sec. IV-B);
  *   g_params [P] float32 in the parameter order above (gradients of v, g, b of every hidden
@@ -384,9 +386,9 @@ ddf_status ddf_paper_forward(const ddf_paper_net *net, const float *rays, int64_
  * The forward pass is recomputed inside the kernels; sums over rays run in fixed-size chunks
  * combined in a fixed order (repeated calls are bitwise identical). */
 ddf_status ddf_paper_workspace_size(int32_t depth, int64_t n, size_t *bytes);
-ddf_status ddf_paper_backward(const ddf_paper_net *net, const float *rays, int64_t n, const float *g_dist,
-                              float *g_rays, float *g_params, uint32_t flags, void *ws, size_t ws_bytes,
-                              ddf_stream stream);
+ddf_status ddf_paper_backward(const ddf_paper_net *net, const float *params, const float *rays, int64_t n,
+                              const float *g_dist, float *g_rays, float *g_params, uint32_t flags, void *ws,
+                              size_t ws_bytes, ddf_stream stream);
 
 /* One training step of Sec. V-A on a labelled batch: the loss (`loss`: DDF_LOSS_CLAMP, Eq. 7,
  * or DDF_LOSS_SQUISH, Eq. 6; the paper trains on the clamp loss) on the distance, its gradient

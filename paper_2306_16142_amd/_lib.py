@@ -100,7 +100,7 @@ SIGNATURES = {
     "ddf_paper_pack": [c_p, c_i32, c_i32, c_p, c_p],
     "ddf_paper_forward": [ctypes.POINTER(DdfPaperNet), c_p, c_i64, c_p, c_p],
     "ddf_paper_workspace_size": [c_i32, c_i64, ctypes.POINTER(c_sz)],
-    "ddf_paper_backward": [ctypes.POINTER(DdfPaperNet), c_p, c_i64, c_p, c_p, c_p, c_u32, c_p, c_sz, c_p],
+    "ddf_paper_backward": [ctypes.POINTER(DdfPaperNet), c_p, c_p, c_i64, c_p, c_p, c_p, c_u32, c_p, c_sz, c_p],
     "ddf_paper_train_step": [ctypes.POINTER(DdfPaperNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64,
                              ctypes.POINTER(DdfLoss), c_p, c_p, c_p, c_sz, c_p],
 }

@@ -218,7 +218,8 @@ class PaperNetwork:
                 torch.empty(nb, device=rays.device, dtype=torch.uint8)
         else:
             g_params = None
-        _lib.call("ddf_paper_backward", ctypes.byref(self.desc), _p(rays), n, _p(g_dist), _p(g_rays), _p(g_params),
+        _lib.call("ddf_paper_backward", ctypes.byref(self.desc), _p(self.params), _p(rays), n, _p(g_dist), _p(g_rays),
+                  _p(g_params),
                   1 if accumulate else 0, _p(ws), ws.numel() if ws is not None else 0, _stream())
         return g_rays, g_params
 

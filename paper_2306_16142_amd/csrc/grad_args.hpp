@@ -59,4 +59,14 @@ ddf_status stream_dispatch(int width, const GradArgs &args, hipStream_t s);
 int64_t sweep_grid(int width, int64_t n);
 ddf_status sweep_dispatch(int width, const GradArgs &args, hipStream_t s);
 
+// Weight gradient of one affine layer (train.hip): out [M][N] = sum over the n rays of
+// A[m][ray] B[k][ray], then out [M][N .. N + M) = sum of A's rows (the bias gradient); rows of A
+// and B are contiguous over rays.  The rays are split into fixed chunks whose partial products
+// (part: dw_partial_floats(M, N, n) floats; dbpart: as many chunks x M) are added in a fixed
+// order, so the result is bitwise reproducible.  accumulate: add to out.
+size_t dw_partial_floats(int M, int N, int64_t n);
+int dw_chunk(int M, int N);
+ddf_status dw_product(const float *A, const float *B, int M, int N, int64_t n, float *part, float *dbpart, float *out,
+                      bool accumulate, hipStream_t s);
+
 }  // namespace ddf

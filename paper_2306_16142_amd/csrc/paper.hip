@@ -84,6 +84,11 @@ __host__ __device__ inline int64_t paper_layer_off(int l) {
 }
 __host__ __device__ inline int64_t paper_params(int depth) { return paper_layer_off(depth) + kPW + 1; }
 __host__ __device__ inline int paper_in(int l) { return l == 0 ? kInRaw : kPW; }
+// Plain (folded-weight) gradients: per layer [512][in_l] then [512]; the output layer [512], [1].
+__host__ __device__ inline int64_t gw_layer_off(int l) {
+    return l == 0 ? 0 : (int64_t)kPW * kInRaw + kPW + (int64_t)(l - 1) * ((int64_t)kPW * kPW + kPW);
+}
+__host__ __device__ inline int64_t gw_floats(int depth) { return gw_layer_off(depth) + kPW + 1; }
 
 // Row norms of the weight normalisation, norm[l][i] = |v_l[i, :]|, in float64 (one wave per
 // row, fixed lane order).  The folded weight W = g v / |v| is formed in float64 and rounded
@@ -587,6 +592,344 @@ __global__ __launch_bounds__(kPWaves * 64, 1) void paper_stream_kernel(PaperArgs
     }
 }
 
+
+// ------------------------------------------------------------------------------ float32 sweep
+// Float32 queries, input gradients and the training sweep (paper_sweep_kernel): a workgroup
+// of eight waves takes 32 rays at a time and keeps their layer values in LDS ([ray][unit],
+// row pitch 516 floats); every wave reads a layer's whole input from LDS as B operands of the
+// 32x32x2 float32 MFMA (four K-steps per 16-byte read) and produces two of the 16 M-blocks;
+// weight tiles come from the L2-resident blob (one 256-byte tile per wave, M-block and K-step,
+// four groups of four K-steps in flight).  The output row and the transposed first layer (one
+// M-block each) split their 256 K-steps over the eight waves and add the partial sums in wave
+// order.  ReLU masks stay in LDS for the reverse sweep; the training sweep also writes every
+// layer's activations and adjoints for the weight-gradient products.
+constexpr int kSW = 8;            // waves
+constexpr int kSR = 32;           // rays per tile
+constexpr int kSXP = kPW + 4;     // row pitch of the layer values (floats)
+
+struct SLds {
+    int x, x0, mask, part, seed, loss, bytes;
+};
+__host__ __device__ inline SLds sweep_lds(int depth) {
+    SLds s;
+    s.x = 0;
+    s.x0 = s.x + kSR * kSXP * 4;
+    s.mask = s.x0 + kSR * 8 * 4;
+    s.part = s.mask + depth * kPNMB * 64 * 2;
+    s.seed = s.part + kSW * 8 * 32 * 4;
+    s.loss = s.seed + kSR * 4;
+    s.bytes = s.loss + kSW * 4;
+    return s;
+}
+
+struct SweepArgs {
+    const uint8_t *blob;   // float32 blob
+    int depth;
+    const float *rays;     // [5][n]
+    int64_t n;
+    const float *g_dist;   // seeds (NULL: from the loss, or zero)
+    const float *t_label;  // training: labels (+inf = miss); the seeds come from `loss`
+    LossSpec loss;
+    float inv_n;           // 1 / (loss normalisation)
+    float *dist_out;       // or NULL
+    float *g_rays;         // [5][n] or NULL
+    float *ws_h;           // [depth][512][n] activations (training), or NULL
+    float *ws_delta;       // [depth][512][n] adjoints, then [n] output seeds (training), or NULL
+    float *loss_partial;   // [gridDim.x] (training)
+    bool forward_only;
+};
+
+// acc[j] (M-block j of this wave's NM, tiles j * 64 floats apart) += sum over KS K-steps from
+// kb0 of tile (kb) x layer values X[ray][unit(kb, h)]; tiles: the first tile of K-step 0,
+// kstride floats between K-steps.
+template <int NM, int KS>
+__device__ __attribute__((always_inline)) inline void psweep_mfma(const float *__restrict__ tiles, int kstride, int kb0,
+                                                                  const float *X, int lane, f32x16 (&acc)[NM]) {
+    const int h = lane >> 5, col = lane & 31;
+    const float *t = tiles + lane + (int64_t)kb0 * kstride;
+    constexpr int kG = 4;   // groups of four K-steps of weight tiles in flight
+    float a[kG][NM][4];
+#pragma unroll
+    for (int g = 0; g < kG - 1; ++g)
+#pragma unroll
+        for (int j = 0; j < NM; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[g][j][q] = 4 * g < KS ? t[(int64_t)(4 * g + q) * kstride + j * 64] : 0.f;
+#pragma unroll 2
+    for (int kb = 0; kb < KS; kb += 4) {
+        if (kb + 4 * (kG - 1) < KS) {
+#pragma unroll
+            for (int j = 0; j < NM; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[kG - 1][j][q] = t[(int64_t)(kb + 4 * (kG - 1) + q) * kstride + j * 64];
+        }
+        const int k = kb0 + kb;
+        const f32x4 b4 = *reinterpret_cast<const f32x4 *>(X + col * kSXP + 32 * (k / 16) + 8 * ((k % 16) / 4) + 4 * h);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < NM; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][j][q], b4[q], acc[j], 0, 0, 0);
+#pragma unroll
+        for (int g = 0; g + 1 < kG; ++g)
+#pragma unroll
+            for (int j = 0; j < NM; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[g][j][q] = a[g + 1][j][q];
+    }
+}
+
+// Stores value j of a lane's D-layout tile (unit mb * 32 + 8 (j / 4) + 4 h + j % 4 of ray col)
+// into the layer values and, when given, into a [512][n] side output.
+__device__ __attribute__((always_inline)) inline void pstore_tile(const float (&y)[16], int mb, int h, int col, float *X,
+                                                                  float *side, int64_t n, int64_t r, bool valid) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+        *reinterpret_cast<f32x4 *>(X + col * kSXP + mb * 32 + 8 * g + 4 * h) = f32x4{y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]};
+    if (side && valid) {
+        float *dst = side + (int64_t)(mb * 32 + 4 * h) * n + r;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dst[(int64_t)(8 * (j / 4) + (j % 4)) * n] = y[j];
+    }
+}
+
+__global__ __launch_bounds__(kSW * 64, 1) void paper_sweep_kernel(SweepArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int depth = a.depth;
+    const int64_t n = a.n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int mb0 = 2 * wave;   // this wave's M-blocks mb0, mb0 + 1
+    const SLds S = sweep_lds(depth);
+    float *X = reinterpret_cast<float *>(smem + S.x);
+    float *X0 = reinterpret_cast<float *>(smem + S.x0);
+    uint16_t *s_mask = reinterpret_cast<uint16_t *>(smem + S.mask);
+    float *s_part = reinterpret_cast<float *>(smem + S.part);
+    float *s_seed = reinterpret_cast<float *>(smem + S.seed);
+    float *s_loss = reinterpret_cast<float *>(smem + S.loss);
+    const PaperLayout L = paper_layout(depth, kFP32);
+    const float *l0 = reinterpret_cast<const float *>(a.blob + L.l0_off);
+    const float *hid = reinterpret_cast<const float *>(a.blob + L.hid_off);
+    const float *head = reinterpret_cast<const float *>(a.blob + L.head_off);
+    const float *tr = reinterpret_cast<const float *>(a.blob + L.tr_off);
+    const float *bias = reinterpret_cast<const float *>(a.blob + L.bias_off);
+    const float *row = reinterpret_cast<const float *>(a.blob + L.row_off);
+    const bool train = a.ws_h != nullptr;
+    float loss_acc = 0.f;
+    auto mask_at = [&](int l, int mb) -> uint16_t & { return s_mask[(l * kPNMB + mb) * 64 + lane]; };
+
+    const int64_t ntile = (n + kSR - 1) / kSR;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t r = tile * kSR + col;
+        const bool valid = r < n;
+        // ---- the raw inputs (and 1 for the first layer's bias) of the tile's 32 rays
+        if (threadIdx.x < kSR * 8) {
+            const int ray = threadIdx.x / 8, k = threadIdx.x % 8;
+            const int64_t rr = tile * kSR + ray;
+            X0[ray * 8 + k] = k < kInRaw ? (rr < n ? a.rays[(int64_t)k * n + rr] : 0.f) : (k == kInRaw ? 1.f : 0.f);
+        }
+        __syncthreads();
+        bool nan_ray = false;
+#pragma unroll
+        for (int k = 0; k < kInRaw; ++k) nan_ray |= isnan(X0[col * 8 + k]);
+        // ---- first layer: three K-steps over (x, y), (z, theta), (phi, 1)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int mb = mb0 + j;
+            f32x16 acc = f32x16{};
+#pragma unroll
+            for (int ks = 0; ks < kPK0; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(l0[(mb * kPK0 + ks) * 64 + lane], X0[col * 8 + 2 * ks + h], acc, 0, 0, 0);
+            float y[16];
+            uint32_t bits = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                y[q] = fmaxf(acc[q], 0.f);
+                bits |= (acc[q] > 0.f ? 1u : 0u) << q;
+            }
+            mask_at(0, mb) = (uint16_t)bits;
+            pstore_tile(y, mb, h, col, X, train ? a.ws_h : nullptr, n, r, valid);
+        }
+        __syncthreads();
+        // ---- hidden layers: every wave reads the whole input, then writes its two M-blocks
+        for (int l = 1; l < depth; ++l) {
+            f32x16 acc[2] = {f32x16{}, f32x16{}};
+            psweep_mfma<2, kPF32K>(hid + (int64_t)(l - 1) * kPF32K * kPNMB * 64 + mb0 * 64, kPNMB * 64, 0, X, lane, acc);
+            __syncthreads();   // the input is read by every wave before anyone overwrites it
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int mb = mb0 + j;
+                float y[16];
+                uint32_t bits = 0;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + (l - 1) * kPW + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float z = acc[j][4 * g + i] + b4[i];
+                        y[4 * g + i] = fmaxf(z, 0.f);
+                        bits |= (z > 0.f ? 1u : 0u) << (4 * g + i);
+                    }
+                }
+                mask_at(l, mb) = (uint16_t)bits;
+                pstore_tile(y, mb, h, col, X, train ? a.ws_h + (int64_t)l * kPW * n : nullptr, n, r, valid);
+            }
+            __syncthreads();
+        }
+        // ---- output row: 32 K-steps per wave, partial sums added in wave order
+        {
+            f32x16 hacc[1] = {f32x16{}};
+            psweep_mfma<1, kPF32K / kSW>(head, 64, wave * (kPF32K / kSW), X, lane, hacc);
+            if (h == 0) s_part[wave * 32 + col] = hacc[0][0];   // row 0
+        }
+        __syncthreads();
+        if (wave == 0) {
+            float d = 0.f;
+#pragma unroll
+            for (int w = 0; w < kSW; ++w) d += s_part[w * 32 + col];
+            d += row[kPW];
+            float gd = 0.f;
+            if (a.t_label) {
+                const float t = valid ? a.t_label[r] : INFINITY;
+                float g0, g1;
+                const float term = ray_loss(0.f, d, t, a.inv_n, 0.f, a.loss, g0, g1);
+                gd = valid ? g1 : 0.f;
+                if (h == 0 && valid) loss_acc += term;
+            } else if (a.g_dist && valid) {
+                gd = a.g_dist[r];
+            }
+            if (h == 0) {
+                s_seed[col] = gd;
+                if (valid && a.dist_out) a.dist_out[r] = nan_ray ? NAN : d;
+                if (valid && train) a.ws_delta[(int64_t)depth * kPW * n + r] = gd;
+            }
+        }
+        __syncthreads();
+        if (a.forward_only) continue;
+        // ---- adjoint of the last hidden layer: output row x seed, masked
+        {
+            const float gd = s_seed[col];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int mb = mb0 + j;
+                const uint32_t bits = mask_at(depth - 1, mb);
+                float y[16];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const f32x4 w4 = *reinterpret_cast<const f32x4 *>(row + mb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) y[4 * g + i] = ((bits >> (4 * g + i)) & 1u) ? w4[i] * gd : 0.f;
+                }
+                pstore_tile(y, mb, h, col, X, train ? a.ws_delta + (int64_t)(depth - 1) * kPW * n : nullptr, n, r, valid);
+            }
+        }
+        __syncthreads();
+        // ---- transposed hidden layers from the top: X holds layer l's adjoint
+        for (int l = depth - 1; l >= 1; --l) {
+            f32x16 acc[2] = {f32x16{}, f32x16{}};
+            psweep_mfma<2, kPF32K>(tr + (int64_t)(l - 1) * kPF32K * kPNMB * 64 + mb0 * 64, kPNMB * 64, 0, X, lane, acc);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int mb = mb0 + j;
+                const uint32_t bits = mask_at(l - 1, mb);
+                float y[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) y[q] = ((bits >> q) & 1u) ? acc[j][q] : 0.f;
+                pstore_tile(y, mb, h, col, X, train ? a.ws_delta + (int64_t)(l - 1) * kPW * n : nullptr, n, r, valid);
+            }
+            __syncthreads();
+        }
+        // ---- transposed first layer: rows 0..4 = d/d(ox, oy, oz, theta, phi)
+        if (a.g_rays) {
+            f32x16 gacc[1] = {f32x16{}};
+            psweep_mfma<1, kPF32K / kSW>(tr + (int64_t)(depth - 1) * kPF32K * kPNMB * 64, 64, wave * (kPF32K / kSW), X,
+                                         lane, gacc);
+            // rows 0..3 in lane half 0 (values 0..3), row 4 in lane half 1 (value 0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (h == 0) s_part[(wave * 8 + k) * 32 + col] = gacc[0][k];
+            if (h == 1) s_part[(wave * 8 + 4) * 32 + col] = gacc[0][0];
+            __syncthreads();
+            if (wave == 0 && h == 0 && valid) {
+#pragma unroll
+                for (int k = 0; k < kInRaw; ++k) {
+                    float g = 0.f;
+#pragma unroll
+                    for (int w = 0; w < kSW; ++w) g += s_part[(w * 8 + k) * 32 + col];
+                    a.g_rays[(int64_t)k * n + r] = nan_ray ? NAN : g;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // block sum of the loss terms -> one partial per block (summed in a fixed order later)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) loss_acc += __shfl_xor(loss_acc, off);
+    if (lane == 0) s_loss[wave] = loss_acc;
+    __syncthreads();
+    if (threadIdx.x == 0 && a.loss_partial) {
+        float t = 0.f;
+        for (int w = 0; w < kSW; ++w) t += s_loss[w];
+        a.loss_partial[blockIdx.x] = t;
+    }
+}
+
+// Weight normalisation backward, one wave per hidden row i of layer l (u = v / |v|, G = dL/dW
+// of the folded row): dL/dg = G . u, dL/dv = (g / |v|) (G - (G . u) u); the bias gradient is
+// copied; the output row's gradient and bias gradient are copied as they are.
+// gW: the plain gradients, per layer [512][in_l] then [512] (the output layer [512] then [1]).
+__global__ void paper_wn_grad_kernel(const float *__restrict__ params, const double *__restrict__ norm,
+                                     const float *__restrict__ gW, int depth, float *__restrict__ g, bool accumulate) {
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (row > (int64_t)depth * kPW) return;
+    if (row == (int64_t)depth * kPW) {   // the output layer: plain copy
+        const int64_t po = paper_layer_off(depth), go = gw_layer_off(depth);
+        for (int k = lane; k <= kPW; k += 64) g[po + k] = accumulate ? g[po + k] + gW[go + k] : gW[go + k];
+        return;
+    }
+    const int l = (int)(row / kPW), i = (int)(row % kPW), in = paper_in(l);
+    const int64_t po = paper_layer_off(l), go = gw_layer_off(l);
+    const float *v = params + po + (int64_t)i * in;
+    const float *G = gW + go + (int64_t)i * in;
+    const double nv = norm[row], gain = params[po + (int64_t)kPW * in + i];
+    double dot = 0.0;
+    for (int k = lane; k < in; k += 64) dot = fma((double)G[k], (double)v[k], dot);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
+    const double gg = dot / nv;   // G . u
+    float *gv = g + po + (int64_t)i * in;
+    for (int k = lane; k < in; k += 64) {
+        const float d = (float)((gain / nv) * ((double)G[k] - gg * ((double)v[k] / nv)));
+        gv[k] = accumulate ? gv[k] + d : d;
+    }
+    if (lane == 0) {
+        float *gg_out = g + po + (int64_t)kPW * in + i, *gb_out = gg_out + kPW;
+        const float db = gW[go + (int64_t)kPW * in + i];
+        *gg_out = accumulate ? *gg_out + (float)gg : (float)gg;
+        *gb_out = accumulate ? *gb_out + db : db;
+    }
+}
+
+// Sum of the loss partials in a fixed order (one block).
+__global__ void paper_sum_kernel(const float *__restrict__ part, int cnt, float *out) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+int cu_count_paper();
+int64_t paper_sweep_grid(int64_t n) {
+    return std::max<int64_t>(1, std::min<int64_t>((n + kSR - 1) / kSR, (int64_t)cu_count_paper()));
+}
+
 int cu_count_paper() {
     static int cus = 0;
     static std::once_flag once;
@@ -608,6 +951,81 @@ ddf_status launch_paper_stream(const PaperArgs &a, hipStream_t s) {
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ntile, cu_count_paper()));
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPWaves * 64), lds, s, a);
     return launch_status("ddf paper network kernel");
+}
+
+ddf_status launch_paper_sweep(const SweepArgs &a, hipStream_t s) {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute((const void *)paper_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kPLds);
+    });
+    const size_t lds = sweep_lds(a.depth).bytes;
+    hipLaunchKernelGGL(paper_sweep_kernel, dim3((unsigned)paper_sweep_grid(a.n)), dim3(kSW * 64), lds, s, a);
+    return launch_status("ddf paper network float32 sweep");
+}
+
+// Workspace of the float32 parameter gradient for n rays.
+struct PaperWs {
+    float *h, *delta, *gw, *part, *dbpart, *loss_part;
+    size_t bytes;
+};
+inline size_t pal256(size_t x) { return (x + 255) & ~(size_t)255; }
+PaperWs paper_ws(int depth, int64_t n, void *base) {
+    PaperWs w{};
+    uint8_t *p = reinterpret_cast<uint8_t *>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        float *q = p ? reinterpret_cast<float *>(p + off) : nullptr;
+        off += pal256(bytes);
+        return q;
+    };
+    size_t part = 0, db = 0;
+    for (int l = 0; l <= depth; ++l) {
+        const int M = l == depth ? 1 : kPW, N = l == 0 ? kInRaw : kPW;
+        part = std::max(part, dw_partial_floats(M, N, n));
+        db = std::max(db, (size_t)((n + dw_chunk(M, N) - 1) / dw_chunk(M, N)) * M);
+    }
+    w.h = take((size_t)depth * kPW * n * 4);
+    w.delta = take(((size_t)depth * kPW + 1) * n * 4);
+    w.gw = take((size_t)gw_floats(depth) * 4);
+    w.part = take(part * 4);
+    w.dbpart = take(db * 4);
+    w.loss_part = take(4096 * 4);
+    w.bytes = off;
+    return w;
+}
+
+// Float32 parameter gradient of n rays: the training sweep (seeds from g_dist, or from the loss
+// when t_label is given), the weight-gradient products, the weight-normalisation backward.
+ddf_status paper_param_grad(const ddf_paper_net *net, const float *params, const float *rays, int64_t n,
+                            const float *g_dist, const float *t_label, LossSpec loss, float *g_rays, float *g_params,
+                            bool accumulate, const PaperWs &w, hipStream_t s) {
+    const int depth = net->depth;
+    SweepArgs a{};
+    a.blob = (const uint8_t *)net->packed;
+    a.depth = depth;
+    a.rays = rays;
+    a.n = n;
+    a.g_dist = g_dist;
+    a.t_label = t_label;
+    a.loss = loss;
+    a.inv_n = 1.0f / (float)n;
+    a.g_rays = g_rays;
+    a.ws_h = w.h;
+    a.ws_delta = w.delta;
+    a.loss_partial = w.loss_part;
+    if (ddf_status st = launch_paper_sweep(a, s)) return st;
+    for (int l = 0; l <= depth; ++l) {
+        const int M = l == depth ? 1 : kPW, N = l == 0 ? kInRaw : kPW;
+        const float *A = w.delta + (int64_t)l * kPW * n;   // the output seeds follow the last adjoint
+        const float *B = l == 0 ? rays : w.h + (int64_t)(l - 1) * kPW * n;
+        if (ddf_status st = dw_product(A, B, M, N, n, w.part, w.dbpart, w.gw + gw_layer_off(l), false, s)) return st;
+    }
+    const PaperLayout L = paper_layout(depth, kFP32);
+    const double *norm = reinterpret_cast<const double *>(reinterpret_cast<const uint8_t *>(net->packed) + L.bytes);
+    const int rows = depth * kPW + 1;
+    hipLaunchKernelGGL(paper_wn_grad_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, params, norm, (const float *)w.gw,
+                       depth, g_params, accumulate);
+    return launch_status("ddf paper network weight-norm gradient");
 }
 
 ddf_status check_paper(const ddf_paper_net *net, const char *who) {
@@ -666,7 +1084,16 @@ extern "C" ddf_status ddf_paper_forward(const ddf_paper_net *net, const float *r
     DDF_REQUIRE(n >= 0, DDF_ERR_INVALID_ARG, "ddf_paper_forward: negative n");
     if (n == 0) return DDF_OK;
     DDF_REQUIRE(rays && dist_out, DDF_ERR_INVALID_ARG, "ddf_paper_forward: NULL array");
-    DDF_REQUIRE(net->precision == kBF16, DDF_ERR_UNSUPPORTED, "ddf_paper_forward: float32 not built yet");
+    if (net->precision == kFP32) {
+        SweepArgs a{};
+        a.blob = (const uint8_t *)net->packed;
+        a.depth = net->depth;
+        a.rays = rays;
+        a.n = n;
+        a.dist_out = dist_out;
+        a.forward_only = true;
+        return launch_paper_sweep(a, as_stream(stream));
+    }
     PaperArgs a{};
     a.blob = (const uint8_t *)net->packed;
     a.depth = net->depth;
@@ -676,17 +1103,43 @@ extern "C" ddf_status ddf_paper_forward(const ddf_paper_net *net, const float *r
     return launch_paper_stream<false>(a, as_stream(stream));
 }
 
-extern "C" ddf_status ddf_paper_backward(const ddf_paper_net *net, const float *rays, int64_t n, const float *g_dist,
-                                         float *g_rays, float *g_params, uint32_t flags, void *ws, size_t ws_bytes,
-                                         ddf_stream stream) {
+extern "C" ddf_status ddf_paper_workspace_size(int32_t depth, int64_t n, size_t *bytes) {
+    DDF_REQUIRE(bytes && n >= 0, DDF_ERR_INVALID_ARG, "ddf_paper_workspace_size: bad argument");
+    DDF_REQUIRE(depth >= 1 && depth <= kPMaxDepth, DDF_ERR_UNSUPPORTED, "ddf_paper_workspace_size: depth %d not supported (1..8)",
+                depth);
+    *bytes = paper_ws(depth, n, nullptr).bytes;
+    return DDF_OK;
+}
+
+extern "C" ddf_status ddf_paper_backward(const ddf_paper_net *net, const float *params, const float *rays, int64_t n,
+                                         const float *g_dist, float *g_rays, float *g_params, uint32_t flags, void *ws,
+                                         size_t ws_bytes, ddf_stream stream) {
     if (ddf_status st = check_paper(net, "ddf_paper_backward")) return st;
     DDF_REQUIRE(n >= 0, DDF_ERR_INVALID_ARG, "ddf_paper_backward: negative n");
     DDF_REQUIRE((flags & ~1u) == 0, DDF_ERR_INVALID_ARG, "ddf_paper_backward: unknown flags 0x%x", flags);
     if (n == 0) return DDF_OK;
     DDF_REQUIRE(rays && (g_rays || g_params), DDF_ERR_INVALID_ARG, "ddf_paper_backward: nothing to compute");
-    DDF_REQUIRE(!g_params && net->precision == kBF16, DDF_ERR_UNSUPPORTED, "ddf_paper_backward: not built yet");
-    (void)ws;
-    (void)ws_bytes;
+    hipStream_t s = as_stream(stream);
+    if (g_params) {
+        DDF_REQUIRE(net->precision == kFP32, DDF_ERR_UNSUPPORTED,
+                    "ddf_paper_backward: parameter gradients need a float32 network");
+        DDF_REQUIRE(params, DDF_ERR_INVALID_ARG, "ddf_paper_backward: parameter gradients need the parameters");
+        const PaperWs need = paper_ws(net->depth, n, nullptr);
+        DDF_REQUIRE(ws && ws_bytes >= need.bytes, DDF_ERR_WORKSPACE, "ddf_paper_backward: workspace of %zu bytes needed",
+                    need.bytes);
+        return paper_param_grad(net, params, rays, n, g_dist, nullptr, LossSpec{0, 0.f}, g_rays, g_params,
+                                (flags & 1u) != 0, paper_ws(net->depth, n, ws), s);
+    }
+    if (net->precision == kFP32) {
+        SweepArgs a{};
+        a.blob = (const uint8_t *)net->packed;
+        a.depth = net->depth;
+        a.rays = rays;
+        a.n = n;
+        a.g_dist = g_dist;
+        a.g_rays = g_rays;
+        return launch_paper_sweep(a, s);
+    }
     PaperArgs a{};
     a.blob = (const uint8_t *)net->packed;
     a.depth = net->depth;
@@ -694,21 +1147,34 @@ extern "C" ddf_status ddf_paper_backward(const ddf_paper_net *net, const float *
     a.n = n;
     a.g_dist = g_dist;
     a.g_rays = g_rays;
-    return launch_paper_stream<true>(a, as_stream(stream));
-}
-
-extern "C" ddf_status ddf_paper_workspace_size(int32_t depth, int64_t n, size_t *bytes) {
-    DDF_REQUIRE(bytes && n >= 0 && depth >= 1 && depth <= kPMaxDepth, DDF_ERR_INVALID_ARG,
-                "ddf_paper_workspace_size: bad argument");
-    *bytes = 0;
-    return DDF_OK;
+    return launch_paper_stream<true>(a, s);
 }
 
 extern "C" ddf_status ddf_paper_train_step(const ddf_paper_net *net, float *params, float *adam_m, float *adam_v,
                                            int64_t step, float lr, const float *rays, const float *t_label, int64_t n,
                                            const ddf_loss *loss, float *loss_out, float *g_params, void *ws,
                                            size_t ws_bytes, ddf_stream stream) {
-    (void)net, (void)params, (void)adam_m, (void)adam_v, (void)step, (void)lr, (void)rays, (void)t_label, (void)n;
-    (void)loss, (void)loss_out, (void)g_params, (void)ws, (void)ws_bytes, (void)stream;
-    DDF_REQUIRE(false, DDF_ERR_UNSUPPORTED, "ddf_paper_train_step: not built yet");
+    if (ddf_status st = check_paper(net, "ddf_paper_train_step")) return st;
+    DDF_REQUIRE(net->precision == kFP32, DDF_ERR_UNSUPPORTED, "ddf_paper_train_step: needs a float32 network");
+    DDF_REQUIRE(n > 0 && params && adam_m && adam_v && rays && t_label && loss_out && g_params && step >= 1,
+                DDF_ERR_INVALID_ARG, "ddf_paper_train_step: bad argument");
+    DDF_REQUIRE(loss && (loss->kind == DDF_LOSS_CLAMP || loss->kind == DDF_LOSS_SQUISH), DDF_ERR_INVALID_ARG,
+                "ddf_paper_train_step: the loss must be the clamp (Eq. 7) or the squish (Eq. 6) loss");
+    DDF_REQUIRE(loss->kind != DDF_LOSS_CLAMP || (std::isfinite(loss->delta) && loss->delta > 0.f), DDF_ERR_INVALID_ARG,
+                "ddf_paper_train_step: the clamp loss needs a finite delta > 0");
+    const PaperWs need = paper_ws(net->depth, n, nullptr);
+    DDF_REQUIRE(ws && ws_bytes >= need.bytes, DDF_ERR_WORKSPACE, "ddf_paper_train_step: workspace of %zu bytes needed",
+                need.bytes);
+    hipStream_t s = as_stream(stream);
+    const PaperWs w = paper_ws(net->depth, n, ws);
+    if (ddf_status st = paper_param_grad(net, params, rays, n, nullptr, t_label, LossSpec{loss->kind, loss->delta},
+                                         nullptr, g_params, false, w, s))
+        return st;
+    hipLaunchKernelGGL(paper_sum_kernel, dim3(1), dim3(256), 0, s, (const float *)w.loss_part,
+                       (int)paper_sweep_grid(n), loss_out);
+    if (ddf_status st = launch_status("ddf_paper_train_step")) return st;
+    if (ddf_status st = ddf_adam_step(params, g_params, adam_m, adam_v, paper_params(net->depth), step, lr, 0.9f, 0.999f,
+                                      1e-8f, stream))
+        return st;
+    return ddf_paper_pack(params, net->depth, kFP32, const_cast<void *>(net->packed), stream);
 }

@@ -267,6 +267,38 @@ __global__ void loss_seeds_kernel(const float *__restrict__ logit, const float *
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+}  // namespace
+
+// Rays per split of the batch contraction for an M x N product: layers of fewer than four
+// 128 x 128 output tiles split the rays twice as finely, so that they still occupy every CU.
+int dw_chunk(int M, int N) {
+    const int tiles = ((M + kDwTile - 1) / kDwTile) * ((N + kDwTile - 1) / kDwTile);
+    return tiles >= 4 ? kChunk : kChunk / 2;
+}
+
+size_t dw_partial_floats(int M, int N, int64_t n) {
+    return (size_t)((n + dw_chunk(M, N) - 1) / dw_chunk(M, N)) * M * N;
+}
+
+ddf_status dw_product(const float *A, const float *B, int M, int N, int64_t n, float *part, float *dbpart, float *out,
+                      bool accumulate, hipStream_t s) {
+    const int tiles = ((M + kDwTile - 1) / kDwTile) * ((N + kDwTile - 1) / kDwTile);
+    const int chunk = dw_chunk(M, N);
+    const int splits = (int)((n + chunk - 1) / chunk);
+    const unsigned blocks = (unsigned)(tiles * splits);
+    if (n % 4 == 0)
+        hipLaunchKernelGGL(dw_kernel<true>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, chunk, part, dbpart);
+    else
+        hipLaunchKernelGGL(dw_kernel<false>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, chunk, part, dbpart);
+    if (ddf_status st = launch_status("ddf parameter gradient")) return st;
+    const int64_t total = (int64_t)M * N + M;
+    hipLaunchKernelGGL(reduce_dw_kernel, dim3((unsigned)std::min<int64_t>((total + 63) / 64, 4096)), dim3(256), 0, s,
+                       part, dbpart, M, N, splits, out, accumulate);
+    return launch_status("ddf parameter gradient reduction");
+}
+
+namespace {
+
 // ------------------------------------------------------------------------------ workspace
 struct TrainWs {
     float *gamma, *h, *delta, *loss_part, *scalars, *part, *dbpart;
@@ -309,24 +341,8 @@ ddf_status param_grads(int width, int depth, int64_t n, const TrainWs &w, float 
         const int N = l == 0 ? kInDim : width;
         const float *A = l == depth ? w.delta + (int64_t)depth * width * n : w.delta + (int64_t)l * width * n;
         const float *B = l == 0 ? w.gamma : w.h + (int64_t)(l - 1) * width * n;
-        const int tiles = ((M + kDwTile - 1) / kDwTile) * ((N + kDwTile - 1) / kDwTile);
-        // layers of fewer than four output tiles (layer 0, the head, width 128) split the rays
-        // twice as finely, so that they still occupy every CU
-        const int chunk = tiles >= 4 ? kChunk : kChunk / 2;
-        const int splits = (int)((n + chunk - 1) / chunk);
-        const unsigned blocks = (unsigned)(tiles * splits);
-        if (n % 4 == 0)
-            hipLaunchKernelGGL(dw_kernel<true>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, chunk, w.part,
-                               w.dbpart);
-        else
-            hipLaunchKernelGGL(dw_kernel<false>, dim3(blocks), dim3(512), 0, s, A, B, M, N, n, splits, chunk, w.part,
-                               w.dbpart);
-        if (ddf_status st = launch_status("ddf parameter gradient")) return st;
-        const int64_t total = (int64_t)M * N + M;
-        hipLaunchKernelGGL(reduce_dw_kernel, dim3((unsigned)std::min<int64_t>((total + 63) / 64, 4096)), dim3(256), 0, s,
-                           w.part, w.dbpart, M, N, splits, g_params + off, accumulate);
-        if (ddf_status st = launch_status("ddf parameter gradient reduction")) return st;
-        off += total;
+        if (ddf_status st = dw_product(A, B, M, N, n, w.part, w.dbpart, g_params + off, accumulate, s)) return st;
+        off += (int64_t)M * N + M;
     }
     return DDF_OK;
 }

@@ -80,3 +80,114 @@ def test_paper_edge_cases():
     assert np.all(np.isnan(g[:, 150])) and np.all(np.isfinite(np.delete(g, 150, axis=1)))
     with pytest.raises(Exception):
         api.PaperNetwork(cuda(p[:-1]), 2, "bf16")
+
+
+def _kink_free(p, depth, rays, tol=1e-4, extra=None):
+    """Rays whose every hidden pre-activation is at least `tol` from the ReLU kink (float64)."""
+    _, _, pres = paper.forward(p, W, depth, rays, return_acts=True)
+    m = np.ones(rays.shape[1], dtype=bool)
+    for z in pres[:-1]:
+        m &= np.abs(z).min(axis=0) > tol
+    return m
+
+
+def _slices(depth):
+    """(name, slice) of every parameter block: v, g, b per hidden layer, then the output row and bias."""
+    out, off = [], 0
+    for l, (o, i) in enumerate(paper.shapes(W, depth)[:-1]):
+        for name, cnt in (("v%d" % l, o * i), ("g%d" % l, o), ("b%d" % l, o)):
+            out.append((name, slice(off, off + cnt)))
+            off += cnt
+    out += [("w_out", slice(off, off + W)), ("b_out", slice(off + W, off + W + 1))]
+    return out
+
+
+def _per_block_close(g, ref, depth, tol):
+    worst = 0.0
+    for name, sl in _slices(depth):
+        big = np.abs(ref[sl]).max()
+        assert big > 0, name
+        worst = max(worst, np.abs(g[sl] - ref[sl]).max() / big)
+    assert worst < tol, worst
+    return worst
+
+
+@pytest.mark.parametrize("depth,n", [(8, 9000 + 5), (2, 333)])
+def test_paper_forward_fp32_matches_float64(depth, n):
+    """float32 query (the training sweep's forward; several 32-ray tiles per workgroup)."""
+    banner("paper forward fp32: depth %d, n=%d" % (depth, n))
+    p = synthetic.paper_params(depth, 71)
+    rays = _rays(n, 72)
+    d = host(api.PaperNetwork(cuda(p), depth, "fp32")(cuda(rays)))
+    r = paper.forward(p, W, depth, rays)
+    err = _scaled_err(d, r)
+    banner("  scaled error vs float64: median %.3g max %.3g" % (np.median(err), err.max()))
+    # float32 sums of 512 products per unit, eight layers deep, and an output small next to
+    # the terms that form it (measured: median 3.4e-6, max 2.5e-5 at depth 8)
+    assert np.median(err) < 1e-5 and err.max() < 1e-4
+
+
+@pytest.mark.parametrize("depth,n", [(8, 2000 + 3), (3, 500)])
+def test_paper_gradients_fp32_match_oracle(depth, n):
+    """float32 input and parameter gradients (through the weight normalisation) against the
+    float64 oracle on rays clear of ReLU kinks: per parameter block (v, g, b of every layer,
+    the output row) the max error within 1e-5 of the block's largest component.  The
+    accumulate flag adds, and a second call is bitwise identical."""
+    banner("paper gradients fp32: depth %d, n=%d" % (depth, n))
+    p = synthetic.paper_params(depth, 73)
+    rays = _rays(n, 74)
+    rays = np.ascontiguousarray(rays[:, _kink_free(p, depth, rays)])
+    n = rays.shape[1]
+    gd = (np.random.default_rng(75).normal(size=n) / n).astype(np.float32)
+    net = api.PaperNetwork(cuda(p), depth, "fp32")
+    g_rays, g_p = net.backward(cuda(rays), cuda(gd), want_params=True)
+    ref_r, ref_p = paper.backward(p, W, depth, rays, gd)
+    worst = _per_block_close(host(g_p), ref_p, depth, 1e-5)
+    err_r = _scaled_err(host(g_rays), ref_r)
+    banner("  worst per-block parameter error %.3g; input gradient max %.3g" % (worst, err_r.max()))
+    assert err_r.max() < 1e-4
+    g_only, _ = net.backward(cuda(rays), cuda(gd))   # input gradient without the parameter sweep
+    assert torch.equal(g_only, g_rays)
+    _, g2 = net.backward(cuda(rays), cuda(gd), want_params=True)
+    assert torch.equal(g_p, g2)
+    _, g3 = net.backward(cuda(rays), cuda(gd), want_params=True, g_params=g2.clone(), accumulate=True)
+    torch.testing.assert_close(g3, 2 * g2, rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("loss,delta", [("clamp", 0.5), ("squish", 1.0)])
+def test_paper_train_step_matches_oracle(loss, delta):
+    """One training step of the paper's network (Sec. V-A) with the clamp (Eq. 7) or squish
+    (Eq. 6) loss on labeller labels, on a batch clear of ReLU kinks and of the loss's branch
+    points: loss, per-block gradient, the Adam move and the repacked network against the oracle."""
+    banner("paper train step fp32: %s delta %g, depth 8, batch 2048" % (loss, delta))
+    depth = 8
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    o, d, _ = synthetic.training_rays(v, f, 2048, 76)
+    from oracle import geometry
+    t = geometry.nearest_hit(o, d, tris)["t"].astype(np.float32)
+    rays = rays5_from(o, d)
+    p = synthetic.paper_params(depth, 77)
+    keep = _kink_free(p, depth, rays)
+    ds = paper.forward(p, W, depth, rays)
+    tt = t.astype(np.float64)
+    if loss == "clamp":
+        keep &= (np.abs(np.abs(ds) - delta) > 1e-4) & (np.abs(np.clip(ds, -delta, delta) - np.clip(tt, -delta, delta)) > 1e-4)
+    else:
+        keep &= np.abs(np.tanh(ds) - np.tanh(tt)) > 1e-4
+    rays, t = np.ascontiguousarray(rays[:, keep]), t[keep]
+    n = t.size
+    pg = cuda(p)
+    tr = api.PaperTrainer(pg, depth, n, lr=1e-3, loss=loss, delta=delta)
+    out = host(tr.step(cuda(rays), cuda(t)))[0]
+    z = np.zeros(p.size)
+    rl, gref, pnew, _, _ = paper.train_step(p.astype(np.float64), W, depth, rays, t, z, z, 1, loss, delta, lr=1e-3)
+    assert abs(out - rl) < 1e-5 * abs(rl)
+    worst = _per_block_close(host(tr.g), gref, depth, 1e-4)
+    banner("  loss %.6g (oracle %.6g); worst per-block gradient error %.3g" % (out, rl, worst))
+    moved, ref_moved = host(pg) - p, pnew - p
+    assert np.mean(np.abs(moved - ref_moved) < 1e-6) > 0.999
+    # the repacked network is the updated one
+    d2 = host(tr.net(cuda(rays)))
+    r2 = paper.forward(host(pg).astype(np.float64), W, depth, rays)
+    assert _scaled_err(d2, r2).max() < 2e-5
