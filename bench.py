@@ -247,6 +247,87 @@ def bench_eikonal_training(args, torch, api, dev, steps=1500, lam=1.0, h=0.02, b
     return {"eikonal_training": out}
 
 
+def paper_flop_per_query(depth, width=512):
+    return 2 * (5 * width + (depth - 1) * width * width + width)
+
+
+def bench_paper_network(args, torch, api, dev, depth=8):
+    """The paper's own network (Sec. V-A: 8 weight-normalised hidden layers of 512 on the raw
+    ray, one distance output): bf16 and float32 queries, bf16 input gradients (normals) and the
+    float32 training step with the clamp loss (Eq. 7) on icosphere labels.  Weights: the
+    weight-norm start (g = |v|) from a seed, untrained (throughput)."""
+    import synthetic
+    p = torch.from_numpy(synthetic.paper_params(depth, 81)).to(dev)
+    nets = {pr: api.PaperNetwork(p, depth, pr) for pr in ("bf16", "fp32")}
+    out = {"workload": "paper network %d x 512 (weight norm folded, raw 5-value input, one output), "
+                       "uniform rays; training: batch 65,536, clamp loss delta 1" % depth,
+           "flop_per_query": paper_flop_per_query(depth)}
+    sizes = {"bf16": 1 << 22, "fp32": 1 << 20}
+    for pr, n in sizes.items():
+        o, d = synthetic.uniform_cube_rays(n, 82)
+        rays = api.assemble_rays(torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev))
+        dist = torch.empty(n, device=dev)
+        nets[pr](rays, dist)
+        torch.cuda.synchronize()
+        timer = event_timer(torch)
+        for _ in range(5 if pr == "bf16" else 3):
+            timer.start()
+            nets[pr](rays, dist)
+            timer.stop()
+        torch.cuda.synchronize()
+        ms = timer.mean_ms()
+        tf = paper_flop_per_query(depth) * n / (ms * 1e-3) / 1e12
+        out[pr] = {"rays": n, "forward_ms": ms, "queries_per_s": n / (ms * 1e-3), "tflops": tf,
+                   "roofline_frac": tf / PEAK[pr]}
+        if pr == "bf16":
+            g = torch.ones(n, device=dev)
+            nets[pr].backward(rays, g)
+            torch.cuda.synchronize()
+            timer = event_timer(torch)
+            for _ in range(3):
+                timer.start()
+                nets[pr].backward(rays, g)
+                timer.stop()
+            torch.cuda.synchronize()
+            gms = timer.mean_ms()
+            out[pr]["input_gradient_ms"] = gms
+            out[pr]["input_gradients_per_s"] = n / (gms * 1e-3)
+            out[pr]["input_gradient_tflops"] = 2 * paper_flop_per_query(depth) * n / (gms * 1e-3) / 1e12
+            if not args.quick:
+                from oracle import paper
+                idx = np.arange(0, n, n // 2048)[:2048]
+                sub = rays[:, idx].cpu().numpy().astype(np.float64)
+                ref = paper.forward(p.cpu().numpy(), 512, depth, sub)
+                got = dist[idx].cpu().numpy()
+                e = np.abs(got - ref)
+                out[pr]["abs_err_vs_fp64"] = {"mean": float(e.mean()), "p99": float(np.quantile(e, 0.99)),
+                                              "max": float(e.max()), "ref_rms": float(np.sqrt(np.mean(ref ** 2)))}
+    # float32 training step (clamp loss) on icosphere labels
+    v, f = synthetic.icosphere(2, 0.8)
+    tris = torch.from_numpy(synthetic.tri_soup(v, f)).to(dev)
+    batch = 65536
+    o, d, _ = synthetic.training_rays(v, f, batch, 83)
+    og, dg = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+    t, _, _ = api.label_rays(og, dg, tris)
+    rays = api.assemble_rays(og, dg)
+    tr = api.PaperTrainer(p.clone(), depth, batch, lr=1e-4, loss="clamp", delta=1.0)
+    first = float(tr.step(rays, t))
+    torch.cuda.synchronize()
+    steps = 5
+    timer = event_timer(torch)
+    for _ in range(steps):
+        timer.start()
+        tr.step(rays, t)
+        timer.stop()
+    torch.cuda.synchronize()
+    ms = timer.mean_ms()
+    out["train"] = {"batch": batch, "ms_per_step": ms, "steps_per_s": 1e3 / ms,
+                    "tflops": 3 * paper_flop_per_query(depth) * batch / (ms * 1e-3) / 1e12,
+                    "loss_first": first, "loss_after": float(tr.loss), "steps": 1 + steps}
+    out["train"]["roofline_frac_fp32"] = out["train"]["tflops"] / PEAK["fp32"]
+    return {"paper_network": out}
+
+
 def bench_dataset(args, torch, api, dev):
     """Training-data sampler of Sec. V-B (Eqs. 8-12) on the 20,480-triangle mesh."""
     import synthetic
@@ -578,6 +659,8 @@ def main():
         extra.update(bench_dataset(args, torch, api, dev))
         progress("unsigned distance field")
         extra.update(bench_udf(args, torch, api, dev, nets["bf16"], 0.8))
+        progress("the paper's 8 x 512 network")
+        extra.update(bench_paper_network(args, torch, api, dev))
         progress("Eikonal residual and Eikonal training")
         extra["eikonal_fp32"] = bench_eikonal(torch, api, dev, nets["fp32"], o_g, d_g, rays)
         extra.update(bench_eikonal_training(args, torch, api, dev))
