@@ -91,6 +91,10 @@ def parse():
     ap.add_argument("--render-train-steps", type=int, default=5000)
     ap.add_argument("--multi-train-steps", type=int, default=100)
     ap.add_argument("--dataset-s", type=int, default=10, help="s_fc = s_dr = s_p of the dataset sampler workload")
+    ap.add_argument("--only", default=None,
+                    help="comma list of the workloads to run besides the bf16 primary line (for profiling): "
+                         "fp32, fp8, render (labeller, training and render), multi, dataset, udf, paper, eikonal; "
+                         "no CPU baseline is taken then")
     ap.add_argument("--save-params", default=None,
                     help="write the in-run trained 4 x 128 icosphere network's float32 parameters to this .npy file")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -414,8 +418,11 @@ def bench_label_train_render(args, torch, api, dev):
         trainer.step(*batches[i % nb])
     losses.append(float(trainer.loss))
     torch.cuda.synchronize()
+    step_flop = 3 * flop_per_query(width, depth) * batch   # forward, adjoints and weight gradients
     out["train"] = {"workload": "6x256 fp32, batch 65,536, Adam 1e-3, labels from the labeller (%d valid rays)" % nvalid,
                     "ms_per_step": tms, "steps_per_s": 1e3 / tms,
+                    "algorithmic_flop_per_step": step_flop, "tflops": step_flop / (tms * 1e-3) / 1e12,
+                    "roofline_frac_fp32": step_flop / (tms * 1e-3) / 1e12 / PEAK["fp32"],
                     "loss_first_step": losses[0], "loss_after_%d_steps" % (3 + args.train_steps): losses[-2],
                     "loss_after_%d_steps" % (3 + args.train_steps + args.render_train_steps): losses[-1]}
     # render: 1920 x 1080, spp samples, 4 bounces, Russian roulette after bounce 2, bf16 queries
@@ -577,7 +584,9 @@ def main():
             timer.stop()
 
     results = {}
-    for prec in (["bf16"] if args.quick else ["bf16", "fp32", "fp8"]):
+    only = None if args.only is None else set(args.only.split(","))
+    want = (lambda name: not args.quick and (only is None or name in only))
+    for prec in ["bf16"] + [pr for pr in ("fp32", "fp8") if want(pr)]:
         progress("precision workload, %s" % prec)
         net = nets[prec]
         steps = args.steps if prec != "fp32" else max(3, args.steps // 4)
@@ -600,7 +609,7 @@ def main():
                          "forward_tflops": flop_per_query(W, D) * n / (kern_ms * 1e-3) / 1e12,
                          "cold_first_step_ms": cold_ms, "steps": steps}
         # accuracy against the float64 oracle on a fixed sample of the batch
-        if not args.quick:
+        if not args.quick and only is None:
             from oracle import mlp
             idx = np.arange(0, n, max(1, n // 65536))[:65536]
             sub = rays[:, idx].cpu().numpy()
@@ -650,21 +659,26 @@ def main():
     extra["icosphere_training"] = train_info
     extra["bf16"] = {k: v for k, v in bf.items() if k not in ("queries_per_s",)}
 
-    if not args.quick:
+    if want("render"):
         progress("labeller, training and render workloads")
         extra.update(bench_label_train_render(args, torch, api, dev))
+    if want("multi"):
         progress("multi-object render")
         extra.update(bench_multi(args, torch, api, dev))
+    if want("dataset"):
         progress("training-data sampler")
         extra.update(bench_dataset(args, torch, api, dev))
+    if want("udf"):
         progress("unsigned distance field")
         extra.update(bench_udf(args, torch, api, dev, nets["bf16"], 0.8))
+    if want("paper"):
         progress("the paper's 8 x 512 network")
         extra.update(bench_paper_network(args, torch, api, dev))
+    if want("eikonal"):
         progress("Eikonal residual and Eikonal training")
         extra["eikonal_fp32"] = bench_eikonal(torch, api, dev, nets["fp32"], o_g, d_g, rays)
         extra.update(bench_eikonal_training(args, torch, api, dev))
-    if not args.quick:
+    if not args.quick and only is None:
         # the float64 oracle on the host cores, bounded sample of the same query workload
         from oracle import mlp
         from threadpoolctl import threadpool_info
