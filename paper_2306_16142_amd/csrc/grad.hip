@@ -400,10 +400,10 @@ int64_t grad_grid(int width, int precision, int64_t n) {
 ddf_status grad_dispatch(const ddf_net *net, const GradArgs &args, bool train, hipStream_t s) {
     const int cap = cu_count_grad() * tuning(DDF_TUNE_GRAD_WG_PER_CU);
     const int w = net->width, p = net->precision;
-    if (train) {
-        if (p == kFP32 && !args.g_rays && args.n_nets == 0) return sweep_dispatch(w, args, s);
-        if (w == 128) return p == kBF16 ? launch_grad<kBF16, 128, 2, true>(args, s, cap) : launch_grad<kFP32, 128, 1, true>(args, s, cap);
-        return p == kBF16 ? launch_grad<kBF16, 256, 1, true>(args, s, cap) : launch_grad<kFP32, 256, 1, true>(args, s, cap);
+    if (train) {   // parameter gradients: float32 networks only (ddf_backward checks)
+        DDF_REQUIRE(p == kFP32, DDF_ERR_UNSUPPORTED, "parameter gradients need a float32 network");
+        if (!args.g_rays && args.n_nets == 0) return sweep_dispatch(w, args, s);
+        return w == 128 ? launch_grad<kFP32, 128, 1, true>(args, s, cap) : launch_grad<kFP32, 256, 1, true>(args, s, cap);
     }
     if (p == kBF16) return stream_dispatch(w, args, s);   // weights streamed through LDS
     return w == 128 ? launch_grad<kFP32, 128, 1, false>(args, s, cap) : launch_grad<kFP32, 256, 1, false>(args, s, cap);

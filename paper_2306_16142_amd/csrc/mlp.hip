@@ -119,7 +119,7 @@ __device__ inline float grad_weight(const float *params, const NetLayout &L, int
 __device__ inline void store_slot(uint8_t *tile_base, int prec, int lane, int s, float w, float scale) {
     if (prec == kFP32) reinterpret_cast<float *>(tile_base)[lane] = w;
     else if (prec == kBF16) reinterpret_cast<uint16_t *>(tile_base)[lane * 8 + s] = bf16_bits(w);
-    else tile_base[lane * 32 + s] = fp8_bits(scale > 0.f ? w / scale : 0.f);
+    else tile_base[(s / 16) * 1024 + lane * 16 + s % 16] = fp8_bits(scale > 0.f ? w / scale : 0.f);   // load_a's halves
 }
 
 // One thread per packed element: forward tile slots, biases, scales, transposed tile
@@ -1005,9 +1005,8 @@ ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, co
         return stream_dispatch(net->width, a, s);
     }
     if (net->width == 128) {
-        if (net->precision == kBF16)
-            return lds ? launch_forward<kBF16, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
-                       : launch_forward<kBF16, 128, 2, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
+        if (net->precision == kBF16)   // (bf16 networks beyond LDS took the streamed kernel above)
+            return launch_forward<kBF16, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
         // fp8 from L2 runs one 32-ray block per wave (two blocks spilled in that variant)
         if (net->precision == kFP8)
             return lds ? launch_forward<kFP8, 128, 2, true>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s)
@@ -1016,6 +1015,19 @@ ddf_status forward_dispatch(const ddf_net *net, const float *rays, int64_t n, co
     }
     if (net->precision == kBF16) return launch_forward<kBF16, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
     if (net->precision == kFP8) return launch_forward<kFP8, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
+    if (!absmax && !count_dev) {
+        // float32 at width 256: the training sweep's forward (layer values of 64 rays in LDS);
+        // the per-wave kernel would hold a whole layer's operands and outputs in registers
+        GradArgs a{};
+        a.blob = (const uint8_t *)net->packed;
+        a.depth = net->depth;
+        a.rays = rays;
+        a.n = n;
+        a.logit_out = logit;
+        a.dist_out = dist;
+        a.forward_only = true;
+        return sweep_dispatch(256, a, s);
+    }
     return launch_forward<kFP32, 256, 1, false>(L, net->packed, rays, n, count_dev, logit, dist, absmax, s);
 }
 

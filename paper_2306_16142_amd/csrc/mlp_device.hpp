@@ -96,11 +96,20 @@ __device__ inline f32x16 mfma(typename OpOf<P>::T a, typename OpOf<P>::T b, f32x
     else return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// A operand of one lane.  An fp8 tile (32 bytes per lane) is stored as two 1 KiB halves,
+// bytes 0-15 of every lane then bytes 16-31 of every lane, so that each of the two 16-byte
+// reads covers consecutive addresses across the lanes (free of LDS bank conflicts).
 template <int P>
 __device__ inline typename OpOf<P>::T load_a(const uint8_t *src, int64_t tile, int lane) {
     using Op = typename OpOf<P>::T;
-    const uint8_t *p = src + tile * tile_bytes(P) + (int64_t)lane * (tile_bytes(P) / 64);
-    return *reinterpret_cast<const Op *>(p);
+    if constexpr (P == kFP8) {
+        const uint8_t *p = src + tile * tile_bytes(P) + (int64_t)lane * 16;
+        const i32x4 lo = *reinterpret_cast<const i32x4 *>(p), hi = *reinterpret_cast<const i32x4 *>(p + 1024);
+        return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    } else {
+        const uint8_t *p = src + tile * tile_bytes(P) + (int64_t)lane * (tile_bytes(P) / 64);
+        return *reinterpret_cast<const Op *>(p);
+    }
 }
 
 // Packs 4 non-negative floats (already clamped to the e4m3 range) into one dword.

@@ -93,8 +93,16 @@ __device__ __attribute__((always_inline)) inline void sweep_mfma(const uint8_t *
     }
 }
 
+// Occupancy: at width 256 one workgroup per CU (two waves per SIMD, up to 256 registers: no
+// spill); at width 128 two workgroups per CU (four waves per SIMD, 128 registers, which spills
+// 176 bytes per lane of the head-chunk state).  Measured on MI355X, training step at batch
+// 65,536: width 256 1.40 ms against 1.44 ms with two workgroups and the spill; width 128
+// 0.46 ms with two workgroups and the spill against 0.51 ms with one and none.
 template <int W>
-__global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) {
+constexpr int sweep_wg_per_cu() { return W == 256 ? 1 : 2; }
+
+template <int W>
+__global__ __launch_bounds__(kSweepWaves * 64, sweep_wg_per_cu<W>() * 2) void sweep_kernel(GradArgs a) {
     using G = SweepGeo<W>;
     constexpr int NMB = G::NMB, NKB = G::NKB, NBW = G::NBW, XP = G::XP;
     constexpr int K0 = layer0_kblocks(kFP32);
@@ -148,7 +156,7 @@ __global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) 
             for (int f = 0; f < kFeatPerVar; ++f) {
                 dst[f] = valid ? feat[f] : 0.f;
                 const int c = feature_column(hh, kFeatPerVar * g + f);
-                if (valid && c >= 0) a.ws_gamma[(int64_t)c * n + r] = feat[f];
+                if (valid && c >= 0 && a.ws_gamma) a.ws_gamma[(int64_t)c * n + r] = feat[f];
             }
             if (hh == 0 && g == 2) dst[kFeatPerVar] = 0.f;   // pad slot 39 of lane half 0
         }
@@ -181,7 +189,7 @@ __global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) 
                     bits |= (z > 0.f ? 1u : 0u) << j;
                 }
                 mask_at(l, nb0 + nb) = (uint16_t)bits;
-                if (r < n) {
+                if (r < n && a.ws_h) {
                     float *dst = a.ws_h + ((int64_t)l * W + mb * 32 + 4 * h) * n + r;
 #pragma unroll
                     for (int j = 0; j < 16; ++j) dst[(int64_t)(8 * (j / 4) + (j % 4)) * n] = y[j];
@@ -242,10 +250,16 @@ __global__ __launch_bounds__(kSweepWaves * 64, 4) void sweep_kernel(GradArgs a) 
                 }
                 if (h == 0) {
                     if (valid) {
-                        if (a.logit_out) a.logit_out[r] = z;
-                        if (a.dist_out) a.dist_out[r] = dd;
-                        a.ws_delta[(int64_t)depth * W * n + r] = gl;
-                        a.ws_delta[(int64_t)depth * W * n + n + r] = gd;
+                        // a query with a NaN input gives NaN outputs (the ReLUs would hide it)
+                        bool nan_ray = false;
+#pragma unroll
+                        for (int j = 0; j < kInRaw; ++j) nan_ray |= isnan(a.rays[(int64_t)j * rstride + r]);
+                        if (a.logit_out) a.logit_out[r] = nan_ray ? NAN : z;
+                        if (a.dist_out) a.dist_out[r] = nan_ray ? NAN : dd;
+                        if (a.ws_delta) {
+                            a.ws_delta[(int64_t)depth * W * n + r] = gl;
+                            a.ws_delta[(int64_t)depth * W * n + n + r] = gd;
+                        }
                     }
                     s_seed[ray] = gl;
                     s_seed[kSweepRays + ray] = gd;
@@ -351,11 +365,12 @@ ddf_status launch_sweep(const GradArgs &a, hipStream_t s) {
 
 }  // namespace
 
-// Workgroups of the training sweep for n rays (each writes one loss partial): two per CU.
+// Workgroups of the training sweep for n rays (each writes one loss partial): one per CU at
+// width 256, two at width 128.
 int64_t sweep_grid(int width, int64_t n) {
-    (void)width;
     const int64_t tiles = (n + kSweepRays - 1) / kSweepRays;
-    return std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cu_count_sweep() * 2));
+    const int per_cu = width == 256 ? sweep_wg_per_cu<256>() : sweep_wg_per_cu<128>();
+    return std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cu_count_sweep() * per_cu));
 }
 
 // Float32 training sweep of one network (no input gradient): features, activations, adjoints,

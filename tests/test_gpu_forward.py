@@ -226,6 +226,12 @@ def test_forward_edge_cases():
     lg, ds = host(lg), host(ds)
     assert np.isnan(lg[3]) and np.isnan(ds[3])
     assert np.all(np.isfinite(np.delete(lg, 3))) and np.all(np.isfinite(np.delete(ds, 3)))
+    # float32 at width 256 (the sweep's forward) propagates NaN inputs too
+    net32 = api.Network(cuda(synthetic.random_params(256, 2, 17)), 256, 2, "fp32")
+    lg, ds = net32(cuda(rays))
+    lg, ds = host(lg), host(ds)
+    assert np.isnan(lg[3]) and np.isnan(ds[3])
+    assert np.all(np.isfinite(np.delete(lg, 3))) and np.all(np.isfinite(np.delete(ds, 3)))
 
 
 def test_fp8_scales_not_powers_of_two_give_nan():
