@@ -33,8 +33,11 @@
  *             HIP graph (those needing a workspace clear it with kernels).
  *   Errors    Arguments are validated before anything is enqueued.  On error
  *             nothing is launched, a non-zero ddf_status is returned and
- *             ddf_last_error() returns a thread-local message.  n == 0 is a no-op.
- *             No C++ exception crosses this boundary.
+ *             ddf_last_error() returns a thread-local message.  n == 0 is a no-op,
+ *             except where a loss is formed: ddf_loss_seeds(_ex), ddf_train_step(_chunked,
+ *             _ex, _eikonal) and ddf_paper_train_step reject an empty batch with
+ *             INVALID_ARG (the mean loss of no rays is undefined, and an Adam step on it
+ *             would still move the parameters).  No C++ exception crosses this boundary.
  */
 #ifndef DDF_H
 #define DDF_H
@@ -332,7 +335,8 @@ ddf_status ddf_train_step_ex(const ddf_net *net, float *params, float *adam_m, f
  * passes only: forward of both halves, seeds, one parameter-gradient sweep, Adam, repack.
  *   orig, dir [3][n] origins and directions (any non-zero length; normalised for the move);
  *   t_label [n] labels (+inf = miss); loss_out: device scalar (both terms, before the update);
- *   ws: ddf_eikonal_workspace_size(width, depth, n) bytes.
+ *   ws: ddf_eikonal_workspace_size(width, depth, n) bytes: the doubled batch is swept whole
+ *   (activations of 2 n rays, (65 + 2 depth width) x 8 n bytes; there is no chunked form).
  * Float32 networks only.  Errors: INVALID_ARG for a bad argument, h <= 0 or not finite,
  * lambda < 0 or not finite, a bad loss; WORKSPACE when ws is too small. */
 ddf_status ddf_eikonal_workspace_size(int32_t width, int32_t depth, int64_t n, size_t *bytes);

@@ -335,7 +335,11 @@ class Trainer:
 
     def step_eikonal(self, orig, dirs, t_label, h=0.02, lam=0.1):
         """One step with the directed Eikonal penalty of Eq. 2 added (forward difference along
-        each ray with step ``h``, weight ``lam``): rays given as origins + directions."""
+        each ray with step ``h``, weight ``lam``): rays given as origins + directions.  The
+        doubled batch is swept whole: a Trainer built with ``chunk`` refuses this step."""
+        if self.chunk:
+            raise ValueError("the Eikonal step sweeps the doubled batch whole; it has no chunked form "
+                             "(build the Trainer without chunk)")
         _dev(orig, torch.float32, "orig", 3)
         _dev(dirs, torch.float32, "dirs", 3)
         _dev(t_label, torch.float32, "t_label")

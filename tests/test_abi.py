@@ -226,3 +226,58 @@ def test_tuning_knobs_validate_and_round_trip(lib):
     assert lib.ddf_set_tuning(k, 4096) == _lib.DDF_OK
     assert lib.ddf_get_tuning(k, ctypes.byref(v)) == _lib.DDF_OK and v.value == 4096
     assert lib.ddf_set_tuning(k, 2048) == _lib.DDF_OK
+
+
+def test_empty_batch_is_rejected_where_a_loss_is_formed(lib):
+    """The header's exception to "n == 0 is a no-op": every entry point that forms a loss
+    rejects an empty batch before launching anything."""
+    from paper_2306_16142_amd import _lib
+    big = 1 << 40
+    f32 = _lib.DdfNet(128, 4, 0, 1)
+    clamp = _lib.DdfLoss(1, 1.0)
+    assert lib.ddf_loss_seeds(1, 1, 1, 0, 1, 1, 1, 1, big, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_loss_seeds_ex(1, 1, 1, 0, None, 1, 1, 1, 1, big, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_train_step(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 0, 1, 1, 1, big, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_train_step_chunked(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 0, 10, 1, 1, 1, big, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_train_step_ex(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 0, 0, None, 1, 1, 1, big, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_train_step_eikonal(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 1, 0, 0.01, 0.1, None, 1, 1, 1, big,
+                                      None) == _lib.DDF_ERR_INVALID_ARG
+    paper = _lib.DdfPaperNet(8, 0, 1)
+    assert lib.ddf_paper_train_step(ctypes.byref(paper), 1, 1, 1, 1, 1e-3, 1, 1, 0, ctypes.byref(clamp), 1, 1, 1, big,
+                                    None) == _lib.DDF_ERR_INVALID_ARG
+    # the queries and gradients stay no-ops on an empty batch
+    assert lib.ddf_forward(ctypes.byref(f32), None, 0, None, None, None) == _lib.DDF_OK
+    assert lib.ddf_paper_forward(ctypes.byref(_lib.DdfPaperNet(8, 1, 1)), None, 0, None, None) == _lib.DDF_OK
+    assert lib.ddf_paper_backward(ctypes.byref(paper), None, None, 0, None, None, None, 0, None, 0, None) == _lib.DDF_OK
+
+
+def test_paper_network_validation(lib):
+    from paper_2306_16142_amd import _lib
+    c, b = ctypes.c_int64(0), ctypes.c_size_t(0)
+    assert lib.ddf_paper_param_count(8, ctypes.byref(c)) == _lib.DDF_OK
+    assert c.value == 5 * 512 + 7 * 512 * 512 + 2 * 8 * 512 + 512 + 1
+    assert lib.ddf_paper_param_count(9, ctypes.byref(c)) == _lib.DDF_ERR_UNSUPPORTED
+    assert lib.ddf_paper_packed_bytes(8, 2, ctypes.byref(b)) == _lib.DDF_ERR_UNSUPPORTED   # no fp8 form
+    assert lib.ddf_paper_packed_bytes(8, 1, ctypes.byref(b)) == _lib.DDF_OK and b.value > 7 * 512 * 512 * 2
+    bf = _lib.DdfPaperNet(8, 1, 1)
+    # parameter gradients need float32 and the parameters
+    assert lib.ddf_paper_backward(ctypes.byref(bf), 1, 1, 10, None, None, 1, 0, 1, 1 << 40, None) == \
+        _lib.DDF_ERR_UNSUPPORTED
+    f32 = _lib.DdfPaperNet(8, 0, 1)
+    assert lib.ddf_paper_backward(ctypes.byref(f32), None, 1, 10, None, None, 1, 0, 1, 1 << 40, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_paper_backward(ctypes.byref(f32), 1, 1, 10, None, None, 1, 0, 1, 16, None) == _lib.DDF_ERR_WORKSPACE
+    # the paper's network trains on its own losses only (clamp, squish)
+    assert lib.ddf_paper_train_step(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 10, ctypes.byref(_lib.DdfLoss(0, 1.0)),
+                                    1, 1, 1, 1 << 40, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_paper_train_step(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 10, None, 1, 1, 1, 1 << 40, None) == \
+        _lib.DDF_ERR_INVALID_ARG
+
+
+def test_udf_noalloc_validation(lib):
+    from paper_2306_16142_amd import _lib
+    net = _lib.DdfNet(128, 4, 1, 1)
+    assert lib.ddf_udf_noalloc(ctypes.byref(net), 1, 10, 1, 65537, 1, 1, None) == _lib.DDF_ERR_UNSUPPORTED
+    assert b"65536" in lib.ddf_last_error()
