@@ -439,7 +439,12 @@ def bench_label_train_render(args, torch, api, dev):
     torch.cuda.synchronize()
     rs = (time.perf_counter() - t0) / reps
     paths = cfg.width * cfg.height * cfg.spp
-    stats = [int(x) for x in r.stats.cpu().numpy()]
+    entering, shadows, _ = r.path_stats()
+    entering, shadows = [int(x) for x in entering], [int(x) for x in shadows]
+    # network work of the frame from the device queue counts: every path entering a bounce is
+    # one query plus its input gradient (the transposed product, the same multiply-adds as the
+    # forward), every shadow ray one query
+    frame_flop = (2 * sum(entering) + sum(shadows)) * flop_per_query(width, depth)
     # shading normals against the mesh normal at the brute-force hit point (primary hits)
     cfg1 = synthetic.full_render(1)
     cfg1.bounces = 1
@@ -454,7 +459,10 @@ def bench_label_train_render(args, torch, api, dev):
     hit_agree = float((torch.isfinite(rm.depth) == torch.isfinite(rn.depth)).float().mean()) * 100
     out["render"] = {"workload": "1920x1080, %d spp, 4 bounces, RR after bounce 2, bf16 6x256 network "
                                  "(trained %d steps)" % (cfg.spp, 3 + args.train_steps + args.render_train_steps),
-                     "seconds_per_frame": rs, "path_samples_per_s": paths / rs, "timing": "warm hipGraph replay of the whole frame", "paths_per_bounce": stats,
+                     "seconds_per_frame": rs, "path_samples_per_s": paths / rs, "timing": "warm hipGraph replay of the whole frame",
+                     "paths_per_bounce": entering, "shadow_rays_per_bounce": shadows,
+                     "network_flop_per_frame": frame_flop, "network_tflops": frame_flop / rs / 1e12,
+                     "roofline_frac_bf16": frame_flop / rs / 1e12 / PEAK["bf16"],
                      "normal_angle_err_deg_mean": float(ang.mean()) if ang.size else None,
                      "normal_angle_err_deg_median": float(np.median(ang)) if ang.size else None,
                      "primary_hit_agreement_vs_mesh_pct": hit_agree}
@@ -509,7 +517,7 @@ def bench_multi(args, torch, api, dev):
         r.replay()
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
-    paths, per_net = r.path_stats()
+    paths, _, per_net = r.path_stats()
     per_net = per_net.astype(np.float64)
     imb = [float(row.max() / row.mean()) if row.mean() > 0 else None for row in per_net]
     return {"multi_object": {

@@ -192,13 +192,14 @@ def render(scene, cfg, pixels=None):
     Returns a dict: ``radiance`` [3, H, W] (mean over samples), ``depth`` [H, W]
     and ``normal`` [3, H, W] of sample 0's primary hit (depth +inf and normal 0
     on a miss), ``robust`` [H, W] (every query of every sample of the pixel was
-    decided away from its threshold), and ``active`` per bounce (number of
-    paths that entered the bounce).
+    decided away from its threshold), ``active`` per bounce (number of
+    paths that entered the bounce) and ``shadow`` per bounce (number of shadow
+    rays traced: hits whose normal faces the light).
 
     ``pixels``: optional flat pixel indices (row * W + column).  Only those pixels
     are traced (every path is independent, so each one is traced exactly as in the
     whole frame) and the per-pixel arrays come back as [3, len] / [len] in that
-    order; ``active`` then counts the paths of those pixels only.
+    order; ``active`` and ``shadow`` then count the paths of those pixels only.
     """
     W, H, S = cfg.width, cfg.height, cfg.spp
     pix = np.arange(W * H, dtype=np.int64) if pixels is None else np.asarray(pixels, dtype=np.int64)
@@ -218,7 +219,7 @@ def render(scene, cfg, pixels=None):
     robust = np.ones(P, dtype=bool)
     depth0 = np.full(P, np.inf)
     normal0 = np.zeros((3, P))
-    active = []
+    active, shadow = [], []
     for b in range(cfg.bounces):
         idx = np.nonzero(alive)[0]
         active.append(int(idx.size))
@@ -247,6 +248,7 @@ def render(scene, cfg, pixels=None):
         l = lv / r[None]
         cosl = np.sum(n * l, axis=0)
         lit = cosl > 0.0
+        shadow.append(int(lit.sum()))
         vis = np.zeros(idx.size, dtype=bool)
         if lit.any():
             occ, ok = scene.occluded(xs[:, lit], l[:, lit], r[lit])
@@ -283,4 +285,5 @@ def render(scene, cfg, pixels=None):
         "normal": normal0[:, first].reshape((3,) + shape),
         "robust": robust.reshape(npx, S).all(axis=1).reshape(shape),
         "active": active,
+        "shadow": shadow,
     }

@@ -425,7 +425,7 @@ class Renderer:
         self.radiance = torch.empty((3, H, W), device=device, dtype=torch.float32)
         self.depth = torch.empty((H, W), device=device, dtype=torch.float32)
         self.normal = torch.empty((3, H, W), device=device, dtype=torch.float32)
-        nstats = cfg.bounces * (1 + (len(nets) if nets is not None else 0))
+        nstats = cfg.bounces * (2 + (len(nets) if nets is not None else 0))
         self.stats = torch.empty(nstats, device=device, dtype=torch.int32)
 
     def render(self):
@@ -451,12 +451,13 @@ class Renderer:
         return self.radiance
 
     def path_stats(self):
-        """Paths entering each bounce, and (multi-object scenes) pairs per network per bounce."""
+        """Paths entering each bounce, shadow rays traced in each bounce, and (multi-object
+        scenes) pairs per network per bounce."""
         st = self.stats.cpu().numpy()
         b = self.cfg.bounces
-        paths = st[:b]
-        per_net = st[b:].reshape(b, -1) if st.size > b else None
-        return paths, per_net
+        paths, shadows = st[:b], st[b:2 * b]
+        per_net = st[2 * b:].reshape(b, -1) if st.size > 2 * b else None
+        return paths, shadows, per_net
 
 
 def fp8_scales(params, width, depth, calib_rays, net_fp32=None):

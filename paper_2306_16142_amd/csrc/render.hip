@@ -530,9 +530,13 @@ __global__ void fill_kernel(float *img, int64_t n, float v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) img[i] = v;
 }
 
+// Per bounce: paths entering it (stats[b]) and shadow rays it traced (stats[bounces + b]).
 __global__ void stats_kernel(const int *counts, int bounces, uint32_t *stats) {
     const int b = threadIdx.x;
-    if (b < bounces) stats[b] += (uint32_t)counts[2 * b];
+    if (b < bounces) {
+        stats[b] += (uint32_t)counts[2 * b];
+        stats[bounces + b] += (uint32_t)counts[2 * b + 1];
+    }
 }
 
 
@@ -873,7 +877,7 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
         hipLaunchKernelGGL(fill_kernel, dim3(grid_for(w.P)), dim3(256), 0, s, w.pb.ones, w.P, 1.0f);
     }
     hipLaunchKernelGGL(fill_kernel, dim3(grid_for(3 * hw)), dim3(256), 0, s, radiance, 3 * hw, 0.f);
-    const int64_t nstats = (int64_t)p->bounces * (multi ? 1 + scene->n_nets : 1);
+    const int64_t nstats = (int64_t)p->bounces * (multi ? 2 + scene->n_nets : 2);
     if (stats) hipLaunchKernelGGL(fill_kernel, dim3(grid_for(nstats)), dim3(256), 0, s, (float *)stats, nstats, 0.f);
     for (int base = 0; base < p->spp; base += S) {
         const int Sc = std::min(S, p->spp - base);
@@ -902,7 +906,7 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
                 if (ddf_status st = grad_dispatch(scene->net, a, false, s)) return st;
             } else if (multi) {
                 if (ddf_status st = multi_query(scene, mp, w, Cc, q, cnt, ps.o, ps.d, false,
-                                                stats ? stats + p->bounces + (int64_t)b * scene->n_nets : nullptr,
+                                                stats ? stats + 2 * p->bounces + (int64_t)b * scene->n_nets : nullptr,
                                                 nullptr, s))
                     return st;
                 qdist = w.hit_t;

@@ -45,10 +45,12 @@ def test_label_icosphere_uniform_rays():
 
 
 def test_label_training_mesh_subset_ragged():
-    banner("label: training mesh 20480 tris x 3001 training rays (seed 1)")
+    """The labeller workload's mesh and ray mix (20,480 triangles, training rays) on a 2^14-ray
+    subset plus a ragged tail of 5 (the float64 oracle takes about half a minute)."""
+    banner("label: training mesh 20480 tris x 16389 training rays (seed 1)")
     v, f = synthetic.training_mesh(1)
     tris = synthetic.tri_soup(v, f)
-    o, d, _ = synthetic.training_rays(v, f, 3001, 1)
+    o, d, _ = synthetic.training_rays(v, f, (1 << 14) + 5, 1)
     frac_ok, frac_hit = _check(o, d, tris)
     assert frac_ok > 0.99 and frac_hit > 0.5
 

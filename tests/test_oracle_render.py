@@ -189,3 +189,25 @@ def test_pixel_subset_equals_whole_frame():
     np.testing.assert_array_equal(part["normal"], whole["normal"][:, r, c])
     np.testing.assert_array_equal(part["robust"], whole["robust"][r, c])
     assert whole["radiance"][:, r, c].max() > 0 and np.isfinite(whole["depth"][r, c]).any()
+
+
+def test_shadow_ray_counts():
+    """Shadow rays are traced exactly for hits whose normal faces the light: with the light at
+    the centre of the closed convex icosphere every outward normal faces away from it (no
+    shadow rays, a black image), with the light outside some hits face it; a split of the
+    pixels into two sets splits both counts."""
+    from synthetic.scenes import Light
+    v, f = synthetic.icosphere(1, 0.8)
+    scene = render.MeshScene(synthetic.tri_soup(v, f))
+    cfg = synthetic.RenderConfig(16, 12, 2, 3, 1, 2)
+    out = render.render(scene, cfg)
+    assert out["shadow"][0] > 0 and all(s <= a for s, a in zip(out["shadow"], out["active"]))
+    inside = synthetic.RenderConfig(16, 12, 2, 3, 1, 2, light=Light(position=(0.0, 0.0, 0.0)))
+    dark = render.render(scene, inside)
+    assert dark["active"][0] == 16 * 12 * 2 and dark["active"][1] > 0
+    assert sum(dark["shadow"]) == 0 and dark["radiance"].max() == 0
+    pix = np.arange(16 * 12)
+    a, b = render.render(scene, cfg, pixels=pix[::2]), render.render(scene, cfg, pixels=pix[1::2])
+    pad = lambda c: c + [0] * (cfg.bounces - len(c))
+    assert [x + y for x, y in zip(pad(a["shadow"]), pad(b["shadow"]))] == pad(out["shadow"])
+    assert [x + y for x, y in zip(pad(a["active"]), pad(b["active"]))] == pad(out["active"])
