@@ -299,34 +299,44 @@ __device__ inline void paper_phase(const PaperLayout &L, int q, int64_t &off, in
 }
 
 // The ring of one workgroup: global phase counter g (phase g % NP of the workgroup's tile
-// g / NP), phases beyond `gend` do not exist.
+// g / NP), phases beyond `gend` do not exist.  The blob is read through a buffer resource
+// (loads past its end return zero instead of faulting).
 struct PRing {
-    const uint8_t *blob;
+    __amdgpu_buffer_rsrc_t blob;
     PaperLayout L;
     int np;          // phases per tile
+    int qf;          // phase within its tile of the next phase to fetch, (g + 2) % np
     int64_t gend;    // phases of this workgroup
     int64_t g;       // current phase
 };
 
-// This wave's share of phase gq's 16 tiles, loaded straight into its stage (16 bytes per lane:
-// one instruction moves a whole 1 KiB tile): tiles wave, wave + 4, wave + 8, wave + 12.
-__device__ inline void paper_fetch(const PRing &rg, int64_t gq, lds_u8 *ring, int wave, int lane) {
+// This wave's share of phase gq's 16 tiles (q = gq % np, kept by the caller), loaded straight
+// into its stage (16 bytes per lane: one instruction moves a whole 1 KiB tile): tiles wave,
+// wave + 4, wave + 8, wave + 12.  Buffer loads that write LDS (not the global form) keep the
+// compiler's waits for the ring's LDS reads exact: after a global load into LDS it waits for
+// every outstanding LDS read instead of only the one an MFMA needs.
+__device__ inline void paper_fetch(const PRing &rg, int64_t gq, int q, lds_u8 *ring, int wave, int lane) {
     if (gq >= rg.gend) return;   // wave-uniform
     int64_t off;
     int cnt;
-    paper_phase(rg.L, (int)(gq % rg.np), off, cnt);
+    paper_phase(rg.L, q, off, cnt);
     lds_u8 *stage = ring + (int)(gq % kPStages) * kPStageBytes;
-    gbl_u8 *g = (gbl_u8 *)(rg.blob + off) + lane * 16;
     (void)cnt;   // every phase has 16 tiles
 #pragma unroll
     for (int j = 0; j < 16 / kPWaves; ++j) {
         const int i = wave + kPWaves * j;
-        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(g + i * 1024),
-                                         (__attribute__((address_space(3))) void *)(stage + i * 1024), 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rg.blob, (__attribute__((address_space(3))) void *)(stage + i * 1024),
+                                                 16, (int)off + i * 1024 + lane * 16, 0, 0, 0);
     }
 }
 
-// The LDS writes of global_load_lds are not tracked by the compiler: wait for them (vmcnt(0))
+// Fetches phase g + 2 and advances the fetch phase index.
+__device__ inline void paper_fetch_next(PRing &rg, lds_u8 *ring, int wave, int lane) {
+    paper_fetch(rg, rg.g + 2, rg.qf, ring, wave, lane);
+    rg.qf = rg.qf + 1 == rg.np ? 0 : rg.qf + 1;
+}
+
+// The LDS writes of the buffer loads are not tracked by the compiler: wait for them (vmcnt(0))
 // before the barrier that publishes a stage.
 __device__ inline void paper_stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
@@ -360,6 +370,16 @@ __device__ __attribute__((always_inline)) inline void pchain(const lds_u8 *st, c
 #pragma unroll
         for (int j = 0; j < kPAR; ++j) ar.r[j] = t.r[(KS + j) % kPAR];
     }
+    // Schedule: the ring's first reads (when loaded here), then per K-step its MFMA and the LDS
+    // read that refills the slot it freed, so that kPAR - 1 MFMAs cover each read's latency.
+    // Left to itself the compiler sinks every read to just before its MFMA (two reads, a wait
+    // for both, two MFMAs), exposing the LDS latency at every other step.
+    if constexpr (kLoadFirst) __builtin_amdgcn_sched_group_barrier(0x100, kPAR, 0);   // LDS read
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+        if (ks + kPAR < KS || kNext) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
 }
 
 __device__ inline const lds_u8 *pstage(lds_u8 *ring, int64_t g) { return ring + (int)(g % kPStages) * kPStageBytes; }
@@ -370,10 +390,10 @@ __device__ __attribute__((always_inline)) inline void paper_pair(PRing &rg, lds_
                                                                  const bf16x8 (&bin)[kPNKB][1], f32x16 &acc,
                                                                  const f32x16 &init, int wave, int lane) {
     acc = init;
-    paper_fetch(rg, rg.g + 2, ring, wave, lane);
+    paper_fetch_next(rg, ring, wave, lane);
     pchain<16, 0, true, true>(pstage(ring, rg.g), pstage(ring, rg.g + 1), ar, bin, acc, lane);
     ++rg.g;
-    paper_fetch(rg, rg.g + 2, ring, wave, lane);
+    paper_fetch_next(rg, ring, wave, lane);
     pchain<16, 16, false, false>(pstage(ring, rg.g), nullptr, ar, bin, acc, lane);
     ++rg.g;
     paper_stage_wait();
@@ -489,11 +509,12 @@ __global__ __launch_bounds__(kPWaves * 64, 1) void paper_stream_kernel(PaperArgs
     const int64_t ntile = (n + kPRays - 1) / kPRays;
     if ((int64_t)blockIdx.x >= ntile) return;   // the whole workgroup
     PRing rg;
-    rg.blob = a.blob;
+    rg.blob = __builtin_amdgcn_make_buffer_rsrc((void *)a.blob, 0, (int)L.bytes, 0x00020000);
     rg.L = L;
     rg.np = 2 * kPNMB * (depth - 1) + 2 + (kGrad ? 2 * kPNMB * (depth - 1) + 2 : 0);
     rg.gend = ((ntile - blockIdx.x + gridDim.x - 1) / gridDim.x) * rg.np;
     rg.g = 0;
+    rg.qf = 2 % rg.np;
     {   // first-layer tiles and the output row stay in LDS; phases 0 and 1 into stages 0 and 1
         const i32x4 *src = reinterpret_cast<const i32x4 *>(a.blob + L.l0_off);
         for (int i = threadIdx.x; i < kPNMB * kPK0 * 16; i += blockDim.x)
@@ -502,8 +523,8 @@ __global__ __launch_bounds__(kPWaves * 64, 1) void paper_stream_kernel(PaperArgs
         for (int i = threadIdx.x; i < kPW + 4; i += blockDim.x) reinterpret_cast<float *>(smem + S.row)[i] = row[i];
         const float *bias = reinterpret_cast<const float *>(a.blob + L.bias_off);
         for (int i = threadIdx.x; i < (depth - 1) * kPW; i += blockDim.x) reinterpret_cast<float *>(smem + S.bias)[i] = bias[i];
-        paper_fetch(rg, 0, ring, wave, lane);
-        paper_fetch(rg, 1, ring, wave, lane);
+        paper_fetch(rg, 0, 0, ring, wave, lane);
+        paper_fetch(rg, 1, 1 % rg.np, ring, wave, lane);
         paper_stage_wait();
         __syncthreads();
     }

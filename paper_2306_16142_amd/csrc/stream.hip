@@ -4,7 +4,7 @@
 // A workgroup evaluates 256 rays at a time and streams the weight tiles through an LDS ring
 // that all its waves read.  One "phase" is one 32-row M-block of one layer (its K-blocks,
 // plus the bias K-block of a hidden layer).  At the start of phase p each wave issues its
-// share of phase p + 2 as loads that write LDS directly (global_load_lds) and waits for them
+// share of phase p + 2 as buffer loads that write LDS directly and waits for them
 // before the next barrier, which publishes the stages: at width 128 one barrier per phase
 // (three stages), at width 256 one per pair of phases (four stages).  The table lookup that locates a phase's tiles is done one phase
 // early, across the previous barrier, so a phase begins with its loads and its MFMA chain.
@@ -191,23 +191,27 @@ __device__ inline lds_u8 *stage_ptr(lds_u8 *ring, int st) {
 }
 
 // Fetches this wave's share of the phase that `d` describes straight into its LDS stage
-// (global_load_lds, 16 bytes per lane: one instruction moves one whole 1 KiB tile, lane-major,
-// which is the tile's layout).  Branch-free over the share: slot i takes tile min(i, ks - 1),
-// so extra loads of a short phase rewrite its last tile with the same bytes.
+// (buffer loads that write LDS, 16 bytes per lane: one instruction moves one whole 1 KiB tile,
+// lane-major, which is the tile's layout).  Branch-free over the share: slot i takes tile
+// min(i, ks - 1), so extra loads of a short phase rewrite its last tile with the same bytes.
+// The buffer form (not the global one) keeps the compiler's waits for the ring's LDS reads
+// exact: after a global load into LDS it waits for every outstanding LDS read instead of only
+// the one an MFMA needs.  The resource covers exactly the phase's tiles.
 template <int W>
 __device__ inline void stage_fetch(Stage<W> &sg, const Desc &d, lds_u8 *stage, int wave, int lane) {
     sg.cnt = d.live;
     if (!sg.cnt) return;
-    gbl_u8 *g = (gbl_u8 *)d.addr + lane * 16;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)d.addr, 0, (d.ks - 1) * d.stride + 1024, 0x00020000);
 #pragma unroll
     for (int j = 0; j < Stage<W>::kMax; ++j) {
         const int i = min(wave + Geo<W>::kWaves * j, d.ks - 1);
-        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(g + i * d.stride),
-                                         (__attribute__((address_space(3))) void *)(stage + i * 1024), 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)(stage + i * 1024), 16,
+                                                 i * d.stride + lane * 16, 0, 0, 0);
     }
 }
 
-// The compiler does not track the LDS writes of global_load_lds: wait for them explicitly
+// The compiler does not track the LDS writes of the buffer loads: wait for them explicitly
 // (vmcnt(0), other counters left alone) before the barrier that publishes the stage.
 __device__ inline void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
