@@ -269,33 +269,21 @@ __host__ __device__ inline PLds paper_lds(int depth, bool grad) {
     return s;
 }
 
-// Phase q of a tile's program -> (byte offset of its first tile in the blob, tile count):
-// hidden layers (l, mb, half), the output row's two halves, then for gradients the
-// transposed hidden layers from the top and the transposed first layer.
-__device__ inline void paper_phase(const PaperLayout &L, int q, int64_t &off, int &cnt) {
-    const int nh = 2 * kPNMB * (L.depth - 1);
-    if (q < nh) {
-        const int l = 1 + q / (2 * kPNMB), mb = (q % (2 * kPNMB)) / 2, half = q & 1;
-        off = L.hid_off + ((int64_t)((l - 1) * kPNMB + mb) * kPNKB + 16 * half) * 1024;
-        cnt = 16;
-        return;
-    }
-    q -= nh;
-    if (q < 2) {
-        off = L.head_off + (int64_t)16 * q * 1024;
-        cnt = 16;
-        return;
-    }
-    q -= 2;
-    if (q < nh) {
-        const int l = L.depth - 1 - q / (2 * kPNMB), mb = (q % (2 * kPNMB)) / 2, half = q & 1;
-        off = L.tr_off + ((int64_t)((l - 1) * kPNMB + mb) * kPNKB + 16 * half) * 1024;
-        cnt = 16;
-        return;
-    }
-    q -= nh;
-    off = L.tr_off + ((int64_t)(L.depth - 1) * kPNMB * kPNKB + 16 * q) * 1024;
-    cnt = 16;
+// Phase q of a tile's program -> byte offset of its 16 tiles in the blob: the hidden layers
+// (l, mb, half) and the output row's two halves lie back to back (phase q at hid_off + q x 16
+// KiB), then for gradients the transposed hidden layers from the top and the transposed first
+// layer.  Selects instead of branches: the fetch runs between MFMAs of a wave that is alone on
+// its SIMD, where every taken branch idles the matrix core.
+__device__ inline int paper_phase_off(const PaperLayout &L, int q) {
+    const int nh = L.depth - 1;
+    const int nfw = 32 * nh + 2;   // phases of the forward program
+    const int q2 = q - nfw;
+    // transposed hidden layer from the top: (nh - 1 - q2 / 32) x 512 + (q2 % 32) x 16 KiB; past
+    // them the transposed first layer: nh x 512 + (q2 - 32 nh) x 16 KiB
+    const int last = -(int)(q2 >= 32 * nh);   // all ones in the transposed first layer
+    const int tr_kib = (((nh - 1 - (q2 >> 5)) * 512 + (q2 & 31) * 16) & ~last) | ((nh * 512 + (q2 - 32 * nh) * 16) & last);
+    const int fw = -(int)(q < nfw);
+    return (((int)L.hid_off + q * 16384) & fw) | (((int)L.tr_off + tr_kib * 1024) & ~fw);
 }
 
 // The ring of one workgroup: global phase counter g (phase g % NP of the workgroup's tile
@@ -317,16 +305,13 @@ struct PRing {
 // every outstanding LDS read instead of only the one an MFMA needs.
 __device__ inline void paper_fetch(const PRing &rg, int64_t gq, int q, lds_u8 *ring, int wave, int lane) {
     if (gq >= rg.gend) return;   // wave-uniform
-    int64_t off;
-    int cnt;
-    paper_phase(rg.L, q, off, cnt);
-    lds_u8 *stage = ring + (int)(gq % kPStages) * kPStageBytes;
-    (void)cnt;   // every phase has 16 tiles
+    const int off = paper_phase_off(rg.L, q);
+    lds_u8 *stage = ring + (int)((uint32_t)gq % kPStages) * kPStageBytes;
 #pragma unroll
     for (int j = 0; j < 16 / kPWaves; ++j) {
         const int i = wave + kPWaves * j;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rg.blob, (__attribute__((address_space(3))) void *)(stage + i * 1024),
-                                                 16, (int)off + i * 1024 + lane * 16, 0, 0, 0);
+                                                 16, off + i * 1024 + lane * 16, 0, 0, 0);
     }
 }
 
@@ -382,7 +367,7 @@ __device__ __attribute__((always_inline)) inline void pchain(const lds_u8 *st, c
     }
 }
 
-__device__ inline const lds_u8 *pstage(lds_u8 *ring, int64_t g) { return ring + (int)(g % kPStages) * kPStageBytes; }
+__device__ inline const lds_u8 *pstage(lds_u8 *ring, int64_t g) { return ring + (int)((uint32_t)g % kPStages) * kPStageBytes; }
 
 // A pair of phases (the two halves of one M-block's contraction) between barriers; the
 // accumulation starts from `init` (the M-block's float32 biases, or zero).
