@@ -331,12 +331,15 @@ ddf_status ddf_train_step_ex(const ddf_net *net, float *params, float *adam_m, f
  * taken as a forward difference along the ray, r = (phi(x + h d) - phi(x)) / h + 1, and the
  * loss is `loss`'s (NULL: DDF_LOSS_BCE_L1) on the rays plus lambda / n * sum r^2 over rays
  * whose label is a hit farther than h.  The batch is doubled internally (the rays at their
- * origins and moved by h along their unit direction), so the gradient needs first-order
- * passes only: forward of both halves, seeds, one parameter-gradient sweep, Adam, repack.
+ * origins and moved by h along their unit direction, each ray and its moved copy in the same
+ * 64-column tile of the training sweep), so the gradient needs first-order passes only: one
+ * sweep forms both outputs of every pair, the pair's loss and penalty seeds in its workgroup,
+ * and the adjoints; then the weight-gradient products, Adam, repack.
  *   orig, dir [3][n] origins and directions (any non-zero length; normalised for the move);
  *   t_label [n] labels (+inf = miss); loss_out: device scalar (both terms, before the update);
  *   ws: ddf_eikonal_workspace_size(width, depth, n) bytes: the doubled batch is swept whole
- *   (activations of 2 n rays, (65 + 2 depth width) x 8 n bytes; there is no chunked form).
+ *   (activations of 2 n rays (n rounded up to 32), about (65 + 2 depth width) x 8 n bytes;
+ *   there is no chunked form).
  * Float32 networks only.  Errors: INVALID_ARG for a bad argument, h <= 0 or not finite,
  * lambda < 0 or not finite, a bad loss; WORKSPACE when ws is too small. */
 ddf_status ddf_eikonal_workspace_size(int32_t width, int32_t depth, int64_t n, size_t *bytes);

@@ -22,6 +22,11 @@ struct GradArgs {
     const float *t_label;        // training: label distance, +inf = miss (NULL: seeds from g_*_in)
     const float *loss_scalars;   // training: {1 / N, 1 / n_hit}
     LossSpec loss;               // training: which loss forms the seeds (zero: BCE + L1)
+    int64_t eik_n;               // training sweep only, > 0: directed Eikonal pairs of eik_n rays
+                                 // (64-column tiles: 32 rays, then the same rays moved by eik_h
+                                 // along their directions; t_label indexed by ray); the seeds add
+                                 // the penalty eik_lam / N sum ((d(x + h d) - d(x)) / h + 1)^2
+    float eik_h, eik_lam;
     float *logit_out;            // optional
     float *dist_out;             // optional
     float *g_rays;               // optional [5][n]

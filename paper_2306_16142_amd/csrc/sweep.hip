@@ -222,22 +222,41 @@ __global__ __launch_bounds__(kSweepWaves * 64, sweep_wg_per_cu<W>() * 2) void sw
         __syncthreads();
         if (mb == 0) {
             const float hb0 = bias[W * depth], hb1 = bias[W * depth + 1];
+            // head output `row` (0: logit, 1: distance) of ray col of ray block blk
+            auto head_sum = [&](int blk, int row) {
+                float v = 0.f;
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) v += s_hpart[((c * 2 + blk) * 2 + row) * 32 + col];
+                return v + (row ? hb1 : hb0);
+            };
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) {
-                const int ray = (nb0 + nb) * 32 + col;
+                const int blk = nb0 + nb;
+                const int ray = blk * 32 + col;
                 const int64_t r = base + ray;
                 const bool valid = r < n;
-                float z = 0.f, dd = 0.f;
-#pragma unroll
-                for (int c = 0; c < kChunks; ++c) {
-                    const float *hp = s_hpart + ((c * 2 + nb0 + nb) * 2) * 32 + col;
-                    z += hp[0];
-                    dd += hp[32];
-                }
-                z += hb0;
-                dd += hb1;
+                const float z = head_sum(blk, 0), dd = head_sum(blk, 1);
                 float gl = 0.f, gd = 0.f;
-                if (a.t_label) {
+                if (a.eik_n > 0) {
+                    // directed Eikonal pairs: block 0 holds rays base / 2 + col, block 1 the same
+                    // rays moved by h along their directions; residual r = (d(x + h d) - d(x)) / h + 1
+                    const int64_t i = base / 2 + col;
+                    const bool ok = i < a.eik_n;
+                    const float t = ok ? a.t_label[i] : INFINITY;
+                    const float d_at = blk == 0 ? dd : head_sum(0, 1), d_moved = blk == 0 ? head_sum(1, 1) : dd;
+                    const bool on = ok && t < INFINITY && t > a.eik_h;
+                    const float res = on ? (d_moved - d_at) / a.eik_h + 1.f : 0.f;
+                    const float g = 2.f * a.eik_lam * res * inv_n / a.eik_h;
+                    if (blk == 0) {
+                        float g0, g1;
+                        const float term = ray_loss(z, dd, t, inv_n, inv_nhit, a.loss, g0, g1);
+                        gl = ok ? g0 : 0.f;
+                        gd = ok ? g1 - g : 0.f;
+                        if (h == 0 && ok) loss_acc += term + a.eik_lam * res * res * inv_n;
+                    } else {
+                        gd = g;
+                    }
+                } else if (a.t_label) {
                     const float t = valid ? a.t_label[r] : INFINITY;
                     float g0, g1;
                     const float term = ray_loss(z, dd, t, inv_n, inv_nhit, a.loss, g0, g1);

@@ -601,80 +601,51 @@ namespace ddf {
 namespace {
 
 // rays [5][2n]: columns 0..n-1 at the origins, n..2n-1 moved by h along the unit direction.
-__global__ void eikonal_pairs_kernel(const float *__restrict__ orig, const float *__restrict__ dir, int64_t n, float h,
-                                     float *__restrict__ rays) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Directed Eikonal pairs in the training sweep's 64-column tiles: tile j holds rays 32 j ..
+// 32 j + 31 (columns 64 j + c), then the same rays moved by h along their unit directions
+// (columns 64 j + 32 + c); columns past the n rays are zero rays (their seeds are zero).
+__global__ void eikonal_pairs_kernel(const float *__restrict__ orig, const float *__restrict__ dir, int64_t n,
+                                     int64_t m, float h, float *__restrict__ rays) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // ray slot, < m / 2
+    if (2 * i >= m) return;
+    const int64_t ca = (i / 32) * 64 + i % 32, cb = ca + 32;
+    if (i >= n) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) rays[c * m + ca] = rays[c * m + cb] = 0.f;
+        return;
+    }
     const float dx = dir[i], dy = dir[n + i], dz = dir[2 * n + i];
     float theta, phi;
     dir_angles(dx, dy, dz, theta, phi);
     const float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
     const float d[3] = {dx * inv, dy * inv, dz * inv};
-    const int64_t m = 2 * n;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const float o = orig[c * n + i];
-        rays[c * m + i] = o;
-        rays[c * m + n + i] = fmaf(h, d[c], o);
+        rays[c * m + ca] = o;
+        rays[c * m + cb] = fmaf(h, d[c], o);
     }
-    rays[3 * m + i] = rays[3 * m + n + i] = theta;
-    rays[4 * m + i] = rays[4 * m + n + i] = phi;
+    rays[3 * m + ca] = rays[3 * m + cb] = theta;
+    rays[4 * m + ca] = rays[4 * m + cb] = phi;
 }
 
-// Adds the penalty's seeds to g_dist[0..n), writes them to g_dist[n..2n) (g_logit there 0),
-// and one partial of lam / n * sum r^2 per block.
-__global__ void eikonal_seeds_kernel(const float *__restrict__ dist, const float *__restrict__ t_label, int64_t n,
-                                     float h, float lam, float *__restrict__ g_logit, float *__restrict__ g_dist,
-                                     float *__restrict__ part) {
-    __shared__ float red[256];
-    const float inv_n = 1.f / (float)n;
-    float acc = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float t = t_label[i];
-        const bool on = t < INFINITY && t > h;
-        const float r = on ? (dist[n + i] - dist[i]) / h + 1.f : 0.f;
-        const float g = 2.f * lam * r * inv_n / h;
-        g_dist[i] -= g;
-        g_dist[n + i] = g;
-        g_logit[n + i] = 0.f;
-        acc += lam * r * r * inv_n;
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
+// Columns of the paired batch of n rays: 64 per 32 rays (the last tile padded).
+inline int64_t eik_cols(int64_t n) { return (n + 31) / 32 * 64; }
 
-// Workspace: rays [5][2n] | logit, dist, g_logit, g_dist [2n] | loss scratch | backward workspace.
+// Workspace: the paired rays [5][cols] | the training sweep's workspace for cols columns.
 struct EikWs {
-    float *rays, *logit, *dist, *g_logit, *g_dist, *loss_ws;
-    void *bws;
-    size_t bws_bytes, bytes;
+    float *rays;
+    TrainWs tw;
+    size_t bytes;
 };
 
 EikWs eik_ws(int width, int depth, int64_t n, void *base) {
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     EikWs w{};
-    uint8_t *b = (uint8_t *)base;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        uint8_t *p = b ? b + off : nullptr;
-        off += al(bytes);
-        return p;
-    };
-    const int64_t m = 2 * n;
-    w.rays = (float *)take(5 * m * 4);
-    w.logit = (float *)take(m * 4);
-    w.dist = (float *)take(m * 4);
-    w.g_logit = (float *)take(m * 4);
-    w.g_dist = (float *)take(m * 4);
-    w.loss_ws = (float *)take(1024 * 4 + 64);
-    w.bws_bytes = train_ws(width, depth, m, nullptr).bytes;
-    w.bws = take(w.bws_bytes);
-    w.bytes = off;
+    const int64_t m = eik_cols(n);
+    const size_t rb = align256((size_t)5 * m * 4);
+    w.rays = base ? (float *)base : nullptr;
+    w.tw = train_ws(width, depth, m, base ? (uint8_t *)base + rb : nullptr);
+    w.bytes = rb + w.tw.bytes;
     return w;
 }
 
@@ -703,22 +674,32 @@ extern "C" ddf_status ddf_train_step_eikonal(const ddf_net *net, float *params, 
     DDF_REQUIRE(ws && ws_bytes >= need.bytes, DDF_ERR_WORKSPACE,
                 "ddf_train_step_eikonal: workspace of %zu bytes needed", need.bytes);
     const EikWs w = eik_ws(net->width, net->depth, n, ws);
+    const int64_t m = eik_cols(n);
     hipStream_t s = as_stream(stream);
-    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(eikonal_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, orig, dir, n, h,
+    hipLaunchKernelGGL(eikonal_pairs_kernel, dim3((unsigned)((m / 2 + 255) / 256)), dim3(256), 0, s, orig, dir, n, m, h,
                        w.rays);
+    launch_loss_scalars(t_label, n, reinterpret_cast<unsigned int *>(w.tw.loss_part), w.tw.scalars, w.tw.count, s);
     if (ddf_status st = launch_status("ddf_train_step_eikonal")) return st;
-    if (ddf_status st = ddf_forward(net, w.rays, 2 * n, w.logit, w.dist, stream)) return st;
-    if (ddf_status st = ddf_loss_seeds_ex(w.logit, w.dist, t_label, n, loss, w.g_logit, w.g_dist, loss_out,
-                                          w.loss_ws, 1024 * 4 + 64, stream))
-        return st;
-    const unsigned eb = std::min<unsigned>(blocks, 1024);
-    hipLaunchKernelGGL(eikonal_seeds_kernel, dim3(eb), dim3(256), 0, s, w.dist, t_label, n, h, lambda, w.g_logit,
-                       w.g_dist, w.loss_ws);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, w.loss_ws, (int64_t)eb, loss_out, true);
-    if (ddf_status st = launch_status("ddf_train_step_eikonal")) return st;
-    if (ddf_status st = ddf_backward(net, w.rays, 2 * n, w.g_logit, w.g_dist, nullptr, g_params, 0u, w.bws,
-                                     w.bws_bytes, stream))
-        return st;
+    // one training sweep over the pairs: forward, the loss and penalty seeds of each pair in
+    // its workgroup, adjoints; then the weight-gradient products of the m columns
+    GradArgs a{};
+    a.blob = (const uint8_t *)net->packed;
+    a.depth = net->depth;
+    a.rays = w.rays;
+    a.n = m;
+    a.t_label = t_label;
+    a.loss_scalars = w.tw.scalars;
+    a.loss = ls;
+    a.eik_n = n;
+    a.eik_h = h;
+    a.eik_lam = lambda;
+    a.ws_gamma = w.tw.gamma;
+    a.ws_h = w.tw.h;
+    a.ws_delta = w.tw.delta;
+    a.loss_partial = w.tw.loss_part;
+    if (ddf_status st = sweep_dispatch(net->width, a, s)) return st;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, w.tw.loss_part, sweep_grid(net->width, m), loss_out,
+                       false);
+    if (ddf_status st = param_grads(net->width, net->depth, m, w.tw, g_params, false, s)) return st;
     return adam_and_repack(net, params, adam_m, adam_v, g_params, step, lr, stream);
 }
