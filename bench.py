@@ -425,9 +425,29 @@ def bench_label_train_render(args, torch, api, dev):
                     "roofline_frac_fp32": step_flop / (tms * 1e-3) / 1e12 / PEAK["fp32"],
                     "loss_first_step": losses[0], "loss_after_%d_steps" % (3 + args.train_steps): losses[-2],
                     "loss_after_%d_steps" % (3 + args.train_steps + args.render_train_steps): losses[-1]}
+    # the rendered network: trained as many steps on the rays a renderer asks (cube-entry,
+    # surface-leaving and training rays) with the directed Eikonal penalty (Eq. 2, lam 1,
+    # h 0.02); the plain network above is its comparison
+    ro, rd = synthetic.render_rays(v, f, nl, 1)
+    ro_g, rd_g = torch.from_numpy(ro).to(dev), torch.from_numpy(rd).to(dev)
+    rt, _, rcr = api.label_rays(ro_g, rd_g, tris)
+    rkeep = (rcr % 2) == 0
+    ro_g, rd_g, rt = ro_g[:, rkeep].contiguous(), rd_g[:, rkeep].contiguous(), rt[rkeep].contiguous()
+    rparams = torch.from_numpy(synthetic.xavier_params(width, depth, 1)).to(dev)
+    rtrainer = api.Trainer(rparams, width, depth, batch, lr=1e-3)
+    rnb = ro_g.shape[1] // batch
+    rbatches = [(ro_g[:, i * batch:(i + 1) * batch].contiguous(), rd_g[:, i * batch:(i + 1) * batch].contiguous(),
+                 rt[i * batch:(i + 1) * batch].contiguous()) for i in range(rnb)]
+    rsteps = 3 + args.train_steps + args.render_train_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(rsteps):
+        rtrainer.step_eikonal(*rbatches[i % rnb], h=0.02, lam=1.0)
+    torch.cuda.synchronize()
+    eik_ms = (time.perf_counter() - t0) * 1e3 / rsteps
     # render: 1920 x 1080, spp samples, 4 bounces, Russian roulette after bounce 2, bf16 queries
     cfg = synthetic.full_render(args.render_spp)
-    net16 = api.Network(params, width, depth, "bf16")
+    net16 = api.Network(rparams, width, depth, "bf16")
     r = api.Renderer(cfg, net=net16)
     r.capture()   # the frame as one HIP graph; path samples/s from its warm replays
     r.replay()
@@ -445,27 +465,39 @@ def bench_label_train_render(args, torch, api, dev):
     # one query plus its input gradient (the transposed product, the same multiply-adds as the
     # forward), every shadow ray one query
     frame_flop = (2 * sum(entering) + sum(shadows)) * flop_per_query(width, depth)
-    # shading normals against the mesh normal at the brute-force hit point (primary hits)
+    # shading normals against the mesh normal at the brute-force hit point (primary hits), and
+    # primary-hit agreement, for the rendered network and the plain one
     cfg1 = synthetic.full_render(1)
     cfg1.bounces = 1
     rm = api.Renderer(cfg1, tris=tris)
     rm.render()
-    rn = api.Renderer(cfg1, net=net16)
-    rn.render()
-    torch.cuda.synchronize()
-    both = torch.isfinite(rm.depth) & torch.isfinite(rn.depth)
-    cosang = (rm.normal * rn.normal).sum(0)[both].clamp(-1, 1)
-    ang = torch.rad2deg(torch.acos(cosang)).cpu().numpy()
-    hit_agree = float((torch.isfinite(rm.depth) == torch.isfinite(rn.depth)).float().mean()) * 100
-    out["render"] = {"workload": "1920x1080, %d spp, 4 bounces, RR after bounce 2, bf16 6x256 network "
-                                 "(trained %d steps)" % (cfg.spp, 3 + args.train_steps + args.render_train_steps),
+
+    def quality(p16):
+        rn = api.Renderer(cfg1, net=p16)
+        rn.render()
+        torch.cuda.synchronize()
+        both = torch.isfinite(rm.depth) & torch.isfinite(rn.depth)
+        cosang = (rm.normal * rn.normal).sum(0)[both].clamp(-1, 1)
+        ang = torch.rad2deg(torch.acos(cosang)).cpu().numpy()
+        agree = float((torch.isfinite(rm.depth) == torch.isfinite(rn.depth)).float().mean()) * 100
+        return {"normal_angle_err_deg_mean": float(ang.mean()) if ang.size else None,
+                "normal_angle_err_deg_median": float(np.median(ang)) if ang.size else None,
+                "primary_hit_agreement_vs_mesh_pct": agree}
+
+    q_render = quality(net16)
+    q_plain = quality(api.Network(params, width, depth, "bf16"))
+    out["render"] = {"workload": "1920x1080, %d spp, 4 bounces, RR after bounce 2, bf16 6x256 network trained %d "
+                                 "directed-Eikonal steps (lam 1, h 0.02) on render rays" % (cfg.spp, rsteps),
                      "seconds_per_frame": rs, "path_samples_per_s": paths / rs, "timing": "warm hipGraph replay of the whole frame",
                      "paths_per_bounce": entering, "shadow_rays_per_bounce": shadows,
                      "network_flop_per_frame": frame_flop, "network_tflops": frame_flop / rs / 1e12,
                      "roofline_frac_bf16": frame_flop / rs / 1e12 / PEAK["bf16"],
-                     "normal_angle_err_deg_mean": float(ang.mean()) if ang.size else None,
-                     "normal_angle_err_deg_median": float(np.median(ang)) if ang.size else None,
-                     "primary_hit_agreement_vs_mesh_pct": hit_agree}
+                     **q_render,
+                     "render_network_training": {"rays": "render_rays: 1/3 entering the cube, 1/3 leaving the surface, "
+                                                         "1/3 training rays (%d kept)" % ro_g.shape[1],
+                                                 "eikonal_ms_per_step": eik_ms, "loss_last": float(rtrainer.loss)},
+                     "plain_network": {"training": "%d plain steps on training rays (the train workload's network)" % rsteps,
+                                       **q_plain}}
     return out
 
 

@@ -17,6 +17,15 @@ done here.
   needed so that the origin stays inside the cube [-1,1]^3.  Rays whose origin
   lies inside the mesh are not removed here: the labeller's crossing count
   decides that, and the training loop drops them.
+* ``render_rays``: the rays a renderer asks of an object's network, for training
+  a network that is rendered: a third enter the cube [-1,1]^3 from a point
+  uniform on its surface (a face, then a point on it) in a direction uniform over
+  the inward hemisphere (a camera ray starts its query where it enters the cube);
+  a third leave the surface (an area-weighted point moved 1e-3 off the surface
+  along its face normal, to a side chosen at random, in a direction uniform over
+  that side's hemisphere: the bounce and shadow rays); the rest follow
+  ``training_rays``.  Origins inside the mesh are left to the labeller's crossing
+  count, as there.
 """
 import numpy as np
 
@@ -110,3 +119,31 @@ def grid_points(n_side, half=0.95):
     c = np.linspace(-half, half, n_side)
     z, y, x = np.meshgrid(c, c, c, indexing="ij")
     return np.ascontiguousarray(np.stack([x.ravel(), y.ravel(), z.ravel()]).astype(np.float32))
+
+
+def render_rays(v, f, n, seed):
+    """Returns ``(orig [3][n], dirs [3][n])``: cube-entry rays, surface-leaving rays, training rays."""
+    rng = np.random.default_rng(seed)
+    n_c = n // 3
+    n_b = n // 3
+    # entering the cube: face (axis k, side sg), point on it, inward hemisphere
+    k = rng.integers(0, 3, n_c)
+    sg = np.where(rng.random(n_c) < 0.5, -1.0, 1.0)
+    o_c = rng.uniform(-1.0, 1.0, size=(n_c, 3))
+    o_c[np.arange(n_c), k] = sg
+    d_c = _unit_dirs(rng, n_c)
+    out = d_c[np.arange(n_c), k] * sg > 0
+    d_c[np.arange(n_c)[out], k[out]] *= -1.0
+    # leaving the surface: point, side of its face, that side's hemisphere
+    q, tri = area_weighted_surface_points(v, f, n_b, rng)
+    a, b, c = v[f[tri, 0]], v[f[tri, 1]], v[f[tri, 2]]
+    nrm = np.cross(b - a, c - a)
+    nrm /= np.maximum(np.linalg.norm(nrm, axis=1, keepdims=True), 1e-30)
+    side = np.where(rng.random(n_b) < 0.5, -1.0, 1.0)[:, None] * nrm
+    o_b = np.clip(q + 1e-3 * side, -1.0, 1.0)
+    d_b = _unit_dirs(rng, n_b)
+    d_b = np.where(np.sum(d_b * side, axis=1, keepdims=True) < 0, -d_b, d_b)
+    o_t, d_t, _ = training_rays(v, f, n - n_c - n_b, int(rng.integers(0, 2 ** 31)))
+    o = np.concatenate([o_c, o_b, o_t.T.astype(np.float64)])
+    d = np.concatenate([d_c, d_b, d_t.T.astype(np.float64)])
+    return _soa(o, d)

@@ -66,3 +66,32 @@ def test_render_oracle_network_backend_runs():
     assert out["radiance"].shape == (3, 10, 12)
     assert np.all(np.isfinite(out["radiance"])) and np.all(out["radiance"] >= 0)
     assert out["active"][0] == 240
+
+
+def test_render_rays_mix():
+    """Cube-entry rays start on the cube's surface and point into it; surface-leaving rays start
+    1e-3 off a face of the mesh and leave to that side; all directions are unit; the draw is
+    fixed by the seed."""
+    v, f = synthetic.icosphere(2, 0.8)
+    n = 3000
+    o, d = synthetic.render_rays(v, f, n, 5)
+    o2, d2 = synthetic.render_rays(v, f, n, 5)
+    np.testing.assert_array_equal(o, o2)
+    np.testing.assert_array_equal(d, d2)
+    assert o.shape == d.shape == (3, n) and o.dtype == np.float32
+    np.testing.assert_allclose(np.linalg.norm(d.astype(np.float64), axis=0), 1.0, atol=1e-6)
+    c = n // 3
+    oc, dc = o[:, :c].astype(np.float64), d[:, :c].astype(np.float64)
+    k = np.argmax(np.abs(oc), axis=0)
+    face = oc[k, np.arange(c)]
+    assert np.all(np.abs(face) == 1.0)
+    assert np.all(dc[k, np.arange(c)] * face <= 0)   # into the cube
+    # surface-leaving rays of a mesh of one triangle in the plane z = 0: the origin is 1e-3 off
+    # the plane, over the triangle, and the direction leaves to the origin's side
+    tv = np.array([[-0.5, -0.5, 0.0], [0.5, -0.5, 0.0], [0.0, 0.5, 0.0]])
+    o, d = synthetic.render_rays(tv, np.array([[0, 1, 2]]), n, 6)
+    ob, db = o[:, c:2 * c].astype(np.float64), d[:, c:2 * c].astype(np.float64)
+    np.testing.assert_allclose(np.abs(ob[2]), 1e-3, rtol=1e-4)
+    assert np.all(ob[2] * db[2] >= 0)
+    assert 0.4 < np.mean(ob[2] > 0) < 0.6   # both sides
+    assert np.all((ob[1] >= -0.5) & (ob[1] <= 0.5) & (np.abs(ob[0]) <= 0.5))
