@@ -12,8 +12,14 @@ units, each followed by ReLU and dropout with p = 0.5.  Readings taken here:
 * weight normalisation (Salimans and Kingma, 2016) per output unit of every hidden layer:
   W[i, :] = g[i] v[i, :] / |v[i, :]|; the output layer is a plain affine map (the paper
   normalises the hidden layers); a row of v must not be all zero (its W is undefined);
-* dropout is the identity when the network is queried (inverted dropout scales the kept
-  units by 1 / (1 - p) while training, so the expected activation is the same);
+* dropout is the identity when the network is queried; while training (inverted dropout,
+  the paper's p = 0.5) each hidden unit's ReLU output is kept with probability 1 - p and
+  scaled by 1 / (1 - p), so the expected activation is the query's.  The keep decisions come
+  from a counter-based generator, so that the forward and reverse sweeps (and the GPU) draw
+  the same masks without storing them: with H(x) the first output of a SplitMix64 generator
+  whose state is x (Steele, Lea and Flood, 2014), layer l of training step `step` has the key
+  K = H(H(H(seed) ^ step) ^ l), unit u of ray r is kept when the top 24 bits of
+  H(K ^ (u << 32 | r)), read as a fraction of 2^24, are >= p;
 * the single output is the distance; the paper's losses act on it directly.
 
 Flat parameter vector (float32), per hidden layer l: v_l [width][in_l] row-major, g_l
@@ -82,12 +88,32 @@ def fold(params, width, depth):
     return layers
 
 
-def forward(params, width, depth, rays, return_acts=False):
+def dropout_keep(seed, step, layer, width, n, p):
+    """Keep decisions [width, n] of hidden layer ``layer`` at training step ``step`` for rays
+    0 .. n - 1 (the counter-based draw described in the module docstring)."""
+    from .render import _h, _h_np
+    key = _h(_h(_h(seed) ^ step) ^ layer)
+    u = np.arange(width, dtype=np.uint64)[:, None]
+    r = np.arange(n, dtype=np.uint64)[None, :]
+    k = _h_np(np.uint64(key) ^ ((u << np.uint64(32)) | r))
+    return (k >> np.uint64(40)).astype(np.float64) * 2.0 ** -24 >= p
+
+
+def dropout_masks(seed, step, width, depth, n, p):
+    """Scaled masks [depth][width, n] (0 or 1 / (1 - p)) of one training step; None for p = 0."""
+    if p == 0:
+        return None
+    return [dropout_keep(seed, step, l, width, n, p) / (1.0 - p) for l in range(depth)]
+
+
+def forward(params, width, depth, rays, return_acts=False, masks=None):
     """Float64 forward of the paper's network on the raw rays [5, N]: h_0 = ray,
-    h_l = max(0, W_l h_{l-1} + b_l) (dropout: identity), distance = W h_D + b.
+    h_l = max(0, W_l h_{l-1} + b_l), times the scaled dropout mask of layer l when training
+    (``masks``: ``dropout_masks``; None: dropout is the identity), distance = W h_D + b.
 
     Returns dist [N] (and, with ``return_acts``, the layer inputs and pre-activations).
-    Pinned against torch float64 (weight_norm Linear layers, ReLU, Dropout in eval mode).
+    Pinned against torch float64 (weight_norm Linear layers, ReLU, Dropout in eval mode; in
+    training mode with the same masks applied as fixed factors).
     """
     layers = fold(params, width, depth)
     h = np.asarray(rays, dtype=np.float64)
@@ -97,6 +123,8 @@ def forward(params, width, depth, rays, return_acts=False):
         pres.append(z)
         if l < depth:
             h = np.maximum(z, 0.0)
+            if masks is not None:
+                h = h * masks[l]
             acts.append(h)
         else:
             h = z
@@ -124,8 +152,9 @@ def forward_bf16(params, width, depth, rays):
     return ((hi + lo) @ h + layers[depth][1][:, None])[0]
 
 
-def backward(params, width, depth, rays, g_dist):
-    """Reverse-mode gradient of sum(g_dist * dist): returns (g_rays [5, N], g_params [P]).
+def backward(params, width, depth, rays, g_dist, masks=None):
+    """Reverse-mode gradient of sum(g_dist * dist): returns (g_rays [5, N], g_params [P]);
+    ``masks``: the training step's dropout masks (``dropout_masks``), or None.
 
     The input gradient is the derivative with respect to the query point and angles that
     Sec. IV-B takes by automatic differentiation (its origin part gives the normal of
@@ -137,7 +166,7 @@ def backward(params, width, depth, rays, g_dist):
     """
     hidden, _ = unpack(params, width, depth)
     layers = fold(params, width, depth)
-    _, acts, pres = forward(params, width, depth, rays, return_acts=True)
+    _, acts, pres = forward(params, width, depth, rays, return_acts=True, masks=masks)
     delta = np.asarray(g_dist, dtype=np.float64)[None, :]
     g_layers = [None] * (depth + 1)
     for l in range(depth, -1, -1):
@@ -146,6 +175,8 @@ def backward(params, width, depth, rays, g_dist):
         g_in = W.T @ delta
         if l > 0:
             delta = g_in * (pres[l - 1] > 0.0)
+            if masks is not None:
+                delta = delta * masks[l - 1]
     g_hidden = []
     for (v, g, _), (G, gb) in zip(hidden, g_layers[:depth]):
         norm = np.sqrt(np.sum(v * v, axis=1))
@@ -180,13 +211,16 @@ def backward_input_bf16(params, width, depth, rays, g_dist):
     return mlp.round_bf16(W0).T @ mlp.round_bf16(delta)
 
 
-def train_step(params, width, depth, rays, t, m, v, step, kind="clamp", delta=1.0, lr=1e-3):
+def train_step(params, width, depth, rays, t, m, v, step, kind="clamp", delta=1.0, lr=1e-3, dropout=0.0,
+               seed=0):
     """One training step of Sec. V-A: the paper's loss (``mlp.paper_loss_and_seeds``: the
-    clamp loss of Eq. 7 or the squish loss of Eq. 6) on the distance, its gradient with
+    clamp loss of Eq. 7 or the squish loss of Eq. 6) on the distance of the network with
+    dropout ``dropout`` (the paper: 0.5; masks of this step from ``seed``), its gradient with
     respect to (v, g, b) of every layer, and one Adam update of those parameters.
     Returns (loss, grad, params, m, v)."""
-    dist = forward(params, width, depth, rays)
+    masks = dropout_masks(seed, step, width, depth, np.asarray(rays).shape[1], dropout)
+    dist = forward(params, width, depth, rays, masks=masks)
     loss, seeds = mlp.paper_loss_and_seeds(dist, t, kind, delta)
-    _, grad = backward(params, width, depth, rays, seeds)
+    _, grad = backward(params, width, depth, rays, seeds, masks=masks)
     p, m, v = mlp.adam_step(params, grad, m, v, step, lr)
     return loss, grad, p, m, v

@@ -250,3 +250,122 @@ def test_train_step_is_loss_backward_adam():
     big = np.abs(grad) > 1e-5
     assert big.mean() > 0.5
     np.testing.assert_allclose(np.abs(p1 - p)[big], 1e-3, rtol=1e-3)
+
+
+# ---------------------------------------------------------------------------- training dropout
+class _FixedMask(torch.nn.Module):
+    """Multiplies by a fixed tensor: torch's Dropout in training mode with a given mask."""
+
+    def __init__(self, m):
+        super().__init__()
+        self.m = m
+
+    def forward(self, x):
+        return x * self.m
+
+
+def _torch_train_model(params, width, depth, masks):
+    """The torch model of the paper's network with each Dropout replaced by its training-mode
+    action under the given masks (kept units scaled by 1 / (1 - p))."""
+    model = _torch_model(params, width, depth)
+    mods, l = [], 0
+    for mod in model:
+        if isinstance(mod, torch.nn.Dropout):
+            mods.append(_FixedMask(torch.from_numpy(masks[l].T.copy())))
+            l += 1
+        else:
+            mods.append(mod)
+    return torch.nn.Sequential(*mods)
+
+
+@pytest.mark.parametrize("p_drop", [0.25, 0.5, 0.9])
+def test_dropout_keep_rate_and_independence(p_drop):
+    """Each unit of each ray is kept with probability 1 - p: the keep rate of a layer, of every
+    unit and of every ray lies within binomial bounds; layers, steps and seeds draw different
+    masks, with the agreement of independent draws, p^2 + (1 - p)^2."""
+    w, n = 256, 2048
+    k = paper.dropout_keep(11, 5, 1, w, n, p_drop)
+    q = 1.0 - p_drop
+    sd = np.sqrt(q * (1 - q))
+    assert abs(k.mean() - q) < 5 * sd / np.sqrt(w * n)
+    assert np.all(np.abs(k.mean(axis=1) - q) < 6 * sd / np.sqrt(n))
+    assert np.all(np.abs(k.mean(axis=0) - q) < 6 * sd / np.sqrt(w))
+    agree = p_drop ** 2 + q ** 2
+    for other in (paper.dropout_keep(11, 5, 2, w, n, p_drop), paper.dropout_keep(11, 6, 1, w, n, p_drop),
+                  paper.dropout_keep(12, 5, 1, w, n, p_drop)):
+        assert abs(np.mean(k == other) - agree) < 6 * np.sqrt(agree * (1 - agree) / (w * n))
+    # neighbouring units and rays are independent too
+    assert abs(np.mean(k[1:] == k[:-1]) - agree) < 6 * np.sqrt(agree * (1 - agree) / (w * n))
+    assert abs(np.mean(k[:, 1:] == k[:, :-1]) - agree) < 6 * np.sqrt(agree * (1 - agree) / (w * n))
+
+
+def test_dropout_zero_is_the_query_network():
+    width, depth = 16, 3
+    p = _params(width, depth, 21).astype(np.float64)
+    rays = _rays(50, 22).astype(np.float64)
+    t = np.linspace(0.1, 1.0, 50)
+    z = np.zeros_like(p)
+    a = paper.train_step(p, width, depth, rays, t, z, z, 3, "clamp", 0.5, dropout=0.0, seed=9)
+    b = paper.train_step(p, width, depth, rays, t, z, z, 3, "clamp", 0.5)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_dropout_expected_activation_is_the_query():
+    """Inverted dropout: the mean over many training steps' masks of the dropout network's
+    first-layer output is the query network's (the 1 / (1 - p) scale makes it unbiased)."""
+    width, depth = 32, 1
+    p = _params(width, depth, 23).astype(np.float64)
+    rays = _rays(8, 24).astype(np.float64)
+    _, acts, _ = paper.forward(p, width, depth, rays, return_acts=True)
+    steps = 4000
+    s = np.zeros_like(acts[1])
+    for step in range(1, steps + 1):
+        m = paper.dropout_masks(3, step, width, depth, 8, 0.5)
+        s += paper.forward(p, width, depth, rays, return_acts=True, masks=m)[1][1]
+    mean = s / steps
+    # each entry is h x 2 or 0 with equal probability: standard deviation h / sqrt(steps)
+    assert np.all(np.abs(mean - acts[1]) <= 5 * acts[1] / np.sqrt(steps) + 1e-12)
+
+
+@pytest.mark.parametrize("p_drop", [0.5, 0.3])
+def test_dropout_forward_and_gradients_match_torch(p_drop):
+    """Forward, input and parameter gradients with one step's dropout masks against torch float64
+    autograd on the weight-normalised model whose Dropout layers apply the same masks."""
+    width, depth = 16, 4
+    p = _params(width, depth, 25)
+    rays = _rays(120, 26)
+    masks = paper.dropout_masks(7, 4, width, depth, 120, p_drop)
+    model = _torch_train_model(p, width, depth, masks)
+    x = torch.from_numpy(rays.T.astype(np.float64)).requires_grad_(True)
+    out = model(x)[:, 0]
+    np.testing.assert_allclose(paper.forward(p, width, depth, rays, masks=masks), out.detach().numpy(),
+                               rtol=1e-12, atol=1e-12)
+    gd = np.random.default_rng(27).normal(size=120)
+    (out * torch.from_numpy(gd)).sum().backward()
+    ref = []
+    for mod in model:
+        if isinstance(mod, torch.nn.Linear):
+            if hasattr(mod, "parametrizations"):
+                ref += [mod.parametrizations.weight.original1.grad.numpy().ravel(),
+                        mod.parametrizations.weight.original0.grad.numpy().ravel(), mod.bias.grad.numpy()]
+            else:
+                ref += [mod.weight.grad.numpy().ravel(), mod.bias.grad.numpy()]
+    g_rays, g_p = paper.backward(p, width, depth, rays, gd, masks=masks)
+    np.testing.assert_allclose(g_p, np.concatenate(ref), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(g_rays, x.grad.numpy().T, rtol=1e-10, atol=1e-12)
+
+
+def test_dropout_train_step_uses_the_step_masks():
+    width, depth = 8, 2
+    p = _params(width, depth, 28).astype(np.float64)
+    rays = _rays(64, 29).astype(np.float64)
+    t = np.where(np.arange(64) % 4 == 0, np.inf, np.linspace(0.1, 1.5, 64))
+    z = np.zeros_like(p)
+    loss, grad, _, _, _ = paper.train_step(p, width, depth, rays, t, z, z, 2, "clamp", 0.7, dropout=0.5, seed=31)
+    masks = paper.dropout_masks(31, 2, width, depth, 64, 0.5)
+    l_ref, seeds = mlp.paper_loss_and_seeds(paper.forward(p, width, depth, rays, masks=masks), t, "clamp", 0.7)
+    assert loss == l_ref
+    np.testing.assert_array_equal(grad, paper.backward(p, width, depth, rays, seeds, masks=masks)[1])
+    other = paper.train_step(p, width, depth, rays, t, z, z, 3, "clamp", 0.7, dropout=0.5, seed=31)[1]
+    assert not np.array_equal(grad, other)   # the next step draws other masks
