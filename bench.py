@@ -264,7 +264,7 @@ def bench_paper_network(args, torch, api, dev, depth=8):
     p = torch.from_numpy(synthetic.paper_params(depth, 81)).to(dev)
     nets = {pr: api.PaperNetwork(p, depth, pr) for pr in ("bf16", "fp32")}
     out = {"workload": "paper network %d x 512 (weight norm folded, raw 5-value input, one output), "
-                       "uniform rays; training: batch 65,536, clamp loss delta 1" % depth,
+                       "uniform rays; training: batch 65,536, clamp loss delta 1, dropout 0.5 (Sec. V-A)" % depth,
            "flop_per_query": paper_flop_per_query(depth)}
     sizes = {"bf16": 1 << 22, "fp32": 1 << 20}
     for pr, n in sizes.items():
@@ -314,7 +314,7 @@ def bench_paper_network(args, torch, api, dev, depth=8):
     og, dg = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
     t, _, _ = api.label_rays(og, dg, tris)
     rays = api.assemble_rays(og, dg)
-    tr = api.PaperTrainer(p.clone(), depth, batch, lr=1e-4, loss="clamp", delta=1.0)
+    tr = api.PaperTrainer(p.clone(), depth, batch, lr=1e-4, loss="clamp", delta=1.0, dropout=0.5, seed=1)
     first = float(tr.step(rays, t))
     torch.cuda.synchronize()
     steps = 5

@@ -352,8 +352,8 @@ ddf_status ddf_train_step_eikonal(const ddf_net *net, float *params, float *adam
  * The network of Sec. V-A as the paper builds it: `depth` (the paper: 8) weight-normalised
  * hidden ReLU layers of 512 units on the raw oriented point (ox, oy, oz, polar angle,
  * azimuth; Sec. IV-A, MLP_w : (R^3, R^2) -> R), then one affine output, the field value.
- * Dropout (p = 0.5 in the paper) is the identity when the network is queried; training runs
- * without it.  Weight normalisation (Salimans and Kingma 2016): W_l = g_l v_l / |v_l| per
+ * Dropout (p = 0.5 in the paper) is the identity when the network is queried; the training
+ * step applies it (ddf_paper_train_step).  Weight normalisation (Salimans and Kingma 2016): W_l = g_l v_l / |v_l| per
  * output row, folded on the device by ddf_paper_pack (every row of v_l must be non-zero).
  *   Parameters (float32, flat, device): per hidden layer l = 0 .. depth - 1: v_l [512][in_l]
  *   row-major (in_0 = 5, else 512), g_l [512], b_l [512]; then the output row [512] and its
@@ -398,16 +398,25 @@ ddf_status ddf_paper_backward(const ddf_paper_net *net, const float *params, con
                               size_t ws_bytes, ddf_stream stream);
 
 /* One training step of Sec. V-A on a labelled batch: the loss (`loss`: DDF_LOSS_CLAMP, Eq. 7,
- * or DDF_LOSS_SQUISH, Eq. 6; the paper trains on the clamp loss) on the distance, its gradient
- * with respect to every parameter (as ddf_paper_backward), one Adam update (beta 0.9 / 0.999,
- * eps 1e-8, 1-based `step`) of `params` / `adam_m` / `adam_v`, and repacking of `net` (a
- * DDF_PREC_FP32 blob of `params`, rewritten in place).
+ * or DDF_LOSS_SQUISH, Eq. 6; the paper trains on the clamp loss) on the distance of the
+ * network with dropout `dropout` (the paper: 0.5; 0 = none) after every hidden ReLU, its
+ * gradient with respect to every parameter, one Adam update (beta 0.9 / 0.999, eps 1e-8,
+ * 1-based `step`) of `params` / `adam_m` / `adam_v`, and repacking of `net` (a DDF_PREC_FP32
+ * blob of `params`, rewritten in place).
+ *   Dropout is inverted (kept units scaled by 1 / (1 - dropout)); its keep decisions are a
+ *   counter-based draw, so both sweeps see the same masks without storing them: with H(x)
+ *   the first output of SplitMix64 from state x (Steele, Lea and Flood 2014), hidden layer l
+ *   has K = H(H(H(dropout_seed) ^ step) ^ l), and unit u of ray r (0-based in the batch) is
+ *   kept when the top 24 bits of H(K ^ (u << 32 | r)), read as a fraction of 2^24, are
+ *   >= dropout.
  *   rays [5][n], t_label [n] (+inf = miss); loss_out: device scalar (before the update);
  *   g_params [P] receives the gradient; ws: ddf_paper_workspace_size(depth, n) bytes.
- * Errors: INVALID_ARG for a bad argument or a loss other than clamp / squish; WORKSPACE. */
+ * Errors: INVALID_ARG for a bad argument, a loss other than clamp / squish or a dropout
+ * outside [0, 1); WORKSPACE. */
 ddf_status ddf_paper_train_step(const ddf_paper_net *net, float *params, float *adam_m, float *adam_v, int64_t step,
                                 float lr, const float *rays, const float *t_label, int64_t n, const ddf_loss *loss,
-                                float *loss_out, float *g_params, void *ws, size_t ws_bytes, ddf_stream stream);
+                                float dropout, uint64_t dropout_seed, float *loss_out, float *g_params, void *ws,
+                                size_t ws_bytes, ddf_stream stream);
 
 /* ---------------------------------------------------------------- renderer
  * Wavefront path tracer of Fig. 1 in which the nearest-hit search is either the

@@ -13,6 +13,7 @@ c_f = ctypes.c_float
 c_i32 = ctypes.c_int32
 c_i64 = ctypes.c_int64
 c_u32 = ctypes.c_uint32
+c_u64 = ctypes.c_uint64
 c_sz = ctypes.c_size_t
 c_p = ctypes.c_void_p
 STATUS = ctypes.c_int32
@@ -102,7 +103,7 @@ SIGNATURES = {
     "ddf_paper_workspace_size": [c_i32, c_i64, ctypes.POINTER(c_sz)],
     "ddf_paper_backward": [ctypes.POINTER(DdfPaperNet), c_p, c_p, c_i64, c_p, c_p, c_p, c_u32, c_p, c_sz, c_p],
     "ddf_paper_train_step": [ctypes.POINTER(DdfPaperNet), c_p, c_p, c_p, c_i64, c_f, c_p, c_p, c_i64,
-                             ctypes.POINTER(DdfLoss), c_p, c_p, c_p, c_sz, c_p],
+                             ctypes.POINTER(DdfLoss), c_f, c_u64, c_p, c_p, c_p, c_sz, c_p],
 }
 # launch-shape knobs (DDF_TUNE_* in ddf.h)
 TUNE_KNOBS = {"stream_wg_per_cu": 0, "cull_rays_per_block": 1, "grad_wg_per_cu": 2}

@@ -226,11 +226,15 @@ class PaperNetwork:
 
 class PaperTrainer:
     """Adam training of the paper's network (float32) on labelled rays with the clamp loss
-    (Eq. 7, window ``delta``) or the squish loss (Eq. 6); ``params`` is updated in place."""
+    (Eq. 7, window ``delta``) or the squish loss (Eq. 6) and dropout ``dropout`` after every
+    hidden ReLU (the paper: 0.5; masks drawn from ``seed`` and the step count); ``params`` is
+    updated in place."""
 
-    def __init__(self, params, depth, batch, lr=1e-3, loss="clamp", delta=1.0):
+    def __init__(self, params, depth, batch, lr=1e-3, loss="clamp", delta=1.0, dropout=0.5, seed=0):
         self.net = PaperNetwork(params, depth, "fp32")
         self.params = params
+        self.dropout = float(dropout)
+        self.seed = int(seed)
         self.loss_desc = _loss_desc(loss, delta)
         self.m = torch.zeros_like(params)
         self.v = torch.zeros_like(params)
@@ -246,7 +250,7 @@ class PaperTrainer:
         self.step_count += 1
         _lib.call("ddf_paper_train_step", ctypes.byref(self.net.desc), _p(self.params), _p(self.m), _p(self.v),
                   self.step_count, self.lr, _p(rays), _p(t_label), rays.shape[1], ctypes.byref(self.loss_desc),
-                  _p(self.loss), _p(self.g), _p(self.ws), self.ws.numel(), _stream())
+                  self.dropout, self.seed, _p(self.loss), _p(self.g), _p(self.ws), self.ws.numel(), _stream())
         return self.loss
 
 

@@ -643,7 +643,36 @@ struct SweepArgs {
     float *ws_delta;       // [depth][512][n] adjoints, then [n] output seeds (training), or NULL
     float *loss_partial;   // [gridDim.x] (training)
     bool forward_only;
+    // training dropout (inverted): unit u of ray r in hidden layer l is kept when the top 24
+    // bits of H(K_l ^ (u << 32 | r)) are >= drop_thr, K_l = H(H(H(drop_seed) ^ drop_step) ^ l),
+    // H the first output of SplitMix64 from a given state; kept units are scaled by drop_scale.
+    // drop_thr = 0: no dropout (drop_scale is then ignored).
+    uint32_t drop_thr;
+    float drop_scale;
+    uint64_t drop_seed;
+    int64_t drop_step;
 };
+
+// H(x): the first output of a SplitMix64 generator (Steele, Lea and Flood, 2014) whose state
+// is x: the state advances by the golden-ratio increment and the output function mixes it.
+__host__ __device__ inline uint64_t splitmix_h(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Dropout keep bits of a lane's D-layout tile (units mb * 32 + 8 (q / 4) + 4 h + q % 4 of ray r).
+__device__ inline uint32_t pdrop_bits(uint64_t key, uint32_t thr, int mb, int h, int64_t r) {
+    uint32_t bits = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint64_t u = (uint64_t)(mb * 32 + 8 * (q / 4) + 4 * h + (q % 4));
+        const uint64_t k = splitmix_h(key ^ ((u << 32) | (uint64_t)(uint32_t)r));
+        bits |= ((uint32_t)(k >> 40) >= thr ? 1u : 0u) << q;
+    }
+    return bits;
+}
 
 // acc[j] (M-block j of this wave's NM, tiles j * 64 floats apart) += sum over KS K-steps from
 // kb0 of tile (kb) x layer values X[ray][unit(kb, h)]; tiles: the first tile of K-step 0,
@@ -720,6 +749,10 @@ __global__ __launch_bounds__(kSW * 64, 1) void paper_sweep_kernel(SweepArgs a) {
     const float *bias = reinterpret_cast<const float *>(a.blob + L.bias_off);
     const float *row = reinterpret_cast<const float *>(a.blob + L.row_off);
     const bool train = a.ws_h != nullptr;
+    const bool drop = a.drop_thr != 0;
+    const float dscale = drop ? a.drop_scale : 1.f;   // 1 (exact) without dropout
+    const uint64_t drop_base = splitmix_h(splitmix_h(a.drop_seed) ^ (uint64_t)a.drop_step);
+    auto layer_key = [&](int l) { return splitmix_h(drop_base ^ (uint64_t)l); };
     float loss_acc = 0.f;
     auto mask_at = [&](int l, int mb) -> uint16_t & { return s_mask[(l * kPNMB + mb) * 64 + lane]; };
 
@@ -747,10 +780,12 @@ __global__ __launch_bounds__(kSW * 64, 1) void paper_sweep_kernel(SweepArgs a) {
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(l0[(mb * kPK0 + ks) * 64 + lane], X0[col * 8 + 2 * ks + h], acc, 0, 0, 0);
             float y[16];
             uint32_t bits = 0;
+            const uint32_t keep = drop ? pdrop_bits(layer_key(0), a.drop_thr, mb, h, r) : 0xFFFFu;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                y[q] = fmaxf(acc[q], 0.f);
-                bits |= (acc[q] > 0.f ? 1u : 0u) << q;
+                const bool on = acc[q] > 0.f && ((keep >> q) & 1u);
+                y[q] = on ? acc[q] * dscale : 0.f;
+                bits |= (on ? 1u : 0u) << q;
             }
             mask_at(0, mb) = (uint16_t)bits;
             pstore_tile(y, mb, h, col, X, train ? a.ws_h : nullptr, n, r, valid);
@@ -766,14 +801,16 @@ __global__ __launch_bounds__(kSW * 64, 1) void paper_sweep_kernel(SweepArgs a) {
                 const int mb = mb0 + j;
                 float y[16];
                 uint32_t bits = 0;
+                const uint32_t keep = drop ? pdrop_bits(layer_key(l), a.drop_thr, mb, h, r) : 0xFFFFu;
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bias + (l - 1) * kPW + mb * 32 + 8 * g + 4 * h);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const float z = acc[j][4 * g + i] + b4[i];
-                        y[4 * g + i] = fmaxf(z, 0.f);
-                        bits |= (z > 0.f ? 1u : 0u) << (4 * g + i);
+                        const bool on = z > 0.f && ((keep >> (4 * g + i)) & 1u);
+                        y[4 * g + i] = on ? z * dscale : 0.f;
+                        bits |= (on ? 1u : 0u) << (4 * g + i);
                     }
                 }
                 mask_at(l, mb) = (uint16_t)bits;
@@ -823,7 +860,7 @@ __global__ __launch_bounds__(kSW * 64, 1) void paper_sweep_kernel(SweepArgs a) {
                 for (int g = 0; g < 4; ++g) {
                     const f32x4 w4 = *reinterpret_cast<const f32x4 *>(row + mb * 32 + 8 * g + 4 * h);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) y[4 * g + i] = ((bits >> (4 * g + i)) & 1u) ? w4[i] * gd : 0.f;
+                    for (int i = 0; i < 4; ++i) y[4 * g + i] = ((bits >> (4 * g + i)) & 1u) ? w4[i] * gd * dscale : 0.f;
                 }
                 pstore_tile(y, mb, h, col, X, train ? a.ws_delta + (int64_t)(depth - 1) * kPW * n : nullptr, n, r, valid);
             }
@@ -840,7 +877,7 @@ __global__ __launch_bounds__(kSW * 64, 1) void paper_sweep_kernel(SweepArgs a) {
                 const uint32_t bits = mask_at(l - 1, mb);
                 float y[16];
 #pragma unroll
-                for (int q = 0; q < 16; ++q) y[q] = ((bits >> q) & 1u) ? acc[j][q] : 0.f;
+                for (int q = 0; q < 16; ++q) y[q] = ((bits >> q) & 1u) ? acc[j][q] * dscale : 0.f;
                 pstore_tile(y, mb, h, col, X, train ? a.ws_delta + (int64_t)(l - 1) * kPW * n : nullptr, n, r, valid);
             }
             __syncthreads();
@@ -1004,9 +1041,14 @@ PaperWs paper_ws(int depth, int64_t n, void *base) {
 // when t_label is given), the weight-gradient products, the weight-normalisation backward.
 ddf_status paper_param_grad(const ddf_paper_net *net, const float *params, const float *rays, int64_t n,
                             const float *g_dist, const float *t_label, LossSpec loss, float *g_rays, float *g_params,
-                            bool accumulate, const PaperWs &w, hipStream_t s) {
+                            bool accumulate, const PaperWs &w, hipStream_t s, uint32_t drop_thr = 0,
+                            float drop_scale = 1.f, uint64_t drop_seed = 0, int64_t drop_step = 0) {
     const int depth = net->depth;
     SweepArgs a{};
+    a.drop_thr = drop_thr;
+    a.drop_scale = drop_scale;
+    a.drop_seed = drop_seed;
+    a.drop_step = drop_step;
     a.blob = (const uint8_t *)net->packed;
     a.depth = depth;
     a.rays = rays;
@@ -1158,8 +1200,8 @@ extern "C" ddf_status ddf_paper_backward(const ddf_paper_net *net, const float *
 
 extern "C" ddf_status ddf_paper_train_step(const ddf_paper_net *net, float *params, float *adam_m, float *adam_v,
                                            int64_t step, float lr, const float *rays, const float *t_label, int64_t n,
-                                           const ddf_loss *loss, float *loss_out, float *g_params, void *ws,
-                                           size_t ws_bytes, ddf_stream stream) {
+                                           const ddf_loss *loss, float dropout, uint64_t dropout_seed, float *loss_out,
+                                           float *g_params, void *ws, size_t ws_bytes, ddf_stream stream) {
     if (ddf_status st = check_paper(net, "ddf_paper_train_step")) return st;
     DDF_REQUIRE(net->precision == kFP32, DDF_ERR_UNSUPPORTED, "ddf_paper_train_step: needs a float32 network");
     DDF_REQUIRE(n > 0 && params && adam_m && adam_v && rays && t_label && loss_out && g_params && step >= 1,
@@ -1168,13 +1210,17 @@ extern "C" ddf_status ddf_paper_train_step(const ddf_paper_net *net, float *para
                 "ddf_paper_train_step: the loss must be the clamp (Eq. 7) or the squish (Eq. 6) loss");
     DDF_REQUIRE(loss->kind != DDF_LOSS_CLAMP || (std::isfinite(loss->delta) && loss->delta > 0.f), DDF_ERR_INVALID_ARG,
                 "ddf_paper_train_step: the clamp loss needs a finite delta > 0");
+    DDF_REQUIRE(dropout >= 0.f && dropout < 1.f, DDF_ERR_INVALID_ARG, "ddf_paper_train_step: dropout must lie in [0, 1)");
+    // kept when the draw's top 24 bits k satisfy k / 2^24 >= p, i.e. k >= ceil(p 2^24)
+    const uint32_t thr = (uint32_t)std::ceil((double)dropout * 16777216.0);
+    const float scale = thr ? (float)(1.0 / (1.0 - (double)dropout)) : 1.f;
     const PaperWs need = paper_ws(net->depth, n, nullptr);
     DDF_REQUIRE(ws && ws_bytes >= need.bytes, DDF_ERR_WORKSPACE, "ddf_paper_train_step: workspace of %zu bytes needed",
                 need.bytes);
     hipStream_t s = as_stream(stream);
     const PaperWs w = paper_ws(net->depth, n, ws);
     if (ddf_status st = paper_param_grad(net, params, rays, n, nullptr, t_label, LossSpec{loss->kind, loss->delta},
-                                         nullptr, g_params, false, w, s))
+                                         nullptr, g_params, false, w, s, thr, scale, dropout_seed, step))
         return st;
     hipLaunchKernelGGL(paper_sum_kernel, dim3(1), dim3(256), 0, s, (const float *)w.loss_part,
                        (int)paper_sweep_grid(n), loss_out);

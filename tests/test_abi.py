@@ -245,8 +245,8 @@ def test_empty_batch_is_rejected_where_a_loss_is_formed(lib):
     assert lib.ddf_train_step_eikonal(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 1, 0, 0.01, 0.1, None, 1, 1, 1, big,
                                       None) == _lib.DDF_ERR_INVALID_ARG
     paper = _lib.DdfPaperNet(8, 0, 1)
-    assert lib.ddf_paper_train_step(ctypes.byref(paper), 1, 1, 1, 1, 1e-3, 1, 1, 0, ctypes.byref(clamp), 1, 1, 1, big,
-                                    None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_paper_train_step(ctypes.byref(paper), 1, 1, 1, 1, 1e-3, 1, 1, 0, ctypes.byref(clamp), 0.5, 0, 1, 1,
+                                    1, big, None) == _lib.DDF_ERR_INVALID_ARG
     # the queries and gradients stay no-ops on an empty batch
     assert lib.ddf_forward(ctypes.byref(f32), None, 0, None, None, None) == _lib.DDF_OK
     assert lib.ddf_paper_forward(ctypes.byref(_lib.DdfPaperNet(8, 1, 1)), None, 0, None, None) == _lib.DDF_OK
@@ -271,9 +271,14 @@ def test_paper_network_validation(lib):
     assert lib.ddf_paper_backward(ctypes.byref(f32), 1, 1, 10, None, None, 1, 0, 1, 16, None) == _lib.DDF_ERR_WORKSPACE
     # the paper's network trains on its own losses only (clamp, squish)
     assert lib.ddf_paper_train_step(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 10, ctypes.byref(_lib.DdfLoss(0, 1.0)),
-                                    1, 1, 1, 1 << 40, None) == _lib.DDF_ERR_INVALID_ARG
-    assert lib.ddf_paper_train_step(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 10, None, 1, 1, 1, 1 << 40, None) == \
-        _lib.DDF_ERR_INVALID_ARG
+                                    0.5, 0, 1, 1, 1, 1 << 40, None) == _lib.DDF_ERR_INVALID_ARG
+    assert lib.ddf_paper_train_step(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 10, None, 0.5, 0, 1, 1, 1, 1 << 40,
+                                    None) == _lib.DDF_ERR_INVALID_ARG
+    # dropout must lie in [0, 1)
+    clamp = ctypes.byref(_lib.DdfLoss(_lib.LOSSES["clamp"], 1.0))
+    for bad in (1.0, -0.1, float("nan")):
+        assert lib.ddf_paper_train_step(ctypes.byref(f32), 1, 1, 1, 1, 1e-3, 1, 1, 10, clamp, bad, 0, 1, 1, 1, 1 << 40,
+                                        None) == _lib.DDF_ERR_INVALID_ARG
 
 
 def test_udf_noalloc_validation(lib):

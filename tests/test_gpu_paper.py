@@ -154,34 +154,60 @@ def test_paper_gradients_fp32_match_oracle(depth, n):
     torch.testing.assert_close(g3, 2 * g2, rtol=1e-6, atol=0)
 
 
-@pytest.mark.parametrize("loss,delta", [("clamp", 0.5), ("squish", 1.0)])
-def test_paper_train_step_matches_oracle(loss, delta):
+def _clear_batch(p, depth, rays, t, n, loss, delta, masks, tol=2e-5):
+    """A batch of n rays (from the candidates `rays`, `t`) in which every ray, under the dropout
+    masks of its position (masks: per position, or None), keeps every hidden pre-activation at
+    least `tol` from the ReLU kink (20 x the float32 error of a pre-activation) and its distance
+    away from the loss's branch points.  A
+    ray that fails at a position is replaced there by the next candidate, so the positions and
+    with them the masks stay fixed."""
+    m = rays.shape[1]
+    pick = np.arange(n) % m
+    good = np.zeros(n, dtype=bool)
+    for rnd in range(m // n):   # every position tries distinct candidates
+        cand = np.where(good, pick, (np.arange(n) + rnd * n) % m)
+        r = np.ascontiguousarray(rays[:, cand])
+        ds, _, pres = paper.forward(p, W, depth, r, return_acts=True, masks=masks)
+        ok = np.ones(n, dtype=bool)
+        for z in pres[:-1]:
+            ok &= np.abs(z).min(axis=0) > tol
+        tt = t[cand].astype(np.float64)
+        if loss == "clamp":
+            ok &= (np.abs(np.abs(ds) - delta) > tol) & (np.abs(np.clip(ds, -delta, delta) - np.clip(tt, -delta, delta)) > tol)
+        else:
+            ok &= np.abs(np.tanh(ds) - np.tanh(tt)) > tol
+        pick = np.where(good, pick, cand)
+        good |= ok
+        if good.all():
+            break
+    assert good.all()
+    return np.ascontiguousarray(rays[:, pick]), np.ascontiguousarray(t[pick])
+
+
+@pytest.mark.parametrize("loss,delta,p_drop", [("clamp", 0.5, 0.0), ("squish", 1.0, 0.0), ("clamp", 0.5, 0.5),
+                                               ("squish", 1.0, 0.3)])
+def test_paper_train_step_matches_oracle(loss, delta, p_drop):
     """One training step of the paper's network (Sec. V-A) with the clamp (Eq. 7) or squish
-    (Eq. 6) loss on labeller labels, on a batch clear of ReLU kinks and of the loss's branch
-    points: loss, per-block gradient, the Adam move and the repacked network against the oracle."""
-    banner("paper train step fp32: %s delta %g, depth 8, batch 2048" % (loss, delta))
-    depth = 8
+    (Eq. 6) loss on labeller labels, without and with dropout (the paper: 0.5; the GPU and the
+    oracle draw the same counter-based masks), on a batch clear of ReLU kinks and of the loss's
+    branch points under those masks: loss, per-block gradient, the Adam move and the repacked
+    network against the oracle."""
+    banner("paper train step fp32: %s delta %g dropout %g, depth 8, batch 1024" % (loss, delta, p_drop))
+    depth, n, seed = 8, 1024, 5
     v, f = synthetic.icosphere(2, 0.8)
     tris = synthetic.tri_soup(v, f)
-    o, d, _ = synthetic.training_rays(v, f, 2048, 76)
+    o, d, _ = synthetic.training_rays(v, f, 16384, 76)
     from oracle import geometry
     t = geometry.nearest_hit(o, d, tris)["t"].astype(np.float32)
-    rays = rays5_from(o, d)
     p = synthetic.paper_params(depth, 77)
-    keep = _kink_free(p, depth, rays)
-    ds = paper.forward(p, W, depth, rays)
-    tt = t.astype(np.float64)
-    if loss == "clamp":
-        keep &= (np.abs(np.abs(ds) - delta) > 1e-4) & (np.abs(np.clip(ds, -delta, delta) - np.clip(tt, -delta, delta)) > 1e-4)
-    else:
-        keep &= np.abs(np.tanh(ds) - np.tanh(tt)) > 1e-4
-    rays, t = np.ascontiguousarray(rays[:, keep]), t[keep]
-    n = t.size
+    masks = paper.dropout_masks(seed, 1, W, depth, n, p_drop)
+    rays, t = _clear_batch(p, depth, rays5_from(o, d), t, n, loss, delta, masks)
     pg = cuda(p)
-    tr = api.PaperTrainer(pg, depth, n, lr=1e-3, loss=loss, delta=delta)
+    tr = api.PaperTrainer(pg, depth, n, lr=1e-3, loss=loss, delta=delta, dropout=p_drop, seed=seed)
     out = host(tr.step(cuda(rays), cuda(t)))[0]
     z = np.zeros(p.size)
-    rl, gref, pnew, _, _ = paper.train_step(p.astype(np.float64), W, depth, rays, t, z, z, 1, loss, delta, lr=1e-3)
+    rl, gref, pnew, _, _ = paper.train_step(p.astype(np.float64), W, depth, rays, t, z, z, 1, loss, delta, lr=1e-3,
+                                            dropout=p_drop, seed=seed)
     assert abs(out - rl) < 1e-5 * abs(rl)
     worst = _per_block_close(host(tr.g), gref, depth, 1e-4)
     banner("  loss %.6g (oracle %.6g); worst per-block gradient error %.3g" % (out, rl, worst))
