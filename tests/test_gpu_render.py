@@ -430,10 +430,12 @@ def test_render_network_full_frame_crop_and_normal_subset():
     ref = render.render(scene, cfg_d, pixels=crop)
     rob4 = ref["robust"]
     rad_g, rad_r = host(rd.radiance).reshape(3, -1)[:, crop], ref["radiance"]
-    rerr = np.abs(rad_g - rad_r)[:, rob4] / max(rad_r.max(), 1e-6)
+    rerr = np.abs(rad_g - rad_r)[:, rob4].max(axis=0) / max(rad_r.max(), 1e-6)
     assert rob4.mean() > 0.5
     assert np.mean(rad_r.max(axis=0)[rob4] > 0) > 0.3   # lit pixels among them
-    assert rerr.mean() < 1e-3 and rerr.max() < 3e-2
+    # normals that turn with a hidden unit at its ReLU kink move a pixel's direct light (the
+    # oracle's margins cover hit decisions only): at most 1% of robust pixels beyond 3e-2
+    assert rerr.mean() < 1e-3 and np.mean(rerr > 3e-2) <= 0.01
     # sample 0's primary hit (hit, depth, normal; the frame's depth and normal outputs): the
     # oracle's camera ray of (pixel, sample 0) and the scene's nearest-hit query, per pixel on
     # the crop and on 2^16 pixels spread over the frame, where the oracle's margins make the
@@ -458,4 +460,76 @@ def test_render_network_full_frame_crop_and_normal_subset():
            "robust %.3f, err mean %.2e max %.2e" % (rob.mean(), both.sum(), np.quantile(derr, 0.99), derr.max(),
                                                     np.quantile(dots, 0.01), np.mean(dots < 0.999), rob4.mean(),
                                                     rerr.mean(), rerr.max()))
+    assert np.mean(dots < 0.999) <= 0.01
+
+
+def test_render_multi_object_full_frame_crop():
+    """The multi-object configuration at full resolution: 8 procedural objects (seeds 2-9) with
+    their own bf16 networks (widths 128 / 256, depths 4-8, each trained 100 steps on its
+    labelled rays), 16 rigid instances, 1280 x 720 at 4 samples.  Against the emulated-bf16
+    oracle tracing the same paths: a 64 x 64 crop at the frame centre per pixel (direct lighting
+    with one bounce where every query of the pixel is robust; sample 0's primary hit, depth and
+    normal where its query is) and the primary hits and normals of 4,096 pixels spread over the
+    frame (the oracle queries every instance for every ray, so the spread set is smaller than the
+    single-network test's)."""
+    from oracle import mlp, multi
+    banner("render multi-object bf16: 16 instances of 8 trained networks, 1280x720 4spp, crop vs the emulated oracle")
+    nets, nets_p = [], []
+    for seed in range(2, 10):
+        v, f = synthetic.multi_object_mesh(seed)
+        width, depth = synthetic.multi_object_network_shape(seed)
+        tris = cuda(synthetic.tri_soup(v, f))
+        o, d, _ = synthetic.training_rays(v, f, 1 << 18, seed)
+        og, dg = cuda(o), cuda(d)
+        t, _, cr = api.label_rays(og, dg, tris)
+        keep = (cr % 2) == 0
+        rays = api.assemble_rays(og, dg)[:, keep].contiguous()
+        t = t[keep].contiguous()
+        params = cuda(synthetic.xavier_params(width, depth, seed))
+        batch = 32768
+        tr = api.Trainer(params, width, depth, batch)
+        for i in range(100):
+            j = i % (rays.shape[1] // batch)
+            tr.step(rays[:, j * batch:(j + 1) * batch].contiguous(), t[j * batch:(j + 1) * batch].contiguous())
+        nets.append(api.Network(params, width, depth, "bf16"))
+        nets_p.append((host(params).astype(np.float64), width, depth))
+    inst = synthetic.instance_layout(16, 8, seed=10)
+    cfg = synthetic.multi_object_render(4)
+    cfg.bounces = 1
+    W, H = cfg.width, cfg.height
+    r = api.Renderer(cfg, nets=nets, instances=inst)
+    r.render()
+    torch.cuda.synchronize()
+    scene = multi.MultiScene(nets_p, inst, logit_margin=2e-2, precision="bf16")
+    rows, cols = np.meshgrid(np.arange(328, 392), np.arange(608, 672), indexing="ij")
+    crop = (rows * W + cols).ravel()
+    ref = render.render(scene, cfg, pixels=crop)
+    rob4 = ref["robust"]
+    rad_g, rad_r = host(r.radiance).reshape(3, -1)[:, crop], ref["radiance"]
+    rerr = np.abs(rad_g - rad_r)[:, rob4].max(axis=0) / max(rad_r.max(), 1e-6)
+    assert rob4.mean() > 0.5 and np.mean(rad_r.max(axis=0)[rob4] > 0) > 0.05
+    # a normal can turn with one hidden unit whose pre-activation lies within bf16 rounding of
+    # its ReLU kink (the oracle's margins cover hit decisions, not that), which moves the
+    # pixel's direct light: at most 1% of the robust pixels may differ by more than 3e-2
+    assert rerr.mean() < 1e-3 and np.mean(rerr > 3e-2) <= 0.01
+    spread = np.random.default_rng(12).choice(W * H, 4096, replace=False)
+    pix = np.concatenate([crop, spread])
+    zero = np.zeros(pix.size, dtype=np.int64)
+    o, d = render.camera_rays(cfg, pix, zero, render.path_keys(cfg.seed, pix, zero))
+    hit, t, g, ok = scene.intersect(o, d, np.inf)
+    dr = np.where(hit, t, np.inf)
+    dg = host(r.depth).ravel()[pix]
+    assert ok.mean() > 0.8
+    np.testing.assert_array_equal(np.isfinite(dg)[ok], np.isfinite(dr)[ok])
+    both = ok & np.isfinite(dr)
+    assert both.sum() > 0.05 * pix.size
+    derr = np.abs(dg[both] - dr[both]) / np.maximum(np.abs(dr[both]), 1.0)
+    assert np.quantile(derr, 0.99) < 1e-3 and derr.max() < 2e-2
+    nref = np.zeros((3, pix.size))
+    nref[:, hit] = mlp.normals(g[:, hit], d[:, hit])
+    dots = np.sum(host(r.normal).reshape(3, -1)[:, pix][:, both] * nref[:, both], axis=0)
+    banner("  crop direct light: robust %.3f, err mean %.2e max %.2e; primary: robust %.3f, hits %d, depth err p99 %.2e, "
+           "normal dot p1 %.5f, below 0.999 %.4f" % (rob4.mean(), rerr.mean(), rerr.max(), ok.mean(), both.sum(),
+                                                       np.quantile(derr, 0.99), np.quantile(dots, 0.01),
+                                                       np.mean(dots < 0.999)))
     assert np.mean(dots < 0.999) <= 0.01
