@@ -39,19 +39,24 @@ PROFILE = os.path.join(ROOT, "profiles", "forward_bf16_w128d4_2e24rays.md")
 KERNEL_SOURCES = ("mlp.hip", "mlp_device.hpp", "mlp_layout.hpp", "rays_device.hpp")
 
 
-def committed_traffic():
-    """HBM bytes per forward launch from the committed rocprofv3 counter summary, or None when
-    the kernel sources have changed since those counters were taken."""
+def committed_profile_field(name):
+    """A figure of the committed rocprofv3 counter summary of the forward kernel (HBM bytes per
+    launch, the clock under load), or None when the kernel sources have changed since those
+    counters were taken."""
     import hashlib
     try:
         text = open(PROFILE).read()
     except OSError:
         return None
-    fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch", "kernel_source_sha256")))
+    fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith((name, "kernel_source_sha256")))
     src = "".join(open(os.path.join(ROOT, "paper_2306_16142_amd", "csrc", f)).read() for f in KERNEL_SOURCES)
-    if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src.encode()).hexdigest():
+    if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src.encode()).hexdigest() or name not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[name])
+
+
+def committed_traffic():
+    return committed_profile_field("traffic_bytes_per_launch")
 
 
 def progress(msg):
@@ -671,6 +676,7 @@ def main():
     results.pop("mesh", None)
 
     bf = results["bf16"]
+    clock = committed_profile_field("clock_under_load_GHz")
     line = {
         "metric": "DDF queries/s (bf16 MFMA forward incl. ray assembly)",
         "value": bf["queries_per_s"],
@@ -693,7 +699,11 @@ def main():
                      "algorithmic_bytes_per_launch": 32 * n,
                      "kernel": "forward_kernel<bf16,128,2,lds> with ray assembly fused (ddf_query)",
                      "algorithmic_flop_per_query": flop_per_query(W, D),
-                     "issued_flop_per_query": issued_flop_per_query(W, D, "bf16")},
+                     "issued_flop_per_query": issued_flop_per_query(W, D, "bf16"),
+                     # the dense peak scales with the clock, which drops under this load
+                     # (GRBM_GUI_ACTIVE per XCD over the kernel time, committed profile)
+                     "clock_under_load_GHz": clock,
+                     "frac_at_measured_clock": (bf["forward_tflops"] / (PEAK["bf16"] * clock / 2.4)) if clock else None},
     }
     extra = {k: v for k, v in results.items() if k != "bf16"}
     extra["icosphere_training"] = train_info
