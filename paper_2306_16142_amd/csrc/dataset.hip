@@ -94,10 +94,11 @@ __global__ void ds_pair_kernel(const float *__restrict__ tris, int64_t m, const 
     const int64_t f = face_first + i / per_face;
     const int64_t pc = f * s_fc + (i / s_dr) % s_fc;   // column of the point's uniforms
     const int64_t dc = f * s_dr + i % s_dr;            // column of the direction's uniforms
-    // Eq. 8 with the fold of (a, b) outside the face; the test is exact in float64, so
-    // a sum that float32 would round to 1 still folds
+    // Eq. 8 with the fold of (a, b) outside the face; the test is exact (the float32 sum and
+    // its rounding error, Knuth's two-sum), so a sum that float32 rounds to 1 still folds
     float a = face_uv[pc], b = face_uv[m * s_fc + pc];
-    if ((double)a + (double)b > 1.0) {
+    const float ab = a + b, bb = ab - a, ab_err = (a - (ab - bb)) + (b - bb);
+    if (ab > 1.f || (ab == 1.f && ab_err > 0.f)) {
         a = 1.f - a;
         b = 1.f - b;
     }

@@ -90,42 +90,91 @@ __host__ __device__ inline int64_t gw_layer_off(int l) {
 }
 __host__ __device__ inline int64_t gw_floats(int depth) { return gw_layer_off(depth) + kPW + 1; }
 
-// Row norms of the weight normalisation, norm[l][i] = |v_l[i, :]|, in float64 (one wave per
-// row, fixed lane order).  The folded weight W = g v / |v| is formed in float64 and rounded
-// once to float32, so the bf16 rounding of a weight is decided from the same float32 value
-// whatever order the norm was summed in.
-__global__ void paper_norm_kernel(const float *__restrict__ params, int depth, double *__restrict__ norm) {
+// Float-float numbers (hi + lo, |lo| <= half an ulp of hi) on the error-free transforms of
+// Knuth (the rounding error of a sum) and Dekker (of a product, here by one fused
+// multiply-add): about 48 significant bits from float32 arithmetic alone, so that the fold
+// below rounds to the float32 nearest the exact weight without float64 on the GPU.  The
+// transforms need every sum and product rounded as written: contraction of a product into a
+// neighbouring sum (the compiler's default) is switched off inside them.
+struct FF {
+    float hi, lo;
+};
+__device__ inline FF ff_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+    const float s = a + b, bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ inline FF ff_fast_two_sum(float a, float b) {   // |a| >= |b|
+#pragma clang fp contract(off)
+    const float s = a + b;
+    return {s, b - (s - a)};
+}
+__device__ inline FF ff_two_prod(float a, float b) {
+#pragma clang fp contract(off)
+    const float p = a * b;
+    return {p, fmaf(a, b, -p)};
+}
+__device__ inline FF ff_add(FF x, FF y) {
+#pragma clang fp contract(off)
+    const FF s = ff_two_sum(x.hi, y.hi);
+    return ff_fast_two_sum(s.hi, s.lo + (x.lo + y.lo));
+}
+// sqrt(x) for x = hi + lo > 0: one Newton correction of the float32 root.
+__device__ inline FF ff_sqrt(FF x) {
+#pragma clang fp contract(off)
+    const float r = sqrtf(x.hi);
+    const FF rr = ff_two_prod(r, r);
+    return ff_fast_two_sum(r, (((x.hi - rr.hi) - rr.lo) + x.lo) / (2.f * r));
+}
+// (a b) / d rounded to float32, for float32 a, b and float-float d > 0: a quotient and one
+// correction from the exact remainder.
+__device__ inline float ff_mul_div(float a, float b, FF d) {
+#pragma clang fp contract(off)
+    const FF n = ff_two_prod(a, b);
+    const float q = n.hi / d.hi;
+    const FF qd = ff_two_prod(q, d.hi);
+    const float rem = (((n.hi - qd.hi) - qd.lo) + n.lo) - q * d.lo;
+    return q + rem / d.hi;
+}
+
+// Row norms of the weight normalisation, norm[l][i] = |v_l[i, :]| as a float-float pair (one
+// wave per row: float-float partial sums of the exact squares, added in a fixed lane order).
+// The folded weight W = g v / |v| is formed to about 48 bits and rounded once to float32, so
+// the bf16 rounding of a weight is decided from the float32 nearest the exact value, whatever
+// order the norm was summed in (a float32 fold flips the float32 value of ~3e-5 of the weights,
+// and each flip can move the bf16 rounding of that weight for every ray).
+__global__ void paper_norm_kernel(const float *__restrict__ params, int depth, FF *__restrict__ norm) {
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const int lane = threadIdx.x & 63;
     if (row >= (int64_t)depth * kPW) return;
     const int l = (int)(row / kPW), i = (int)(row % kPW);
     const int in = paper_in(l);
     const float *v = params + paper_layer_off(l) + (int64_t)i * in;
-    double s = 0.0;
-    for (int k = lane; k < in; k += 64) s = fma((double)v[k], (double)v[k], s);
+    FF s{0.f, 0.f};
+    for (int k = lane; k < in; k += 64) s = ff_add(s, ff_two_prod(v[k], v[k]));
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) norm[row] = sqrt(s);
+    for (int off = 32; off > 0; off >>= 1) s = ff_add(s, FF{__shfl_xor(s.hi, off), __shfl_xor(s.lo, off)});
+    if (lane == 0) norm[row] = ff_sqrt(s);
 }
 
-// Folded weight W_l[i][k] = (g_l[i] v_l[i][k]) / |v_l[i, :]| (float64), as float32.
-__device__ inline float paper_w(const float *params, const double *norm, int l, int i, int k) {
+// Folded weight W_l[i][k] = (g_l[i] v_l[i][k]) / |v_l[i, :]|, rounded to float32.
+__device__ inline float paper_w(const float *params, const FF *norm, int l, int i, int k) {
     const int in = paper_in(l);
-    const double g = params[paper_layer_off(l) + (int64_t)kPW * in + i];
-    return (float)((g * (double)params[paper_layer_off(l) + (int64_t)i * in + k]) / norm[(int64_t)l * kPW + i]);
+    const float g = params[paper_layer_off(l) + (int64_t)kPW * in + i];
+    return ff_mul_div(g, params[paper_layer_off(l) + (int64_t)i * in + k], norm[(int64_t)l * kPW + i]);
 }
 __device__ inline float paper_b(const float *params, int l, int i) {
     return params[paper_layer_off(l) + (int64_t)kPW * paper_in(l) + kPW + i];
 }
 
 // Float32 first-layer slot: M-block mb, K-step ks, lane -> W0[row][2 ks + lane / 32] (slot 5 = bias).
-__device__ inline float l0_slot(const float *params, const double *scale, int mb, int ks, int lane) {
+__device__ inline float l0_slot(const float *params, const FF *scale, int mb, int ks, int lane) {
     const int row = mb * 32 + (lane & 31), k = 2 * ks + (lane >> 5);
     return k < kInRaw ? paper_w(params, scale, 0, row, k) : paper_b(params, 0, row);
 }
 
 // One thread per packed element.
-__global__ void paper_pack_kernel(const float *__restrict__ params, const double *__restrict__ scale, int depth, int prec,
+__global__ void paper_pack_kernel(const float *__restrict__ params, const FF *__restrict__ scale, int depth, int prec,
                                   uint8_t *__restrict__ blob) {
     const PaperLayout L = paper_layout(depth, prec);
     const int nh = depth - 1;
@@ -921,7 +970,7 @@ __global__ __launch_bounds__(kSW * 64, 1) void paper_sweep_kernel(SweepArgs a) {
 // of the folded row): dL/dg = G . u, dL/dv = (g / |v|) (G - (G . u) u); the bias gradient is
 // copied; the output row's gradient and bias gradient are copied as they are.
 // gW: the plain gradients, per layer [512][in_l] then [512] (the output layer [512] then [1]).
-__global__ void paper_wn_grad_kernel(const float *__restrict__ params, const double *__restrict__ norm,
+__global__ void paper_wn_grad_kernel(const float *__restrict__ params, const FF *__restrict__ norm,
                                      const float *__restrict__ gW, int depth, float *__restrict__ g, bool accumulate) {
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const int lane = threadIdx.x & 63;
@@ -935,21 +984,22 @@ __global__ void paper_wn_grad_kernel(const float *__restrict__ params, const dou
     const int64_t po = paper_layer_off(l), go = gw_layer_off(l);
     const float *v = params + po + (int64_t)i * in;
     const float *G = gW + go + (int64_t)i * in;
-    const double nv = norm[row], gain = params[po + (int64_t)kPW * in + i];
-    double dot = 0.0;
-    for (int k = lane; k < in; k += 64) dot = fma((double)G[k], (double)v[k], dot);
+    const float nv = norm[row].hi + norm[row].lo, gain = params[po + (int64_t)kPW * in + i];
+    float dot = 0.f;
+    for (int k = lane; k < in; k += 64) dot = fmaf(G[k], v[k], dot);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
-    const double gg = dot / nv;   // G . u
+    const float gg = dot / nv;   // G . u
+    const float scale = gain / nv;
     float *gv = g + po + (int64_t)i * in;
     for (int k = lane; k < in; k += 64) {
-        const float d = (float)((gain / nv) * ((double)G[k] - gg * ((double)v[k] / nv)));
+        const float d = scale * (G[k] - gg * (v[k] / nv));
         gv[k] = accumulate ? gv[k] + d : d;
     }
     if (lane == 0) {
         float *gg_out = g + po + (int64_t)kPW * in + i, *gb_out = gg_out + kPW;
         const float db = gW[go + (int64_t)kPW * in + i];
-        *gg_out = accumulate ? *gg_out + (float)gg : (float)gg;
+        *gg_out = accumulate ? *gg_out + gg : gg;
         *gb_out = accumulate ? *gb_out + db : db;
     }
 }
@@ -1069,7 +1119,7 @@ ddf_status paper_param_grad(const ddf_paper_net *net, const float *params, const
         if (ddf_status st = dw_product(A, B, M, N, n, w.part, w.dbpart, w.gw + gw_layer_off(l), false, s)) return st;
     }
     const PaperLayout L = paper_layout(depth, kFP32);
-    const double *norm = reinterpret_cast<const double *>(reinterpret_cast<const uint8_t *>(net->packed) + L.bytes);
+    const FF *norm = reinterpret_cast<const FF *>(reinterpret_cast<const uint8_t *>(net->packed) + L.bytes);
     const int rows = depth * kPW + 1;
     hipLaunchKernelGGL(paper_wn_grad_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, params, norm, (const float *)w.gw,
                        depth, g_params, accumulate);
@@ -1117,11 +1167,11 @@ extern "C" ddf_status ddf_paper_pack(const float *params, int32_t depth, int32_t
     hipStream_t s = as_stream(stream);
     const PaperLayout L = paper_layout(depth, precision);
     // the row scales g / |v| live after the blob proper
-    double *norm = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(packed) + L.bytes);
+    FF *norm = reinterpret_cast<FF *>(reinterpret_cast<uint8_t *>(packed) + L.bytes);
     const int rows = depth * kPW;
     hipLaunchKernelGGL(paper_norm_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, params, depth, norm);
     if (ddf_status st = launch_status("ddf_paper_pack")) return st;
-    hipLaunchKernelGGL(paper_pack_kernel, dim3(2048), dim3(256), 0, s, params, (const double *)norm, depth, precision,
+    hipLaunchKernelGGL(paper_pack_kernel, dim3(2048), dim3(256), 0, s, params, (const FF *)norm, depth, precision,
                        (uint8_t *)packed);
     return launch_status("ddf_paper_pack");
 }
