@@ -464,12 +464,14 @@ def bench_label_train_render(args, torch, api, dev):
     torch.cuda.synchronize()
     rs = (time.perf_counter() - t0) / reps
     paths = cfg.width * cfg.height * cfg.spp
-    entering, shadows, _ = r.path_stats()
+    entering, shadows, hits, queries, _ = r.path_stats()
     entering, shadows = [int(x) for x in entering], [int(x) for x in shadows]
-    # network work of the frame from the device queue counts: every path entering a bounce is
-    # one query plus its input gradient (the transposed product, the same multiply-adds as the
-    # forward), every shadow ray one query
-    frame_flop = (2 * sum(entering) + sum(shadows)) * flop_per_query(width, depth)
+    hits, queries = [int(x) for x in hits], [int(x) for x in queries]
+    # network work of the frame from the device queue counts: every ray of a bounce that enters
+    # the cube is one query, every hit one input gradient for its normal (the transposed
+    # product, the same multiply-adds as the forward), every shadow ray one query.  The kernel
+    # runs the reverse sweep for every wave of 32 queries that holds a hit, so it issues more.
+    frame_flop = (sum(queries) + sum(hits) + sum(shadows)) * flop_per_query(width, depth)
     # shading normals against the mesh normal at the brute-force hit point (primary hits), and
     # primary-hit agreement, for the rendered network and the plain one
     cfg1 = synthetic.full_render(1)
@@ -494,7 +496,8 @@ def bench_label_train_render(args, torch, api, dev):
     out["render"] = {"workload": "1920x1080, %d spp, 4 bounces, RR after bounce 2, bf16 6x256 network trained %d "
                                  "directed-Eikonal steps (lam 1, h 0.02) on render rays" % (cfg.spp, rsteps),
                      "seconds_per_frame": rs, "path_samples_per_s": paths / rs, "timing": "warm hipGraph replay of the whole frame",
-                     "paths_per_bounce": entering, "shadow_rays_per_bounce": shadows,
+                     "paths_per_bounce": entering, "queries_per_bounce": queries, "hits_per_bounce": hits,
+                     "shadow_rays_per_bounce": shadows,
                      "network_flop_per_frame": frame_flop, "network_tflops": frame_flop / rs / 1e12,
                      "roofline_frac_bf16": frame_flop / rs / 1e12 / PEAK["bf16"],
                      **q_render,
@@ -554,7 +557,7 @@ def bench_multi(args, torch, api, dev):
         r.replay()
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
-    paths, _, per_net = r.path_stats()
+    paths, _, _, _, per_net = r.path_stats()
     per_net = per_net.astype(np.float64)
     imb = [float(row.max() / row.mean()) if row.mean() > 0 else None for row in per_net]
     return {"multi_object": {

@@ -481,10 +481,13 @@ ddf_status ddf_render_workspace_size(const ddf_scene *scene, const ddf_render_pa
 /* radiance [3][height][width] (mean over samples; row 0 at the top); depth [height][width]
  * and normal [3][height][width] of sample 0's primary hit (+inf / 0 on a miss) or NULL;
  * stats: device uint32, summed over chunks, or NULL: [bounces] paths entering each bounce,
- * then [bounces] shadow rays traced in each bounce (one per hit facing the light); for MULTI
- * followed by [bounces][n_nets] (ray, instance) pairs queried per network in each bounce's
- * nearest-hit pass (the queue balance across networks).  These counts give the network work
- * of a frame: every path entering a bounce is one query with its input gradient, every
+ * then [bounces] shadow rays traced in each bounce (one per hit facing the light); for MESH
+ * and NET followed by [bounces] hits in each bounce and [bounces] rays of each bounce's
+ * nearest-hit pass (NET queries only the rays that enter the cube [-1, 1]^3, where the field
+ * is defined: a ray that misses it misses the object; MESH traces every path); for MULTI by
+ * [bounces][n_nets] (ray, instance) pairs queried per network in each bounce's nearest-hit
+ * pass (the queue balance across networks).  For NET these counts give the network work of
+ * a frame: every queried ray is one query, every hit one input gradient (the normal), every
  * shadow ray one query. */
 ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_render_params *p, float *radiance,
                                 float *depth, float *normal, uint32_t *stats, void *ws, size_t ws_bytes,

@@ -193,13 +193,15 @@ def render(scene, cfg, pixels=None):
     and ``normal`` [3, H, W] of sample 0's primary hit (depth +inf and normal 0
     on a miss), ``robust`` [H, W] (every query of every sample of the pixel was
     decided away from its threshold), ``active`` per bounce (number of
-    paths that entered the bounce) and ``shadow`` per bounce (number of shadow
-    rays traced: hits whose normal faces the light).
+    paths that entered the bounce), ``queried`` per bounce (rays of the nearest-hit pass: a
+    network scene queries only the rays that enter the domain cube, any other scene traces
+    them all), ``hits`` per bounce (paths whose query hit) and ``shadow`` per bounce (number
+    of shadow rays traced: hits whose normal faces the light).
 
     ``pixels``: optional flat pixel indices (row * W + column).  Only those pixels
     are traced (every path is independent, so each one is traced exactly as in the
     whole frame) and the per-pixel arrays come back as [3, len] / [len] in that
-    order; ``active`` and ``shadow`` then count the paths of those pixels only.
+    order; the per-bounce counts then count the paths of those pixels only.
     """
     W, H, S = cfg.width, cfg.height, cfg.spp
     pix = np.arange(W * H, dtype=np.int64) if pixels is None else np.asarray(pixels, dtype=np.int64)
@@ -219,14 +221,19 @@ def render(scene, cfg, pixels=None):
     robust = np.ones(P, dtype=bool)
     depth0 = np.full(P, np.inf)
     normal0 = np.zeros((3, P))
-    active, shadow = [], []
+    active, queried, hits, shadow = [], [], [], []
     for b in range(cfg.bounces):
         idx = np.nonzero(alive)[0]
         active.append(int(idx.size))
         if idx.size == 0:
             break
+        if isinstance(scene, NetworkScene):   # a ray that misses the cube misses the object
+            queried.append(int(geometry.cube_entry(o[:, idx], d[:, idx])[2].sum()))
+        else:
+            queried.append(int(idx.size))
         hit, t, n, ok = scene.intersect(o[:, idx], d[:, idx], np.inf)
         robust[idx] &= ok
+        hits.append(int(hit.sum()))
         if b == 0:
             depth0[idx] = np.where(hit, t, np.inf)
         alive[idx[~hit]] = False
@@ -285,5 +292,7 @@ def render(scene, cfg, pixels=None):
         "normal": normal0[:, first].reshape((3,) + shape),
         "robust": robust.reshape(npx, S).all(axis=1).reshape(shape),
         "active": active,
+        "queried": queried,
+        "hits": hits,
         "shadow": shadow,
     }

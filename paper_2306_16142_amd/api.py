@@ -429,7 +429,7 @@ class Renderer:
         self.radiance = torch.empty((3, H, W), device=device, dtype=torch.float32)
         self.depth = torch.empty((H, W), device=device, dtype=torch.float32)
         self.normal = torch.empty((3, H, W), device=device, dtype=torch.float32)
-        nstats = cfg.bounces * (2 + (len(nets) if nets is not None else 0))
+        nstats = cfg.bounces * (2 + len(nets) if nets is not None else 4)
         self.stats = torch.empty(nstats, device=device, dtype=torch.int32)
 
     def render(self):
@@ -455,13 +455,16 @@ class Renderer:
         return self.radiance
 
     def path_stats(self):
-        """Paths entering each bounce, shadow rays traced in each bounce, and (multi-object
-        scenes) pairs per network per bounce."""
+        """Per bounce: paths entering it, shadow rays traced, hits and rays of the nearest-hit
+        pass (mesh and single-network scenes; a network scene queries only the rays that enter
+        the cube [-1, 1]^3), pairs per network (multi-object scenes); None where a scene has
+        no such count."""
         st = self.stats.cpu().numpy()
         b = self.cfg.bounces
         paths, shadows = st[:b], st[b:2 * b]
-        per_net = st[2 * b:].reshape(b, -1) if st.size > 2 * b else None
-        return paths, shadows, per_net
+        if self.keep[2] is not None:   # multi-object
+            return paths, shadows, None, None, st[2 * b:].reshape(b, -1)
+        return paths, shadows, st[2 * b:3 * b], st[3 * b:4 * b], None
 
 
 def fp8_scales(params, width, depth, calib_rays, net_fp32=None):

@@ -202,6 +202,10 @@ struct PathState {
 struct RenderWs {
     PathState ps;
     int *qa, *qb, *counts;
+    // single-network and mesh scenes (after every other buffer): queue position -> query slot
+    // (-1: the ray misses the cube [-1, 1]^3 and is not queried), and per bounce its hits
+    // [bounces] and the rays of its nearest-hit pass [bounces]
+    int *cmap, *xcounts;
     float *rays5, *t0, *logit, *dist, *grad, *ones;
     float *tq;
     int *triq;
@@ -281,6 +285,10 @@ RenderWs render_ws(int64_t C, int bounces, int n_inst, void *base) {
         w.mc.seg_count = (int *)take(4 * 2 * kMaxNets);
         w.mc.total = (int *)take(16);
     }
+    if (n_inst == 0) {
+        w.cmap = (int *)take(f);
+        w.xcounts = (int *)take((size_t)2 * bounces * 4);
+    }
     w.bytes = off;
     return w;
 }
@@ -350,18 +358,37 @@ __global__ void raygen_kernel(ddf_render_params p, Cam cam, int64_t C, int sampl
     }
 }
 
+// Network scenes: the queue's rays that enter the cube [-1, 1]^3 (where the field is
+// defined; a ray that misses it misses the object) become the bounce's network queries,
+// compacted; cmap[q] is the query slot of queue position q, or -1.
 __global__ void prep_kernel(int64_t C, const int *__restrict__ queue, const int *__restrict__ count, PathState ps,
-                            float *__restrict__ rays5, float *__restrict__ t0) {
+                            float *__restrict__ rays5, float *__restrict__ t0, int *__restrict__ cmap,
+                            int *__restrict__ query_count) {
     const int n = *count;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        const int id = queue[q];
-        const Vec3 o = load3(ps.o, C, id), d = load3(ps.d, C, id);
-        const float te = cube_entry(o, d);
-        t0[q] = te;
-        write_query(rays5, C, q, o, d, te);
+    // every thread of the block reaches the append (block-aggregated atomics)
+    __shared__ Append2 s_app;
+    const int64_t span = ((int64_t)n + blockDim.x - 1) / blockDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < span; q += (int64_t)gridDim.x * blockDim.x) {
+        Vec3 o{}, d{};
+        float te = NAN;
+        if (q < n) {
+            const int id = queue[q];
+            o = load3(ps.o, C, id);
+            d = load3(ps.d, C, id);
+            te = cube_entry(o, d);
+            t0[q] = te;
+        }
+        const bool enters = q < n && !isnan(te);
+        int slot, unused;
+        block_append2(query_count, enters, query_count, false, &s_app, slot, unused);
+        if (q < n) cmap[q] = enters ? slot : -1;
+        if (enters) write_query(rays5, C, slot, o, d, te);
     }
 }
 
+// kCount (single-network and mesh scenes): network answers through the compaction map, and
+// the bounce's hits counted into hits_out.
+template <bool kCount>
 __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int backend, const int *__restrict__ queue,
                              int *counts, int *__restrict__ next_queue, PathState ps, const float *__restrict__ t0,
                              const float *__restrict__ logit, const float *__restrict__ dist,
@@ -369,12 +396,15 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
                              const float *__restrict__ tris, int64_t m, int *__restrict__ sq, float *__restrict__ srays,
                              float *__restrict__ st0, float *__restrict__ stmax, float *__restrict__ scontrib,
                              float *__restrict__ depth, float *__restrict__ normal,
-                             const unsigned long long *__restrict__ best) {
+                             const unsigned long long *__restrict__ best, const int *__restrict__ cmap,
+                             int *__restrict__ hits_out) {
     const int n = counts[2 * bounce];
     const Vec3 light = v3(p.light_pos[0], p.light_pos[1], p.light_pos[2]);
     const int64_t hw = (int64_t)p.width * p.height;
     // every thread of the block reaches the append (block-aggregated atomics)
     __shared__ Append2 s_app;
+    __shared__ int s_hits;
+    int wave_hits = 0;   // kCount: hits among this wave's paths (wave-uniform)
     const int64_t span = ((int64_t)n + blockDim.x - 1) / blockDim.x * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < span; q += (int64_t)gridDim.x * blockDim.x) {
         bool hit = false, shadow = false, alive = false;
@@ -387,15 +417,23 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
             float t = 0.f;
             Vec3 nrm{};
             if (backend != DDF_BACKEND_MESH) {
-                if (backend == DDF_BACKEND_NET) {
+                int64_t qs = q;   // where the query's answers are
+                if (backend == DDF_BACKEND_NET && kCount) {
+                    const int c = cmap[q];   // -1: the ray misses the cube and was not queried
+                    if (c >= 0) {
+                        t = t0[q] + dist[c];
+                        hit = logit[c] > 0.f && t >= 0.f;   // a hit needs a non-negative distance
+                    }
+                    qs = c >= 0 ? c : 0;
+                } else if (backend == DDF_BACKEND_NET) {
                     const float te = t0[q];
                     t = te + dist[q];
-                    hit = !isnan(te) && logit[q] > 0.f && t >= 0.f;   // a hit needs a non-negative distance
+                    hit = !isnan(te) && logit[q] > 0.f && t >= 0.f;
                 } else {   // MULTI: nearest instance hit, its distance and world-space gradient
                     hit = best[q] != ~0ull;
                     t = dist[q];
                 }
-                const Vec3 g = load3(grad, C, q);
+                const Vec3 g = load3(grad, C, qs);
                 const float gn = sqrtf(dot(g, g)), gd = dot(g, d);
                 const float kappa = gd > 0.f ? -1.f : 1.f;   // Eq. 3: n . d < 0
                 nrm = gn > 0.f ? (kappa / gn) * g : (-1.0f / sqrtf(dot(d, d))) * d;
@@ -462,6 +500,7 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
                 }
             }
         }
+        if constexpr (kCount) wave_hits += (int)__popcll(__ballot(hit));
         int sslot, nslot;
         block_append2(&counts[2 * bounce + 1], shadow, &counts[2 * (bounce + 1)], alive, &s_app, sslot, nslot);
         if (shadow) {
@@ -473,12 +512,18 @@ __global__ void shade_kernel(ddf_render_params p, int64_t C, int bounce, int bac
                 st0[sslot] = te;
                 write_query(srays, C, sslot, xs, l, te);
             } else {   // world-space shadow ray: mesh labeller or per-instance culling
-                
                 store3(srays, C, sslot, xs);
                 store3(srays + 3 * C, C, sslot, l);
             }
         }
         if (alive) next_queue[nslot] = id;
+    }
+    if constexpr (kCount) {   // the bounce's hits: one LDS atomic per wave, one global atomic per block
+        if (threadIdx.x == 0) s_hits = 0;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0 && wave_hits) atomicAdd(&s_hits, wave_hits);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_hits) atomicAdd(hits_out, s_hits);
     }
 }
 
@@ -536,6 +581,17 @@ __global__ void stats_kernel(const int *counts, int bounces, uint32_t *stats) {
     if (b < bounces) {
         stats[b] += (uint32_t)counts[2 * b];
         stats[bounces + b] += (uint32_t)counts[2 * b + 1];
+    }
+}
+
+// Single-network and mesh scenes, per bounce: its hits (xstats[b]) and the rays of its
+// nearest-hit pass (xstats[bounces + b]: a network scene queries the rays that enter the
+// cube, the labeller traces them all).
+__global__ void xstats_kernel(const int *counts, const int *xcounts, int bounces, int backend, uint32_t *xstats) {
+    const int b = threadIdx.x;
+    if (b < bounces) {
+        xstats[b] += (uint32_t)xcounts[b];
+        xstats[bounces + b] += (uint32_t)(backend == DDF_BACKEND_NET ? xcounts[bounces + b] : counts[2 * b]);
     }
 }
 
@@ -877,13 +933,14 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
         hipLaunchKernelGGL(fill_kernel, dim3(grid_for(w.P)), dim3(256), 0, s, w.pb.ones, w.P, 1.0f);
     }
     hipLaunchKernelGGL(fill_kernel, dim3(grid_for(3 * hw)), dim3(256), 0, s, radiance, 3 * hw, 0.f);
-    const int64_t nstats = (int64_t)p->bounces * (multi ? 2 + scene->n_nets : 2);
+    const int64_t nstats = (int64_t)p->bounces * (multi ? 2 + scene->n_nets : 4);
     if (stats) hipLaunchKernelGGL(fill_kernel, dim3(grid_for(nstats)), dim3(256), 0, s, (float *)stats, nstats, 0.f);
     for (int base = 0; base < p->spp; base += S) {
         const int Sc = std::min(S, p->spp - base);
         const int64_t Cc = hw * Sc;
         hipLaunchKernelGGL(raygen_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, *p, cam, Cc, base, Sc, w.ps, w.qa,
                            w.counts, ncounts, w.ones, depth, normal);
+        if (!multi) hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(128), 0, s, w.xcounts, 2 * p->bounces);
         // path-state arrays use the chunk's own stride Cc (== C except in a short last chunk)
         PathState ps = w.ps;
         int *q = w.qa, *qn = w.qb;
@@ -891,13 +948,15 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
             const int *cnt = w.counts + 2 * b;
             const float *qdist = w.dist, *qgrad = w.grad;
             if (scene->backend == DDF_BACKEND_NET) {
-                hipLaunchKernelGGL(prep_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, Cc, q, cnt, ps, w.rays5, w.t0);
+                int *qcnt = w.xcounts + p->bounces + b;   // this bounce's queries
+                hipLaunchKernelGGL(prep_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, Cc, q, cnt, ps, w.rays5, w.t0,
+                                   w.cmap, qcnt);
                 GradArgs a{};
                 a.blob = (const uint8_t *)scene->net->packed;
                 a.depth = scene->net->depth;
                 a.rays = w.rays5;
                 a.n = Cc;
-                a.count_dev = cnt;
+                a.count_dev = qcnt;
                 a.g_dist_in = w.ones;
                 a.logit_out = w.logit;
                 a.dist_out = w.dist;
@@ -915,9 +974,16 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
                 if (ddf_status st = label_queue(ps.o, ps.d, Cc, q, cnt, scene->tris, scene->m, 0.f, INFINITY, w.tq, w.triq, s))
                     return st;
             }
-            hipLaunchKernelGGL(shade_kernel, dim3(grid_for(Cc)), dim3(256), 0, s, *p, Cc, b, scene->backend, q, w.counts,
-                               qn, ps, w.t0, w.logit, qdist, qgrad, w.tq, w.triq, scene->tris, scene->m, w.sq, w.srays,
-                               w.st0, w.stmax, w.scontrib, depth, normal, (const unsigned long long *)w.best);
+            if (multi)
+                hipLaunchKernelGGL(shade_kernel<false>, dim3(grid_for(Cc)), dim3(256), 0, s, *p, Cc, b, scene->backend, q,
+                                   w.counts, qn, ps, w.t0, w.logit, qdist, qgrad, w.tq, w.triq, scene->tris, scene->m, w.sq,
+                                   w.srays, w.st0, w.stmax, w.scontrib, depth, normal, (const unsigned long long *)w.best,
+                                   (const int *)nullptr, (int *)nullptr);
+            else
+                hipLaunchKernelGGL(shade_kernel<true>, dim3(grid_for(Cc)), dim3(256), 0, s, *p, Cc, b, scene->backend, q,
+                                   w.counts, qn, ps, w.t0, w.logit, qdist, qgrad, w.tq, w.triq, scene->tris, scene->m, w.sq,
+                                   w.srays, w.st0, w.stmax, w.scontrib, depth, normal, (const unsigned long long *)w.best,
+                                   (const int *)w.cmap, w.xcounts + b);
             if (ddf_status st = launch_status("ddf_render_wavefront (shade)")) return st;
             const int *scnt = w.counts + 2 * b + 1;
             if (scene->backend == DDF_BACKEND_NET) {
@@ -937,6 +1003,9 @@ extern "C" ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_ren
         }
         hipLaunchKernelGGL(accumulate_kernel, dim3(grid_for(hw)), dim3(256), 0, s, hw, Sc, Cc, ps.L, radiance);
         if (stats) hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(64), 0, s, w.counts, p->bounces, stats);
+        if (stats && !multi)
+            hipLaunchKernelGGL(xstats_kernel, dim3(1), dim3(64), 0, s, w.counts, w.xcounts, p->bounces, scene->backend,
+                               stats + 2 * p->bounces);
         if (ddf_status st = launch_status("ddf_render_wavefront")) return st;
     }
     hipLaunchKernelGGL(scale_kernel, dim3(grid_for(3 * hw)), dim3(256), 0, s, radiance, 3 * hw, 1.0f / (float)p->spp);

@@ -211,3 +211,57 @@ def test_shadow_ray_counts():
     pad = lambda c: c + [0] * (cfg.bounces - len(c))
     assert [x + y for x, y in zip(pad(a["shadow"]), pad(b["shadow"]))] == pad(out["shadow"])
     assert [x + y for x, y in zip(pad(a["active"]), pad(b["active"]))] == pad(out["active"])
+
+
+def test_hit_counts():
+    """Hits per bounce: at bounce 0 exactly the camera rays that the brute-force labeller finds
+    hitting the mesh; a bounce ray leaves a closed convex object through the hemisphere of its
+    outward normal, so with the light inside the icosphere (no shadow rays) nothing is hit
+    again; every continuing path was a hit, and before Russian roulette every hit continues;
+    a split of the pixels splits the counts."""
+    from synthetic.scenes import Light
+    from oracle import geometry
+    v, f = synthetic.icosphere(1, 0.8)
+    tris = synthetic.tri_soup(v, f)
+    scene = render.MeshScene(tris)
+    cfg = synthetic.RenderConfig(16, 12, 2, 3, 1, 2)
+    out = render.render(scene, cfg)
+    P = 16 * 12 * 2
+    pid = np.arange(P)
+    pixel, sample = pid // 2, pid % 2
+    o, d = render.camera_rays(cfg, pixel, sample, render.path_keys(cfg.seed, pixel, sample))
+    assert out["hits"][0] == int((geometry.nearest_hit(o, d, tris)["tri"] >= 0).sum()) > 0
+    pad = lambda c: c + [0] * (cfg.bounces - len(c))
+    hits, active, shadow = pad(out["hits"]), pad(out["active"]), pad(out["shadow"])
+    assert all(s <= h <= a for s, h, a in zip(shadow, hits, active))
+    assert all(active[b + 1] <= hits[b] for b in range(cfg.bounces - 1))
+    assert active[1] == hits[0]   # Russian roulette starts after bounce 1
+    inside = synthetic.RenderConfig(16, 12, 2, 3, 1, 2, light=Light(position=(0.0, 0.0, 0.0)))
+    dark = render.render(scene, inside)
+    assert dark["hits"][0] == out["hits"][0] and sum(pad(dark["hits"])[1:]) == 0
+    pix = np.arange(16 * 12)
+    a, b = render.render(scene, cfg, pixels=pix[::2]), render.render(scene, cfg, pixels=pix[1::2])
+    assert [x + y for x, y in zip(pad(a["hits"]), pad(b["hits"]))] == hits
+
+
+def test_queried_rays_of_a_network_scene():
+    """A network scene queries only the rays that enter the domain cube: at bounce 0 the count
+    lies between brute-force counts of camera rays that pass through a slightly smaller and a
+    slightly larger cube (points sampled along each ray, no slab test); the mesh scene traces
+    every path; no count exceeds the paths of its bounce."""
+    p = _hitting(32, 2, 11)
+    cfg = synthetic.RenderConfig(20, 14, 2, 3, 1, 5)
+    cfg.camera.eye = (0.3, -4.5, 1.2)   # the cube fills part of the view
+    out = render.render(render.NetworkScene(p, 32, 2), cfg)
+    P = 20 * 14 * 2
+    pid = np.arange(P)
+    o, d = render.camera_rays(cfg, pid // 2, pid % 2, render.path_keys(cfg.seed, pid // 2, pid % 2))
+    t = np.linspace(0.0, 9.0, 9001)
+    pts = o[:, :, None] + d[:, :, None] * t[None, None, :]
+    inner = int(np.any(np.all(np.abs(pts) <= 1.0 - 2e-3, axis=0), axis=1).sum())
+    outer = int(np.any(np.all(np.abs(pts) <= 1.0 + 2e-3, axis=0), axis=1).sum())
+    assert 0 < inner <= out["queried"][0] <= outer < P
+    assert all(qn <= a for qn, a in zip(out["queried"], out["active"]))
+    v, f = synthetic.icosphere(1, 0.8)
+    mesh = render.render(render.MeshScene(synthetic.tri_soup(v, f)), cfg)
+    assert mesh["queried"] == mesh["active"]
