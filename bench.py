@@ -560,6 +560,12 @@ def bench_multi(args, torch, api, dev):
     paths, _, _, _, per_net = r.path_stats()
     per_net = per_net.astype(np.float64)
     imb = [float(row.max() / row.mean()) if row.mean() > 0 else None for row in per_net]
+    # network work of the nearest-hit passes alone, from the device pair counts: every (ray,
+    # instance) pair is one query of its instance's network.  The normals of the hits and the
+    # shadow pairs come on top (not counted on the device for these scenes), so the rate is
+    # a lower bound on the frame's network work
+    main_flop = float(sum(per_net[b][k] * flop_per_query(*shapes[k]) for b in range(per_net.shape[0])
+                          for k in range(per_net.shape[1])))
     return {"multi_object": {
         "workload": "8 objects (seeds 2-9, %s triangles), 16 instances, 1280x720, %d spp, 3 bounces, bf16 networks "
                     "(width, depth) = %s trained %d steps each" % (tris_counts, cfg.spp, shapes, args.multi_train_steps),
@@ -569,6 +575,8 @@ def bench_multi(args, torch, api, dev):
                      "median_ms": {k: {str(v): round(ms, 3) for v, ms in t.items()} for k, t in tuned["median_ms"].items()}},
         "paths_per_bounce": [int(x) for x in paths],
         "pairs_per_network_per_bounce": per_net.astype(np.int64).tolist(),
+        "nearest_hit_pass_flop_per_frame": main_flop, "nearest_hit_pass_tflops": main_flop / sec / 1e12,
+        "roofline_frac_bf16_lower_bound": main_flop / sec / 1e12 / PEAK["bf16"],
         "queue_imbalance_max_over_mean": imb}}
 
 
