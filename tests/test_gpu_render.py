@@ -131,6 +131,32 @@ def test_render_network_bf16_runs_and_is_reproducible():
     assert np.all(hits <= qs) and np.all(qs <= st) and np.all(st[1:] <= hits[:-1])
 
 
+def test_render_network_camera_misses_the_cube():
+    """A camera that looks away from the domain cube: no ray enters it, so nothing is queried
+    (an empty query queue through the streamed kernel), nothing is hit, the image is black;
+    then the same network seen from the front is queried for exactly the rays that enter."""
+    banner("render network bf16: camera looking away from the cube (empty queries), then towards it")
+    p = _hitting_params(256, 2, 61)
+    net = api.Network(cuda(p), 256, 2, "bf16")
+    cfg = synthetic.RenderConfig(16, 12, 2, 2, 1, 4)
+    cfg.camera.eye = (0.0, -5.0, 0.0)
+    cfg.camera.target = (0.0, -10.0, 0.0)
+    r = api.Renderer(cfg, net=net)
+    r.render()
+    torch.cuda.synchronize()
+    paths, shadows, hits, queries, _ = r.path_stats()
+    assert paths[0] == 16 * 12 * 2 and queries[0] == 0 and hits[0] == 0 and shadows[0] == 0 and paths[1] == 0
+    assert float(host(r.radiance).max()) == 0.0 and np.all(np.isinf(host(r.depth)))
+    cfg.camera.target = (0.0, 0.0, 0.0)
+    r = api.Renderer(cfg, net=net)
+    r.render()
+    torch.cuda.synchronize()
+    paths, shadows, hits, queries, _ = r.path_stats()
+    ref = render.render(render.NetworkScene(p, 256, 2, logit_margin=2e-2, precision="bf16"), cfg)
+    assert 0 < queries[0] < paths[0] and abs(int(queries[0]) - ref["queried"][0]) <= 1
+    assert abs(int(hits[0]) - ref["hits"][0]) <= 2
+
+
 def _compare_bf16(r, ref, name):
     """bf16 kernels against the oracle evaluating the same networks in emulated bfloat16
     (bfloat16 operands, float64 sums): decisions agree where the oracle's margins make them
