@@ -86,7 +86,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--quick", action="store_true", help="primary line only (no secondary workloads)")
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--train-steps", type=int, default=20)
