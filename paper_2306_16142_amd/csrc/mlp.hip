@@ -766,9 +766,9 @@ __global__ __launch_bounds__(NB == 2 ? 512 : 256) void forward_kernel(
             valid_any |= r < n;
             nan_ray[nb] = isnan(v[0]) || isnan(v[1]) || isnan(v[2]) || isnan(v[3]) || isnan(v[4]);
             float feat[kSlotsPerHalf];
-            encode_var<P == kFP32>(h ? v[3] : v[0], feat);
-            encode_var<P == kFP32>(h ? v[4] : v[1], feat + kFeatPerVar);
-            encode_var<P == kFP32>(h ? 0.f : v[2], feat + 2 * kFeatPerVar);
+            encode_var<P == kFP32, P == kFP8>(h ? v[3] : v[0], feat);
+            encode_var<P == kFP32, P == kFP8>(h ? v[4] : v[1], feat + kFeatPerVar);
+            encode_var<P == kFP32, P == kFP8>(h ? 0.f : v[2], feat + 2 * kFeatPerVar);
             feat[kSlotsPerHalf - 1] = 0.f;
             if constexpr (P == kBF16) {
                 feat[kBiasSlot0] = h ? 1.f : feat[kBiasSlot0];

@@ -45,16 +45,32 @@ __device__ inline void sincos_moderate(float v, float &s, float &c) {
     c = __uint_as_float(__float_as_uint(co) ^ ((uint32_t)((q + 1) & 2) << 30));
 }
 
+// sin and cos of v from the hardware's sine and cosine (whose argument is in turns), for
+// features that are rounded to e4m3 (3 mantissa bits): the units' error, amplified 32x by the
+// double-angle recurrence at the top frequency, stays far below one e4m3 step.  A wavefront
+// holding any argument beyond kSinCosFastMax (or infinite or NaN) calls sincosf.
+__device__ inline void sincos_hw(float v, float &s, float &c) {
+    if (__builtin_expect(__any(!(fabsf(v) <= kSinCosFastMax)), 0)) {
+        sincosf(v, &s, &c);
+        return;
+    }
+    const float turns = v * 0x1.45f306p-3f;   // 1 / (2 pi)
+    s = __builtin_amdgcn_sinf(turns);
+    c = __builtin_amdgcn_cosf(turns);
+}
+
 // Features of one variable: raw, sin(2^k v), cos(2^k v), k = 0..5.  In float32 mode every
 // frequency calls sincosf (arguments 2^k v are exact); in reduced precision the base pair
-// comes from sincos_moderate and the higher frequencies follow the double-angle recurrence.
-// (The hardware sine was tried for the base frequency: its error, amplified 32x by the
-// recurrence, flipped visibly more bf16 roundings than float32 rounding does.)
-template <bool kExact>
+// comes from sincos_moderate (bf16) or the hardware units (kHw: fp8) and the higher
+// frequencies follow the double-angle recurrence.  (The hardware sine was tried for the bf16
+// base frequency: its error, amplified 32x by the recurrence, flipped visibly more bf16
+// roundings than float32 rounding does.)
+template <bool kExact, bool kHw = false>
 __device__ inline void encode_var(float v, float *f) {
     f[0] = v;
     float s, c;
     if constexpr (kExact) sincosf(v, &s, &c);
+    else if constexpr (kHw) sincos_hw(v, s, c);
     else sincos_moderate(v, s, c);
     f[1] = s;
     f[1 + kNFreq] = c;
