@@ -488,7 +488,8 @@ ddf_status ddf_render_workspace_size(const ddf_scene *scene, const ddf_render_pa
  * [bounces][n_nets] (ray, instance) pairs queried per network in each bounce's nearest-hit
  * pass (the queue balance across networks).  For NET these counts give the network work of
  * a frame: every queried ray is one query, every hit one input gradient (the normal), every
- * shadow ray one query. */
+ * shadow ray one query.  stats holds 4 x bounces values (MESH, NET) or (2 + n_nets) x bounces
+ * (MULTI). */
 ddf_status ddf_render_wavefront(const ddf_scene *scene, const ddf_render_params *p, float *radiance,
                                 float *depth, float *normal, uint32_t *stats, void *ws, size_t ws_bytes,
                                 ddf_stream stream);
