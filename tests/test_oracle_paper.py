@@ -299,6 +299,17 @@ def test_dropout_keep_rate_and_independence(p_drop):
     assert abs(np.mean(k[:, 1:] == k[:, :-1]) - agree) < 6 * np.sqrt(agree * (1 - agree) / (w * n))
 
 
+def test_dropout_keep_boundary():
+    """The draw is a 24-bit uniform u on {0, 2^-24, ..., 1 - 2^-24}; keeping u >= p keeps a unit
+    with probability exactly 1 - p for every p on that grid, and so keeps every unit at p = 0.
+    This sample of 2^24 draws holds a draw in the lowest bin (u = 0: dropped at p = 2^-24), so a
+    strict comparison, which drops it at p = 0, fails here."""
+    w, n = 512, 32768
+    assert paper.dropout_keep(1, 0, 0, w, n, 0.0).all()
+    low = ~paper.dropout_keep(1, 0, 0, w, n, 2.0 ** -24)
+    assert 1 <= low.sum() <= 8   # about one draw per 2^24 lands in the lowest bin
+
+
 def test_dropout_zero_is_the_query_network():
     width, depth = 16, 3
     p = _params(width, depth, 21).astype(np.float64)
