@@ -161,6 +161,7 @@ struct InstDev {
     int pad[3];
 };
 constexpr int kMaxInstances = 64;
+constexpr int kMaxCullBlocks = 8192;   // workgroups of one culling pass
 constexpr int kInstChunk = 8;
 struct InstChunk {
     InstDev v[kInstChunk];
@@ -192,6 +193,7 @@ struct MultiCounts {
     int *inst_count, *inst_cursor, *inst_off;   // [kMaxInstances]
     int *seg_offset, *seg_count;                // [n_nets]
     int *total;                                 // [1]
+    int *block_count;                           // [culling block][kMaxInstances]: pass 0's counts
 };
 
 struct PathState {
@@ -284,6 +286,7 @@ RenderWs render_ws(int64_t C, int bounces, int n_inst, void *base) {
         w.mc.seg_offset = (int *)take(4 * 2 * kMaxNets);
         w.mc.seg_count = (int *)take(4 * 2 * kMaxNets);
         w.mc.total = (int *)take(16);
+        w.mc.block_count = (int *)take((size_t)kMaxCullBlocks * kMaxInstances * 4);
     }
     if (n_inst == 0) {
         w.cmap = (int *)take(f);
@@ -601,7 +604,9 @@ __global__ void xstats_kernel(const int *counts, const int *xcounts, int bounces
 // grouped by instance (and so by network: instances are ordered by network).  Each block
 // owns a contiguous range of the queue and aggregates in LDS, so the global counters see
 // one atomic per block and instance (per-wave atomics on the same few counters serialised
-// in L2).  Pass 1 culls its range twice: once to reserve its slots, once to write.
+// in L2).  Both passes run the same grid, so each block covers the same range in both: pass 0
+// keeps its per-instance counts, from which pass 1 reserves its slots before its one culling
+// sweep that writes.
 constexpr int kCullBlock = 256;
 
 template <bool kScatter>
@@ -653,16 +658,18 @@ __global__ __launch_bounds__(kCullBlock) void cull_kernel(int64_t C, const int *
             }
         }
     };
-    sweep(false);
-    __syncthreads();
+    int *const bcount = mc.block_count + (int64_t)blockIdx.x * kMaxInstances;
     if constexpr (!kScatter) {
-        for (int i = threadIdx.x; i < n_inst; i += blockDim.x)
+        sweep(false);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+            bcount[i] = s_cnt[i];
             if (s_cnt[i]) atomicAdd(&mc.inst_count[i], s_cnt[i]);
-        return;
+        }
     } else {
         for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
-            s_base[i] = mc.inst_off[i] + (s_cnt[i] ? atomicAdd(&mc.inst_cursor[i], s_cnt[i]) : 0);
-            s_cnt[i] = 0;
+            const int c = bcount[i];
+            s_base[i] = mc.inst_off[i] + (c ? atomicAdd(&mc.inst_cursor[i], c) : 0);
         }
         __syncthreads();
         sweep(true);
@@ -843,7 +850,7 @@ ddf_status multi_query(const ddf_scene *scene, const MultiPlan &mp, RenderWs &w,
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(kMaxInstances), 0, s, w.mc.inst_count, kMaxInstances);
     // a few thousand rays per block (a tuning knob): one global atomic per block and instance
     const int64_t rpb = tuning(DDF_TUNE_CULL_RAYS_PER_BLOCK);
-    const unsigned gCull = (unsigned)std::max<int64_t>(1, std::min<int64_t>((C + rpb - 1) / rpb, 8192));
+    const unsigned gCull = (unsigned)std::max<int64_t>(1, std::min<int64_t>((C + rpb - 1) / rpb, kMaxCullBlocks));
     hipLaunchKernelGGL(cull_kernel<false>, dim3(gCull), dim3(kCullBlock), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);
     hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(64), 0, s, mp.n_inst, w.inst, mp.n_nets, w.mc, net_stats, map);
     hipLaunchKernelGGL(cull_kernel<true>, dim3(gCull), dim3(kCullBlock), 0, s, C, queue, count, po, pd, w.inst, mp.n_inst, w.mc, w.pb, w.P);
