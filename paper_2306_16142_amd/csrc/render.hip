@@ -158,7 +158,8 @@ struct InstDev {
     float R[9];
     float T[3];
     int net;
-    int pad[3];
+    float r2;   // squared radius of a world sphere about T holding the instance's cube (INF: none)
+    int pad[2];
 };
 constexpr int kMaxInstances = 64;
 constexpr int kMaxCullBlocks = 8192;   // workgroups of one culling pass
@@ -638,9 +639,19 @@ __global__ __launch_bounds__(kCullBlock) void cull_kernel(int64_t C, const int *
                 d = load3(pd, C, src);
             }
             for (int i = 0; i < n_inst; ++i) {
-                Vec3 oo, dd;
-                to_object(s_inst[i], o, d, oo, dd);
-                const float te = live ? cube_entry(oo, dd) : NAN;
+                // A ray whose line passes farther than r from T, or that starts outside the
+                // sphere heading away from it, cannot enter the cube; every other ray takes
+                // the exact test (NaN arguments reject nothing).
+                const InstDev &in = s_inst[i];
+                const Vec3 c = v3(in.T[0], in.T[1], in.T[2]) - o;
+                const Vec3 x = cross(c, d);
+                const bool away = dot(x, x) > in.r2 * dot(d, d) || (dot(c, c) > in.r2 && dot(c, d) < 0.f);
+                Vec3 oo{}, dd{};
+                float te = NAN;
+                if (live && !away) {
+                    to_object(in, o, d, oo, dd);
+                    te = cube_entry(oo, dd);
+                }
                 const bool want = !isnan(te);
                 if (!write) {
                     const uint64_t mask = __ballot(want);
@@ -835,6 +846,16 @@ MultiPlan make_plan(const ddf_scene *scene) {
         for (int j = 0; j < 9; ++j) d.R[j] = scene->instances[i].R[j];
         for (int j = 0; j < 3; ++j) d.T[j] = scene->instances[i].T[j];
         d.net = pos[scene->instances[i].net];
+        // a rotation (R R^T = I) moves the cube [-1, 1]^3 within sqrt(3) of T; the radius is
+        // widened by half a percent to cover rounding, and any other R culls exactly only
+        double err = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double e = a == b ? -1.0 : 0.0;
+                for (int k = 0; k < 3; ++k) e += (double)d.R[3 * a + k] * d.R[3 * b + k];
+                err = std::max(err, std::fabs(e));
+            }
+        d.r2 = err <= 1e-4 ? 3.0f * 1.01f : INFINITY;
         mp.inst.push_back(d);
     }
     return mp;
