@@ -641,11 +641,13 @@ __global__ __launch_bounds__(kCullBlock) void cull_kernel(int64_t C, const int *
             for (int i = 0; i < n_inst; ++i) {
                 // A ray whose line passes farther than r from T, or that starts outside the
                 // sphere heading away from it, cannot enter the cube; every other ray takes
-                // the exact test (NaN arguments reject nothing).
+                // the exact test (NaN arguments reject nothing).  The line test's margin grows
+                // with |c|^2: the rounding of |c x d|^2 is below 1e-6 |c|^2 |d|^2.
                 const InstDev &in = s_inst[i];
                 const Vec3 c = v3(in.T[0], in.T[1], in.T[2]) - o;
                 const Vec3 x = cross(c, d);
-                const bool away = dot(x, x) > in.r2 * dot(d, d) || (dot(c, c) > in.r2 && dot(c, d) < 0.f);
+                const float cc = dot(c, c);
+                const bool away = dot(x, x) > (in.r2 + 4e-6f * cc) * dot(d, d) || (cc > in.r2 && dot(c, d) < 0.f);
                 Vec3 oo{}, dd{};
                 float te = NAN;
                 if (live && !away) {
